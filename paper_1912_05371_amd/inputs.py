@@ -1,0 +1,224 @@
+"""Seeded synthetic inputs shared by the HIP path and the oracle.
+
+This module produces leaf sets (levels and block indices of 2:1-balanced
+periodic octrees) and initial fields sampled at grid points.  It holds none of
+the method's arithmetic (no derivatives, no wavelet prediction, no mask, no
+time stepping): only grid geometry, random numbers and closed-form initial
+conditions.  Block positions follow the non-redundant reading of the paper's
+nested dyadic grids (Sec. 3.1): level J has 2^J blocks per axis and the
+interior point i of block b sits at x = (b bs + i) L / (2^J bs).
+
+Leaves are returned in Morton order (level-1 octal digit most significant,
+digit = xbit + 2 ybit + 4 zbit, Sec. 4.1), which keeps neighbours close in
+memory.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+REF = 20
+
+
+def morton_key(lev, ix, iy, iz) -> np.ndarray:
+    lev = np.asarray(lev, np.int64)
+    ix, iy, iz = (np.asarray(a, np.int64) for a in (ix, iy, iz))
+    key = np.zeros(lev.shape, np.uint64)
+    for b in range(REF):
+        sh = REF - 1 - b  # bit of the coordinate scaled to the reference level
+        xs = (ix << (REF - lev)) >> sh & 1
+        ys = (iy << (REF - lev)) >> sh & 1
+        zs = (iz << (REF - lev)) >> sh & 1
+        key = (key << np.uint64(3)) | (xs + 2 * ys + 4 * zs).astype(np.uint64)
+    return key
+
+
+def _sorted(leaves):
+    lev = np.array([l[0] for l in leaves], np.int32)
+    ix = np.array([l[1] for l in leaves], np.int64)
+    iy = np.array([l[2] for l in leaves], np.int64)
+    iz = np.array([l[3] for l in leaves], np.int64)
+    order = np.argsort(morton_key(lev, ix, iy, iz), kind="stable")
+    return lev[order], ix[order], iy[order], iz[order]
+
+
+def uniform_leaves(J: int):
+    n = 1 << J
+    return _sorted([(J, x, y, z) for z in range(n) for y in range(n) for x in range(n)])
+
+
+# --------------------------------------------------------------------------
+# Leaf dictionaries with 26-neighbour 2:1 balancing (grid generation only).
+# --------------------------------------------------------------------------
+class LeafSet:
+    """Mutable set of leaves {(lev, x, y, z)} of a periodic octree."""
+
+    def __init__(self, leaves, jmin: int):
+        self.s = set((int(a), int(b), int(c), int(d)) for a, b, c, d in leaves)
+        self.jmin = jmin
+
+    def leaf_covering(self, J, x, y, z):
+        """Leaf of level <= J containing the level-J box (x,y,z) (wrapped), or None."""
+        n = 1 << J
+        x, y, z = x % n, y % n, z % n
+        for K in range(J, self.jmin - 1, -1):
+            s = J - K
+            key = (K, x >> s, y >> s, z >> s)
+            if key in self.s:
+                return key
+        return None
+
+    def refine(self, leaf):
+        """Split a leaf into 8 children, first refining coarser neighbours."""
+        J, x, y, z = leaf
+        if leaf not in self.s:
+            return
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    if dx == dy == dz == 0:
+                        continue
+                    nb = self.leaf_covering(J, x + dx, y + dy, z + dz)
+                    if nb is not None and nb[0] < J:
+                        self.refine(nb)
+        self.s.discard(leaf)
+        for c in range(8):
+            self.s.add((J + 1, 2 * x + (c & 1), 2 * y + (c >> 1 & 1), 2 * z + (c >> 2 & 1)))
+
+    def arrays(self):
+        return _sorted(sorted(self.s))
+
+
+def random_balanced_leaves(seed: int, j0: int, jmax: int, target: int):
+    """Refine random leaves of level < jmax from a uniform level-j0 grid, keeping
+    the tree 2:1 balanced over 26 neighbours, until at least `target` leaves."""
+    rng = np.random.default_rng(seed)
+    ls = LeafSet([(j0, x, y, z) for z in range(1 << j0) for y in range(1 << j0)
+                  for x in range(1 << j0)], j0)
+    while len(ls.s) < target:
+        cand = sorted(l for l in ls.s if l[0] < jmax)
+        pick = cand[int(rng.integers(len(cand)))]
+        ls.refine(pick)
+    return ls.arrays()
+
+
+def ball_leaves(L: float, j0: int, centre, radius: float):
+    """Level j0 everywhere, level j0+1 in every level-j0 block meeting the open
+    ball |x - centre| < radius."""
+    n = 1 << j0
+    w = L / n
+    leaves = []
+    c = np.asarray(centre, float)
+    for z in range(n):
+        for y in range(n):
+            for x in range(n):
+                lo = np.array([x, y, z]) * w
+                hi = lo + w
+                d = np.sqrt(np.sum(np.maximum(0.0, np.maximum(lo - c, c - hi)) ** 2))
+                if d < radius:
+                    for k in range(8):
+                        leaves.append((j0 + 1, 2 * x + (k & 1), 2 * y + (k >> 1 & 1),
+                                       2 * z + (k >> 2 & 1)))
+                else:
+                    leaves.append((j0, x, y, z))
+    return _sorted(leaves)
+
+
+def box_refined_leaves(L: float, jmin: int, jtop: int, lo, hi):
+    """Refine every block meeting the axis-aligned box [lo, hi] up to level jtop,
+    with 2:1 balancing, starting from a uniform level-jmin grid."""
+    ls = LeafSet([(jmin, x, y, z) for z in range(1 << jmin) for y in range(1 << jmin)
+                  for x in range(1 << jmin)], jmin)
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    changed = True
+    while changed:
+        changed = False
+        for leaf in sorted(ls.s):
+            J, x, y, z = leaf
+            if J >= jtop or leaf not in ls.s:
+                continue
+            w = L / (1 << J)
+            blo = np.array([x, y, z]) * w
+            bhi = blo + w
+            if np.all(bhi >= lo) and np.all(blo <= hi):
+                ls.refine(leaf)
+                changed = True
+    return ls.arrays()
+
+
+# --------------------------------------------------------------------------
+# Sampling fields at interior points.
+# --------------------------------------------------------------------------
+def interior_coords(bs: int, L: float, lev, ix, iy, iz):
+    """x, y, z of interior points, each of shape (nb, bs, bs, bs) in (z, y, x) order."""
+    lev = np.asarray(lev)
+    h = L / ((2.0 ** lev) * bs)
+    i = np.arange(bs, dtype=np.float64)
+    X = ((np.asarray(ix, np.float64)[:, None] * bs + i[None, :]) * h[:, None])
+    Y = ((np.asarray(iy, np.float64)[:, None] * bs + i[None, :]) * h[:, None])
+    Z = ((np.asarray(iz, np.float64)[:, None] * bs + i[None, :]) * h[:, None])
+    nb = len(lev)
+    x = np.broadcast_to(X[:, None, None, :], (nb, bs, bs, bs))
+    y = np.broadcast_to(Y[:, None, :, None], (nb, bs, bs, bs))
+    z = np.broadcast_to(Z[:, :, None, None], (nb, bs, bs, bs))
+    return x, y, z
+
+
+def pack(fields, bs: int, ng: int, fill: float = 0.0) -> np.ndarray:
+    """Place 4 interior fields of shape (nb, bs, bs, bs) into a padded pool
+    (nb, 4, P, P, P); ghost points get `fill`."""
+    nb = fields[0].shape[0]
+    P = bs + 2 * ng
+    U = np.full((nb, 4, P, P, P), fill, np.float64)
+    for c in range(4):
+        U[:, c, ng:ng + bs, ng:ng + bs, ng:ng + bs] = fields[c]
+    return U
+
+
+def interior(U: np.ndarray, bs: int, ng: int) -> np.ndarray:
+    return U[..., ng:ng + bs, ng:ng + bs, ng:ng + bs]
+
+
+def taylor_green(x, y, z):
+    u = np.sin(x) * np.cos(y) * np.cos(z)
+    v = -np.cos(x) * np.sin(y) * np.cos(z)
+    w = np.zeros_like(u)
+    p = np.zeros_like(u)
+    return [u, v, w, p]
+
+
+def fourier_modes(seed: int, nfields: int = 4, nmodes: int = 16, kmax: int = 8,
+                  amp: float = 1.0 / 16.0, kmin: int = 1) -> np.ndarray:
+    """Per field `nmodes` modes (kx, ky, kz, a, phi): integer k with
+    kmin <= |k|_inf <= kmax, a ~ amp U(-1,1), phi ~ U(0, 2 pi)."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((nfields, nmodes, 5))
+    for f in range(nfields):
+        m = 0
+        while m < nmodes:
+            k = rng.integers(-kmax, kmax + 1, size=3)
+            if np.max(np.abs(k)) < kmin:
+                continue
+            out[f, m, :3] = k
+            out[f, m, 3] = amp * rng.uniform(-1.0, 1.0)
+            out[f, m, 4] = rng.uniform(0.0, 2.0 * math.pi)
+            m += 1
+    return out
+
+
+def fourier_eval(modes_f: np.ndarray, x, y, z, L: float):
+    """sum_m a_m cos(2 pi/L (k . x) + phi_m) for one field's modes."""
+    s = 2.0 * math.pi / L
+    out = np.zeros(np.shape(x))
+    for kx, ky, kz, a, ph in modes_f:
+        out += a * np.cos(s * (kx * x + ky * y + kz * z) + ph)
+    return out
+
+
+def fourier_fields(seed: int, bs: int, L: float, lev, ix, iy, iz, nmodes=16, kmax=8,
+                   amp=1.0 / 16.0):
+    modes = fourier_modes(seed, 4, nmodes, kmax, amp)
+    x, y, z = interior_coords(bs, L, lev, ix, iy, iz)
+    return [fourier_eval(modes[c], x, y, z, L) for c in range(4)]
