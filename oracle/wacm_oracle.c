@@ -54,20 +54,23 @@ struct orc_grid {
 /*        + 2 sin 3eta,                                                         */
 /* with the integrals written out in closed form below.                       */
 /* ------------------------------------------------------------------------ */
-static double int_sin_sin(int m, int n, double X) { /* int_0^X sin(m e) sin(n e) de */
-  if (m == n) return X / 2.0 - sin(2.0 * m * X) / (4.0 * m);
-  return sin((double)(m - n) * X) / (2.0 * (m - n)) - sin((double)(m + n) * X) / (2.0 * (m + n));
+/* The closed forms cancel strongly; they are evaluated in long double so the
+ * result rounds correctly to double. */
+static long double int_sin_sin(int m, int n, long double X) { /* int_0^X sin(m e) sin(n e) de */
+  if (m == n) return X / 2.0L - sinl(2.0L * m * X) / (4.0L * m);
+  return sinl((long double)(m - n) * X) / (2.0L * (m - n)) -
+         sinl((long double)(m + n) * X) / (2.0L * (m + n));
 }
-static double int_e_sin(int m, double X) { /* int_0^X e sin(m e) de */
-  return sin(m * X) / ((double)m * m) - X * cos(m * X) / m;
+static long double int_e_sin(int m, long double X) { /* int_0^X e sin(m e) de */
+  return sinl(m * X) / ((long double)m * m) - X * cosl(m * X) / m;
 }
 
 void orc_tam_webb(double a[3]) {
-  const double X = 1.1;
+  const long double X = 1.1L;
   /* f0 = sum_m c0[m] sin(m e) - e ; f1 = sum_m c1[m] sin(m e), m = 1..3 */
-  const double c0[4] = {0.0, 4.0 / 3.0, -1.0 / 6.0, 0.0};
-  const double c1[4] = {0.0, 10.0, -8.0, 2.0};
-  double f0f1 = 0.0, f1f1 = 0.0;
+  const long double c0[4] = {0.0L, 4.0L / 3.0L, -1.0L / 6.0L, 0.0L};
+  const long double c1[4] = {0.0L, 10.0L, -8.0L, 2.0L};
+  long double f0f1 = 0.0L, f1f1 = 0.0L;
   for (int m = 1; m <= 3; ++m) {
     for (int n = 1; n <= 3; ++n) {
       f0f1 += c0[m] * c1[n] * int_sin_sin(m, n, X);
@@ -75,10 +78,10 @@ void orc_tam_webb(double a[3]) {
     }
     f0f1 -= c1[m] * int_e_sin(m, X);
   }
-  double t = -f0f1 / f1f1;
-  a[0] = 2.0 / 3.0 + 5.0 * t;
-  a[1] = -1.0 / 12.0 - 4.0 * t;
-  a[2] = t;
+  long double t = -f0f1 / f1f1;
+  a[0] = (double)(2.0L / 3.0L + 5.0L * t);
+  a[1] = (double)(-1.0L / 12.0L - 4.0L * t);
+  a[2] = (double)t;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -41,6 +41,16 @@ def test_tam_webb_matches_published_and_constraints(orc):
 
 def test_tam_webb_is_least_squares_optimum(orc):
     a = orc.tam_webb()
+    # 40-digit quadrature of the optimum: the oracle must agree to 1 ulp
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    f0 = lambda e: mpmath.mpf(4) / 3 * mpmath.sin(e) - mpmath.sin(2 * e) / 6 - e
+    f1 = lambda e: 10 * mpmath.sin(e) - 8 * mpmath.sin(2 * e) + 2 * mpmath.sin(3 * e)
+    X = mpmath.mpf("1.1")
+    t = -mpmath.quad(lambda e: f0(e) * f1(e), [0, X]) / mpmath.quad(lambda e: f1(e) ** 2, [0, X])
+    exact = [mpmath.mpf(2) / 3 + 5 * t, -mpmath.mpf(1) / 12 - 4 * t, t]
+    for v, e in zip(a, exact):
+        assert abs(v - float(e)) <= np.spacing(abs(float(e)))
 
     def obj(t):
         b = np.array([2 / 3 + 5 * t, -1 / 12 - 4 * t, t])
