@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Throughput of the RK4 block stage loop on one MI355X.
+
+Workload: a fixed, seeded random 2:1-balanced periodic octree on [0, 2 pi]^3
+(levels 3..7, >= 20000 blocks of 24^3 interior points, 4 ghost layers), seeded
+smooth random-Fourier velocity and pressure (16 modes per field, |k| <= 8),
+nu 1e-2, C0 20, C_gamma 1, no mask, CFL 0.5 (time step recomputed on the GPU
+every step).  A step is one classical RK4 step: 4 x (ghost synchronisation +
+fused rhs/RK stage) plus the CFL reduction.  Inputs are resident in HBM
+before the timed region.
+
+Metric: RK4 block-point updates/s = interior points x 4 stages / s.  The
+primary line is the FP64 path; the FP32 path is reported beside it with its
+speed-up.  The roofline object refers to the fused rhs + RK stage kernel: its
+algorithmic bytes (16 values per interior point per stage -- reading U_s, U^n
+and the accumulator, writing the accumulator and the next stage input,
+averaged over the 4 stages) divided by its average duration, measured with
+HIP events on the launch stream inside the timed region.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def build_case(target: int, seed: int):
+    from paper_1912_05371_amd import cases
+    return cases.random_octree(bs=24, ng=4, target=target, j0=3, jmax=7, seed=seed,
+                               with_fields=False)
+
+
+def run_gpu(case, dtype_code: int, steps: int, warmup: int, use_graph: bool):
+    import torch
+
+    from paper_1912_05371_amd import inputs, wacm
+
+    g = wacm.Grid.from_case(case, dtype=dtype_code)
+    slots, codes, levels = g.info()
+    pool = g.pool()
+    modes = inputs.fourier_modes(case_seed(case), 4, 16, 8, 1.0 / 16.0)
+    # leaf i of the case is in pool slot i
+    inputs.fourier_fill_device(pool, modes, case.bs, case.ng, case.L, case.lev, case.ix, case.iy,
+                               case.iz, np.arange(case.nb))
+    work = g.work()
+    t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    p = wacm.make_params(case.params)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        g.rk4_step(None, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_CFL, _p=p)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, kernel classes timed with events on the stream
+    g.profile_enable(True)
+    g.profile_read()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        g.rk4_step(None, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_CFL, _p=p)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = ev0.elapsed_time(ev1)
+    kms, kn = g.profile_read()
+    g.profile_enable(False)
+
+    res = dict(ms_per_step=ms_total / steps, wall_s=wall, kernel_ms=kms.tolist(),
+               kernel_launches=kn.tolist())
+    if use_graph:
+        graph = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            g.rk4_step(None, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_CFL, _p=p)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph):
+            g.rk4_step(None, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_CFL, _p=p)
+        graph.replay()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(steps):
+            graph.replay()
+        ev1.record()
+        torch.cuda.synchronize()
+        res["graph_ms_per_step"] = ev0.elapsed_time(ev1) / steps
+    out = torch.zeros(9, dtype=torch.float64, device="cuda")
+    g.diagnostics(case.params, float(t_dev.item()), pool, out)
+    res["t_end"] = float(t_dev.item())
+    res["dt_last"] = float(dt_dev.item())
+    res["diag"] = out.cpu().tolist()
+    res["finite"] = bool(np.isfinite(res["diag"]).all())
+    del pool, work
+    g.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def case_seed(case):
+    return case.extra.get("seed", 12345)
+
+
+def roofline(res, npts: int, es: int):
+    stage_ms = res["kernel_ms"][2] / max(res["kernel_launches"][2], 1)
+    bytes_per_launch = 16 * es * npts  # mean over the 4 stages (12, 20, 20, 12 values)
+    achieved = bytes_per_launch / (stage_ms * 1e-3) / 1e9
+    step_bytes = 64 * es * npts
+    return {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "kernel": "stage_kernel (fused rhs + RK4 stage)",
+        "kernel_avg_ms": round(stage_ms, 4),
+        "bytes_per_launch": bytes_per_launch,
+        "whole_step_frac": round(step_bytes / (res["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 4),
+    }
+
+
+def cpu_baseline(seed: int):
+    """The FP64 oracle on a bounded sample of the same workload: one RK4 step
+    (with its CFL time step) on a smaller random octree built by the same
+    generator (bs 24, 4 ghost layers, levels 2..4)."""
+    from oracle import oracle
+    from paper_1912_05371_amd import cases
+    oracle.build(force=False)
+    c = cases.random_octree(bs=24, ng=4, target=600, j0=2, jmax=4, seed=seed)
+    og = oracle.Grid(c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix, c.iy, c.iz)
+    U = c.padded()
+    t0 = time.perf_counter()
+    dt = og.dt(c.params, U)
+    og.rk4_step(c.params, 0.0, dt, U)
+    el = time.perf_counter() - t0
+    npts = c.nb * c.bs ** 3
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return {
+        "value": round(npts * 4 / el, 1),
+        "unit": "block-point updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"1 RK4 step (+CFL dt) of the FP64 oracle on a {c.nb}-block random octree "
+                  f"(bs 24, ng 4, levels 2-4, {npts} interior points), same generator; "
+                  f"{el:.2f} s wall with OpenMP over blocks",
+        "seconds": round(el, 3),
+        "core_seconds_per_point_rhs": el * threads / (npts * 4),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--target", type=int, default=20000, help="minimum number of blocks")
+    ap.add_argument("--seed", type=int, default=12345)
+    ap.add_argument("--dtype", choices=["both", "f64", "f32"], default="both")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the block pool of this workload is resident on "
+              "a single MI355X and no multi-GPU path is built (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_1912_05371_amd import wacm
+
+    wacm.lib()
+    t0 = time.perf_counter()
+    case = build_case(args.target, args.seed)
+    case.extra["seed"] = args.seed
+    npts = case.nb * case.bs ** 3
+    levels = {int(l): int(n) for l, n in zip(*np.unique(case.lev, return_counts=True))}
+    log(f"workload: {case.nb} blocks {levels}, {npts} interior points "
+        f"(generated in {time.perf_counter() - t0:.1f} s)")
+
+    results = {}
+    for name, code, es in (("f64", wacm.F64, 8), ("f32", wacm.F32, 4)):
+        if args.dtype not in ("both", name):
+            continue
+        log(f"running {name}: warmup {args.warmup}, steps {args.steps}")
+        r = run_gpu(case, code, args.steps, args.warmup, not args.no_graph)
+        r["value"] = npts * 4 / (r["ms_per_step"] * 1e-3)
+        r["roofline"] = roofline(r, npts, es)
+        log(f"  {name}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4e} updates/s, stage kernel "
+            f"{r['roofline']['kernel_avg_ms']:.3f} ms = {r['roofline']['achieved']:.0f} GB/s "
+            f"({100 * r['roofline']['frac']:.1f} %), graph {r.get('graph_ms_per_step', 0):.3f} "
+            f"ms/step, kernels {r['kernel_ms']} ms / {r['kernel_launches']}")
+        results[name] = r
+
+    prim = "f64" if "f64" in results else "f32"
+    R = results[prim]
+    line = {
+        "metric": "RK4 block-point updates/s",
+        "value": round(R["value"], 1),
+        "unit": "block-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(R["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prim,
+        "data": "synthetic",
+        "config": {
+            "workload": f"random_octree_bs24_ng4_L3-7_{case.nb}blocks",
+            "blocks": case.nb,
+            "levels": levels,
+            "bs": case.bs,
+            "ng": case.ng,
+            "interior_points": npts,
+            "dt": "CFL 0.5 on device every step",
+        },
+        "roofline": R["roofline"],
+    }
+    if "graph_ms_per_step" in R:
+        line["graph_ms_per_step"] = round(R["graph_ms_per_step"], 4)
+    other = "f32" if prim == "f64" else None
+    if other and other in results:
+        O = results[other]
+        line["f32"] = {
+            "value": round(O["value"], 1),
+            "ms_per_step": round(O["ms_per_step"], 4),
+            "roofline": O["roofline"],
+            "speedup_vs_f64": round(R["ms_per_step"] / O["ms_per_step"], 3),
+            "graph_ms_per_step": round(O.get("graph_ms_per_step", 0.0), 4),
+        }
+    line["kernel_ms_per_step"] = {
+        k: round(v / args.steps, 4)
+        for k, v in zip(["dt", "sync", "stage", "time"], R["kernel_ms"])}
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a sample")
+        line["cpu_baseline"] = cpu_baseline(args.seed)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

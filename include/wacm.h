@@ -1,0 +1,247 @@
+/*
+ * wacm.h -- C ABI of the MI355X (gfx950) hot path of the wavelet-adaptive
+ * block method for the penalized artificial-compressibility equations of
+ * Engels, Schneider, Reiss & Farge (arXiv:1912.05371).
+ *
+ * The method advances U = (u, v, w, p) on a 2:1-balanced periodic octree of
+ * cubic blocks (Sec. 4.1): each classical RK4 stage (Sec. 2.3) synchronises
+ * ghost nodes (Sec. 4.2; same-level copy, fine->coarse decimation, coarse->fine
+ * 4th-order Deslauriers-Dubuc prediction, Sec. 3.1) and evaluates the
+ * penalized right-hand side (Sec. 2.2).  Wavelet details (Sec. 3.1, 3.3-3.4)
+ * decide coarsening, and the grid is refined and coarsened around each step
+ * (Sec. 3.5).
+ *
+ * Conventions shared by every call
+ * ---------------------------------
+ * - Return value: WACM_OK (0) or a negative WACM_E_* code.  No exception
+ *   crosses the ABI.  Arguments are checked on the host before any launch;
+ *   a failed check launches nothing and leaves every buffer untouched.
+ *   wacm_last_error() gives a text for the last failure of the calling thread.
+ * - Asynchrony: calls that take a stream only enqueue work on it and return;
+ *   errors raised by the device surface at the next synchronising call.
+ *   Calls documented as "synchronous" wait for the stream.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ * - Device memory for the state is owned by the caller.  The library owns the
+ *   opaque grid handle, its host metadata and small device tables (neighbour
+ *   tables, block lists, reduction partials) allocated in wacm_grid_create /
+ *   wacm_adapt and released by wacm_grid_destroy.
+ *
+ * Block pool layout ("pool"): a device array of `capacity` slots; slot s holds
+ * 4 fields (u, v, w, p), each a padded cube of P^3 values, P = bs + 2 ng,
+ * x fastest:  pool[((s*4 + c)*P + (k+ng))*P + (j+ng))*P + (i+ng)] for local
+ * indices i, j, k in [-ng, bs+ng).  Interior points are [0, bs)^3; the others
+ * are ghost nodes.  The element type is float (WACM_F32) or double (WACM_F64)
+ * as chosen at grid creation.  Only slots of active blocks are read or written.
+ *
+ * Geometry: domain [0,L]^3, periodic in all directions.  A block at level J
+ * with block index (bx,by,bz) in [0,2^J)^3 has spacing h_J = L/(2^J bs) and
+ * interior point i at x = (bx bs + i) h_J (non-redundant blocks; bs even).
+ * Treecode: one octal digit per level, level-1 digit most significant,
+ * digit = xbit + 2 ybit + 4 zbit (Sec. 4.1).
+ */
+#ifndef WACM_H
+#define WACM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+#pragma GCC visibility push(default)
+
+#define WACM_OK 0
+#define WACM_E_INVAL (-1)      /* bad argument or size                         */
+#define WACM_E_NOMEM (-2)      /* host or device allocation failed             */
+#define WACM_E_CAPACITY (-3)   /* adaptation needs more pool slots             */
+#define WACM_E_UNBALANCED (-4) /* leaves are not 2:1 graded (26 neighbours)     */
+#define WACM_E_HIP (-5)        /* a HIP runtime call failed                    */
+#define WACM_E_NONFINITE (-6)  /* NaN or Inf found in the state                */
+#define WACM_E_TILING (-7)     /* leaves overlap, repeat or leave gaps          */
+
+#define WACM_F32 1
+#define WACM_F64 2
+
+#define WACM_DT_FIXED 0 /* rk4_step reads dt from *dt_dev                       */
+#define WACM_DT_CFL 1   /* rk4_step computes dt from U and writes it to *dt_dev */
+
+#define WACM_REFINE_ALL 1 /* split every block below jmax into 8 children      */
+#define WACM_COARSEN 2    /* one merge pass over flagged sister groups          */
+
+#define WACM_MASK_NONE 0
+#define WACM_MASK_SPHERE 1 /* static sphere, chi = (1 - tanh(d/w))/2            */
+#define WACM_MASK_PLATE 2  /* thin plate pitching about an axis parallel to y   */
+
+typedef struct wacm_grid wacm_grid;
+
+typedef struct {
+  int32_t bs;       /* interior points per axis; even, >= 2 (ng + 3)            */
+  int32_t ng;       /* ghost layers; >= 3                                        */
+  int32_t jmin;     /* coarsest level allowed                                    */
+  int32_t jmax;     /* finest level allowed, <= 18 (Sec. 3.5)                    */
+  int32_t dtype;    /* WACM_F32 or WACM_F64                                      */
+  int32_t reserved; /* must be 0                                                 */
+  int64_t capacity; /* number of pool slots                                      */
+  double L;         /* domain edge length                                        */
+} wacm_grid_desc;
+
+/* Parameters of the penalized ACM model (Sec. 2.1-2.3). */
+typedef struct {
+  double nu;        /* kinematic viscosity                                        */
+  double c0;        /* artificial speed of sound C0                               */
+  double c_gamma;   /* dashpot damping C_gamma                                    */
+  double c_eta;     /* penalization permeability C_eta                            */
+  double c_sp;      /* sponge constant C_sp                                       */
+  double l_sp;      /* sponge width at each face of [0,L]^3 (binary sponge)       */
+  double u_inf[3];  /* sponge velocity                                            */
+  double p_inf;     /* sponge pressure                                            */
+  int32_t mask;     /* WACM_MASK_*                                                */
+  int32_t sponge;   /* 0 off, 1 on                                                */
+  int32_t clip;     /* 1: mask values below 1e-8 become exactly 0                 */
+  int32_t reserved; /* must be 0                                                  */
+  double w;         /* mask smoothing width                                       */
+  double sph_c[3];  /* sphere centre                                              */
+  double sph_r;     /* sphere radius                                              */
+  double x_le[3];   /* plate: a point on its rotation axis (leading edge)          */
+  double lo[3];     /* plate: body-frame box lower corner                         */
+  double hi[3];     /* plate: body-frame box upper corner                         */
+  double amp, freq, phase; /* plate pitch angle amp*sin(2 pi freq t + phase)     */
+  double cfl, cfl_eta, cfl_nu; /* time-step constants (Sec. 2.3)                 */
+} wacm_params;
+
+/* Text of the last error on the calling thread ("" if none). */
+const char* wacm_last_error(void);
+
+/* Treecode helpers (Sec. 4.1). */
+uint64_t wacm_treecode_encode(int32_t level, int64_t ix, int64_t iy, int64_t iz);
+void wacm_treecode_decode(uint64_t code, int32_t level, int64_t* ix, int64_t* iy, int64_t* iz);
+
+/*
+ * wacm_grid_create -- build a grid from `nleaves` leaves (Sec. 4.1).
+ * treecodes/levels: host arrays of nleaves entries.  Leaf i is placed in pool
+ * slot i (so nleaves <= capacity); the active block list is kept in Morton
+ * order.  Validation: sizes (WACM_E_INVAL), exact tiling of the periodic
+ * domain (WACM_E_TILING), 2:1 grading over faces, edges and corners
+ * (WACM_E_UNBALANCED).  On success *out receives a new handle.  Synchronous.
+ */
+int wacm_grid_create(const wacm_grid_desc* desc, int64_t nleaves, const uint64_t* treecodes,
+                     const int8_t* levels, wacm_grid** out);
+
+/* Release the handle and its device tables.  NULL is accepted. */
+int wacm_grid_destroy(wacm_grid* grid);
+
+/* Number of active blocks. */
+int64_t wacm_grid_nb(const wacm_grid* grid);
+
+/*
+ * wacm_grid_info -- active blocks in Morton order.  Each non-NULL host array
+ * receives nb entries: pool slot, treecode, level.
+ */
+int wacm_grid_info(const wacm_grid* grid, int64_t* slots, uint64_t* treecodes, int8_t* levels);
+
+/* Bytes of the `work` buffer wacm_rk4_step needs (3 RK registers for every
+ * pool slot), 256-byte aligned by the caller. */
+size_t wacm_work_bytes(const wacm_grid* grid);
+
+/*
+ * wacm_sync_ghosts -- ghost-node synchronisation (Sec. 4.2) of every active
+ * block of the pool U, in place; interiors are not modified.  A ghost point
+ * takes the value of the leaf that holds it: a copy if that leaf is on the
+ * same level, the coincident fine point if it is finer (decimation, Sec. 3.1),
+ * and the tensor-product 4th-order Deslauriers-Dubuc prediction from the
+ * coarse lattice (Sec. 3.1) if it is coarser; coarse lattice values are read
+ * from the interiors of their own leaves.  All `ng` layers including edges and
+ * corners are filled.
+ */
+int wacm_sync_ghosts(wacm_grid* grid, void* U, void* stream);
+
+/*
+ * wacm_rhs_acm -- right-hand side of the penalized ACM equations (Sec. 2.2)
+ * with Tam-Webb 4th-order first derivatives and the 4th-order centred second
+ * derivative (Sec. 2.3), in advective form, at time t.
+ * U: ghost-synchronised pool (read).  dU: pool-shaped output; interiors of
+ * active blocks are written.  dus: optional (NULL) extra solid velocity, a
+ * device array [capacity][3][bs^3] (x fastest) added to u_s.
+ */
+int wacm_rhs_acm(wacm_grid* grid, const wacm_params* prm, double t, const void* U, void* dU,
+                 const void* dus, void* stream);
+
+/*
+ * wacm_compute_dt -- time step from the stability limits of Sec. 2.3:
+ * min(cfl h_min/u_eig, cfl_eta C_eta [mask], cfl_eta C_sp [sponge],
+ * cfl_nu h_min^2/nu), u_eig = |u|max + sqrt(|u|max^2 + C0^2), |u|max the
+ * largest Euclidean velocity over interiors, h_min of the finest active level.
+ * Writes one double to the device pointer dt_dev.  FP64 reduction.
+ */
+int wacm_compute_dt(wacm_grid* grid, const wacm_params* prm, const void* U, double* dt_dev,
+                    void* stream);
+
+/*
+ * wacm_rk4_step -- one classical RK4 step (Sec. 2.3) in place on U on the
+ * current grid.  Each stage synchronises ghosts and evaluates the rhs at the
+ * stage time t + (0, 1/2, 1/2, 1) dt.  t_dev, dt_dev: device doubles; with
+ * WACM_DT_CFL dt is first computed from U (as wacm_compute_dt) and stored in
+ * *dt_dev, with WACM_DT_FIXED it is read from *dt_dev.  *t_dev is advanced by
+ * dt.  work: device buffer of wacm_work_bytes().  dus: as in wacm_rhs_acm.
+ * No host synchronisation and no allocation: the call may be captured in a
+ * HIP graph as long as the grid is not changed.
+ */
+int wacm_rk4_step(wacm_grid* grid, const wacm_params* prm, double* t_dev, double* dt_dev,
+                  void* U, void* work, const void* dus, int32_t dt_mode, void* stream);
+
+/*
+ * wacm_diagnostics -- FP64 reductions over interiors at time t:
+ * out[0] max Euclidean |u|, out[1..4] max |u|,|v|,|w|,|p|,
+ * out[5..7] penalization force C_eta^-1 sum chi (u - u_s) h^3 (Sec. 2.2,
+ * midpoint rule), out[8] energy 1/2 sum |u|^2 h^3.  out: 9 device doubles.
+ */
+int wacm_diagnostics(wacm_grid* grid, const wacm_params* prm, double t, const void* U,
+                     const void* dus, double* out, void* stream);
+
+/*
+ * wacm_threshold_blocks -- wavelet details (Sec. 3.1) of a ghost-synchronised
+ * pool U, normalised per component by the global max norm over interiors
+ * (Sec. 3.4; a zero norm counts as 1).  For active block i (Morton order):
+ * dmax[i] = largest normalised |u - P R u| over interior points with an odd
+ * local index; mrange[i] = max chi - min chi over interior points at time t;
+ * flags[i] = 1 (coarsen) iff level > jmin and either (dealias and level ==
+ * jmax) or (dmax < eps and mrange == 0) (Sec. 3.3, 3.5).  dmax, mrange: device
+ * doubles; flags: device int8; nb entries each.
+ */
+int wacm_threshold_blocks(wacm_grid* grid, const wacm_params* prm, double t, const void* U,
+                          double eps, int32_t dealias, double* dmax, double* mrange,
+                          int8_t* flags, void* stream);
+
+/*
+ * wacm_adapt -- change the grid (Sec. 3.5).  Synchronous.
+ * WACM_REFINE_ALL: ghosts of U are synchronised, then every active block below
+ *   jmax is replaced by its 8 children (even child points copy the parent,
+ *   odd points take the tensor DD4 prediction, Sec. 3.1).  `flags` unused.
+ * WACM_COARSEN: flags is a host int8 array of nb entries (Morton order, as
+ *   from wacm_threshold_blocks).  8 sisters merge into their parent by
+ *   decimation iff all are active and flagged and no active block touching the
+ *   parent's box is finer than the sisters (grading).  One pass.
+ * New blocks take free pool slots; the grid is unchanged on error
+ * (WACM_E_CAPACITY if free slots run out).  *nb_out (may be NULL) receives the
+ * new number of active blocks.
+ */
+int wacm_adapt(wacm_grid* grid, int32_t op, const int8_t* flags, void* U, int64_t* nb_out,
+               void* stream);
+
+/*
+ * Measurement support (not part of the method).  wacm_profile_enable(g, 1)
+ * makes wacm_rk4_step record a HIP event pair around each group of kernels it
+ * launches on its stream; do not enable it while the stream is being captured
+ * into a graph.  wacm_profile_read waits for the recorded events and returns,
+ * per kernel class [0 time-step reduction, 1 ghost synchronisation, 2 fused
+ * rhs + RK stage, 3 time update], the summed milliseconds and the number of
+ * timed launches since the last read (host arrays of 4), then resets them.
+ */
+int wacm_profile_enable(wacm_grid* grid, int32_t on);
+int wacm_profile_read(wacm_grid* grid, double* ms, int64_t* launches);
+
+#pragma GCC visibility pop
+#ifdef __cplusplus
+}
+#endif
+#endif

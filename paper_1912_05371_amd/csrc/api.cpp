@@ -1,0 +1,414 @@
+// extern "C" entry points of libwacm (declared in include/wacm.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+
+#include "wacm_internal.h"
+
+using namespace wacm;
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hipfail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return WACM_E_HIP;
+}
+
+bool elem_ok(const wacm_grid* g) { return g && (g->d.dtype == WACM_F32 || g->d.dtype == WACM_F64); }
+
+int check_params(const wacm_params* p) {
+  if (!p) return fail(WACM_E_INVAL, "params is NULL");
+  if (p->mask < 0 || p->mask > 2) return fail(WACM_E_INVAL, "unknown mask kind");
+  if (p->mask && !(p->c_eta > 0)) return fail(WACM_E_INVAL, "c_eta must be > 0 with a mask");
+  if (p->mask && !(p->w > 0)) return fail(WACM_E_INVAL, "mask width w must be > 0");
+  if (p->sponge && !(p->c_sp > 0)) return fail(WACM_E_INVAL, "c_sp must be > 0 with a sponge");
+  if (p->nu < 0) return fail(WACM_E_INVAL, "nu must be >= 0");
+  return WACM_OK;
+}
+
+void free_dev(wacm_grid* g) {
+  (void)profile_flush(g);
+  for (hipEvent_t e : g->prof.spare) (void)hipEventDestroy(e);
+  g->prof.spare.clear();
+  if (g->d_tab) (void)hipFree(g->d_tab);
+  if (g->d_part) (void)hipFree(g->d_part);
+  if (g->d_norm) (void)hipFree(g->d_norm);
+  if (g->d_list) (void)hipFree(g->d_list);
+  g->d_tab = nullptr;
+  g->d_part = nullptr;
+  g->d_norm = nullptr;
+  g->d_list = nullptr;
+}
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+namespace wacm {
+void set_error(const std::string& s) { g_err = s; }
+}  // namespace wacm
+
+extern "C" {
+
+const char* wacm_last_error(void) { return g_err.c_str(); }
+
+uint64_t wacm_treecode_encode(int32_t level, int64_t ix, int64_t iy, int64_t iz) {
+  uint64_t code = 0;
+  for (int l = 1; l <= level; ++l) {
+    int sh = level - l;
+    uint64_t d = ((uint64_t)(ix >> sh) & 1u) | (((uint64_t)(iy >> sh) & 1u) << 1) |
+                 (((uint64_t)(iz >> sh) & 1u) << 2);
+    code = (code << 3) | d;
+  }
+  return code;
+}
+
+void wacm_treecode_decode(uint64_t code, int32_t level, int64_t* ix, int64_t* iy, int64_t* iz) {
+  int64_t x = 0, y = 0, z = 0;
+  for (int l = 1; l <= level; ++l) {
+    uint64_t d = (code >> (3 * (level - l))) & 7u;
+    x = (x << 1) | (int64_t)(d & 1u);
+    y = (y << 1) | (int64_t)((d >> 1) & 1u);
+    z = (z << 1) | (int64_t)((d >> 2) & 1u);
+  }
+  if (ix) *ix = x;
+  if (iy) *iy = y;
+  if (iz) *iz = z;
+}
+
+int wacm_grid_create(const wacm_grid_desc* d, int64_t nleaves, const uint64_t* treecodes,
+                     const int8_t* levels, wacm_grid** out) {
+  if (!d || !out || !treecodes || !levels) return fail(WACM_E_INVAL, "NULL argument");
+  *out = nullptr;
+  if (d->bs % 2 || d->bs < 2 * (d->ng + 3) || d->ng < 3 || d->bs > 64)
+    return fail(WACM_E_INVAL, "bs must be even with 2(ng+3) <= bs <= 64 and ng >= 3");
+  if (d->jmin < 0 || d->jmax > 18 || d->jmin > d->jmax)
+    return fail(WACM_E_INVAL, "need 0 <= jmin <= jmax <= 18");
+  if (d->dtype != WACM_F32 && d->dtype != WACM_F64) return fail(WACM_E_INVAL, "bad dtype");
+  if (d->reserved != 0) return fail(WACM_E_INVAL, "reserved must be 0");
+  if (!(d->L > 0)) return fail(WACM_E_INVAL, "L must be > 0");
+  if (nleaves <= 0 || nleaves > d->capacity || d->capacity > (int64_t)1 << 30)
+    return fail(WACM_E_INVAL, "need 0 < nleaves <= capacity <= 2^30");
+  if (d->bs != 16 && d->bs != 24 && d->bs != 32)
+    return fail(WACM_E_INVAL, "kernels are built for bs in {16, 24, 32}");
+
+  wacm_grid* g = new (std::nothrow) wacm_grid();
+  if (!g) return fail(WACM_E_NOMEM, "host allocation");
+  g->d = *d;
+  g->P = d->bs + 2 * d->ng;
+  g->leaves.resize(nleaves);
+  g->slots.resize(nleaves);
+  // tiling: unique, in range, no leaf inside another, volumes add up
+  std::unordered_map<uint64_t, int32_t> seen;
+  seen.reserve(nleaves * 2);
+  unsigned __int128 vol = 0;
+  for (int64_t i = 0; i < nleaves; ++i) {
+    int J = levels[i];
+    if (J < d->jmin || J > d->jmax) {
+      delete g;
+      return fail(WACM_E_INVAL, "leaf level outside [jmin, jmax]");
+    }
+    if (J < 21 && (treecodes[i] >> (3 * J)) != 0) {
+      delete g;
+      return fail(WACM_E_INVAL, "treecode has digits beyond its level");
+    }
+    Leaf l;
+    l.J = J;
+    wacm_treecode_decode(treecodes[i], J, &l.x, &l.y, &l.z);
+    if (!seen.emplace(leaf_key(J, l.x, l.y, l.z), (int32_t)i).second) {
+      delete g;
+      return fail(WACM_E_TILING, "repeated leaf");
+    }
+    g->leaves[i] = l;
+    g->slots[i] = (int32_t)i;
+    vol += (unsigned __int128)1 << (3 * (d->jmax - J));
+  }
+  for (int64_t i = 0; i < nleaves; ++i) {
+    const Leaf& l = g->leaves[i];
+    for (int K = d->jmin; K < l.J; ++K) {
+      int s = l.J - K;
+      if (seen.count(leaf_key(K, l.x >> s, l.y >> s, l.z >> s))) {
+        delete g;
+        return fail(WACM_E_TILING, "a leaf lies inside another leaf");
+      }
+    }
+  }
+  if (vol != ((unsigned __int128)1 << (3 * d->jmax))) {
+    delete g;
+    return fail(WACM_E_TILING, "leaves do not cover the domain");
+  }
+  for (int64_t s = d->capacity - 1; s >= nleaves; --s) g->free_slots.push_back((int32_t)s);
+  reorder_leaves(g);
+
+  std::vector<Tab> tabs;
+  std::string err;
+  int rc = build_tables(g, tabs, err);
+  if (rc) {
+    delete g;
+    return fail(rc, err);
+  }
+  hipError_t e;
+  if ((e = hipMalloc(&g->d_tab, sizeof(Tab) * d->capacity)) != hipSuccess ||
+      (e = hipMalloc(&g->d_part, sizeof(double) * 16 * (d->capacity + 1024))) != hipSuccess ||
+      (e = hipMalloc(&g->d_norm, sizeof(double) * 16)) != hipSuccess ||
+      (e = hipMalloc(&g->d_list, sizeof(int32_t) * 10 * d->capacity)) != hipSuccess) {
+    free_dev(g);
+    delete g;
+    return hipfail(e, "hipMalloc of grid tables");
+  }
+  rc = upload_tables(g, tabs, err);
+  if (rc) {
+    free_dev(g);
+    delete g;
+    return fail(rc, err);
+  }
+  *out = g;
+  return WACM_OK;
+}
+
+int wacm_grid_destroy(wacm_grid* g) {
+  if (!g) return WACM_OK;
+  free_dev(g);
+  delete g;
+  return WACM_OK;
+}
+
+int64_t wacm_grid_nb(const wacm_grid* g) { return g ? g->nb : -1; }
+
+int wacm_grid_info(const wacm_grid* g, int64_t* slots, uint64_t* treecodes, int8_t* levels) {
+  if (!g) return fail(WACM_E_INVAL, "NULL grid");
+  for (int64_t i = 0; i < g->nb; ++i) {
+    const Leaf& l = g->leaves[i];
+    if (slots) slots[i] = g->slots[i];
+    if (treecodes) treecodes[i] = wacm_treecode_encode(l.J, l.x, l.y, l.z);
+    if (levels) levels[i] = (int8_t)l.J;
+  }
+  return WACM_OK;
+}
+
+size_t wacm_work_bytes(const wacm_grid* g) { return g ? work_bytes(g) : 0; }
+
+int wacm_sync_ghosts(wacm_grid* g, void* U, void* stream) {
+  if (!elem_ok(g) || !U) return fail(WACM_E_INVAL, "NULL argument");
+  hipError_t e = launch_sync(g, U, 0, S(stream));
+  return e == hipSuccess ? WACM_OK : hipfail(e, "sync_ghosts launch");
+}
+
+int wacm_rhs_acm(wacm_grid* g, const wacm_params* p, double t, const void* U, void* dU,
+                 const void* dus, void* stream) {
+  if (!elem_ok(g) || !U || !dU) return fail(WACM_E_INVAL, "NULL argument");
+  if (int rc = check_params(p)) return rc;
+  hipError_t e = launch_rhs(g, p, t, U, dU, dus, S(stream));
+  return e == hipSuccess ? WACM_OK : hipfail(e, "rhs_acm launch");
+}
+
+int wacm_compute_dt(wacm_grid* g, const wacm_params* p, const void* U, double* dt_dev,
+                    void* stream) {
+  if (!elem_ok(g) || !U || !dt_dev) return fail(WACM_E_INVAL, "NULL argument");
+  if (int rc = check_params(p)) return rc;
+  hipError_t e = launch_dt(g, p, U, dt_dev, S(stream));
+  return e == hipSuccess ? WACM_OK : hipfail(e, "compute_dt launch");
+}
+
+int wacm_rk4_step(wacm_grid* g, const wacm_params* p, double* t_dev, double* dt_dev, void* U,
+                  void* work, const void* dus, int32_t dt_mode, void* stream) {
+  if (!elem_ok(g) || !U || !work || !t_dev || !dt_dev)
+    return fail(WACM_E_INVAL, "NULL argument");
+  if (dt_mode != WACM_DT_FIXED && dt_mode != WACM_DT_CFL) return fail(WACM_E_INVAL, "dt_mode");
+  if (reinterpret_cast<uintptr_t>(work) % 256) return fail(WACM_E_INVAL, "work not 256-aligned");
+  if (int rc = check_params(p)) return rc;
+  hipError_t e = launch_rk4(g, p, t_dev, dt_dev, U, work, dus, dt_mode, S(stream));
+  return e == hipSuccess ? WACM_OK : hipfail(e, "rk4_step launch");
+}
+
+int wacm_diagnostics(wacm_grid* g, const wacm_params* p, double t, const void* U,
+                     const void* dus, double* out, void* stream) {
+  if (!elem_ok(g) || !U || !out) return fail(WACM_E_INVAL, "NULL argument");
+  if (int rc = check_params(p)) return rc;
+  hipError_t e = launch_diag(g, p, t, U, dus, out, S(stream));
+  return e == hipSuccess ? WACM_OK : hipfail(e, "diagnostics launch");
+}
+
+int wacm_threshold_blocks(wacm_grid* g, const wacm_params* p, double t, const void* U,
+                          double eps, int32_t dealias, double* dmax, double* mrange,
+                          int8_t* flags, void* stream) {
+  if (!elem_ok(g) || !U || !dmax || !mrange || !flags) return fail(WACM_E_INVAL, "NULL argument");
+  if (int rc = check_params(p)) return rc;
+  if (!(eps >= 0)) return fail(WACM_E_INVAL, "eps must be >= 0");
+  hipError_t e = launch_threshold(g, p, t, U, eps, dealias, dmax, mrange, flags, S(stream));
+  return e == hipSuccess ? WACM_OK : hipfail(e, "threshold_blocks launch");
+}
+
+int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* nb_out,
+               void* stream) {
+  if (!elem_ok(g) || !U) return fail(WACM_E_INVAL, "NULL argument");
+  hipStream_t st = S(stream);
+  const int bs = g->d.bs;
+  (void)bs;
+  std::vector<int32_t> list;
+  std::vector<Leaf> newleaves;
+  std::vector<int32_t> newslots;
+  std::vector<int32_t> freed;
+  std::vector<int32_t> freelist = g->free_slots;
+  auto take = [&](int32_t& s) -> bool {
+    if (freelist.empty()) return false;
+    s = freelist.back();
+    freelist.pop_back();
+    return true;
+  };
+  int64_t nwork = 0;
+  if (op == WACM_REFINE_ALL) {
+    for (int64_t i = 0; i < g->nb; ++i) {
+      const Leaf& l = g->leaves[i];
+      if (l.J >= g->d.jmax) {
+        newleaves.push_back(l);
+        newslots.push_back(g->slots[i]);
+        continue;
+      }
+      for (int c = 0; c < 8; ++c) {
+        Leaf ch{l.J + 1, 2 * l.x + (c & 1), 2 * l.y + ((c >> 1) & 1), 2 * l.z + ((c >> 2) & 1)};
+        int32_t s;
+        if (!take(s)) return fail(WACM_E_CAPACITY, "refinement needs more pool slots");
+        newleaves.push_back(ch);
+        newslots.push_back(s);
+        list.push_back(g->slots[i]);
+        list.push_back(s);
+        list.push_back(c);
+        ++nwork;
+      }
+      freed.push_back(g->slots[i]);
+    }
+  } else if (op == WACM_COARSEN) {
+    if (!flags) return fail(WACM_E_INVAL, "flags is NULL");
+    // a family merges iff its 8 sisters are active and flagged and no active
+    // block touching the parent box is finer than the sisters
+    std::vector<char> done(g->nb, 0);
+    for (int64_t i = 0; i < g->nb; ++i) {
+      if (done[i]) continue;
+      const Leaf& l = g->leaves[i];
+      bool merge = flags[i] && l.J > g->d.jmin;
+      int32_t sis[8];
+      int64_t sidx[8];
+      int64_t px = l.x >> 1, py = l.y >> 1, pz = l.z >> 1;
+      if (merge) {
+        for (int c = 0; c < 8 && merge; ++c) {
+          auto it = g->index.find(
+              leaf_key(l.J, 2 * px + (c & 1), 2 * py + ((c >> 1) & 1), 2 * pz + ((c >> 2) & 1)));
+          if (it == g->index.end() || !flags[it->second]) {
+            merge = false;
+          } else {
+            sidx[c] = it->second;
+            sis[c] = g->slots[it->second];
+          }
+        }
+      }
+      if (merge) {
+        // grading: the parent (level J-1) must not touch leaves of level J+1;
+        // check the level-(J+1) boxes around the parent box
+        const int64_t n1 = int64_t(1) << (l.J + 1);
+        int64_t base[3] = {4 * px, 4 * py, 4 * pz};  // parent origin in level-(J+1) boxes
+        for (int dz = -1; dz <= 4 && merge; ++dz)
+          for (int dy = -1; dy <= 4 && merge; ++dy)
+            for (int dx = -1; dx <= 4 && merge; ++dx) {
+              bool inside = dx >= 0 && dx < 4 && dy >= 0 && dy < 4 && dz >= 0 && dz < 4;
+              if (inside) continue;
+              int64_t bx = ((base[0] + dx) % n1 + n1) % n1;
+              int64_t by = ((base[1] + dy) % n1 + n1) % n1;
+              int64_t bz = ((base[2] + dz) % n1 + n1) % n1;
+              // is this level-(J+1) box covered by a leaf of level <= J ?
+              bool covered = false;
+              for (int K = l.J; K >= g->d.jmin && !covered; --K) {
+                int s = l.J + 1 - K;
+                covered = g->index.count(leaf_key(K, bx >> s, by >> s, bz >> s)) > 0;
+              }
+              if (!covered) merge = false;
+            }
+      }
+      if (!merge) {
+        done[i] = 1;
+        newleaves.push_back(l);
+        newslots.push_back(g->slots[i]);
+        continue;
+      }
+      int32_t s;
+      if (!take(s)) return fail(WACM_E_CAPACITY, "coarsening needs a free pool slot");
+      Leaf p{l.J - 1, px, py, pz};
+      newleaves.push_back(p);
+      newslots.push_back(s);
+      list.push_back(s);
+      for (int c = 0; c < 8; ++c) {
+        list.push_back(sis[c]);
+        done[sidx[c]] = 1;
+        freed.push_back(sis[c]);
+      }
+      list.push_back(0);
+      ++nwork;
+    }
+  } else {
+    return fail(WACM_E_INVAL, "unknown adapt op");
+  }
+  // commit: new leaf set and its tables (validated before anything on the device changes)
+  wacm_grid tmp;
+  tmp.d = g->d;
+  tmp.P = g->P;
+  tmp.leaves = newleaves;
+  tmp.slots = newslots;
+  reorder_leaves(&tmp);
+  std::vector<Tab> tabs;
+  std::string err;
+  int rc = build_tables(&tmp, tabs, err);
+  if (rc) return fail(rc, err);
+  hipError_t e;
+  if (nwork > 0) {
+    if (op == WACM_REFINE_ALL) {
+      e = launch_sync(g, U, 0, st);
+      if (e != hipSuccess) return hipfail(e, "adapt sync");
+    }
+    e = hipMemcpyAsync(g->d_list, list.data(), sizeof(int32_t) * list.size(),
+                       hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hipfail(e, "adapt list upload");
+    e = op == WACM_REFINE_ALL ? launch_prolong(g, U, nwork, st) : launch_decimate(g, U, nwork, st);
+    if (e != hipSuccess) return hipfail(e, "adapt kernel");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hipfail(e, "adapt synchronize");
+  }
+  for (int32_t s : freed) freelist.push_back(s);
+  g->leaves.swap(tmp.leaves);
+  g->slots.swap(tmp.slots);
+  g->index.swap(tmp.index);
+  g->nb = tmp.nb;
+  g->jfine = tmp.jfine;
+  g->free_slots.swap(freelist);
+  rc = upload_tables(g, tabs, err);
+  if (rc) return fail(rc, err);
+  if (nb_out) *nb_out = g->nb;
+  return WACM_OK;
+}
+
+int wacm_profile_enable(wacm_grid* g, int32_t on) {
+  if (!g) return fail(WACM_E_INVAL, "NULL grid");
+  g->prof.on = on != 0;
+  return WACM_OK;
+}
+
+int wacm_profile_read(wacm_grid* g, double* ms, int64_t* launches) {
+  if (!g || !ms || !launches) return fail(WACM_E_INVAL, "NULL argument");
+  hipError_t e = profile_flush(g);
+  for (int c = 0; c < 4; ++c) {
+    ms[c] = g->prof.ms[c];
+    launches[c] = g->prof.n[c];
+    g->prof.ms[c] = 0.0;
+    g->prof.n[c] = 0;
+  }
+  return e == hipSuccess ? WACM_OK : hipfail(e, "profile events");
+}
+
+}  // extern "C"

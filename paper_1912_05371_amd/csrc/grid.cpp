@@ -1,0 +1,135 @@
+// Host-side block tree of libwacm: leaf index, 2:1 checks and the per-block
+// neighbour tables the kernels use to resolve ghost points (Sec. 4.1-4.2).
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "wacm_internal.h"
+
+namespace wacm {
+
+uint64_t morton_key(const Leaf& l) {
+  // treecode scaled to level 20: 3 bits per level, x in the lowest bit
+  uint64_t k = 0;
+  for (int b = 19; b >= 0; --b) {
+    int sh = b - (20 - l.J);  // bit of the level-J index that lands on bit b
+    uint64_t xb = sh >= 0 ? ((uint64_t)l.x >> sh) & 1u : 0;
+    uint64_t yb = sh >= 0 ? ((uint64_t)l.y >> sh) & 1u : 0;
+    uint64_t zb = sh >= 0 ? ((uint64_t)l.z >> sh) & 1u : 0;
+    k = (k << 3) | (xb | (yb << 1) | (zb << 2));
+  }
+  return k;
+}
+
+static inline int64_t wrapi(int64_t a, int64_t n) {
+  int64_t r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+// Slot of the active leaf (J, x, y, z), or -1.
+static int32_t find_slot(const wacm_grid* g, int J, int64_t x, int64_t y, int64_t z) {
+  if (J < 0) return -1;
+  auto it = g->index.find(leaf_key(J, x, y, z));
+  if (it == g->index.end()) return -1;
+  return g->slots[it->second];
+}
+
+// Sort active blocks into Morton order and rebuild the key index.
+void reorder_leaves(wacm_grid* g) {
+  std::vector<int64_t> ord(g->leaves.size());
+  std::iota(ord.begin(), ord.end(), 0);
+  std::vector<uint64_t> keys(g->leaves.size());
+  for (size_t i = 0; i < keys.size(); ++i) keys[i] = morton_key(g->leaves[i]);
+  std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return keys[a] < keys[b]; });
+  std::vector<Leaf> L(ord.size());
+  std::vector<int32_t> S(ord.size());
+  for (size_t i = 0; i < ord.size(); ++i) {
+    L[i] = g->leaves[ord[i]];
+    S[i] = g->slots[ord[i]];
+  }
+  g->leaves.swap(L);
+  g->slots.swap(S);
+  g->nb = (int64_t)g->leaves.size();
+  g->index.clear();
+  g->index.reserve(g->leaves.size() * 2);
+  g->jfine = g->d.jmin;
+  for (int64_t i = 0; i < g->nb; ++i) {
+    const Leaf& l = g->leaves[i];
+    g->index[leaf_key(l.J, l.x, l.y, l.z)] = (int32_t)i;
+    g->jfine = std::max(g->jfine, l.J);
+  }
+}
+
+
+int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err) {
+  const int64_t nb = g->nb;
+  tabs.assign(nb, Tab{});
+  for (int64_t i = 0; i < nb; ++i) {
+    const Leaf& b = g->leaves[i];
+    Tab& t = tabs[i];
+    std::memset(&t, 0, sizeof(Tab));
+    t.meta[0] = g->slots[i];
+    t.meta[1] = b.J;
+    t.meta[2] = (int32_t)b.x;
+    t.meta[3] = (int32_t)b.y;
+    t.meta[4] = (int32_t)b.z;
+    const int64_t n = int64_t(1) << b.J;
+    for (int rz = 0; rz < 3; ++rz)
+      for (int ry = 0; ry < 3; ++ry)
+        for (int rx = 0; rx < 3; ++rx) {
+          int r = rx + 3 * ry + 9 * rz;
+          for (int s = 0; s < 8; ++s) t.slot[r][s] = -1;
+          int64_t nx = wrapi(b.x + rx - 1, n), ny = wrapi(b.y + ry - 1, n),
+                  nz = wrapi(b.z + rz - 1, n);
+          int32_t s0 = find_slot(g, b.J, nx, ny, nz);
+          if (s0 >= 0) {
+            t.kind[r] = 0;
+            for (int s = 0; s < 8; ++s) t.slot[r][s] = s0;
+            continue;
+          }
+          int32_t sc = b.J > 0 ? find_slot(g, b.J - 1, nx >> 1, ny >> 1, nz >> 1) : -1;
+          if (sc >= 0) {
+            t.kind[r] = -1;
+            for (int s = 0; s < 8; ++s) t.slot[r][s] = sc;
+            continue;
+          }
+          // the neighbour box must be split into level-(J+1) leaves; every
+          // sub-box touching this block has to be a leaf (2:1 grading)
+          bool anyfine = false;
+          for (int s = 0; s < 8; ++s) {
+            int sx = s & 1, sy = (s >> 1) & 1, sz = (s >> 2) & 1;
+            bool touch = (rx == 1 || sx == (rx == 0 ? 1 : 0)) &&
+                         (ry == 1 || sy == (ry == 0 ? 1 : 0)) &&
+                         (rz == 1 || sz == (rz == 0 ? 1 : 0));
+            int32_t sf = find_slot(g, b.J + 1, 2 * nx + sx, 2 * ny + sy, 2 * nz + sz);
+            if (touch && sf < 0) {
+              err = "grid is not 2:1 balanced around block (level " + std::to_string(b.J) +
+                    ", " + std::to_string(b.x) + "," + std::to_string(b.y) + "," +
+                    std::to_string(b.z) + ")";
+              return WACM_E_UNBALANCED;
+            }
+            t.slot[r][s] = sf;
+            anyfine = anyfine || sf >= 0;
+          }
+          if (!anyfine) {
+            err = "no neighbour found";
+            return WACM_E_UNBALANCED;
+          }
+          t.kind[r] = 1;
+        }
+  }
+  return WACM_OK;
+}
+
+int upload_tables(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
+  if (tabs.empty()) return WACM_OK;
+  hipError_t e = hipMemcpy(g->d_tab, tabs.data(), sizeof(Tab) * tabs.size(),
+                           hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    err = std::string("hipMemcpy tables: ") + hipGetErrorString(e);
+    return WACM_E_HIP;
+  }
+  return WACM_OK;
+}
+
+}  // namespace wacm

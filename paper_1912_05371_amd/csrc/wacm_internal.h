@@ -1,0 +1,118 @@
+// Internal declarations shared by the host code and the HIP kernels of libwacm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "wacm.h"
+
+namespace wacm {
+
+// Per active block: geometry and the 27-region neighbour description used to
+// resolve any lattice point within half a block of the block (Sec. 4.1-4.2).
+// Region r = rx + 3 ry + 9 rz, r_d = 0 (below), 1 (inside), 2 (above) the
+// block's index range along axis d.  kind[r]: 0 the level-J box of that
+// region is a leaf (slot[r][0]); -1 it lies inside a level-(J-1) leaf
+// (slot[r][0]); +1 it is split into level-(J+1) leaves slot[r][sx+2sy+4sz]
+// (only the sub-boxes touching the block are guaranteed to be leaves).
+struct alignas(16) Tab {
+  int32_t meta[8];  // slot, level J, bx, by, bz, unused x3
+  int32_t slot[27][8];
+  int8_t kind[32];
+};
+static_assert(sizeof(Tab) == 928, "Tab layout");
+
+// Element layout of one RK register: block slot s, field c, local (i,j,k).
+struct Layout {
+  int64_t bstride;  // elements per slot
+  int64_t fstride;  // elements per field
+  int32_t P;        // edge of the stored cube
+  int32_t ng;       // ghost layers stored
+};
+
+struct Leaf {
+  int32_t J;
+  int64_t x, y, z;
+};
+
+inline uint64_t leaf_key(int J, int64_t x, int64_t y, int64_t z) {
+  return (uint64_t(J) << 57) | (uint64_t(x) << 38) | (uint64_t(y) << 19) | uint64_t(z);
+}
+
+// Event-based timing of the kernels rk4_step launches (measurement only).
+struct Profiler {
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  bool on = false;
+  std::vector<hipEvent_t> spare;
+  std::vector<Rec> recs;
+  double ms[4] = {0, 0, 0, 0};
+  int64_t n[4] = {0, 0, 0, 0};
+};
+
+}  // namespace wacm
+
+struct wacm_grid {
+  wacm_grid_desc d{};
+  int P = 0;
+  int64_t nb = 0;
+  std::vector<wacm::Leaf> leaves;      // active, Morton order
+  std::vector<int32_t> slots;          // pool slot of each active block
+  std::unordered_map<uint64_t, int32_t> index;  // leaf key -> active index
+  std::vector<int32_t> free_slots;     // unused pool slots (stack)
+  // device tables, sized for `capacity` blocks
+  wacm::Tab* d_tab = nullptr;
+  double* d_part = nullptr;      // reduction partials: capacity * 16 doubles
+  double* d_norm = nullptr;      // 8 doubles
+  int32_t* d_list = nullptr;     // adaptation work lists: capacity * 10 int32
+  int jfine = 0;                 // finest active level
+  mutable wacm::Profiler prof;   // kernel timing, off by default
+};
+
+namespace wacm {
+
+// host-side helpers (grid.cpp)
+void reorder_leaves(wacm_grid* g);  // Morton order, key index, finest level
+int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err);
+int upload_tables(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err);
+uint64_t morton_key(const Leaf& l);
+void set_error(const std::string& s);
+
+// kernel launchers (kernels.hip); all enqueue on `st`
+struct Regs {  // pointers and layouts of the RK registers
+  void* U;
+  Layout Lu;
+  void* acc;
+  Layout La;
+  void* ping;
+  void* pong;
+  Layout Ls;
+};
+
+hipError_t launch_sync(const wacm_grid* g, void* U, int face_only, hipStream_t st);
+hipError_t launch_rhs(const wacm_grid* g, const wacm_params* p, double t, const void* U,
+                      void* dU, const void* dus, hipStream_t st);
+hipError_t launch_dt(const wacm_grid* g, const wacm_params* p, const void* U, double* dt_dev,
+                     hipStream_t st);
+hipError_t launch_rk4(const wacm_grid* g, const wacm_params* p, double* t_dev, double* dt_dev,
+                      void* U, void* work, const void* dus, int dt_mode, hipStream_t st);
+hipError_t launch_diag(const wacm_grid* g, const wacm_params* p, double t, const void* U,
+                       const void* dus, double* out, hipStream_t st);
+hipError_t launch_threshold(const wacm_grid* g, const wacm_params* p, double t, const void* U,
+                            double eps, int dealias, double* dmax, double* mrange,
+                            int8_t* flags, hipStream_t st);
+// refine: n entries of (parent slot, child slot, octant); decimate: n entries
+// of (parent slot, 8 child slots); lists already on the device in d_list.
+hipError_t launch_prolong(const wacm_grid* g, void* U, int64_t n, hipStream_t st);
+hipError_t launch_decimate(const wacm_grid* g, void* U, int64_t n, hipStream_t st);
+
+size_t work_bytes(const wacm_grid* g);
+hipError_t profile_flush(const wacm_grid* g);  // accumulate recorded events
+
+}  // namespace wacm

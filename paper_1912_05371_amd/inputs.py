@@ -69,8 +69,9 @@ class LeafSet:
                 return key
         return None
 
-    def refine(self, leaf):
-        """Split a leaf into 8 children, first refining coarser neighbours."""
+    def refine(self, leaf, created=None):
+        """Split a leaf into 8 children, first refining coarser neighbours.
+        New leaves are added to `created` if given."""
         J, x, y, z = leaf
         if leaf not in self.s:
             return
@@ -81,10 +82,13 @@ class LeafSet:
                         continue
                     nb = self.leaf_covering(J, x + dx, y + dy, z + dz)
                     if nb is not None and nb[0] < J:
-                        self.refine(nb)
+                        self.refine(nb, created)
         self.s.discard(leaf)
         for c in range(8):
-            self.s.add((J + 1, 2 * x + (c & 1), 2 * y + (c >> 1 & 1), 2 * z + (c >> 2 & 1)))
+            ch = (J + 1, 2 * x + (c & 1), 2 * y + (c >> 1 & 1), 2 * z + (c >> 2 & 1))
+            self.s.add(ch)
+            if created is not None:
+                created.add(ch)
 
     def arrays(self):
         return _sorted(sorted(self.s))
@@ -92,14 +96,25 @@ class LeafSet:
 
 def random_balanced_leaves(seed: int, j0: int, jmax: int, target: int):
     """Refine random leaves of level < jmax from a uniform level-j0 grid, keeping
-    the tree 2:1 balanced over 26 neighbours, until at least `target` leaves."""
+    the tree 2:1 balanced over 26 neighbours, until at least `target` leaves.
+    Candidates are drawn uniformly from a list of every leaf ever created below
+    jmax (leaves that were refined in the meantime are skipped)."""
     rng = np.random.default_rng(seed)
-    ls = LeafSet([(j0, x, y, z) for z in range(1 << j0) for y in range(1 << j0)
-                  for x in range(1 << j0)], j0)
-    while len(ls.s) < target:
-        cand = sorted(l for l in ls.s if l[0] < jmax)
-        pick = cand[int(rng.integers(len(cand)))]
-        ls.refine(pick)
+    n0 = 1 << j0
+    ls = LeafSet([(j0, x, y, z) for z in range(n0) for y in range(n0) for x in range(n0)], j0)
+    cand = sorted(ls.s) if j0 < jmax else []
+    while len(ls.s) < target and cand:
+        k = int(rng.integers(len(cand)))
+        pick = cand[k]
+        if pick not in ls.s:
+            cand[k] = cand[-1]
+            cand.pop()
+            continue
+        created = set()
+        ls.refine(pick, created=created)
+        cand[k] = cand[-1]
+        cand.pop()
+        cand.extend(sorted(l for l in created if l[0] < jmax))
     return ls.arrays()
 
 
@@ -222,3 +237,35 @@ def fourier_fields(seed: int, bs: int, L: float, lev, ix, iy, iz, nmodes=16, kma
     modes = fourier_modes(seed, 4, nmodes, kmax, amp)
     x, y, z = interior_coords(bs, L, lev, ix, iy, iz)
     return [fourier_eval(modes[c], x, y, z, L) for c in range(4)]
+
+
+def fourier_fill_device(pool, modes: np.ndarray, bs: int, ng: int, L: float, lev, ix, iy, iz,
+                        slots, chunk: int = 512):
+    """Fill the interiors of `pool` (a torch tensor (cap, 4, P, P, P) on the GPU)
+    with the same sum of cosines as fourier_eval, evaluated in float64 on the
+    device block by block (for workloads too large to build on the host)."""
+    import torch
+    dev = pool.device
+    s = 2.0 * math.pi / L
+    md = torch.as_tensor(modes, dtype=torch.float64, device=dev)
+    i = torch.arange(bs, dtype=torch.float64, device=dev)
+    lev_t = torch.as_tensor(np.asarray(lev), dtype=torch.float64, device=dev)
+    h_all = L / (torch.pow(2.0, lev_t) * bs)
+    ixt = torch.as_tensor(np.asarray(ix), dtype=torch.float64, device=dev)
+    iyt = torch.as_tensor(np.asarray(iy), dtype=torch.float64, device=dev)
+    izt = torch.as_tensor(np.asarray(iz), dtype=torch.float64, device=dev)
+    slots_t = torch.as_tensor(np.asarray(slots), dtype=torch.long, device=dev)
+    nb = len(slots)
+    for b0 in range(0, nb, chunk):
+        b1 = min(nb, b0 + chunk)
+        h = h_all[b0:b1, None]
+        X = (ixt[b0:b1, None] * bs + i[None, :]) * h
+        Y = (iyt[b0:b1, None] * bs + i[None, :]) * h
+        Z = (izt[b0:b1, None] * bs + i[None, :]) * h
+        n = b1 - b0
+        for c in range(md.shape[0]):
+            acc = torch.zeros((n, bs, bs, bs), dtype=torch.float64, device=dev)
+            for kx, ky, kz, a, ph in md[c].tolist():
+                acc += a * torch.cos(s * (kx * X[:, None, None, :] + ky * Y[:, None, :, None]
+                                          + kz * Z[:, :, None, None]) + ph)
+            pool[slots_t[b0:b1], c, ng:ng + bs, ng:ng + bs, ng:ng + bs] = acc.to(pool.dtype)

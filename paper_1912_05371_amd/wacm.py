@@ -1,0 +1,301 @@
+"""Python binding of libwacm (the C ABI in include/wacm.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device memory and streams come from PyTorch.  The binding refuses to run if
+the library is missing (build it with ``python -m paper_1912_05371_amd.build``)
+-- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwacm.so")
+
+OK = 0
+E_INVAL, E_NOMEM, E_CAPACITY, E_UNBALANCED, E_HIP, E_NONFINITE, E_TILING = -1, -2, -3, -4, -5, \
+    -6, -7
+F32, F64 = 1, 2
+DT_FIXED, DT_CFL = 0, 1
+REFINE_ALL, COARSEN = 1, 2
+MASK_NONE, MASK_SPHERE, MASK_PLATE = 0, 1, 2
+
+EXPORTS = ["wacm_last_error", "wacm_treecode_encode", "wacm_treecode_decode", "wacm_grid_create",
+           "wacm_grid_destroy", "wacm_grid_nb", "wacm_grid_info", "wacm_work_bytes",
+           "wacm_sync_ghosts", "wacm_rhs_acm", "wacm_compute_dt", "wacm_rk4_step",
+           "wacm_diagnostics", "wacm_threshold_blocks", "wacm_adapt", "wacm_profile_enable",
+           "wacm_profile_read"]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("bs", C.c_int32), ("ng", C.c_int32), ("jmin", C.c_int32), ("jmax", C.c_int32),
+                ("dtype", C.c_int32), ("reserved", C.c_int32), ("capacity", C.c_int64),
+                ("L", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nu", C.c_double), ("c0", C.c_double), ("c_gamma", C.c_double), ("c_eta", C.c_double),
+        ("c_sp", C.c_double), ("l_sp", C.c_double), ("u_inf", C.c_double * 3),
+        ("p_inf", C.c_double), ("mask", C.c_int32), ("sponge", C.c_int32), ("clip", C.c_int32),
+        ("reserved", C.c_int32), ("w", C.c_double), ("sph_c", C.c_double * 3),
+        ("sph_r", C.c_double), ("x_le", C.c_double * 3), ("lo", C.c_double * 3),
+        ("hi", C.c_double * 3), ("amp", C.c_double), ("freq", C.c_double), ("phase", C.c_double),
+        ("cfl", C.c_double), ("cfl_eta", C.c_double), ("cfl_nu", C.c_double),
+    ]
+
+
+def make_params(d: dict) -> Params:
+    p = Params()
+    for name, ctype in Params._fields_:
+        if name == "reserved" or name not in d:
+            continue
+        v = d[name]
+        cur = getattr(p, name)
+        if isinstance(cur, C.Array):
+            for i, x in enumerate(v):
+                cur[i] = float(x)
+        elif ctype is C.c_int32:
+            setattr(p, name, int(v))
+        else:
+            setattr(p, name, float(v))
+    return p
+
+
+class WacmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"wacm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libwacm.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1912_05371_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        L.wacm_last_error.restype = C.c_char_p
+        L.wacm_last_error.argtypes = []
+        L.wacm_treecode_encode.restype = C.c_uint64
+        L.wacm_treecode_encode.argtypes = [i32, i64, i64, i64]
+        L.wacm_treecode_decode.restype = None
+        L.wacm_treecode_decode.argtypes = [C.c_uint64, i32, vp, vp, vp]
+        L.wacm_grid_create.argtypes = [C.POINTER(GridDesc), i64, vp, vp, C.POINTER(vp)]
+        L.wacm_grid_destroy.argtypes = [vp]
+        L.wacm_grid_nb.restype = i64
+        L.wacm_grid_nb.argtypes = [vp]
+        L.wacm_grid_info.argtypes = [vp, vp, vp, vp]
+        L.wacm_work_bytes.restype = C.c_size_t
+        L.wacm_work_bytes.argtypes = [vp]
+        L.wacm_sync_ghosts.argtypes = [vp, vp, vp]
+        L.wacm_rhs_acm.argtypes = [vp, C.POINTER(Params), dbl, vp, vp, vp, vp]
+        L.wacm_compute_dt.argtypes = [vp, C.POINTER(Params), vp, vp, vp]
+        L.wacm_rk4_step.argtypes = [vp, C.POINTER(Params), vp, vp, vp, vp, vp, i32, vp]
+        L.wacm_diagnostics.argtypes = [vp, C.POINTER(Params), dbl, vp, vp, vp, vp]
+        L.wacm_threshold_blocks.argtypes = [vp, C.POINTER(Params), dbl, vp, dbl, i32, vp, vp, vp,
+                                            vp]
+        L.wacm_adapt.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.wacm_profile_enable.argtypes = [vp, i32]
+        L.wacm_profile_read.argtypes = [vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise WacmError(rc, lib().wacm_last_error().decode())
+
+
+def treecode_encode(level, ix, iy, iz) -> int:
+    return int(lib().wacm_treecode_encode(int(level), int(ix), int(iy), int(iz)))
+
+
+def treecode_decode(code, level):
+    x, y, z = C.c_int64(), C.c_int64(), C.c_int64()
+    lib().wacm_treecode_decode(int(code), int(level), C.byref(x), C.byref(y), C.byref(z))
+    return x.value, y.value, z.value
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+class Grid:
+    """Opaque grid handle plus the geometry needed to shape tensors."""
+
+    def __init__(self, bs, ng, L, jmin, jmax, treecodes, levels, dtype=F64, capacity=None):
+        treecodes = np.ascontiguousarray(treecodes, np.uint64)
+        levels = np.ascontiguousarray(levels, np.int8)
+        n = len(treecodes)
+        self.desc = GridDesc(int(bs), int(ng), int(jmin), int(jmax), int(dtype), 0,
+                             int(capacity if capacity is not None else n), float(L))
+        h = C.c_void_p()
+        _check(lib().wacm_grid_create(C.byref(self.desc), n,
+                                      treecodes.ctypes.data_as(C.c_void_p),
+                                      levels.ctypes.data_as(C.c_void_p), C.byref(h)))
+        self._h = h
+        self.bs, self.ng, self.L, self.jmin, self.jmax = int(bs), int(ng), float(L), jmin, jmax
+        self.P = self.bs + 2 * self.ng
+        self.dtype = dtype
+        self.capacity = self.desc.capacity
+
+    @classmethod
+    def from_case(cls, case, dtype=F64, capacity=None):
+        codes = [treecode_encode(l, x, y, z) for l, x, y, z in
+                 zip(case.lev, case.ix, case.iy, case.iz)]
+        return cls(case.bs, case.ng, case.L, case.jmin, case.jmax, codes, case.lev, dtype,
+                   capacity)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().wacm_grid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nb(self) -> int:
+        return int(lib().wacm_grid_nb(self._h))
+
+    def info(self):
+        nb = self.nb
+        slots = np.zeros(nb, np.int64)
+        codes = np.zeros(nb, np.uint64)
+        levels = np.zeros(nb, np.int8)
+        _check(lib().wacm_grid_info(self._h, slots.ctypes.data_as(C.c_void_p),
+                                    codes.ctypes.data_as(C.c_void_p),
+                                    levels.ctypes.data_as(C.c_void_p)))
+        return slots, codes, levels
+
+    def work_bytes(self) -> int:
+        return int(lib().wacm_work_bytes(self._h))
+
+    # ---- tensors ------------------------------------------------------------
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.dtype == F64 else torch.float32
+
+    def pool(self, device="cuda"):
+        import torch
+        return torch.zeros((self.capacity, 4, self.P, self.P, self.P), dtype=self.torch_dtype(),
+                           device=device)
+
+    def work(self, device="cuda"):
+        import torch
+        return torch.empty(self.work_bytes(), dtype=torch.uint8, device=device)
+
+    def _chk_pool(self, U):
+        if tuple(U.shape) != (self.capacity, 4, self.P, self.P, self.P) or \
+                U.dtype != self.torch_dtype() or not U.is_contiguous() or not U.is_cuda:
+            raise ValueError("pool tensor must be a contiguous CUDA tensor of shape "
+                             f"{(self.capacity, 4, self.P, self.P, self.P)} / {self.torch_dtype()}")
+
+    @staticmethod
+    def _chk_vec(t, n, dtype_name, what):
+        import torch
+        dt = {"f64": torch.float64, "i8": torch.int8}[dtype_name]
+        if t is None or not t.is_cuda or t.dtype != dt or not t.is_contiguous() or t.numel() < n:
+            raise ValueError(f"{what} must be a contiguous CUDA {dt} tensor with >= {n} entries")
+
+    def _chk_dus(self, dus):
+        if dus is None:
+            return
+        if tuple(dus.shape) != (self.capacity, 3, self.bs ** 3) or \
+                dus.dtype != self.torch_dtype() or not dus.is_contiguous() or not dus.is_cuda:
+            raise ValueError("dus must be (capacity, 3, bs^3) contiguous on the GPU")
+
+    # ---- entry points (same names as the C ABI) ----------------------------------
+    def sync_ghosts(self, U, stream=None):
+        self._chk_pool(U)
+        _check(lib().wacm_sync_ghosts(self._h, _ptr(U), _stream(stream)))
+
+    def rhs_acm(self, params: dict, t: float, U, dU, dus=None, stream=None):
+        self._chk_pool(U)
+        self._chk_pool(dU)
+        self._chk_dus(dus)
+        p = make_params(params)
+        _check(lib().wacm_rhs_acm(self._h, C.byref(p), float(t), _ptr(U), _ptr(dU), _ptr(dus),
+                                  _stream(stream)))
+
+    def compute_dt(self, params: dict, U, dt_dev, stream=None):
+        self._chk_pool(U)
+        self._chk_vec(dt_dev, 1, "f64", "dt_dev")
+        p = make_params(params)
+        _check(lib().wacm_compute_dt(self._h, C.byref(p), _ptr(U), _ptr(dt_dev), _stream(stream)))
+
+    def rk4_step(self, params: dict, t_dev, dt_dev, U, work, dus=None, dt_mode=DT_CFL,
+                 stream=None, _p=None):
+        self._chk_pool(U)
+        self._chk_dus(dus)
+        self._chk_vec(t_dev, 1, "f64", "t_dev")
+        self._chk_vec(dt_dev, 1, "f64", "dt_dev")
+        if not work.is_cuda or work.numel() * work.element_size() < self.work_bytes():
+            raise ValueError("work buffer too small")
+        p = _p if _p is not None else make_params(params)
+        _check(lib().wacm_rk4_step(self._h, C.byref(p), _ptr(t_dev), _ptr(dt_dev), _ptr(U),
+                                   _ptr(work), _ptr(dus), int(dt_mode), _stream(stream)))
+
+    def diagnostics(self, params: dict, t: float, U, out, dus=None, stream=None):
+        self._chk_pool(U)
+        self._chk_dus(dus)
+        self._chk_vec(out, 9, "f64", "out")
+        p = make_params(params)
+        _check(lib().wacm_diagnostics(self._h, C.byref(p), float(t), _ptr(U), _ptr(dus), _ptr(out),
+                                      _stream(stream)))
+
+    def threshold_blocks(self, params: dict, t: float, U, eps: float, dealias: bool, dmax,
+                         mrange, flags, stream=None):
+        self._chk_pool(U)
+        nb = self.nb
+        self._chk_vec(dmax, nb, "f64", "dmax")
+        self._chk_vec(mrange, nb, "f64", "mrange")
+        self._chk_vec(flags, nb, "i8", "flags")
+        p = make_params(params)
+        _check(lib().wacm_threshold_blocks(self._h, C.byref(p), float(t), _ptr(U), float(eps),
+                                           int(bool(dealias)), _ptr(dmax), _ptr(mrange),
+                                           _ptr(flags), _stream(stream)))
+
+    def adapt(self, op: int, U, flags=None, stream=None) -> int:
+        self._chk_pool(U)
+        nb = C.c_int64()
+        fptr = None
+        if flags is not None:
+            flags = np.ascontiguousarray(flags, np.int8)
+            if len(flags) != self.nb:
+                raise ValueError("flags must have nb entries")
+            fptr = flags.ctypes.data_as(C.c_void_p)
+        _check(lib().wacm_adapt(self._h, int(op), fptr, _ptr(U), C.byref(nb), _stream(stream)))
+        return nb.value
+
+    def profile_enable(self, on: bool = True):
+        _check(lib().wacm_profile_enable(self._h, int(bool(on))))
+
+    def profile_read(self):
+        """(ms[4], launches[4]) per kernel class: dt, sync, stage, time update."""
+        ms = np.zeros(4)
+        n = np.zeros(4, np.int64)
+        _check(lib().wacm_profile_read(self._h, ms.ctypes.data_as(C.c_void_p),
+                                       n.ctypes.data_as(C.c_void_p)))
+        return ms, n

@@ -1,0 +1,116 @@
+// Host harness for the kernels' point resolver (csrc/resolve.h), built for the
+// CPU by tests/test_resolver_cpu.py.  It builds the library's neighbour tables
+// from a leaf list, then runs the very functions the sync kernel runs on the
+// GPU -- shell enumeration and ghost_value -- over every ghost point, with
+// every source access checked to be an interior point of a valid slot.
+//
+//   resolver_harness leaves.txt state_in.bin state_out.bin
+// leaves.txt: "bs ng L jmin jmax capacity n" then n lines "J x y z" (slot i = line i)
+// state: n * 4 * P^3 doubles (pool layout).  Exit 0 on success.
+#include <cstdio>
+#include <cstdlib>
+#include <set>
+#include <tuple>
+#include <vector>
+
+#include "resolve.h"
+#include "wacm_internal.h"
+
+static int g_cap = 0;
+
+namespace wacm {
+void wacm_host_check(int slot, int li, int lj, int lk, int bs) {
+  if (slot < 0 || slot >= g_cap || li < 0 || li >= bs || lj < 0 || lj >= bs || lk < 0 ||
+      lk >= bs) {
+    std::fprintf(stderr, "out-of-bounds source: slot %d local (%d,%d,%d) bs %d\n", slot, li, lj,
+                 lk, bs);
+    std::exit(5);
+  }
+}
+}  // namespace wacm
+
+using namespace wacm;
+
+int main(int argc, char** argv) {
+  if (argc != 4) return 2;
+  FILE* f = std::fopen(argv[1], "r");
+  if (!f) return 2;
+  wacm_grid g;
+  long long cap, n;
+  if (std::fscanf(f, "%d %d %lf %d %d %lld %lld", &g.d.bs, &g.d.ng, &g.d.L, &g.d.jmin, &g.d.jmax,
+                  &cap, &n) != 7)
+    return 2;
+  g.d.capacity = cap;
+  g.d.dtype = WACM_F64;
+  g.P = g.d.bs + 2 * g.d.ng;
+  g_cap = (int)cap;
+  for (long long i = 0; i < n; ++i) {
+    Leaf l;
+    long long x, y, z;
+    if (std::fscanf(f, "%d %lld %lld %lld", &l.J, &x, &y, &z) != 4) return 2;
+    l.x = x;
+    l.y = y;
+    l.z = z;
+    g.leaves.push_back(l);
+    g.slots.push_back((int32_t)i);
+  }
+  std::fclose(f);
+  reorder_leaves(&g);
+  std::vector<Tab> tabs;
+  std::string err;
+  int rc = build_tables(&g, tabs, err);
+  if (rc) {
+    std::fprintf(stderr, "tables: %s\n", err.c_str());
+    return 3;
+  }
+  const int bs = g.d.bs, ng = g.d.ng, P = g.P;
+  Layout L;
+  L.P = P;
+  L.ng = ng;
+  L.fstride = (int64_t)P * P * P;
+  L.bstride = 4 * L.fstride;
+  std::vector<double> U((size_t)cap * L.bstride, 0.0);
+  FILE* fi = std::fopen(argv[2], "rb");
+  if (!fi) return 2;
+  if (std::fread(U.data(), sizeof(double), (size_t)n * L.bstride, fi) != (size_t)n * L.bstride)
+    return 2;
+  std::fclose(fi);
+
+  // enumeration: mode 0 visits every ghost point once, mode 1 the depth-3 face star
+  for (int mode = 0; mode < 2; ++mode) {
+    const int npts = mode == 1 ? 18 * bs * bs : P * P * P - bs * bs * bs;
+    std::set<std::tuple<int, int, int>> seen;
+    for (int p = 0; p < npts; ++p) {
+      int i, j, k;
+      shell_point(p, bs, ng, P, mode, i, j, k);
+      int out = (i < 0 || i >= bs) + (j < 0 || j >= bs) + (k < 0 || k >= bs);
+      bool ok = i >= -ng && i < bs + ng && j >= -ng && j < bs + ng && k >= -ng && k < bs + ng &&
+                out >= 1;
+      if (mode == 1) ok = ok && out == 1 && i >= -3 && i < bs + 3 && j >= -3 && j < bs + 3 &&
+                          k >= -3 && k < bs + 3;
+      if (!ok || !seen.insert({i, j, k}).second) {
+        std::fprintf(stderr, "bad shell point mode %d p %d -> (%d,%d,%d)\n", mode, p, i, j, k);
+        return 4;
+      }
+    }
+  }
+  // the sync kernel's per-point work, in place like on the GPU
+  const int npts = P * P * P - bs * bs * bs;
+  for (int64_t ib = 0; ib < g.nb; ++ib) {
+    const Tab& t = tabs[ib];
+    double* dst = U.data() + (int64_t)t.meta[0] * L.bstride;
+    for (int p = 0; p < npts; ++p) {
+      int i, j, k;
+      shell_point(p, bs, ng, P, 0, i, j, k);
+      double v[4];
+      ghost_value<double>(t, bs, L, U.data(), i, j, k, v);
+      const int64_t o = ((int64_t)(k + ng) * P + (j + ng)) * P + (i + ng);
+      for (int c = 0; c < 4; ++c) dst[o + c * L.fstride] = v[c];
+    }
+  }
+  FILE* fo = std::fopen(argv[3], "wb");
+  if (!fo) return 2;
+  std::fwrite(U.data(), sizeof(double), (size_t)n * L.bstride, fo);
+  std::fclose(fo);
+  return 0;
+}

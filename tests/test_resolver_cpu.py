@@ -1,0 +1,94 @@
+"""CPU check of the GPU sync path's own code: the library's neighbour tables
+and the __host__ __device__ resolver (csrc/resolve.h) are compiled for the
+host and run over every ghost point of several grids.  Every source access is
+bounds-checked (an interior point of a valid slot), the shell enumeration must
+visit each ghost point exactly once, and the resulting ghosts must match the
+oracle's synchronisation."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1912_05371_amd import cases, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1912_05371_amd", "csrc")
+BIN = os.path.join(ROOT, "_build", "resolver_harness")
+
+
+@pytest.fixture(scope="module")
+def harness():
+    os.makedirs(os.path.dirname(BIN), exist_ok=True)
+    cmd = ["/opt/rocm/bin/hipcc", "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-DWACM_HOST_CHECK",
+           "-O1", "-std=c++17", "-I/opt/rocm/include", f"-I{os.path.join(ROOT, 'include')}",
+           f"-I{CSRC}", "-o", BIN, os.path.join(ROOT, "tests", "resolver_harness.cpp"),
+           os.path.join(CSRC, "grid.cpp")]
+    subprocess.run(cmd, check=True)
+    return BIN
+
+
+def run_case(orc, harness, tmp_path, bs, ng, L, jmin, jmax, lev, ix, iy, iz, seed=0):
+    og = orc.Grid(bs, ng, L, jmin, jmax, lev, ix, iy, iz)
+    P = bs + 2 * ng
+    rng = np.random.default_rng(seed)
+    U = rng.standard_normal((og.nb, 4, P, P, P))
+    lf = tmp_path / "leaves.txt"
+    with open(lf, "w") as f:
+        f.write(f"{bs} {ng} {L!r} {jmin} {jmax} {og.nb} {og.nb}\n")
+        for l, x, y, z in zip(lev, ix, iy, iz):
+            f.write(f"{l} {x} {y} {z}\n")
+    U.tofile(tmp_path / "in.bin")
+    r = subprocess.run([harness, str(lf), str(tmp_path / "in.bin"), str(tmp_path / "out.bin")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    Ug = np.fromfile(tmp_path / "out.bin").reshape(U.shape)
+    Uo = U.copy()
+    og.sync(Uo)
+    err = np.max(np.abs(Ug - Uo))
+    assert err <= 8 * np.finfo(float).eps * np.max(np.abs(Uo)), err
+    return og.nb
+
+
+def test_uniform_and_sphere(orc, harness, tmp_path):
+    c = cases.taylor_green()
+    run_case(orc, harness, tmp_path, c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix, c.iy, c.iz)
+    c = cases.sphere_two_level()
+    assert run_case(orc, harness, tmp_path, c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix, c.iy,
+                    c.iz) == 736
+
+
+@pytest.mark.parametrize("bs,ng", [(16, 4), (24, 4), (16, 5), (32, 4)])
+def test_random_trees(orc, harness, tmp_path, bs, ng):
+    for seed in range(2):
+        lev, ix, iy, iz = inputs.random_balanced_leaves(50 + seed, 1, 4, 150)
+        run_case(orc, harness, tmp_path, bs, ng, 1.0, 1, 4, lev, ix, iy, iz, seed)
+
+
+def test_coarse_root_levels(orc, harness, tmp_path):
+    # level 0/1 neighbours wrap onto themselves
+    lev, ix, iy, iz = inputs.uniform_leaves(0)
+    run_case(orc, harness, tmp_path, 16, 4, 1.0, 0, 2, lev, ix, iy, iz)
+    lev, ix, iy, iz = inputs.random_balanced_leaves(3, 0, 2, 20)
+    run_case(orc, harness, tmp_path, 16, 4, 1.0, 0, 2, lev, ix, iy, iz)
+
+
+def test_unbalanced_tables_rejected(orc, harness, tmp_path):
+    lev, ix, iy, iz = inputs.uniform_leaves(1)
+    ls = inputs.LeafSet(zip(lev, ix, iy, iz), 1)
+    ls.s.discard((1, 0, 0, 0))
+    for c in range(8):
+        ls.s.add((2, c & 1, c >> 1 & 1, c >> 2 & 1))
+    ls.s.discard((2, 1, 1, 1))
+    for c in range(8):
+        ls.s.add((3, 2 + (c & 1), 2 + (c >> 1 & 1), 2 + (c >> 2 & 1)))
+    l2, x2, y2, z2 = ls.arrays()
+    lf = tmp_path / "leaves.txt"
+    with open(lf, "w") as f:
+        f.write(f"16 4 1.0 1 3 {len(l2)} {len(l2)}\n")
+        for l, x, y, z in zip(l2, x2, y2, z2):
+            f.write(f"{l} {x} {y} {z}\n")
+    np.zeros(len(l2) * 4 * 24 ** 3).tofile(tmp_path / "in.bin")
+    r = subprocess.run([harness, str(lf), str(tmp_path / "in.bin"), str(tmp_path / "out.bin")],
+                       capture_output=True, text=True)
+    assert r.returncode == 3 and "balanced" in r.stderr
