@@ -121,14 +121,29 @@ int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err) {
   return WACM_OK;
 }
 
+std::vector<int32_t> coarse_faces(const std::vector<Tab>& tabs) {
+  std::vector<int32_t> cf;
+  for (size_t i = 0; i < tabs.size(); ++i)
+    for (int f = 0; f < 6; ++f)
+      if (tabs[i].kind[FACE_REGION[f]] != 0) {
+        cf.push_back((int32_t)i);
+        cf.push_back(f);
+      }
+  return cf;
+}
+
 int upload_tables(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
   if (tabs.empty()) return WACM_OK;
   hipError_t e = hipMemcpy(g->d_tab, tabs.data(), sizeof(Tab) * tabs.size(),
                            hipMemcpyHostToDevice);
+  std::vector<int32_t> cf = coarse_faces(tabs);
+  if (e == hipSuccess && !cf.empty())
+    e = hipMemcpy(g->d_cface, cf.data(), sizeof(int32_t) * cf.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     err = std::string("hipMemcpy tables: ") + hipGetErrorString(e);
     return WACM_E_HIP;
   }
+  g->n_cface = (int64_t)cf.size() / 2;
   return WACM_OK;
 }
 

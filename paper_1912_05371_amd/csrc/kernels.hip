@@ -58,13 +58,22 @@ __global__ __launch_bounds__(NT_GEN) void sync_kernel(const Tab* __restrict__ ta
 // --------------------------------------------------------------------------
 // fused rhs + RK4 stage (Sec. 2.2-2.3)
 // --------------------------------------------------------------------------
+// Barrier that orders LDS traffic only: global loads issued before it stay in
+// flight (they are the next plane's prefetch).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <typename T>
 struct StageArgs {
   const Tab* tab;
   int64_t nb;
-  const T* in;  // stage input, padded, face ghosts valid
+  const T* in;  // stage input register
   Layout Lin;
-  T* un;  // U^n register (pool)
+  const T* hb;  // halo buffer of faces next to other levels [slot][6][4][3][bs][bs]
+  T* un;        // U^n register (the pool)
   Layout Lun;
   T* acc;  // accumulator (compact)
   Layout Lacc;
@@ -75,19 +84,97 @@ struct StageArgs {
   const double* dt_dev;
   double t_host;
   double L;
+  int xcd_map;  // 1: give each XCD a contiguous run of blocks
   wacm_params p;
 };
 
-// MODE 0: dU = rhs(U).  MODE s = 1..4: classical RK4 stage s with registers
-// U^n, acc, and the stage inputs:
+// Persistent block loop.  With xcd_map, workgroup w (dispatched to XCD w % 8)
+// walks a contiguous eighth of the Morton-ordered block list, so blocks that
+// share faces are processed close in time on the same L2.
+struct BlockIter {
+  int64_t ib, end, step;
+  __device__ BlockIter(int64_t nb, int xcd_map) {
+    const int64_t G = gridDim.x, w = blockIdx.x;
+    if (xcd_map && G % 8 == 0 && nb >= G) {
+      const int64_t per = G / 8, xcd = w % 8, lw = w / 8;
+      const int64_t chunk = (nb + 7) / 8;
+      const int64_t start = xcd * chunk;
+      end = start + chunk < nb ? start + chunk : nb;
+      ib = start + lw;
+      step = per;
+    } else {
+      ib = w;
+      end = nb;
+      step = G;
+    }
+  }
+};
+
+// Where the depth-3 halo of one face of the current block lives: element
+// (field c, depth d away from the face, tangential t0 < t1 by axis order) is
+// ptr[c fs + d sd + t0 s0 + t1 s1].  Same-level neighbours are read in place
+// (their interior next to the face); faces next to a coarser or finer leaf
+// point into the halo buffer filled by nlface_kernel; the rhs-only mode reads
+// the block's own synchronised ghost layers.
+template <typename T>
+struct FaceDesc {
+  const T* ptr;
+  int32_t fs, sd, s0, s1;
+};
+
+template <typename T, int BS, bool GHOSTS>
+__device__ __forceinline__ FaceDesc<T> face_desc(const Tab& tb, const StageArgs<T>& a, int f) {
+  const int axis = f >> 1, side = f & 1;
+  const Layout& L = a.Lin;
+  const int sx[3] = {1, L.P, L.P * L.P};
+  const int sa = sx[axis], st0 = sx[axis == 0 ? 1 : 0], st1 = sx[axis == 2 ? 1 : 2];
+  const int slot = tb.meta[0];
+  const int64_t org = ((int64_t)L.ng * L.P + L.ng) * L.P + L.ng;  // local (0,0,0)
+  FaceDesc<T> fd;
+  if (GHOSTS) {
+    fd.ptr = a.in + (int64_t)slot * L.bstride + org + (int64_t)(side ? BS : -1) * sa;
+    fd.fs = (int)L.fstride;
+    fd.sd = side ? sa : -sa;
+    fd.s0 = st0;
+    fd.s1 = st1;
+    return fd;
+  }
+  const int r = (axis == 0 ? 2 * side : 1) + 3 * (axis == 1 ? 2 * side : 1) +
+                9 * (axis == 2 ? 2 * side : 1);
+  if (tb.kind[r] == 0) {
+    fd.ptr = a.in + (int64_t)tb.slot[r][0] * L.bstride + org + (int64_t)(side ? 0 : BS - 1) * sa;
+    fd.fs = (int)L.fstride;
+    fd.sd = side ? sa : -sa;
+    fd.s0 = st0;
+    fd.s1 = st1;
+  } else {
+    fd.ptr = a.hb + ((int64_t)slot * 6 + f) * 12 * BS * BS;
+    fd.fs = 3 * BS * BS;
+    fd.sd = BS * BS;
+    fd.s0 = 1;
+    fd.s1 = BS;
+  }
+  return fd;
+}
+
+// MODE 0: dU = rhs(U) with U's own ghost layers.  MODE s = 1..4: classical
+// RK4 stage s with registers U^n, acc and the stage inputs:
 //   s1: acc = U^n + dt/6 k1, out = U^n + dt/2 k1   (input = U^n)
 //   s2: acc += dt/3 k2,      out = U^n + dt/2 k2
 //   s3: acc += dt/3 k3,      out = U^n + dt k3
 //   s4: U^n = acc + dt/6 k4
-template <typename T, int BS, int MODE>
+// PEN: penalization/sponge terms present.  PREF: load the epilogue operands
+// (U^n, acc) before the barrier instead of after the rhs.  One workgroup per block
+// (persistent), one thread per (x,y) column marching in z: z-neighbours in a
+// register queue, the x/y cross of the current plane in a double-buffered LDS
+// slab, the next plane's loads issued before the barrier.
+template <typename T, int BS, int MODE, bool PEN, bool PREF>
 __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
-  constexpr int H = 3, W = BS + 2 * H, NT = BS * BS;
-  __shared__ T slab[4][W * W];
+  constexpr int H = 3, W = BS + 2 * H, NH = 12 * BS;
+  constexpr bool GH = (MODE == 0);
+  __shared__ T slab[2][4][W * W];
+  __shared__ FaceDesc<T> fds[6];
+  __shared__ int32_t meta[5];
   const int tid = threadIdx.x;
   const int x = tid % BS, y = tid / BS;
   const T a1 = T(TW1), a2 = T(TW2), a3 = T(TW3);
@@ -97,96 +184,136 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
     tc = *a.t_dev;
     dt = *a.dt_dev;
   }
-  const double ts = tc + (MODE == 2 || MODE == 3 ? 0.5 * dt : (MODE == 4 ? dt : 0.0));
-  const wacm_params& p = a.p;
-  const T nu = T(p.nu), c0sq = T(p.c0 * p.c0), cg = T(p.c_gamma);
-  const T iceta = p.mask ? T(1.0 / p.c_eta) : T(0), icsp = p.sponge ? T(1.0 / p.c_sp) : T(0);
+  const T nu = T(a.p.nu), c0sq = T(a.p.c0 * a.p.c0), cg = T(a.p.c_gamma);
   const T fA = T(MODE == 1 ? dt / 6.0 : (MODE == 4 ? dt / 6.0 : dt / 3.0));
   const T fB = T(MODE == 3 ? dt : 0.5 * dt);
-  const int64_t fin = a.Lin.fstride;
-  const int ngi = a.Lin.ng, Pi = a.Lin.P;
+  const int fin = (int)a.Lin.fstride, Pi = a.Lin.P;
   const int cidx = (y + H) * W + (x + H);
+  // this thread's halo point of every plane (threads < NH): faces x-, x+, y-, y+
+  const bool hthr = tid < NH;
+  int hf = 0, hd = 0, hs = 0, hli = 0;
+  if (hthr) {
+    hf = tid / (3 * BS);
+    const int rem = tid - hf * 3 * BS;
+    hd = rem / BS;
+    hs = rem - hd * BS;
+    const int hx = hf == 0 ? -1 - hd : (hf == 1 ? BS + hd : hs);
+    const int hy = hf == 2 ? -1 - hd : (hf == 3 ? BS + hd : hs);
+    hli = (hy + H) * W + (hx + H);
+  }
+  // offsets of this thread's column in the input, accumulator and U^n
+  const int col = (a.Lin.ng * Pi + (y + a.Lin.ng)) * Pi + (x + a.Lin.ng);
+  const int zs = Pi * Pi;
+  const int acol = (a.Lacc.ng * a.Lacc.P + (y + a.Lacc.ng)) * a.Lacc.P + (x + a.Lacc.ng);
+  const int azs = a.Lacc.P * a.Lacc.P, afs = (int)a.Lacc.fstride;
+  const int ucol = (a.Lun.ng * a.Lun.P + (y + a.Lun.ng)) * a.Lun.P + (x + a.Lun.ng);
+  const int uzs = a.Lun.P * a.Lun.P, ufs = (int)a.Lun.fstride;
+  const int ocol = (a.Lout.ng * a.Lout.P + (y + a.Lout.ng)) * a.Lout.P + (x + a.Lout.ng);
+  const int ozs = a.Lout.P * a.Lout.P, ofs = (int)a.Lout.fstride;
 
-  for (int64_t ib = blockIdx.x; ib < a.nb; ib += gridDim.x) {
-    const int32_t* m = a.tab[ib].meta;
-    const int slot = m[0], J = m[1], bx = m[2], by = m[3], bz = m[4];
-    const double hd = a.L / (double(int64_t(1) << J) * BS);
-    const T ih = T(1.0 / hd), ih2 = T(1.0 / (hd * hd));
-    const T* __restrict__ in = a.in + (int64_t)slot * a.Lin.bstride;
-    auto gi = [&](int i, int j, int k) -> int64_t {
-      return ((int64_t)(k + ngi) * Pi + (j + ngi)) * Pi + (i + ngi);
-    };
+  for (BlockIter it(a.nb, a.xcd_map); it.ib < it.end; it.ib += it.step) {
+    lds_barrier();
+    if (tid < 6) fds[tid] = face_desc<T, BS, GH>(a.tab[it.ib], a, tid);
+    if (tid < 5) meta[tid] = a.tab[it.ib].meta[tid];
+    lds_barrier();
+    const int slot = meta[0], J = meta[1];
+    const double hdd = a.L / (double(int64_t(1) << J) * BS);
+    const T ih = T(1.0 / hdd), ih2 = T(1.0 / (hdd * hdd));
+    const T* __restrict__ inb = a.in + (int64_t)slot * a.Lin.bstride + col;
+    T* accb = a.acc + (int64_t)slot * a.Lacc.bstride + acol;
+    T* unb = a.un + (int64_t)slot * a.Lun.bstride + ucol;
+    T* outb = a.out + (int64_t)slot * a.Lout.bstride + ocol;
+    const FaceDesc<T> fzl = fds[4], fzh = fds[5];
+    FaceDesc<T> fh;
+    if (hthr) fh = fds[hf];
+
     T q[4][7];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int mm = 0; mm < 7; ++mm) {
+      const int z = mm - 3;
 #pragma unroll
-      for (int mm = 0; mm < 7; ++mm) q[c][mm] = in[c * fin + gi(x, y, mm - 3)];
+      for (int c = 0; c < 4; ++c)
+        q[c][mm] = z < 0 ? fzl.ptr[c * fzl.fs + (-1 - z) * fzl.sd + x * fzl.s0 + y * fzl.s1]
+                         : inb[c * fin + z * zs];
+    }
+    // plane 0 into slab 0
+#pragma unroll
+    for (int c = 0; c < 4; ++c) slab[0][c][cidx] = q[c][3];
+    if (hthr) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) slab[0][c][hli] = fh.ptr[c * fh.fs + hd * fh.sd + hs * fh.s0];
+    }
 
     for (int z = 0; z < BS; ++z) {
-      // prefetch the next column value
-      T nq[4];
+      T(*sb)[W * W] = slab[z & 1];
+      // loads for the next plane: column value at z+4 and this thread's halo point
+      T nq[4], hnx[4];
       if (z + 1 < BS) {
+        const int zz = z + 4;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) nq[c] = in[c * fin + gi(x, y, z + 4)];
-      }
-      __syncthreads();
+        for (int c = 0; c < 4; ++c)
+          nq[c] = zz < BS ? inb[c * fin + zz * zs]
+                          : fzh.ptr[c * fzh.fs + (zz - BS) * fzh.sd + x * fzh.s0 + y * fzh.s1];
+        if (hthr) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) slab[c][cidx] = q[c][3];
-      for (int pp = tid; pp < 12 * BS; pp += NT) {
-        const int f = pp / (3 * BS);
-        const int rem = pp - f * 3 * BS;
-        const int d = rem / BS, s = rem - d * BS;
-        int hx, hy;
-        if (f == 0) {
-          hx = -1 - d;
-          hy = s;
-        } else if (f == 1) {
-          hx = BS + d;
-          hy = s;
-        } else if (f == 2) {
-          hx = s;
-          hy = -1 - d;
-        } else {
-          hx = s;
-          hy = BS + d;
+          for (int c = 0; c < 4; ++c)
+            hnx[c] = fh.ptr[c * fh.fs + hd * fh.sd + hs * fh.s0 + (z + 1) * fh.s1];
         }
-        const int li = (hy + H) * W + (hx + H);
-        const int64_t g = gi(hx, hy, z);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) slab[c][li] = in[c * fin + g];
       }
-      __syncthreads();
+      // epilogue operands of this point, loaded early if PREF
+      T unv[4], acv[4];
+      if (PREF) {
+        if (MODE == 2 || MODE == 3) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            unv[c] = unb[c * ufs + z * uzs];
+            acv[c] = accb[c * afs + z * azs];
+          }
+        } else if (MODE == 4) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acv[c] = accb[c * afs + z * azs];
+        }
+      }
+      lds_barrier();
 
-      T d1[4][3], d2[3][3], val[4];
+      // rhs, accumulated field by field
+      const T u = q[0][3], v = q[1][3], w = q[2][3], pr = q[3][3];
+      T r[4], div = T(0);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const T* s = slab[c];
-        val[c] = q[c][3];
-        d1[c][0] = (a1 * (s[cidx + 1] - s[cidx - 1]) + a2 * (s[cidx + 2] - s[cidx - 2]) +
-                    a3 * (s[cidx + 3] - s[cidx - 3])) *
-                   ih;
-        d1[c][1] = (a1 * (s[cidx + W] - s[cidx - W]) + a2 * (s[cidx + 2 * W] - s[cidx - 2 * W]) +
-                    a3 * (s[cidx + 3 * W] - s[cidx - 3 * W])) *
-                   ih;
-        d1[c][2] = (a1 * (q[c][4] - q[c][2]) + a2 * (q[c][5] - q[c][1]) +
-                    a3 * (q[c][6] - q[c][0])) *
-                   ih;
+        const T* s = sb[c];
+        const T dx = (a1 * (s[cidx + 1] - s[cidx - 1]) + a2 * (s[cidx + 2] - s[cidx - 2]) +
+                      a3 * (s[cidx + 3] - s[cidx - 3])) *
+                     ih;
+        const T dy = (a1 * (s[cidx + W] - s[cidx - W]) + a2 * (s[cidx + 2 * W] - s[cidx - 2 * W]) +
+                      a3 * (s[cidx + 3 * W] - s[cidx - 3 * W])) *
+                     ih;
+        const T dz = (a1 * (q[c][4] - q[c][2]) + a2 * (q[c][5] - q[c][1]) +
+                      a3 * (q[c][6] - q[c][0])) *
+                     ih;
         if (c < 3) {
-          d2[c][0] = (c2a * s[cidx - 2] + c2b * s[cidx - 1] + c2c * s[cidx] + c2b * s[cidx + 1] +
-                      c2a * s[cidx + 2]) *
-                     ih2;
-          d2[c][1] = (c2a * s[cidx - 2 * W] + c2b * s[cidx - W] + c2c * s[cidx] +
-                      c2b * s[cidx + W] + c2a * s[cidx + 2 * W]) *
-                     ih2;
-          d2[c][2] = (c2a * q[c][1] + c2b * q[c][2] + c2c * q[c][3] + c2b * q[c][4] +
-                      c2a * q[c][5]) *
-                     ih2;
+          const T lap = ((c2a * s[cidx - 2] + c2b * s[cidx - 1] + c2c * s[cidx] +
+                          c2b * s[cidx + 1] + c2a * s[cidx + 2]) +
+                         (c2a * s[cidx - 2 * W] + c2b * s[cidx - W] + c2c * s[cidx] +
+                          c2b * s[cidx + W] + c2a * s[cidx + 2 * W]) +
+                         (c2a * q[c][1] + c2b * q[c][2] + c2c * q[c][3] + c2b * q[c][4] +
+                          c2a * q[c][5])) *
+                        ih2;
+          r[c] = -(u * dx + v * dy + w * dz) + nu * lap;
+          div += c == 0 ? dx : (c == 1 ? dy : dz);
+        } else {
+          r[0] -= dx;
+          r[1] -= dy;
+          r[2] -= dz;
         }
       }
-      T chi = T(0), sp = T(0), us[3] = {T(0), T(0), T(0)};
-      if (p.mask || p.sponge) {
-        const double xg = (double)(bx * BS + x) * hd, yg = (double)(by * BS + y) * hd,
-                     zg = (double)(bz * BS + z) * hd;
+      r[3] = -c0sq * div - cg * pr;
+      if (PEN) {
+        const wacm_params& p = a.p;
+        const double ts = tc + (MODE == 2 || MODE == 3 ? 0.5 * dt : (MODE == 4 ? dt : 0.0));
+        T chi = T(0), sp = T(0), us[3] = {T(0), T(0), T(0)};
+        const double xg = (double)(meta[2] * BS + x) * hdd, yg = (double)(meta[3] * BS + y) * hdd,
+                     zg = (double)(meta[4] * BS + z) * hdd;
         if (p.mask) {
           double cd, u3[3];
           mask_eval(p, ts, xg, yg, zg, cd, u3);
@@ -196,59 +323,60 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
           us[2] = T(u3[2]);
         }
         if (p.sponge) sp = T(sponge_eval(p, a.L, xg, yg, zg));
-      }
-      if (a.dus) {
-        const T* du = a.dus + (int64_t)slot * 3 * BS * BS * BS + (z * BS + y) * BS + x;
-        us[0] += du[0];
-        us[1] += du[BS * BS * BS];
-        us[2] += du[2 * BS * BS * BS];
-      }
-      T r[4];
+        if (a.dus) {
+          const T* du = a.dus + (int64_t)slot * 3 * BS * BS * BS + (z * BS + y) * BS + x;
+          us[0] += du[0];
+          us[1] += du[BS * BS * BS];
+          us[2] += du[2 * BS * BS * BS];
+        }
+        const T iceta = p.mask ? T(1.0 / p.c_eta) : T(0), icsp = p.sponge ? T(1.0 / p.c_sp) : T(0);
+        const T val[4] = {u, v, w, pr};
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        T rc = -(val[0] * d1[c][0] + val[1] * d1[c][1] + val[2] * d1[c][2]) - d1[3][c] +
-               nu * (d2[c][0] + d2[c][1] + d2[c][2]);
-        if (p.mask) rc -= chi * iceta * (val[c] - us[c]);
-        if (p.sponge) rc -= sp * icsp * (val[c] - T(p.u_inf[c]));
-        r[c] = rc;
-      }
-      {
-        T rp = -c0sq * (d1[0][0] + d1[1][1] + d1[2][2]) - cg * val[3];
-        if (p.sponge) rp -= sp * icsp * (val[3] - T(p.p_inf));
-        r[3] = rp;
+        for (int c = 0; c < 3; ++c) {
+          if (p.mask) r[c] -= chi * iceta * (val[c] - us[c]);
+          if (p.sponge) r[c] -= sp * icsp * (val[c] - T(p.u_inf[c]));
+        }
+        if (p.sponge) r[3] -= sp * icsp * (pr - T(p.p_inf));
       }
 
-      if (MODE == 0) {
-        T* o = a.out + (int64_t)slot * a.Lout.bstride;
-        const int64_t oi = ((int64_t)(z + a.Lout.ng) * a.Lout.P + (y + a.Lout.ng)) * a.Lout.P +
-                           (x + a.Lout.ng);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) o[oi + c * a.Lout.fstride] = r[c];
-      } else {
-        T* accp = a.acc + (int64_t)slot * a.Lacc.bstride;
-        const int64_t ai = ((int64_t)(z + a.Lacc.ng) * a.Lacc.P + (y + a.Lacc.ng)) * a.Lacc.P +
-                           (x + a.Lacc.ng);
-        T* unp = a.un + (int64_t)slot * a.Lun.bstride;
-        const int64_t ui = ((int64_t)(z + a.Lun.ng) * a.Lun.P + (y + a.Lun.ng)) * a.Lun.P +
-                           (x + a.Lun.ng);
-        if (MODE == 1 || MODE == 2 || MODE == 3) {
-          T* o = a.out + (int64_t)slot * a.Lout.bstride;
-          const int64_t oi = ((int64_t)(z + a.Lout.ng) * a.Lout.P + (y + a.Lout.ng)) * a.Lout.P +
-                             (x + a.Lout.ng);
+      if (!PREF) {
+        if (MODE == 2 || MODE == 3) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            const T u0 = MODE == 1 ? val[c] : unp[ui + c * a.Lun.fstride];
-            const T ac = MODE == 1 ? u0 : accp[ai + c * a.Lacc.fstride];
-            accp[ai + c * a.Lacc.fstride] = ac + fA * r[c];
-            o[oi + c * a.Lout.fstride] = u0 + fB * r[c];
+            unv[c] = unb[c * ufs + z * uzs];
+            acv[c] = accb[c * afs + z * azs];
           }
-        } else {
+        } else if (MODE == 4) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c)
-            unp[ui + c * a.Lun.fstride] = accp[ai + c * a.Lacc.fstride] + fA * r[c];
+          for (int c = 0; c < 4; ++c) acv[c] = accb[c * afs + z * azs];
+        }
+      }
+      if (MODE == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) outb[c * ofs + z * ozs] = r[c];
+      } else if (MODE == 4) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) unb[c * ufs + z * uzs] = acv[c] + fA * r[c];
+      } else {
+        const T val[4] = {u, v, w, pr};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const T u0 = MODE == 1 ? val[c] : unv[c];
+          const T ac = MODE == 1 ? u0 : acv[c];
+          accb[c * afs + z * azs] = ac + fA * r[c];
+          outb[c * ofs + z * ozs] = u0 + fB * r[c];
         }
       }
       if (z + 1 < BS) {
+        // plane z+1 into the other slab: it was last read before this
+        // plane's barrier, which every thread has passed
+        T(*nb_)[W * W] = slab[(z + 1) & 1];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) nb_[c][cidx] = q[c][4];
+        if (hthr) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) nb_[c][hli] = hnx[c];
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
 #pragma unroll
@@ -256,6 +384,119 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
           q[c][6] = nq[c];
         }
       }
+    }
+  }
+}
+
+// Faces next to a coarser or finer leaf: the depth-3 face halo of the stage
+// input into the halo buffer the stage kernel reads.  A finer neighbour gives
+// its coincident point (decimation, Sec. 3.1).  A coarser neighbour gives the
+// tensor-product DD4 prediction (Sec. 3.1), computed separably: the coarse
+// lattice box around the face (even local indices, read from whichever leaves
+// hold them) is gathered into LDS once, then predicted along the normal and
+// the two tangential axes in turn.
+constexpr int NLF_MAXS = 32 / 2 + 3;  // coarse points per tangential axis, bs <= 32
+constexpr int NLF_MAXN = 5;           // coarse points along the normal
+template <typename T>
+__global__ __launch_bounds__(NT_GEN) void nlface_kernel(const Tab* __restrict__ tab,
+                                                        const int32_t* __restrict__ cf, int64_t n,
+                                                        const T* __restrict__ in, Layout Lin,
+                                                        T* __restrict__ hb, int bs) {
+  __shared__ Tab st;
+  __shared__ int64_t soff[NLF_MAXN * NLF_MAXS * NLF_MAXS];
+  __shared__ T src[NLF_MAXN * NLF_MAXS * NLF_MAXS];
+  __shared__ T pa[3 * NLF_MAXS * NLF_MAXS];
+  __shared__ T pb[3 * NLF_MAXS * 32];
+  const int S = bs / 2 + 3;  // tangential coarse positions -2, 0, ..., bs+2
+  const T w0 = T(DDW0), w1 = T(DDW1);
+  for (int64_t wk = blockIdx.x; wk < n; wk += gridDim.x) {
+    const int32_t ib = cf[2 * wk], f = cf[2 * wk + 1];
+    __syncthreads();
+    load_tab(tab + ib, st);
+    __syncthreads();
+    const int slot = st.meta[0];
+    const int axis = f >> 1, side = f & 1;
+    const int ua = axis == 0 ? 1 : 0, ub = axis == 2 ? 1 : 2;  // tangential axes t0, t1
+    const int r = (axis == 0 ? 2 * side : 1) + 3 * (axis == 1 ? 2 * side : 1) +
+                  9 * (axis == 2 ? 2 * side : 1);
+    T* hbf = hb + ((int64_t)slot * 6 + f) * 12 * bs * bs;
+    if (st.kind[r] > 0) {
+      // finer neighbour: every halo point is a point of a finer leaf
+      for (int p = threadIdx.x; p < 3 * bs * bs; p += blockDim.x) {
+        const int d = p / (bs * bs), qq = p - d * bs * bs;
+        int li[3];
+        li[axis] = side ? bs + d : -1 - d;
+        li[ua] = qq % bs;
+        li[ub] = qq / bs;
+        const int64_t o = point_offset(st, bs, Lin, li[0], li[1], li[2]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) hbf[(int64_t)(c * 3) * bs * bs + p] = in[o + c * Lin.fstride];
+      }
+      continue;
+    }
+    // coarser neighbour.  normal ghost positions g_d = bs + d (side 1) or
+    // -1 - d (side 0); the even positions their stencils use run from n0 in
+    // steps of 2: side 1 [bs-2, bs+4] (4 points), side 0 [-6, 2] (5 points)
+    const int n0 = side ? bs - 2 : -6;
+    const int NN = side ? 4 : 5;
+    const int nsrc = NN * S * S;
+    for (int p = threadIdx.x; p < nsrc; p += blockDim.x) {
+      const int m = p / (S * S), qq = p - m * S * S;
+      int li[3];
+      li[axis] = n0 + 2 * m;
+      li[ua] = 2 * (qq % S) - 2;
+      li[ub] = 2 * (qq / S) - 2;
+      soff[p] = point_offset(st, bs, Lin, li[0], li[1], li[2]);
+    }
+    __syncthreads();
+    for (int c = 0; c < 4; ++c) {
+      for (int p = threadIdx.x; p < nsrc; p += blockDim.x) src[p] = in[soff[p] + c * Lin.fstride];
+      __syncthreads();
+      // along the normal: pa[d][t1'][t0']
+      for (int p = threadIdx.x; p < 3 * S * S; p += blockDim.x) {
+        const int d = p / (S * S), qq = p - d * S * S;
+        const int g = side ? bs + d : -1 - d;
+        T v;
+        if ((g & 1) == 0) {
+          v = src[((g - n0) / 2) * S * S + qq];
+        } else {
+          const int m = (g - 3 - n0) / 2;  // taps g-3, g-1, g+1, g+3
+          v = w0 * src[m * S * S + qq] + w1 * src[(m + 1) * S * S + qq] +
+              w1 * src[(m + 2) * S * S + qq] + w0 * src[(m + 3) * S * S + qq];
+        }
+        pa[p] = v;
+      }
+      __syncthreads();
+      // along t0: pb[d][t1'][t0], t0 in [0, bs)
+      for (int p = threadIdx.x; p < 3 * S * bs; p += blockDim.x) {
+        const int t0 = p % bs, rest = p / bs;  // rest = d * S + t1'
+        const T* row = pa + rest * S;
+        T v;
+        if ((t0 & 1) == 0) {
+          v = row[t0 / 2 + 1];
+        } else {
+          const int m = (t0 - 3) / 2 + 1;  // coarse index of t0-3
+          v = w0 * row[m] + w1 * row[m + 1] + w1 * row[m + 2] + w0 * row[m + 3];
+        }
+        pb[p] = v;
+      }
+      __syncthreads();
+      // along t1: out[d][t1][t0]
+      for (int p = threadIdx.x; p < 3 * bs * bs; p += blockDim.x) {
+        const int d = p / (bs * bs), qq = p - d * bs * bs;
+        const int t0 = qq % bs, t1 = qq / bs;
+        const T* colp = pb + d * S * bs + t0;
+        T v;
+        if ((t1 & 1) == 0) {
+          v = colp[(t1 / 2 + 1) * bs];
+        } else {
+          const int m = (t1 - 3) / 2 + 1;
+          v = w0 * colp[m * bs] + w1 * colp[(m + 1) * bs] + w1 * colp[(m + 2) * bs] +
+              w0 * colp[(m + 3) * bs];
+        }
+        hbf[(int64_t)(c * 3) * bs * bs + p] = v;
+      }
+      __syncthreads();
     }
   }
 }
@@ -706,13 +947,26 @@ static unsigned grid_for(int64_t n, int per_cu) {
   return (unsigned)(n < cap ? (n > 0 ? n : 1) : cap);
 }
 
-size_t work_bytes(const wacm_grid* g) {
+// work buffer: acc, ping, pong (compact, bs^3 per field) and the coarse-face
+// halo buffer (6 faces x 4 fields x 3 x bs^2 per slot), 256-byte aligned parts
+struct WorkParts {
+  size_t acc, ping, pong, hb, total;
+};
+static WorkParts work_parts(const wacm_grid* g) {
   const size_t es = g->d.dtype == WACM_F64 ? 8 : 4;
   const size_t cap = (size_t)g->d.capacity;
-  const size_t P3 = (size_t)g->P * g->P * g->P, b3 = (size_t)g->d.bs * g->d.bs * g->d.bs;
+  const size_t b3 = (size_t)g->d.bs * g->d.bs * g->d.bs, b2 = (size_t)g->d.bs * g->d.bs;
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
-  return up(cap * 4 * b3 * es) + 2 * up(cap * 4 * P3 * es);
+  WorkParts w;
+  w.acc = 0;
+  w.ping = up(cap * 4 * b3 * es);
+  w.pong = w.ping + up(cap * 4 * b3 * es);
+  w.hb = w.pong + up(cap * 4 * b3 * es);
+  w.total = w.hb + up(cap * 6 * 4 * 3 * b2 * es);
+  return w;
 }
+
+size_t work_bytes(const wacm_grid* g) { return work_parts(g).total; }
 
 template <typename T>
 static hipError_t sync_t(const wacm_grid* g, T* U, int mode, hipStream_t st) {
@@ -727,11 +981,33 @@ hipError_t launch_sync(const wacm_grid* g, void* U, int face_only, hipStream_t s
                                 : sync_t(g, (float*)U, face_only ? 1 : 0, st);
 }
 
+// resident workgroups per CU of a kernel (queried once per instantiation)
+template <typename K>
+static int resident_per_cu(K kernel, int threads) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess || n < 1)
+    n = 1;
+  return n;
+}
+
+template <typename T, int BS, int MODE, bool PEN>
+static hipError_t stage_launch_pen(const StageArgs<T>& a, hipStream_t st) {
+  // FP64 keeps the epilogue loads late to stay within the VGPR budget of a
+  // 9-wave workgroup; FP32 has room to issue them early
+  constexpr bool PREF = sizeof(T) == 4;
+  static const int per_cu = resident_per_cu(stage_kernel<T, BS, MODE, PEN, PREF>, BS * BS);
+  int64_t grid = (int64_t)per_cu * num_cus();
+  if (grid > a.nb) grid = a.nb;
+  if (grid < 1) grid = 1;
+  stage_kernel<T, BS, MODE, PEN, PREF><<<(unsigned)grid, BS * BS, 0, st>>>(a);
+  return hipGetLastError();
+}
+
 template <typename T, int BS, int MODE>
 static hipError_t stage_launch(const StageArgs<T>& a, hipStream_t st) {
-  const int per_cu = BS <= 16 ? 8 : 2;
-  stage_kernel<T, BS, MODE><<<grid_for(a.nb, per_cu), BS * BS, 0, st>>>(a);
-  return hipGetLastError();
+  const bool pen = a.p.mask || a.p.sponge || a.dus;
+  return pen ? stage_launch_pen<T, BS, MODE, true>(a, st)
+             : stage_launch_pen<T, BS, MODE, false>(a, st);
 }
 
 template <typename T, int MODE>
@@ -754,6 +1030,7 @@ static StageArgs<T> base_args(const wacm_grid* g, const wacm_params* p) {
   a.tab = g->d_tab;
   a.nb = g->nb;
   a.L = g->d.L;
+  a.xcd_map = 1;
   a.p = *p;
   return a;
 }
@@ -767,6 +1044,10 @@ static hipError_t rhs_t(const wacm_grid* g, const wacm_params* p, double t, cons
   a.Lin = pool_layout(g);
   a.out = dU;
   a.Lout = pool_layout(g);
+  a.un = dU;
+  a.Lun = pool_layout(g);
+  a.acc = dU;
+  a.Lacc = pool_layout(g);
   a.dus = dus;
   a.t_host = t;
   return stage_dispatch<T, 0>(g->d.bs, a, st);
@@ -805,35 +1086,36 @@ static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
     ProfScope ps(g, 0, st);
     if ((e = dt_t<T>(g, p, U, dt_dev, st)) != hipSuccess) return e;
   }
-  const size_t es = sizeof(T);
-  const size_t cap = (size_t)g->d.capacity;
-  const size_t P3 = (size_t)g->P * g->P * g->P, b3 = (size_t)g->d.bs * g->d.bs * g->d.bs;
-  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  const WorkParts wp = work_parts(g);
   char* w = (char*)work;
-  T* acc = (T*)w;
-  T* ping = (T*)(w + up(cap * 4 * b3 * es));
-  T* pong = (T*)(w + up(cap * 4 * b3 * es) + up(cap * 4 * P3 * es));
+  T* acc = (T*)(w + wp.acc);
+  T* ping = (T*)(w + wp.ping);
+  T* pong = (T*)(w + wp.pong);
+  T* hb = (T*)(w + wp.hb);
   StageArgs<T> a = base_args<T>(g, p);
   a.un = U;
   a.Lun = pool_layout(g);
   a.acc = acc;
   a.Lacc = compact_layout(g);
+  a.hb = hb;
   a.dus = dus;
   a.t_dev = t_dev;
   a.dt_dev = dt_dev;
-  const Layout Lp = pool_layout(g);
+  const Layout Lp = pool_layout(g), Lc = compact_layout(g);
   T* ins[4] = {U, ping, pong, ping};
-  T* outs[4] = {ping, pong, ping, nullptr};
+  T* outs[4] = {ping, pong, ping, U};
   for (int s = 0; s < 4; ++s) {
-    {
+    a.in = ins[s];
+    a.Lin = s == 0 ? Lp : Lc;
+    a.out = outs[s];
+    a.Lout = s == 3 ? Lp : Lc;
+    if (g->n_cface > 0) {
       ProfScope ps(g, 1, st);
-      if ((e = sync_t<T>(g, ins[s], 1, st)) != hipSuccess) return e;
+      nlface_kernel<T><<<grid_for(g->n_cface, 8), NT_GEN, 0, st>>>(
+          g->d_tab, g->d_cface, g->n_cface, a.in, a.Lin, hb, g->d.bs);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     ProfScope ps(g, 2, st);
-    a.in = ins[s];
-    a.Lin = Lp;
-    a.out = outs[s];
-    a.Lout = Lp;
     switch (s) {
       case 0:
         e = stage_dispatch<T, 1>(g->d.bs, a, st);

@@ -26,6 +26,9 @@ struct alignas(16) Tab {
 };
 static_assert(sizeof(Tab) == 928, "Tab layout");
 
+// Region index of face f = 2 axis + side (side 0: below, 1: above).
+constexpr int FACE_REGION[6] = {12, 14, 10, 16, 4, 22};
+
 // Element layout of one RK register: block slot s, field c, local (i,j,k).
 struct Layout {
   int64_t bstride;  // elements per slot
@@ -71,6 +74,8 @@ struct wacm_grid {
   double* d_part = nullptr;      // reduction partials: capacity * 16 doubles
   double* d_norm = nullptr;      // 8 doubles
   int32_t* d_list = nullptr;     // adaptation work lists: capacity * 10 int32
+  int32_t* d_cface = nullptr;    // (active index, face) of faces next to another level
+  int64_t n_cface = 0;
   int jfine = 0;                 // finest active level
   mutable wacm::Profiler prof;   // kernel timing, off by default
 };
@@ -81,6 +86,7 @@ namespace wacm {
 void reorder_leaves(wacm_grid* g);  // Morton order, key index, finest level
 int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err);
 int upload_tables(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err);
+std::vector<int32_t> coarse_faces(const std::vector<Tab>& tabs);  // non-same-level faces
 uint64_t morton_key(const Leaf& l);
 void set_error(const std::string& s);
 
