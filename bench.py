@@ -139,6 +139,33 @@ def roofline(res, npts: int, es: int):
     }
 
 
+def copy_probe(gib: float):
+    """Bandwidth of a plain streaming kernel (torch.neg: read and write `gib`
+    GiB once each): the achievable rate, and the reference for scaling the
+    traffic counters (its FETCH_SIZE / WRITE_SIZE must read `gib` GiB)."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    # torch.neg: a plain elementwise kernel that reads and writes n doubles once
+    for _ in range(2):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        torch.neg(a, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    moved = 2 * n * 8
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_buffer": n * 8, "bytes_moved": moved, "ms": round(ms, 4),
+            "GBps": round(moved / (ms * 1e-3) / 1e9, 1)}
+
+
 def cpu_baseline(seed: int):
     """The FP64 oracle on a bounded sample of the same workload: one RK4 step
     (with its CFL time step) on a smaller random octree built by the same
@@ -178,6 +205,9 @@ def main():
     ap.add_argument("--dtype", choices=["both", "f64", "f32"], default="both")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=float, default=2.0,
+                    help="GiB per buffer of a plain device copy timed for the achievable "
+                         "bandwidth (0: skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -198,6 +228,9 @@ def main():
     log(f"workload: {case.nb} blocks {levels}, {npts} interior points "
         f"(generated in {time.perf_counter() - t0:.1f} s)")
 
+    copy = copy_probe(args.copy_probe) if args.copy_probe > 0 else None
+    if copy:
+        log(f"copy probe: {copy['bytes_moved'] / 1e9:.2f} GB moved at {copy['GBps']:.0f} GB/s")
     results = {}
     for name, code, es in (("f64", wacm.F64, 8), ("f32", wacm.F32, 4)):
         if args.dtype not in ("both", name):
@@ -253,6 +286,9 @@ def main():
     line["kernel_ms_per_step"] = {
         k: round(v / args.steps, 4)
         for k, v in zip(["dt", "sync", "stage", "time"], R["kernel_ms"])}
+    if copy:
+        line["copy_probe"] = copy
+        line["roofline"]["frac_of_copy"] = round(R["roofline"]["achieved"] / copy["GBps"], 4)
     if not args.no_cpu_baseline:
         log("timing the oracle on a sample")
         line["cpu_baseline"] = cpu_baseline(args.seed)

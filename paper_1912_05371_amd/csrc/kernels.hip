@@ -157,6 +157,18 @@ __device__ __forceinline__ FaceDesc<T> face_desc(const Tab& tb, const StageArgs<
   return fd;
 }
 
+// Streaming operands (U^n, the accumulator) are touched once per stage: load
+// and store them non-temporally so the caches keep the stage input, whose
+// face layers neighbouring blocks read again.
+template <typename T>
+__device__ __forceinline__ T ntload(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void ntstore(T v, T* p) {
+  __builtin_nontemporal_store(v, p);
+}
+
 // MODE 0: dU = rhs(U) with U's own ghost layers.  MODE s = 1..4: classical
 // RK4 stage s with registers U^n, acc and the stage inputs:
 //   s1: acc = U^n + dt/6 k1, out = U^n + dt/2 k1   (input = U^n)
@@ -266,12 +278,12 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
         if (MODE == 2 || MODE == 3) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            unv[c] = unb[c * ufs + z * uzs];
-            acv[c] = accb[c * afs + z * azs];
+            unv[c] = ntload(unb + c * ufs + z * uzs);
+            acv[c] = ntload(accb + c * afs + z * azs);
           }
         } else if (MODE == 4) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acv[c] = accb[c * afs + z * azs];
+          for (int c = 0; c < 4; ++c) acv[c] = ntload(accb + c * afs + z * azs);
         }
       }
       lds_barrier();
@@ -343,12 +355,12 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
         if (MODE == 2 || MODE == 3) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            unv[c] = unb[c * ufs + z * uzs];
-            acv[c] = accb[c * afs + z * azs];
+            unv[c] = ntload(unb + c * ufs + z * uzs);
+            acv[c] = ntload(accb + c * afs + z * azs);
           }
         } else if (MODE == 4) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acv[c] = accb[c * afs + z * azs];
+          for (int c = 0; c < 4; ++c) acv[c] = ntload(accb + c * afs + z * azs);
         }
       }
       if (MODE == 0) {
@@ -356,14 +368,14 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
         for (int c = 0; c < 4; ++c) outb[c * ofs + z * ozs] = r[c];
       } else if (MODE == 4) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) unb[c * ufs + z * uzs] = acv[c] + fA * r[c];
+        for (int c = 0; c < 4; ++c) ntstore(acv[c] + fA * r[c], unb + c * ufs + z * uzs);
       } else {
         const T val[4] = {u, v, w, pr};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const T u0 = MODE == 1 ? val[c] : unv[c];
           const T ac = MODE == 1 ? u0 : acv[c];
-          accb[c * afs + z * azs] = ac + fA * r[c];
+          ntstore(ac + fA * r[c], accb + c * afs + z * azs);
           outb[c * ofs + z * ozs] = u0 + fB * r[c];
         }
       }
