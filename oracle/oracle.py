@@ -239,6 +239,10 @@ class Grid:
         h = lib().orc_refine_all(self._h, _ptr(U), _ptr(Un))
         return self._child(h), Un
 
+    def coarsen_count(self, flags: np.ndarray) -> int:
+        flags = np.ascontiguousarray(flags, np.int8)
+        return int(lib().orc_coarsen_count(self._h, _ptr(flags)))
+
     def coarsen(self, flags: np.ndarray, U: np.ndarray):
         flags = np.ascontiguousarray(flags, np.int8)
         n = int(lib().orc_coarsen_count(self._h, _ptr(flags)))

@@ -1,0 +1,221 @@
+"""GPU parity of the adaptation rows: wavelet details and coarsening flags,
+refine-all, one coarsening pass, and the refine -> evolve -> coarsen step on
+the rotating-plate case, against the FP64 oracle through the C ABI.
+
+Adaptive runs use flag replay: the GPU follows the oracle's coarsening flags
+(mapped by treecode), so both sides visit the same grids; the GPU's own flags
+are computed as well and the number of disagreements is reported (exact
+agreement is required in FP64, where both sides take the decision from the
+same FP64 details up to rounding).
+"""
+import numpy as np
+import pytest
+
+from paper_1912_05371_amd import cases, inputs, wacm
+
+from gpu_util import from_pool, log, rel_err, slot_map
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def plate_small(clip=1):
+    c = cases.plate_adaptive(jmin=2, jmax=4, jstart=3)
+    c.params = cases.plate_params(4, c.bs, c.L, clip=clip)
+    return c
+
+
+def octree16():
+    return cases.random_octree(bs=16, ng=4, target=200, j0=1, jmax=3, seed=11)
+
+
+CASES = {"sphere": cases.sphere_two_level, "octree16": octree16, "plate": plate_small}
+
+
+def build(orc, c, prec=wacm.F64, capacity=None):
+    og = orc.Grid(c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix, c.iy, c.iz)
+    gg = wacm.Grid.from_case(c, dtype=prec, capacity=capacity or 9 * c.nb + 64)
+    return og, gg
+
+
+def put(gg, og, U, pool=None):
+    """Oracle state (oracle block order) into the GPU pool at the GPU slots."""
+    if pool is None:
+        pool = gg.pool()
+    slots = slot_map(gg, og)
+    pool[torch.as_tensor(slots, device="cuda")] = torch.from_numpy(U).to(
+        device="cuda", dtype=gg.torch_dtype())
+    return pool
+
+
+def active_index(gg, og):
+    slots, codes, levels = gg.info()
+    pos = {(int(l), int(c)): i for i, (c, l) in enumerate(zip(codes, levels))}
+    return np.array([pos[(int(og.lev[b]), wacm.treecode_encode(og.lev[b], og.ix[b], og.iy[b],
+                                                                og.iz[b]))]
+                     for b in range(og.nb)])
+
+
+def same_leaves(gg, og):
+    slots, codes, levels = gg.info()
+    a = sorted(zip(levels.tolist(), codes.tolist()))
+    b = sorted((int(l), wacm.treecode_encode(l, x, y, z))
+               for l, x, y, z in zip(og.lev, og.ix, og.iy, og.iz))
+    return a == b
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_threshold_matches_oracle(orc, name):
+    log(f"threshold {name}")
+    c = CASES[name]()
+    og, gg = build(orc, c)
+    U = c.padded()
+    rng = np.random.default_rng(5)
+    # smooth state plus a few sharp spots so that details spread over decades
+    U[..., c.ng:-c.ng, c.ng:-c.ng, c.ng:-c.ng] += 1e-3 * rng.standard_normal(
+        (og.nb, 4, c.bs, c.bs, c.bs)) * (rng.uniform(size=(og.nb, 1, 1, 1, 1)) < 0.2)
+    t = 0.07
+    og.sync(U)
+    dm_o, mr_o = og.details(c.params, t, U)
+    eps = float(np.median(dm_o))  # a threshold inside the spread of details
+    fl_o = og.flags(dm_o, mr_o, eps, True)
+    pool = put(gg, og, U)
+    gg.sync_ghosts(pool)
+    nb = gg.nb
+    dmax = torch.zeros(nb, dtype=torch.float64, device="cuda")
+    mr = torch.zeros(nb, dtype=torch.float64, device="cuda")
+    fl = torch.zeros(nb, dtype=torch.int8, device="cuda")
+    gg.threshold_blocks(c.params, t, pool, eps, True, dmax, mr, fl)
+    torch.cuda.synchronize()
+    ai = active_index(gg, og)
+    dm_g, mr_g, fl_g = dmax.cpu().numpy()[ai], mr.cpu().numpy()[ai], fl.cpu().numpy()[ai]
+    e = np.max(np.abs(dm_g - dm_o) / np.maximum(dm_o, 1e-300))
+    log(f"  details rel err {e:.2e}; mask-range max diff {np.max(np.abs(mr_g - mr_o)):.2e}; "
+        f"flags set {int(fl_o.sum())}/{og.nb}, disagreements {int(np.sum(fl_g != fl_o))}")
+    assert e < 1e-10
+    assert np.max(np.abs(mr_g - mr_o)) < 1e-12
+    assert np.array_equal((mr_g > 0), (mr_o > 0))
+    assert np.array_equal(fl_g, fl_o)
+
+
+@pytest.mark.parametrize("name", ["octree16", "plate"])
+def test_refine_all_matches_oracle(orc, name):
+    log(f"refine_all {name}")
+    c = CASES[name]()
+    og, gg = build(orc, c)
+    U = c.padded()
+    pool = put(gg, og, U)
+    nb_new = gg.adapt(wacm.REFINE_ALL, pool)
+    Uo = U.copy()
+    og.sync(Uo)
+    og2, Uo2 = og.refine_all(Uo)
+    assert nb_new == og2.nb and same_leaves(gg, og2)
+    Ug = from_pool(pool, slot_map(gg, og2))
+    e = rel_err(Ug, Uo2, c.bs, c.ng)
+    log(f"  {og.nb} -> {og2.nb} blocks, interior rel err {e:.2e}")
+    assert e < 1e-14
+
+
+def test_coarsen_pass_matches_oracle(orc):
+    log("coarsen octree16")
+    c = octree16()
+    og, gg = build(orc, c)
+    U = c.padded()
+    rng = np.random.default_rng(3)
+    flags_o = (rng.uniform(size=og.nb) < 0.7).astype(np.int8)
+    og2, Uo2 = og.coarsen(flags_o, U)
+    pool = put(gg, og, U)
+    ai = active_index(gg, og)
+    flags_g = np.zeros(og.nb, np.int8)
+    flags_g[ai] = flags_o
+    nb_new = gg.adapt(wacm.COARSEN, pool, flags_g)
+    log(f"  {og.nb} -> {og2.nb} blocks")
+    assert og2.nb < og.nb
+    assert nb_new == og2.nb and same_leaves(gg, og2)
+    Ug = from_pool(pool, slot_map(gg, og2))
+    I = slice(c.ng, c.ng + c.bs)
+    assert np.array_equal(Ug[..., I, I, I], Uo2[..., I, I, I])
+
+
+def test_capacity_error_leaves_grid_unchanged(orc):
+    c = octree16()
+    og, gg = build(orc, c, capacity=c.nb + 7)
+    pool = gg.pool()
+    before = gg.info()
+    with pytest.raises(wacm.WacmError) as e:
+        gg.adapt(wacm.REFINE_ALL, pool)
+    assert e.value.code == wacm.E_CAPACITY
+    after = gg.info()
+    assert all(np.array_equal(a, b) for a, b in zip(before, after))
+
+
+def adaptive_step_oracle(og, U, prm, t, eps, dealias):
+    """Sec. 3.5: refine all, one RK4 step, coarsen until no block merges.
+    Returns the new grid, state, dt and the flag lists used by each pass."""
+    og.sync(U)
+    g1, U1 = og.refine_all(U)
+    dt = g1.dt(prm, U1)
+    g1.rk4_step(prm, t, dt, U1)
+    passes = []
+    while True:
+        g1.sync(U1)
+        dm, mr = g1.details(prm, t + dt, U1)
+        fl = g1.flags(dm, mr, eps, dealias)
+        n_new = g1.coarsen_count(fl)
+        if n_new == g1.nb:
+            break
+        passes.append((g1, fl))
+        g1, U1 = g1.coarsen(fl, U1)
+    return g1, U1, dt, passes
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adaptive_plate_replay(orc, prec):
+    """Refine -> evolve -> coarsen (Sec. 3.5) on the rotating plate, 2 steps,
+    each from the oracle's state; GPU follows the oracle's flags."""
+    log(f"adaptive plate {prec}")
+    c = plate_small()
+    eps, dealias = c.extra["eps"], c.extra["dealias"]
+    og = orc.Grid(c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix, c.iy, c.iz)
+    U = c.padded()
+    t = 0.0
+    dtype = wacm.F64 if prec == "f64" else wacm.F32
+    for step in range(2):
+        og_n, U_n, dt, passes = adaptive_step_oracle(og, U.copy(), c.params, t, eps, dealias)
+        # GPU from the same start grid and state
+        lev, ix, iy, iz = og.lev, og.ix, og.iy, og.iz
+        codes = [wacm.treecode_encode(l, x, y, z) for l, x, y, z in zip(lev, ix, iy, iz)]
+        gg = wacm.Grid(c.bs, c.ng, c.L, c.jmin, c.jmax, codes, lev, dtype, capacity=12 * og.nb)
+        Uin = U.astype(np.float32).astype(np.float64) if prec == "f32" else U
+        pool = put(gg, og, Uin)
+        gg.adapt(wacm.REFINE_ALL, pool)
+        work = gg.work()
+        t_dev = torch.tensor([t], dtype=torch.float64, device="cuda")
+        dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
+        gg.rk4_step(c.params, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_FIXED)
+        disagree = 0
+        for g_o, fl_o in passes:
+            assert same_leaves(gg, g_o)
+            gg.sync_ghosts(pool)
+            nb = gg.nb
+            dmax = torch.zeros(nb, dtype=torch.float64, device="cuda")
+            mr = torch.zeros(nb, dtype=torch.float64, device="cuda")
+            fl = torch.zeros(nb, dtype=torch.int8, device="cuda")
+            gg.threshold_blocks(c.params, t + dt, pool, eps, dealias, dmax, mr, fl)
+            ai = active_index(gg, g_o)
+            own = fl.cpu().numpy()[ai]
+            disagree += int(np.sum(own != fl_o))
+            flags_g = np.zeros(nb, np.int8)
+            flags_g[ai] = fl_o
+            gg.adapt(wacm.COARSEN, pool, flags_g)
+        assert same_leaves(gg, og_n)
+        Ug = from_pool(pool, slot_map(gg, og_n))
+        e = rel_err(Ug, U_n, c.bs, c.ng)
+        log(f"  step {step}: {og.nb} -> refine -> {len(passes)} merge passes -> {og_n.nb} blocks;"
+            f" state rel err {e:.2e}; own-flag disagreements {disagree}")
+        assert e < (1e-12 if prec == "f64" else 1e-5)
+        if prec == "f64":
+            assert disagree == 0
+        og, U, t = og_n, U_n, t + dt
+        del gg
