@@ -106,6 +106,14 @@ def lib():
         L.orc_coarsen_count.argtypes = [vp, vp]
         L.orc_coarsen.restype = vp
         L.orc_coarsen.argtypes = [vp, vp, vp, vp]
+        L.orc_rhs_adj.argtypes = [vp, C.POINTER(OrcParams), C.c_double, vp, vp, vp, dp, vp, vp]
+        L.orc_sync_adj.argtypes = [vp, vp]
+        L.orc_force_x.restype = C.c_double
+        L.orc_force_x.argtypes = [vp, C.POINTER(OrcParams), C.c_double, vp, vp]
+        L.orc_force_x_adj.argtypes = [vp, C.POINTER(OrcParams), C.c_double, C.c_double, vp, vp,
+                                      dp, vp, vp]
+        L.orc_rk4_step_adj.argtypes = [vp, C.POINTER(OrcParams), C.c_double, C.c_double, vp,
+                                       vp, dp, vp, vp]
         _lib = L
     return _lib
 
@@ -249,6 +257,61 @@ class Grid:
         Un = np.zeros((n, 4, self.P, self.P, self.P))
         h = lib().orc_coarsen(self._h, _ptr(flags), _ptr(U), _ptr(Un))
         return self._child(h), Un
+
+    # ---- adjoint ----------------------------------------------------------
+    def rhs_adj(self, params, t, U, V, Ubar, dtheta, dusbar=None, dus=None):
+        p = make_params(params)
+        th = (C.c_double * 3)(*dtheta)
+        lib().orc_rhs_adj(self._h, C.byref(p), t, _ptr(U), _ptr(V), _ptr(Ubar), th,
+                          _ptr(dusbar), _ptr(dus))
+        dtheta[:] = list(th)
+
+    def sync_adj(self, Ubar):
+        lib().orc_sync_adj(self._h, _ptr(Ubar))
+
+    def force_x(self, params, t, U, dus=None) -> float:
+        p = make_params(params)
+        return float(lib().orc_force_x(self._h, C.byref(p), t, _ptr(U), _ptr(dus)))
+
+    def force_x_adj(self, params, t, weight, U, Ubar, dtheta, dusbar=None, dus=None):
+        p = make_params(params)
+        th = (C.c_double * 3)(*dtheta)
+        lib().orc_force_x_adj(self._h, C.byref(p), t, weight, _ptr(U), _ptr(Ubar), th,
+                              _ptr(dusbar), _ptr(dus))
+        dtheta[:] = list(th)
+
+    def rk4_step_adj(self, params, t, dt, Un, Lam, dtheta, dusbar=None, dus=None):
+        p = make_params(params)
+        th = (C.c_double * 3)(*dtheta)
+        lib().orc_rk4_step_adj(self._h, C.byref(p), t, dt, _ptr(Un), _ptr(Lam), th,
+                               _ptr(dusbar), _ptr(dus))
+        dtheta[:] = list(th)
+
+    def objective(self, params, U0, dt, nsteps, dus=None):
+        """J = sum_{n=1..N} dt F_x(U^n, t^n) with a fixed dt; returns J and the
+        checkpoints U^0..U^{N-1}."""
+        U = U0.copy()
+        ck = []
+        J = 0.0
+        for n in range(nsteps):
+            ck.append(U.copy())
+            self.rk4_step(params, n * dt, dt, U, dus)
+            J += dt * self.force_x(params, (n + 1) * dt, U, dus)
+        return J, ck, U
+
+    def objective_grad(self, params, U0, dt, nsteps, dus=None):
+        """Gradient of objective() by the discrete adjoint: (dJ/dtheta, dJ/ddus, dJ/dU0)."""
+        J, ck, UN = self.objective(params, U0, dt, nsteps, dus)
+        n3 = self.bs ** 3
+        dth = [0.0, 0.0, 0.0]
+        dusbar = np.zeros((self.nb, 3, n3)) if dus is not None else None
+        lam = np.zeros_like(U0)
+        self.force_x_adj(params, nsteps * dt, dt, UN, lam, dth, dusbar, dus)
+        for n in range(nsteps - 1, -1, -1):
+            self.rk4_step_adj(params, n * dt, dt, ck[n], lam, dth, dusbar, dus)
+            if n >= 1:
+                self.force_x_adj(params, n * dt, dt, ck[n], lam, dth, dusbar, dus)
+        return J, np.array(dth), dusbar, lam
 
     def treecodes(self) -> np.ndarray:
         return np.array([treecode_encode(int(l), int(x), int(y), int(z))

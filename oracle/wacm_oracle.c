@@ -999,3 +999,318 @@ orc_grid* orc_coarsen(const orc_grid* g, const int8_t* flags, const double* U, d
   free(nl);
   return h;
 }
+
+/* ======================================================================== */
+/* Discrete adjoint on a frozen grid with a fixed time step.                  */
+/*                                                                            */
+/* Objective J = sum_n dt F_x(U^n, t^n), F_x the x-component of the          */
+/* penalization force (Sec. 2.2).  Parameters: theta = (A, f, phi) of the      */
+/* plate pitch angle alpha(t) = A sin(2 pi f t + phi), and a static extra      */
+/* solid velocity dus(x) added to u_s.  Every routine below is the exact       */
+/* transpose of the linearisation of the corresponding forward routine,        */
+/* written in scatter form: each forward dependency y += c x becomes          */
+/* xbar += c ybar.                                                             */
+/* ======================================================================== */
+
+/* alpha, alpha_dot and their derivatives with respect to (A, f, phi). */
+static void pitch(const orc_params* p, double t, double* al, double* ad, double dal[3],
+                  double dad[3]) {
+  const double twopi = 6.283185307179586476925286766559;
+  double ps = twopi * p->freq * t + p->phase;
+  double s = sin(ps), c = cos(ps);
+  *al = p->amp * s;
+  *ad = p->amp * twopi * p->freq * c;
+  dal[0] = s;
+  dal[1] = p->amp * c * twopi * t;
+  dal[2] = p->amp * c;
+  dad[0] = twopi * p->freq * c;
+  dad[1] = p->amp * twopi * c - p->amp * twopi * p->freq * s * twopi * t;
+  dad[2] = -p->amp * twopi * p->freq * s;
+}
+
+/* plate mask, its derivative in alpha, and d u_s / d alpha_dot */
+static void plate_point(const orc_params* p, double t, double x, double y, double z, double* chi,
+                        double* dchi, double us[3], double dus_dad[3], double dal[3],
+                        double dad[3]) {
+  double al, ad;
+  pitch(p, t, &al, &ad, dal, dad);
+  double rx = x - p->x_le[0], ry = y - p->x_le[1], rz = z - p->x_le[2];
+  double ca = cos(al), sa = sin(al);
+  double xb[3] = {ca * rx - sa * rz, ry, sa * rx + ca * rz};
+  double dxb[3] = {-xb[2], 0.0, xb[0]}; /* d x'/d alpha */
+  double g[3], gp[3];
+  for (int d = 0; d < 3; ++d) {
+    double a = tanh((xb[d] - p->lo[d]) / p->w), b = tanh((xb[d] - p->hi[d]) / p->w);
+    g[d] = 0.5 * (a - b);
+    gp[d] = 0.5 * ((1.0 - a * a) - (1.0 - b * b)) / p->w;
+  }
+  *chi = g[0] * g[1] * g[2];
+  *dchi = gp[0] * dxb[0] * g[1] * g[2] + g[0] * gp[1] * dxb[1] * g[2] +
+          g[0] * g[1] * gp[2] * dxb[2];
+  if (p->clip && *chi < 1e-8) {
+    *chi = 0.0;
+    *dchi = 0.0;
+  }
+  us[0] = ad * rz;
+  us[1] = 0.0;
+  us[2] = -ad * rx;
+  dus_dad[0] = rz;
+  dus_dad[1] = 0.0;
+  dus_dad[2] = -rx;
+}
+
+/* Transpose of the linearised rhs at the synchronised state U: V holds the
+ * rhs adjoint at interior points (padded layout); Ubar (padded) receives the
+ * state adjoint at interior and ghost points (accumulated); dtheta and dusbar
+ * (may be NULL) accumulate the parameter adjoints. */
+void orc_rhs_adj(const orc_grid* g, const orc_params* p, double t, const double* U,
+                 const double* V, double* Ubar, double dtheta[3], double* dusbar,
+                 const double* dus) {
+  double a[3];
+  orc_tam_webb(a);
+  const double w2[5] = {-1.0 / 12.0, 4.0 / 3.0, -5.0 / 2.0, 4.0 / 3.0, -1.0 / 12.0};
+  const int bs = g->bs;
+  const int64_t n3 = (int64_t)bs * bs * bs;
+  for (int64_t b = 0; b < g->nb; ++b) {
+    double h = hlev(g, g->lev[b]);
+    const double* F[4];
+    const double* R[4];
+    double* B[4];
+    for (int c = 0; c < 4; ++c) {
+      F[c] = cfld(g, U, b, c);
+      R[c] = cfld(g, V, b, c);
+      B[c] = fld(g, Ubar, b, c);
+    }
+    int64_t s[3] = {1, g->P, (int64_t)g->P * g->P};
+    for (int64_t k = 0; k < bs; ++k)
+      for (int64_t j = 0; j < bs; ++j)
+        for (int64_t i = 0; i < bs; ++i) {
+          int64_t q = pidx(g, i, j, k);
+          int64_t qi = (k * bs + j) * bs + i;
+          double v[4], u[4];
+          for (int c = 0; c < 4; ++c) {
+            v[c] = R[c][q];
+            u[c] = F[c][q];
+          }
+          double x = (double)(g->ix[b] * bs + i) * h;
+          double y = (double)(g->iy[b] * bs + j) * h;
+          double z = (double)(g->iz[b] * bs + k) * h;
+          /* velocity equations */
+          for (int c = 0; c < 3; ++c) {
+            for (int d = 0; d < 3; ++d) {
+              /* r_c -= u_d D1_d u_c */
+              double d1 = 0.0;
+              for (int m = 1; m <= 3; ++m)
+                d1 += a[m - 1] * (F[c][q + m * s[d]] - F[c][q - m * s[d]]);
+              d1 /= h;
+              B[d][q] += -v[c] * d1;
+              for (int m = 1; m <= 3; ++m) {
+                B[c][q + m * s[d]] += -v[c] * u[d] * a[m - 1] / h;
+                B[c][q - m * s[d]] += v[c] * u[d] * a[m - 1] / h;
+              }
+              /* r_c += nu D2_d u_c */
+              for (int o = -2; o <= 2; ++o) B[c][q + o * s[d]] += p->nu * v[c] * w2[o + 2] / (h * h);
+            }
+            /* r_c -= D1_c p */
+            for (int m = 1; m <= 3; ++m) {
+              B[3][q + m * s[c]] += -v[c] * a[m - 1] / h;
+              B[3][q - m * s[c]] += v[c] * a[m - 1] / h;
+            }
+          }
+          /* pressure equation: r_p = -C0^2 sum_d D1_d u_d - C_gamma p */
+          for (int d = 0; d < 3; ++d)
+            for (int m = 1; m <= 3; ++m) {
+              B[d][q + m * s[d]] += -p->c0 * p->c0 * v[3] * a[m - 1] / h;
+              B[d][q - m * s[d]] += p->c0 * p->c0 * v[3] * a[m - 1] / h;
+            }
+          B[3][q] += -p->c_gamma * v[3];
+          /* sponge */
+          if (p->sponge) {
+            double sp = sponge_point(p, g->L, x, y, z);
+            for (int c = 0; c < 4; ++c) B[c][q] += -sp / p->c_sp * v[c];
+          }
+          /* penalization and its parameters */
+          if (p->mask == 1) {
+            double chi, us[3];
+            mask_point(p, t, x, y, z, &chi, us);
+            for (int c = 0; c < 3; ++c) {
+              B[c][q] += -chi / p->c_eta * v[c];
+              if (dusbar) dusbar[(b * 3 + c) * n3 + qi] += chi / p->c_eta * v[c];
+            }
+          } else if (p->mask == 2) {
+            double chi, dchi, us[3], dsd[3], dal[3], dad[3];
+            plate_point(p, t, x, y, z, &chi, &dchi, us, dsd, dal, dad);
+            double e[3];
+            for (int c = 0; c < 3; ++c) e[c] = dus ? dus[(b * 3 + c) * n3 + qi] : 0.0;
+            double gal = 0.0, gad = 0.0;
+            for (int c = 0; c < 3; ++c) {
+              B[c][q] += -chi / p->c_eta * v[c];
+              if (dusbar) dusbar[(b * 3 + c) * n3 + qi] += chi / p->c_eta * v[c];
+              gal += -dchi / p->c_eta * (u[c] - us[c] - e[c]) * v[c];
+              gad += chi / p->c_eta * dsd[c] * v[c];
+            }
+            for (int k2 = 0; k2 < 3; ++k2) dtheta[k2] += gal * dal[k2] + gad * dad[k2];
+          }
+        }
+  }
+}
+
+/* Transpose of ghost synchronisation: the adjoint held at each ghost point
+ * goes back to the interior points its value was copied or predicted from
+ * (weights of Sec. 3.1), then the ghost entry is cleared. */
+void orc_sync_adj(const orc_grid* g, double* Ubar) {
+  const int bs = g->bs, ng = g->ng;
+  for (int64_t b = 0; b < g->nb; ++b) {
+    int J = g->lev[b];
+    int64_t ox = g->ix[b] * bs, oy = g->iy[b] * bs, oz = g->iz[b] * bs;
+    for (int c = 0; c < 4; ++c) {
+      double* f = fld(g, Ubar, b, c);
+      for (int64_t k = -ng; k < bs + ng; ++k)
+        for (int64_t j = -ng; j < bs + ng; ++j)
+          for (int64_t i = -ng; i < bs + ng; ++i) {
+            int inside = (i >= 0 && i < bs && j >= 0 && j < bs && k >= 0 && k < bs);
+            if (inside) continue;
+            int64_t q = pidx(g, i, j, k);
+            double gb = f[q];
+            if (gb == 0.0) continue;
+            f[q] = 0.0;
+            int64_t G[3] = {ox + i, oy + j, oz + k};
+            int64_t li, lj, lk;
+            int64_t o = orc_owner(g, J, G[0], G[1], G[2], &li, &lj, &lk);
+            if (o >= 0) {
+              fld(g, Ubar, o, c)[pidx(g, li, lj, lk)] += gb;
+              continue;
+            }
+            int64_t T[3][4];
+            double W[3][4];
+            int N[3];
+            for (int d = 0; d < 3; ++d) {
+              if (wrap(G[d], 2) == 0) {
+                T[d][0] = G[d] / 2;
+                W[d][0] = 1.0;
+                N[d] = 1;
+              } else {
+                for (int m = 0; m < 4; ++m) {
+                  T[d][m] = (G[d] + DD4O[m]) / 2;
+                  W[d][m] = DD4W[m];
+                }
+                N[d] = 4;
+              }
+            }
+            for (int az = 0; az < N[2]; ++az)
+              for (int ay = 0; ay < N[1]; ++ay)
+                for (int ax = 0; ax < N[0]; ++ax) {
+                  int64_t si, sj, sk;
+                  int64_t o2 = orc_owner(g, J - 1, T[0][ax], T[1][ay], T[2][az], &si, &sj, &sk);
+                  double w = (W[2][az] * W[1][ay]) * W[0][ax];
+                  fld(g, Ubar, o2, c)[pidx(g, si, sj, sk)] += w * gb;
+                }
+          }
+    }
+  }
+}
+
+/* x-force F_x at time t and its adjoint (weight * dF_x/d...). */
+double orc_force_x(const orc_grid* g, const orc_params* p, double t, const double* U,
+                   const double* dus) {
+  double out[9];
+  orc_diagnostics(g, p, t, U, dus, out);
+  return out[5];
+}
+
+void orc_force_x_adj(const orc_grid* g, const orc_params* p, double t, double weight,
+                     const double* U, double* Ubar, double dtheta[3], double* dusbar,
+                     const double* dus) {
+  const int bs = g->bs;
+  const int64_t n3 = (int64_t)bs * bs * bs;
+  if (!p->mask) return;
+  for (int64_t b = 0; b < g->nb; ++b) {
+    double h = hlev(g, g->lev[b]);
+    double vol = h * h * h;
+    for (int64_t k = 0; k < bs; ++k)
+      for (int64_t j = 0; j < bs; ++j)
+        for (int64_t i = 0; i < bs; ++i) {
+          int64_t q = pidx(g, i, j, k);
+          int64_t qi = (k * bs + j) * bs + i;
+          double x = (double)(g->ix[b] * bs + i) * h;
+          double y = (double)(g->iy[b] * bs + j) * h;
+          double z = (double)(g->iz[b] * bs + k) * h;
+          double e = dus ? dus[(b * 3 + 0) * n3 + qi] : 0.0;
+          double u = cfld(g, U, b, 0)[q];
+          if (p->mask == 1) {
+            double chi, us[3];
+            mask_point(p, t, x, y, z, &chi, us);
+            fld(g, Ubar, b, 0)[q] += weight * chi * vol / p->c_eta;
+            if (dusbar) dusbar[(b * 3 + 0) * n3 + qi] += -weight * chi * vol / p->c_eta;
+          } else {
+            double chi, dchi, us[3], dsd[3], dal[3], dad[3];
+            plate_point(p, t, x, y, z, &chi, &dchi, us, dsd, dal, dad);
+            fld(g, Ubar, b, 0)[q] += weight * chi * vol / p->c_eta;
+            if (dusbar) dusbar[(b * 3 + 0) * n3 + qi] += -weight * chi * vol / p->c_eta;
+            double gal = weight * dchi * (u - us[0] - e) * vol / p->c_eta;
+            double gad = -weight * chi * dsd[0] * vol / p->c_eta;
+            for (int k2 = 0; k2 < 3; ++k2) dtheta[k2] += gal * dal[k2] + gad * dad[k2];
+          }
+        }
+  }
+}
+
+/* Adjoint of one RK4 step from the checkpoint Un (interiors) at time t with
+ * step dt: Lam holds lambda^{n+1} on interiors on entry and lambda^n on
+ * return (padded layout; ghosts are scratch). */
+void orc_rk4_step_adj(const orc_grid* g, const orc_params* p, double t, double dt,
+                      const double* Un, double* Lam, double dtheta[3], double* dusbar,
+                      const double* dus) {
+  const int64_t tot = g->nb * 4 * (int64_t)g->P * g->P * g->P;
+  double* S[4];
+  double* K = (double*)calloc(tot, sizeof(double));
+  for (int s = 0; s < 4; ++s) S[s] = (double*)calloc(tot, sizeof(double));
+  const double cs[4] = {0.0, 0.5, 0.5, 1.0};
+  const double as[4] = {0.0, 0.5, 0.5, 1.0};
+  /* recompute the synchronised stage inputs */
+  memcpy(S[0], Un, sizeof(double) * tot);
+  orc_sync(g, S[0]);
+  for (int s = 1; s < 4; ++s) {
+    orc_rhs(g, p, t + cs[s - 1] * dt, S[s - 1], dus, K);
+    axpy_interior(g, S[s], Un, as[s] * dt, K);
+    orc_sync(g, S[s]);
+  }
+  /* reverse sweep */
+  const int bs = g->bs;
+  double* lamU = (double*)calloc(tot, sizeof(double));
+  double* kb[4];
+  for (int s = 0; s < 4; ++s) kb[s] = (double*)calloc(tot, sizeof(double));
+  const double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+  for (int64_t b = 0; b < g->nb; ++b)
+    for (int c = 0; c < 4; ++c)
+      for (int64_t k = 0; k < bs; ++k)
+        for (int64_t j = 0; j < bs; ++j)
+          for (int64_t i = 0; i < bs; ++i) {
+            int64_t q = (b * 4 + c) * (int64_t)g->P * g->P * g->P + pidx(g, i, j, k);
+            lamU[q] = Lam[q];
+            for (int s = 0; s < 4; ++s) kb[s][q] = dt * bw[s] * Lam[q];
+          }
+  double* Bb = (double*)calloc(tot, sizeof(double));
+  for (int s = 3; s >= 0; --s) {
+    memset(Bb, 0, sizeof(double) * tot);
+    orc_rhs_adj(g, p, t + cs[s] * dt, S[s], kb[s], Bb, dtheta, dusbar, dus);
+    orc_sync_adj(g, Bb);
+    for (int64_t b = 0; b < g->nb; ++b)
+      for (int c = 0; c < 4; ++c)
+        for (int64_t k = 0; k < bs; ++k)
+          for (int64_t j = 0; j < bs; ++j)
+            for (int64_t i = 0; i < bs; ++i) {
+              int64_t q = (b * 4 + c) * (int64_t)g->P * g->P * g->P + pidx(g, i, j, k);
+              lamU[q] += Bb[q];
+              if (s > 0) kb[s - 1][q] += as[s] * dt * Bb[q];
+            }
+  }
+  memcpy(Lam, lamU, sizeof(double) * tot);
+  free(Bb);
+  free(lamU);
+  for (int s = 0; s < 4; ++s) {
+    free(kb[s]);
+    free(S[s]);
+  }
+  free(K);
+}

@@ -116,6 +116,22 @@ orc_grid* orc_refine_all(const orc_grid* g, const double* U, double* Unew);
 int64_t orc_coarsen_count(const orc_grid* g, const int8_t* flags);
 orc_grid* orc_coarsen(const orc_grid* g, const int8_t* flags, const double* U, double* Unew);
 
+/* ---- discrete adjoint (frozen grid, fixed dt) ---------------------------- */
+/* theta = (amp, freq, phase) of the plate pitch; dus = static extra solid
+ * velocity [nb][3][bs^3].  All adjoint outputs are accumulated. */
+void orc_rhs_adj(const orc_grid* g, const orc_params* p, double t, const double* U,
+                 const double* V, double* Ubar, double dtheta[3], double* dusbar,
+                 const double* dus);
+void orc_sync_adj(const orc_grid* g, double* Ubar);
+double orc_force_x(const orc_grid* g, const orc_params* p, double t, const double* U,
+                   const double* dus);
+void orc_force_x_adj(const orc_grid* g, const orc_params* p, double t, double weight,
+                     const double* U, double* Ubar, double dtheta[3], double* dusbar,
+                     const double* dus);
+void orc_rk4_step_adj(const orc_grid* g, const orc_params* p, double t, double dt,
+                      const double* Un, double* Lam, double dtheta[3], double* dusbar,
+                      const double* dus);
+
 #ifdef __cplusplus
 }
 #endif

@@ -143,23 +143,27 @@ def ball_leaves(L: float, j0: int, centre, radius: float):
 def box_refined_leaves(L: float, jmin: int, jtop: int, lo, hi):
     """Refine every block meeting the axis-aligned box [lo, hi] up to level jtop,
     with 2:1 balancing, starting from a uniform level-jmin grid."""
-    ls = LeafSet([(jmin, x, y, z) for z in range(1 << jmin) for y in range(1 << jmin)
-                  for x in range(1 << jmin)], jmin)
+    n0 = 1 << jmin
+    ls = LeafSet([(jmin, x, y, z) for z in range(n0) for y in range(n0) for x in range(n0)],
+                 jmin)
     lo = np.asarray(lo, float)
     hi = np.asarray(hi, float)
-    changed = True
-    while changed:
-        changed = False
-        for leaf in sorted(ls.s):
-            J, x, y, z = leaf
-            if J >= jtop or leaf not in ls.s:
-                continue
-            w = L / (1 << J)
-            blo = np.array([x, y, z]) * w
-            bhi = blo + w
-            if np.all(bhi >= lo) and np.all(blo <= hi):
-                ls.refine(leaf)
-                changed = True
+
+    def meets(leaf):
+        J, x, y, z = leaf
+        w = L / (1 << J)
+        blo = np.array([x, y, z]) * w
+        return bool(np.all(blo + w >= lo) and np.all(blo <= hi))
+
+    todo = sorted(l for l in ls.s if l[0] < jtop and meets(l))
+    while todo:
+        nxt = []
+        for leaf in todo:
+            if leaf in ls.s:
+                created = set()
+                ls.refine(leaf, created=created)
+                nxt.extend(l for l in created if l[0] < jtop and meets(l))
+        todo = sorted(set(nxt))
     return ls.arrays()
 
 
