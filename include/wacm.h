@@ -229,6 +229,61 @@ int wacm_adapt(wacm_grid* grid, int32_t op, const int8_t* flags, void* U, int64_
                void* stream);
 
 /*
+ * ---- Discrete adjoint (frozen grid, fixed time step) --------------------
+ * Exact transposes of the linearised operations above, for gradients of
+ * J = sum_n dt F_x(U^n, t^n) (F_x: x-component of the penalization force,
+ * Sec. 2.2) with respect to the plate pitch parameters theta = (amp, freq,
+ * phase) and a static extra solid velocity dus.  Conventions: adjoint states
+ * use the pool layout and element type; dtheta is a device array of 3
+ * doubles and dusbar a device array [capacity][3][bs^3] of doubles (NULL:
+ * not wanted); both are accumulated (+=), never cleared.  Reductions run in a
+ * fixed order (bitwise reproducible).  The first call of wacm_sync_ghosts_adj
+ * / wacm_rk4_step_adj on a grid builds a transpose plan of the ghost fill on
+ * the host (synchronous, device memory owned by the grid, dropped by
+ * wacm_adapt).
+ */
+
+/* Bytes of the work buffer wacm_rk4_step_adj needs (8 pool-sized registers). */
+size_t wacm_adj_work_bytes(const wacm_grid* grid);
+
+/*
+ * wacm_sync_ghosts_adj -- transpose of wacm_sync_ghosts: the adjoint held at
+ * every ghost point of Ub is added to the interior points its value was
+ * copied or predicted from (with the prediction weights of Sec. 3.1), then
+ * the ghost points are set to 0.  Interiors are accumulated.
+ */
+int wacm_sync_ghosts_adj(wacm_grid* grid, void* Ub, void* stream);
+
+/*
+ * wacm_rhs_acm_adj -- transpose of the rhs linearised at the ghost-synchronised
+ * state U (Sec. 2.2-2.3): given the rhs adjoint V (interiors), Ub receives the
+ * state adjoint at interior and depth-3 face ghost points (accumulated),
+ * dtheta and dusbar the parameter adjoints at time t.
+ */
+int wacm_rhs_acm_adj(wacm_grid* grid, const wacm_params* prm, double t, const void* U,
+                     const void* V, void* Ub, double* dtheta, double* dusbar, const void* dus,
+                     void* stream);
+
+/*
+ * wacm_force_adj -- adds weight * dF_x/dU (interiors of Ub), weight * dF_x/dtheta
+ * and weight * dF_x/ddus at time t, F_x = C_eta^-1 sum chi (u - u_s) h^3.
+ */
+int wacm_force_adj(wacm_grid* grid, const wacm_params* prm, double t, double weight,
+                   const void* U, void* Ub, double* dtheta, double* dusbar, const void* dus,
+                   void* stream);
+
+/*
+ * wacm_rk4_step_adj -- transpose of one wacm_rk4_step of size dt from time t
+ * (fixed dt): Un is the checkpoint of the step's input (interiors); lam holds
+ * the adjoint of the step's output on entry and of its input on return
+ * (interiors).  Stage inputs are recomputed from Un.  work: device buffer of
+ * wacm_adj_work_bytes(), 256-byte aligned.
+ */
+int wacm_rk4_step_adj(wacm_grid* grid, const wacm_params* prm, double t, double dt,
+                      const void* Un, void* lam, double* dtheta, double* dusbar,
+                      const void* dus, void* work, void* stream);
+
+/*
  * Measurement support (not part of the method).  wacm_profile_enable(g, 1)
  * makes wacm_rk4_step record a HIP event pair around each group of kernels it
  * launches on its stream; do not enable it while the stream is being captured

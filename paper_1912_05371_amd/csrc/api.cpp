@@ -35,6 +35,7 @@ int check_params(const wacm_params* p) {
 }
 
 void free_dev(wacm_grid* g) {
+  free_adj_plans(g);
   (void)profile_flush(g);
   for (hipEvent_t e : g->prof.spare) (void)hipEventDestroy(e);
   g->prof.spare.clear();
@@ -390,10 +391,49 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
   g->nb = tmp.nb;
   g->jfine = tmp.jfine;
   g->free_slots.swap(freelist);
+  free_adj_plans(g);
   rc = upload_tables(g, tabs, err);
   if (rc) return fail(rc, err);
   if (nb_out) *nb_out = g->nb;
   return WACM_OK;
+}
+
+size_t wacm_adj_work_bytes(const wacm_grid* g) { return g ? adj_work_bytes(g) : 0; }
+
+int wacm_sync_ghosts_adj(wacm_grid* g, void* Ub, void* stream) {
+  if (!elem_ok(g) || !Ub) return fail(WACM_E_INVAL, "NULL argument");
+  std::string err;
+  if (int rc = build_adj_plan(g, 0, err)) return fail(rc, err);
+  hipError_t e = launch_sync_adj(g, Ub, 0, S(stream));
+  return e == hipSuccess ? WACM_OK : hipfail(e, "sync_ghosts_adj launch");
+}
+
+int wacm_rhs_acm_adj(wacm_grid* g, const wacm_params* p, double t, const void* U, const void* V,
+                     void* Ub, double* dtheta, double* dusbar, const void* dus, void* stream) {
+  if (!elem_ok(g) || !U || !V || !Ub || !dtheta) return fail(WACM_E_INVAL, "NULL argument");
+  if (int rc = check_params(p)) return rc;
+  hipError_t e = launch_rhs_adj(g, p, t, U, V, Ub, dtheta, dusbar, dus, S(stream));
+  return e == hipSuccess ? WACM_OK : hipfail(e, "rhs_acm_adj launch");
+}
+
+int wacm_force_adj(wacm_grid* g, const wacm_params* p, double t, double weight, const void* U,
+                   void* Ub, double* dtheta, double* dusbar, const void* dus, void* stream) {
+  if (!elem_ok(g) || !U || !Ub || !dtheta) return fail(WACM_E_INVAL, "NULL argument");
+  if (int rc = check_params(p)) return rc;
+  hipError_t e = launch_force_adj(g, p, t, weight, U, Ub, dtheta, dusbar, dus, S(stream));
+  return e == hipSuccess ? WACM_OK : hipfail(e, "force_adj launch");
+}
+
+int wacm_rk4_step_adj(wacm_grid* g, const wacm_params* p, double t, double dt, const void* Un,
+                      void* lam, double* dtheta, double* dusbar, const void* dus, void* work,
+                      void* stream) {
+  if (!elem_ok(g) || !Un || !lam || !dtheta || !work) return fail(WACM_E_INVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(work) % 256) return fail(WACM_E_INVAL, "work not 256-aligned");
+  if (int rc = check_params(p)) return rc;
+  std::string err;
+  if (int rc = build_adj_plan(g, 1, err)) return fail(rc, err);
+  hipError_t e = launch_rk4_adj(g, p, t, dt, Un, lam, dtheta, dusbar, dus, work, S(stream));
+  return e == hipSuccess ? WACM_OK : hipfail(e, "rk4_step_adj launch");
 }
 
 int wacm_profile_enable(wacm_grid* g, int32_t on) {

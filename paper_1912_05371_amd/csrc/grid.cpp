@@ -144,6 +144,7 @@ int upload_tables(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) 
     return WACM_E_HIP;
   }
   g->n_cface = (int64_t)cf.size() / 2;
+  g->h_tab = tabs;
   return WACM_OK;
 }
 

@@ -118,6 +118,46 @@ WACM_HD inline void ghost_value(const Tab& t, int bs, const Layout& L,
   for (int c = 0; c < 4; ++c) out[c] = acc[c];
 }
 
+// The sources of the ghost value at (i,j,k): calls f(offset, weight) once for a
+// copy, or for each tap of the tensor DD4 prediction (z outer, y, x inner).
+// Host code uses it to build the transpose of the ghost fill.
+template <typename T, typename F>
+WACM_HD inline void ghost_taps(const Tab& t, int bs, const Layout& L, int i, int j, int k, F&& f) {
+  const int r = region_of(i, bs) + 3 * region_of(j, bs) + 9 * region_of(k, bs);
+  if (t.kind[r] >= 0 || ((i | j | k) & 1) == 0) {
+    f(point_offset(t, bs, L, i, j, k), T(1));
+    return;
+  }
+  int tq[3][4];
+  T wq[3][4];
+  int nq[3];
+  const int q3[3] = {i, j, k};
+  for (int d = 0; d < 3; ++d) {
+    const int q = q3[d];
+    if ((q & 1) == 0) {
+      tq[d][0] = q;
+      wq[d][0] = T(1);
+      nq[d] = 1;
+    } else {
+      tq[d][0] = q - 3;
+      tq[d][1] = q - 1;
+      tq[d][2] = q + 1;
+      tq[d][3] = q + 3;
+      wq[d][0] = T(DDW0);
+      wq[d][1] = T(DDW1);
+      wq[d][2] = T(DDW1);
+      wq[d][3] = T(DDW0);
+      nq[d] = 4;
+    }
+  }
+  for (int a = 0; a < nq[2]; ++a)
+    for (int b = 0; b < nq[1]; ++b) {
+      const T wzy = wq[2][a] * wq[1][b];
+      for (int e = 0; e < nq[0]; ++e)
+        f(point_offset(t, bs, L, tq[0][e], tq[1][b], tq[2][a]), wzy * wq[0][e]);
+    }
+}
+
 // Mask chi and solid velocity u_s at a point and time (Sec. 2.2): a sphere
 // with a tanh layer, or a thin box pitching about an axis through x_le
 // parallel to y with alpha(t) = amp sin(2 pi freq t + phase).
@@ -144,6 +184,47 @@ WACM_HD inline void mask_eval(const wacm_params& p, double t, double x, double y
     us[2] = -ad * rx;
   }
   if (p.clip && chi < 1e-8) chi = 0.0;
+}
+
+// Plate mask with its derivative in the pitch angle, and the solid velocity
+// with its derivative in the pitch rate; dal/dad: d alpha / d(A, f, phi) and
+// d alpha_dot / d(A, f, phi).  Used by the adjoint kernels.
+WACM_HD inline void plate_eval_adj(const wacm_params& p, double t, double x, double y, double z,
+                                   double& chi, double& dchi, double us[3], double dusd[3],
+                                   double dal[3], double dad[3]) {
+  const double twopi = 6.283185307179586476925286766559;
+  const double ph = twopi * p.freq * t + p.phase;
+  const double s = sin(ph), c = cos(ph);
+  const double al = p.amp * s, ad = p.amp * twopi * p.freq * c;
+  dal[0] = s;
+  dal[1] = p.amp * c * twopi * t;
+  dal[2] = p.amp * c;
+  dad[0] = twopi * p.freq * c;
+  dad[1] = p.amp * twopi * c - p.amp * twopi * p.freq * s * twopi * t;
+  dad[2] = -p.amp * twopi * p.freq * s;
+  const double rx = x - p.x_le[0], ry = y - p.x_le[1], rz = z - p.x_le[2];
+  const double ca = cos(al), sa = sin(al);
+  const double b[3] = {ca * rx - sa * rz, ry, sa * rx + ca * rz};
+  const double db[3] = {-b[2], 0.0, b[0]};
+  double gv[3], gp[3];
+  for (int d = 0; d < 3; ++d) {
+    const double ta = tanh((b[d] - p.lo[d]) / p.w), tb = tanh((b[d] - p.hi[d]) / p.w);
+    gv[d] = 0.5 * (ta - tb);
+    gp[d] = 0.5 * ((1.0 - ta * ta) - (1.0 - tb * tb)) / p.w;
+  }
+  chi = gv[0] * gv[1] * gv[2];
+  dchi = gp[0] * db[0] * gv[1] * gv[2] + gv[0] * gp[1] * db[1] * gv[2] +
+         gv[0] * gv[1] * gp[2] * db[2];
+  if (p.clip && chi < 1e-8) {
+    chi = 0.0;
+    dchi = 0.0;
+  }
+  us[0] = ad * rz;
+  us[1] = 0.0;
+  us[2] = -ad * rx;
+  dusd[0] = rz;
+  dusd[1] = 0.0;
+  dusd[2] = -rx;
 }
 
 WACM_HD inline double sponge_eval(const wacm_params& p, double L, double x, double y,

@@ -59,6 +59,19 @@ struct Profiler {
   int64_t n[4] = {0, 0, 0, 0};
 };
 
+// Transpose of the ghost fill as a gather: for each interior point that some
+// ghost value was read from (rows, element offset of field 0), the ghosts that
+// read it with their weights; plus the list of ghost points to clear.
+struct AdjPlan {
+  int built = 0;
+  int64_t nrows = 0, nnz = 0, nghost = 0;
+  int64_t* d_dst = nullptr;
+  int64_t* d_ptr = nullptr;
+  int64_t* d_src = nullptr;
+  double* d_w = nullptr;
+  int64_t* d_ghost = nullptr;
+};
+
 }  // namespace wacm
 
 struct wacm_grid {
@@ -78,6 +91,8 @@ struct wacm_grid {
   int64_t n_cface = 0;
   int jfine = 0;                 // finest active level
   mutable wacm::Profiler prof;   // kernel timing, off by default
+  std::vector<wacm::Tab> h_tab;  // host copy of the tables
+  wacm::AdjPlan plan[2];         // ghost-fill transposes: all layers / face star
 };
 
 namespace wacm {
@@ -119,6 +134,20 @@ hipError_t launch_prolong(const wacm_grid* g, void* U, int64_t n, hipStream_t st
 hipError_t launch_decimate(const wacm_grid* g, void* U, int64_t n, hipStream_t st);
 
 size_t work_bytes(const wacm_grid* g);
+// adjoint (adjoint.hip)
+size_t adj_work_bytes(const wacm_grid* g);
+int build_adj_plan(wacm_grid* g, int face_only, std::string& err);
+void free_adj_plans(wacm_grid* g);
+hipError_t launch_sync_adj(const wacm_grid* g, void* Ub, int face_only, hipStream_t st);
+hipError_t launch_rhs_adj(const wacm_grid* g, const wacm_params* p, double t, const void* U,
+                          const void* V, void* Ub, double* dtheta, double* dusbar,
+                          const void* dus, hipStream_t st);
+hipError_t launch_force_adj(const wacm_grid* g, const wacm_params* p, double t, double weight,
+                            const void* U, void* Ub, double* dtheta, double* dusbar,
+                            const void* dus, hipStream_t st);
+hipError_t launch_rk4_adj(const wacm_grid* g, const wacm_params* p, double t, double dt,
+                          const void* Un, void* lam, double* dtheta, double* dusbar,
+                          const void* dus, void* work, hipStream_t st);
 hipError_t profile_flush(const wacm_grid* g);  // accumulate recorded events
 
 }  // namespace wacm

@@ -27,7 +27,8 @@ EXPORTS = ["wacm_last_error", "wacm_treecode_encode", "wacm_treecode_decode", "w
            "wacm_grid_destroy", "wacm_grid_nb", "wacm_grid_info", "wacm_work_bytes",
            "wacm_sync_ghosts", "wacm_rhs_acm", "wacm_compute_dt", "wacm_rk4_step",
            "wacm_diagnostics", "wacm_threshold_blocks", "wacm_adapt", "wacm_profile_enable",
-           "wacm_profile_read"]
+           "wacm_profile_read", "wacm_adj_work_bytes", "wacm_sync_ghosts_adj",
+           "wacm_rhs_acm_adj", "wacm_force_adj", "wacm_rk4_step_adj"]
 
 
 class GridDesc(C.Structure):
@@ -104,6 +105,13 @@ def lib():
         L.wacm_threshold_blocks.argtypes = [vp, C.POINTER(Params), dbl, vp, dbl, i32, vp, vp, vp,
                                             vp]
         L.wacm_adapt.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.wacm_adj_work_bytes.restype = C.c_size_t
+        L.wacm_adj_work_bytes.argtypes = [vp]
+        L.wacm_sync_ghosts_adj.argtypes = [vp, vp, vp]
+        L.wacm_rhs_acm_adj.argtypes = [vp, C.POINTER(Params), dbl, vp, vp, vp, vp, vp, vp, vp]
+        L.wacm_force_adj.argtypes = [vp, C.POINTER(Params), dbl, dbl, vp, vp, vp, vp, vp, vp]
+        L.wacm_rk4_step_adj.argtypes = [vp, C.POINTER(Params), dbl, dbl, vp, vp, vp, vp, vp, vp,
+                                        vp]
         L.wacm_profile_enable.argtypes = [vp, i32]
         L.wacm_profile_read.argtypes = [vp, vp, vp]
         _lib = L
@@ -299,3 +307,61 @@ class Grid:
         _check(lib().wacm_profile_read(self._h, ms.ctypes.data_as(C.c_void_p),
                                        n.ctypes.data_as(C.c_void_p)))
         return ms, n
+
+    # ---- adjoint ------------------------------------------------------------
+    def adj_work_bytes(self) -> int:
+        return int(lib().wacm_adj_work_bytes(self._h))
+
+    def adj_work(self, device="cuda"):
+        import torch
+        return torch.empty(self.adj_work_bytes(), dtype=torch.uint8, device=device)
+
+    def _chk_dusbar(self, dusbar):
+        import torch
+        if dusbar is None:
+            return
+        if tuple(dusbar.shape) != (self.capacity, 3, self.bs ** 3) or \
+                dusbar.dtype != torch.float64 or not dusbar.is_contiguous() or not dusbar.is_cuda:
+            raise ValueError("dusbar must be (capacity, 3, bs^3) float64 contiguous on the GPU")
+
+    def sync_ghosts_adj(self, Ub, stream=None):
+        self._chk_pool(Ub)
+        _check(lib().wacm_sync_ghosts_adj(self._h, _ptr(Ub), _stream(stream)))
+
+    def rhs_acm_adj(self, params: dict, t: float, U, V, Ub, dtheta, dusbar=None, dus=None,
+                    stream=None):
+        for a in (U, V, Ub):
+            self._chk_pool(a)
+        self._chk_vec(dtheta, 3, "f64", "dtheta")
+        self._chk_dusbar(dusbar)
+        self._chk_dus(dus)
+        p = make_params(params)
+        _check(lib().wacm_rhs_acm_adj(self._h, C.byref(p), float(t), _ptr(U), _ptr(V), _ptr(Ub),
+                                      _ptr(dtheta), _ptr(dusbar), _ptr(dus), _stream(stream)))
+
+    def force_adj(self, params: dict, t: float, weight: float, U, Ub, dtheta, dusbar=None,
+                  dus=None, stream=None):
+        self._chk_pool(U)
+        self._chk_pool(Ub)
+        self._chk_vec(dtheta, 3, "f64", "dtheta")
+        self._chk_dusbar(dusbar)
+        self._chk_dus(dus)
+        p = make_params(params)
+        _check(lib().wacm_force_adj(self._h, C.byref(p), float(t), float(weight), _ptr(U),
+                                    _ptr(Ub), _ptr(dtheta), _ptr(dusbar), _ptr(dus),
+                                    _stream(stream)))
+
+    def rk4_step_adj(self, params: dict, t: float, dt: float, Un, lam, dtheta, dusbar=None,
+                     dus=None, work=None, stream=None):
+        self._chk_pool(Un)
+        self._chk_pool(lam)
+        self._chk_vec(dtheta, 3, "f64", "dtheta")
+        self._chk_dusbar(dusbar)
+        self._chk_dus(dus)
+        if work is None or not work.is_cuda or \
+                work.numel() * work.element_size() < self.adj_work_bytes():
+            raise ValueError("adjoint work buffer too small")
+        p = make_params(params)
+        _check(lib().wacm_rk4_step_adj(self._h, C.byref(p), float(t), float(dt), _ptr(Un),
+                                       _ptr(lam), _ptr(dtheta), _ptr(dusbar), _ptr(dus),
+                                       _ptr(work), _stream(stream)))

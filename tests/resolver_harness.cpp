@@ -7,6 +7,7 @@
 //   resolver_harness leaves.txt state_in.bin state_out.bin
 // leaves.txt: "bs ng L jmin jmax capacity n" then n lines "J x y z" (slot i = line i)
 // state: n * 4 * P^3 doubles (pool layout).  Exit 0 on success.
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <set>
@@ -106,6 +107,27 @@ int main(int argc, char** argv) {
       ghost_value<double>(t, bs, L, U.data(), i, j, k, v);
       const int64_t o = ((int64_t)(k + ng) * P + (j + ng)) * P + (i + ng);
       for (int c = 0; c < 4; ++c) dst[o + c * L.fstride] = v[c];
+    }
+  }
+  // ghost_taps (used to build the adjoint's transpose plan) must give the
+  // same value as ghost_value, with every tap an interior point of a slot
+  for (int64_t ib = 0; ib < g.nb; ++ib) {
+    const Tab& t = tabs[ib];
+    for (int p = 0; p < npts; ++p) {
+      int i, j, k;
+      shell_point(p, bs, ng, P, 0, i, j, k);
+      double v[4];
+      ghost_value<double>(t, bs, L, U.data(), i, j, k, v);
+      double s[4] = {0, 0, 0, 0};
+      ghost_taps<double>(t, bs, L, i, j, k, [&](int64_t off, double w) {
+        for (int c = 0; c < 4; ++c) s[c] += w * U[off + c * L.fstride];
+      });
+      for (int c = 0; c < 4; ++c)
+        if (std::fabs(s[c] - v[c]) > 1e-12 * (1.0 + std::fabs(v[c]))) {
+          std::fprintf(stderr, "ghost_taps mismatch block %lld point (%d,%d,%d)\n",
+                       (long long)ib, i, j, k);
+          return 6;
+        }
     }
   }
   FILE* fo = std::fopen(argv[3], "wb");
