@@ -46,7 +46,7 @@ def build_case(target: int, seed: int):
                                with_fields=False)
 
 
-def run_gpu(case, dtype_code: int, steps: int, warmup: int, use_graph: bool):
+def run_gpu(case, dtype_code: int, steps: int, warmup: int, use_graph: bool, tune: bool):
     import torch
 
     from paper_1912_05371_amd import inputs, wacm
@@ -63,6 +63,11 @@ def run_gpu(case, dtype_code: int, steps: int, warmup: int, use_graph: bool):
     dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
     p = wacm.make_params(case.params)
     stream = torch.cuda.current_stream()
+    schedule, trials = g.get_schedule(), []
+    if tune:
+        from paper_1912_05371_amd import autotune
+        schedule, trials = autotune.tune(g, case.params, pool, steps=2, use_cache=False)
+        log(f"  autotuned schedule {schedule} (best of {len(trials)})")
     for _ in range(warmup):
         g.rk4_step(None, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_CFL, _p=p)
     torch.cuda.synchronize()
@@ -84,7 +89,8 @@ def run_gpu(case, dtype_code: int, steps: int, warmup: int, use_graph: bool):
     g.profile_enable(False)
 
     res = dict(ms_per_step=ms_total / steps, wall_s=wall, kernel_ms=kms.tolist(),
-               kernel_launches=kn.tolist())
+               kernel_launches=kn.tolist(), schedule=schedule,
+               tuning=[[ms, s] for ms, s in trials])
     if use_graph:
         graph = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
@@ -204,6 +210,7 @@ def main():
     ap.add_argument("--seed", type=int, default=12345)
     ap.add_argument("--dtype", choices=["both", "f64", "f32"], default="both")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default schedule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=2.0,
                     help="GiB per buffer of a plain device copy timed for the achievable "
@@ -236,7 +243,7 @@ def main():
         if args.dtype not in ("both", name):
             continue
         log(f"running {name}: warmup {args.warmup}, steps {args.steps}")
-        r = run_gpu(case, code, args.steps, args.warmup, not args.no_graph)
+        r = run_gpu(case, code, args.steps, args.warmup, not args.no_graph, not args.no_tune)
         r["value"] = npts * 4 / (r["ms_per_step"] * 1e-3)
         r["roofline"] = roofline(r, npts, es)
         log(f"  {name}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4e} updates/s, stage kernel "
@@ -273,6 +280,7 @@ def main():
     }
     if "graph_ms_per_step" in R:
         line["graph_ms_per_step"] = round(R["graph_ms_per_step"], 4)
+    line["schedule"] = R["schedule"]
     other = "f32" if prim == "f64" else None
     if other and other in results:
         O = results[other]
@@ -282,6 +290,7 @@ def main():
             "roofline": O["roofline"],
             "speedup_vs_f64": round(R["ms_per_step"] / O["ms_per_step"], 3),
             "graph_ms_per_step": round(O.get("graph_ms_per_step", 0.0), 4),
+            "schedule": O["schedule"],
         }
     line["kernel_ms_per_step"] = {
         k: round(v / args.steps, 4)

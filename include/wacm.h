@@ -85,6 +85,20 @@ typedef struct {
   double L;         /* domain edge length                                        */
 } wacm_grid_desc;
 
+/* Launch schedule of the fused stage kernel of wacm_rk4_step (performance
+ * only: results do not depend on it).  wg_per_cu: persistent workgroups per
+ * compute unit (0: as many as are resident); xcd_map: 1 gives each of the 8
+ * XCDs a contiguous run of the Morton-ordered blocks (shared faces meet in one
+ * L2); prefetch: 1 loads U^n and the accumulator before a plane's barrier, 0
+ * after the rhs, -1 default; nontemporal: 1 streams U^n and the accumulator
+ * with non-temporal loads/stores.  Default {0, 1, -1, 1}. */
+typedef struct {
+  int32_t wg_per_cu;
+  int32_t xcd_map;
+  int32_t prefetch;
+  int32_t nontemporal;
+} wacm_schedule;
+
 /* Parameters of the penalized ACM model (Sec. 2.1-2.3). */
 typedef struct {
   double nu;        /* kinematic viscosity                                        */
@@ -138,6 +152,11 @@ int64_t wacm_grid_nb(const wacm_grid* grid);
  * receives nb entries: pool slot, treecode, level.
  */
 int wacm_grid_info(const wacm_grid* grid, int64_t* slots, uint64_t* treecodes, int8_t* levels);
+
+/* Set / read the stage-kernel schedule (values checked: wg_per_cu in [0, 16],
+ * xcd_map and nontemporal in {0, 1}, prefetch in {-1, 0, 1}). */
+int wacm_set_schedule(wacm_grid* grid, const wacm_schedule* s);
+int wacm_get_schedule(const wacm_grid* grid, wacm_schedule* s);
 
 /* Bytes of the `work` buffer wacm_rk4_step needs (3 RK registers for every
  * pool slot), 256-byte aligned by the caller. */

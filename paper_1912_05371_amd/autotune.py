@@ -1,0 +1,95 @@
+"""Autotuner for the launch schedule of the fused stage kernel.
+
+The schedule (workgroups per CU, XCD-aware block mapping, early epilogue
+loads, non-temporal streaming) changes only performance, never results.  The
+tuner times whole RK4 steps (HIP events on the launch stream) for each
+candidate on a scratch copy of the caller's state, keeps the fastest, and
+caches the choice per (device, element type, block size, grid shape) in a
+JSON file so later runs on the same workload skip the search.
+"""
+from __future__ import annotations
+
+import hashlib
+import itertools
+import json
+import os
+
+import numpy as np
+
+from . import wacm
+
+CANDIDATES = [dict(wg_per_cu=w, xcd_map=x, prefetch=p, nontemporal=n)
+              for w, x, p, n in itertools.product((0, 2), (0, 1), (0, 1), (0, 1))]
+
+
+def cache_path() -> str:
+    base = os.environ.get("WACM_CACHE_DIR") or os.path.join(
+        os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")), "wacm")
+    return os.path.join(base, "autotune.json")
+
+
+def workload_key(grid: wacm.Grid) -> str:
+    import torch
+    slots, codes, levels = grid.info()
+    hist = np.bincount(levels.astype(np.int64), minlength=19).tolist()
+    h = hashlib.sha1(np.asarray(hist, np.int64).tobytes()).hexdigest()[:12]
+    name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    dt = "f64" if grid.dtype == wacm.F64 else "f32"
+    return f"{name}|{dt}|bs{grid.bs}|ng{grid.ng}|nb{grid.nb}|lev{h}"
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def tune(grid: wacm.Grid, params: dict, pool, dus=None, steps: int = 3, candidates=None,
+         use_cache: bool = True, log=None):
+    """Pick the fastest schedule for `grid` and set it.  Returns
+    (best schedule dict, list of (ms per step, schedule))."""
+    import torch
+    key = workload_key(grid)
+    path = cache_path()
+    if use_cache:
+        hit = _load(path).get(key)
+        if hit:
+            grid.set_schedule(**hit["schedule"])
+            return hit["schedule"], hit.get("trials", [])
+    U = pool.clone()
+    work = grid.work()
+    t_dev = torch.zeros(1, dtype=torch.float64, device=U.device)
+    dt_dev = torch.zeros(1, dtype=torch.float64, device=U.device)
+    p = wacm.make_params(params)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    trials = []
+    for cand in candidates or CANDIDATES:
+        grid.set_schedule(**cand)
+        grid.rk4_step(None, t_dev, dt_dev, U, work, dus, dt_mode=wacm.DT_CFL, _p=p)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            grid.rk4_step(None, t_dev, dt_dev, U, work, dus, dt_mode=wacm.DT_CFL, _p=p)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        trials.append((round(ms, 4), dict(cand)))
+        if log:
+            log(f"  schedule {cand}: {ms:.3f} ms/step")
+    best = min(trials, key=lambda r: r[0])[1]
+    grid.set_schedule(**best)
+    del U, work
+    if use_cache:
+        data = _load(path)
+        data[key] = {"schedule": best, "trials": trials}
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path + ".tmp", "w") as f:
+                json.dump(data, f, indent=1)
+            os.replace(path + ".tmp", path)
+        except OSError:
+            pass
+    return best, trials

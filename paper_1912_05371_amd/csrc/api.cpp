@@ -200,6 +200,21 @@ int wacm_grid_info(const wacm_grid* g, int64_t* slots, uint64_t* treecodes, int8
 
 size_t wacm_work_bytes(const wacm_grid* g) { return g ? work_bytes(g) : 0; }
 
+int wacm_set_schedule(wacm_grid* g, const wacm_schedule* s) {
+  if (!g || !s) return fail(WACM_E_INVAL, "NULL argument");
+  if (s->wg_per_cu < 0 || s->wg_per_cu > 16 || (s->xcd_map != 0 && s->xcd_map != 1) ||
+      s->prefetch < -1 || s->prefetch > 1 || (s->nontemporal != 0 && s->nontemporal != 1))
+    return fail(WACM_E_INVAL, "schedule value out of range");
+  g->sched = *s;
+  return WACM_OK;
+}
+
+int wacm_get_schedule(const wacm_grid* g, wacm_schedule* s) {
+  if (!g || !s) return fail(WACM_E_INVAL, "NULL argument");
+  *s = g->sched;
+  return WACM_OK;
+}
+
 int wacm_sync_ghosts(wacm_grid* g, void* U, void* stream) {
   if (!elem_ok(g) || !U) return fail(WACM_E_INVAL, "NULL argument");
   hipError_t e = launch_sync(g, U, 0, S(stream));

@@ -85,6 +85,7 @@ struct StageArgs {
   double t_host;
   double L;
   int xcd_map;  // 1: give each XCD a contiguous run of blocks
+  int nt;       // 1: non-temporal loads/stores of the streaming operands
   wacm_params p;
 };
 
@@ -161,12 +162,15 @@ __device__ __forceinline__ FaceDesc<T> face_desc(const Tab& tb, const StageArgs<
 // and store them non-temporally so the caches keep the stage input, whose
 // face layers neighbouring blocks read again.
 template <typename T>
-__device__ __forceinline__ T ntload(const T* p) {
-  return __builtin_nontemporal_load(p);
+__device__ __forceinline__ T ntload(const T* p, int nt) {
+  return nt ? __builtin_nontemporal_load(p) : *p;
 }
 template <typename T>
-__device__ __forceinline__ void ntstore(T v, T* p) {
-  __builtin_nontemporal_store(v, p);
+__device__ __forceinline__ void ntstore(T v, T* p, int nt) {
+  if (nt)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
 }
 
 // MODE 0: dU = rhs(U) with U's own ghost layers.  MODE s = 1..4: classical
@@ -278,12 +282,12 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
         if (MODE == 2 || MODE == 3) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            unv[c] = ntload(unb + c * ufs + z * uzs);
-            acv[c] = ntload(accb + c * afs + z * azs);
+            unv[c] = ntload(unb + c * ufs + z * uzs, a.nt);
+            acv[c] = ntload(accb + c * afs + z * azs, a.nt);
           }
         } else if (MODE == 4) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acv[c] = ntload(accb + c * afs + z * azs);
+          for (int c = 0; c < 4; ++c) acv[c] = ntload(accb + c * afs + z * azs, a.nt);
         }
       }
       lds_barrier();
@@ -355,12 +359,12 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
         if (MODE == 2 || MODE == 3) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            unv[c] = ntload(unb + c * ufs + z * uzs);
-            acv[c] = ntload(accb + c * afs + z * azs);
+            unv[c] = ntload(unb + c * ufs + z * uzs, a.nt);
+            acv[c] = ntload(accb + c * afs + z * azs, a.nt);
           }
         } else if (MODE == 4) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acv[c] = ntload(accb + c * afs + z * azs);
+          for (int c = 0; c < 4; ++c) acv[c] = ntload(accb + c * afs + z * azs, a.nt);
         }
       }
       if (MODE == 0) {
@@ -368,14 +372,14 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
         for (int c = 0; c < 4; ++c) outb[c * ofs + z * ozs] = r[c];
       } else if (MODE == 4) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) ntstore(acv[c] + fA * r[c], unb + c * ufs + z * uzs);
+        for (int c = 0; c < 4; ++c) ntstore(acv[c] + fA * r[c], unb + c * ufs + z * uzs, a.nt);
       } else {
         const T val[4] = {u, v, w, pr};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const T u0 = MODE == 1 ? val[c] : unv[c];
           const T ac = MODE == 1 ? u0 : acv[c];
-          ntstore(ac + fA * r[c], accb + c * afs + z * azs);
+          ntstore(ac + fA * r[c], accb + c * afs + z * azs, a.nt);
           outb[c * ofs + z * ozs] = u0 + fB * r[c];
         }
       }
@@ -1002,12 +1006,10 @@ static int resident_per_cu(K kernel, int threads) {
   return n;
 }
 
-template <typename T, int BS, int MODE, bool PEN>
-static hipError_t stage_launch_pen(const StageArgs<T>& a, hipStream_t st) {
-  // FP64 keeps the epilogue loads late to stay within the VGPR budget of a
-  // 9-wave workgroup; FP32 has room to issue them early
-  constexpr bool PREF = sizeof(T) == 4;
-  static const int per_cu = resident_per_cu(stage_kernel<T, BS, MODE, PEN, PREF>, BS * BS);
+template <typename T, int BS, int MODE, bool PEN, bool PREF>
+static hipError_t stage_launch_pp(const StageArgs<T>& a, int wg_per_cu, hipStream_t st) {
+  static const int resident = resident_per_cu(stage_kernel<T, BS, MODE, PEN, PREF>, BS * BS);
+  const int per_cu = wg_per_cu > 0 ? wg_per_cu : resident;
   int64_t grid = (int64_t)per_cu * num_cus();
   if (grid > a.nb) grid = a.nb;
   if (grid < 1) grid = 1;
@@ -1015,22 +1017,31 @@ static hipError_t stage_launch_pen(const StageArgs<T>& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Schedule knobs: prefetch = 1 issues the epilogue loads before the plane's
+// barrier (more bytes in flight, more registers), 0 after the rhs; -1 picks
+// the default (early for FP32, late for FP64, whose 9-wave workgroup is at
+// its VGPR limit).
 template <typename T, int BS, int MODE>
-static hipError_t stage_launch(const StageArgs<T>& a, hipStream_t st) {
+static hipError_t stage_launch(const StageArgs<T>& a, const wacm_schedule& s, hipStream_t st) {
   const bool pen = a.p.mask || a.p.sponge || a.dus;
-  return pen ? stage_launch_pen<T, BS, MODE, true>(a, st)
-             : stage_launch_pen<T, BS, MODE, false>(a, st);
+  const bool pref = s.prefetch < 0 ? sizeof(T) == 4 : s.prefetch != 0;
+  if (pen)
+    return pref ? stage_launch_pp<T, BS, MODE, true, true>(a, s.wg_per_cu, st)
+                : stage_launch_pp<T, BS, MODE, true, false>(a, s.wg_per_cu, st);
+  return pref ? stage_launch_pp<T, BS, MODE, false, true>(a, s.wg_per_cu, st)
+              : stage_launch_pp<T, BS, MODE, false, false>(a, s.wg_per_cu, st);
 }
 
 template <typename T, int MODE>
-static hipError_t stage_dispatch(int bs, const StageArgs<T>& a, hipStream_t st) {
+static hipError_t stage_dispatch(int bs, const StageArgs<T>& a, const wacm_schedule& s,
+                                 hipStream_t st) {
   switch (bs) {
     case 16:
-      return stage_launch<T, 16, MODE>(a, st);
+      return stage_launch<T, 16, MODE>(a, s, st);
     case 24:
-      return stage_launch<T, 24, MODE>(a, st);
+      return stage_launch<T, 24, MODE>(a, s, st);
     case 32:
-      return stage_launch<T, 32, MODE>(a, st);
+      return stage_launch<T, 32, MODE>(a, s, st);
     default:
       return hipErrorInvalidValue;
   }
@@ -1042,7 +1053,8 @@ static StageArgs<T> base_args(const wacm_grid* g, const wacm_params* p) {
   a.tab = g->d_tab;
   a.nb = g->nb;
   a.L = g->d.L;
-  a.xcd_map = 1;
+  a.xcd_map = g->sched.xcd_map;
+  a.nt = g->sched.nontemporal;
   a.p = *p;
   return a;
 }
@@ -1062,7 +1074,7 @@ static hipError_t rhs_t(const wacm_grid* g, const wacm_params* p, double t, cons
   a.Lacc = pool_layout(g);
   a.dus = dus;
   a.t_host = t;
-  return stage_dispatch<T, 0>(g->d.bs, a, st);
+  return stage_dispatch<T, 0>(g->d.bs, a, g->sched, st);
 }
 
 hipError_t launch_rhs(const wacm_grid* g, const wacm_params* p, double t, const void* U,
@@ -1130,16 +1142,16 @@ static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
     ProfScope ps(g, 2, st);
     switch (s) {
       case 0:
-        e = stage_dispatch<T, 1>(g->d.bs, a, st);
+        e = stage_dispatch<T, 1>(g->d.bs, a, g->sched, st);
         break;
       case 1:
-        e = stage_dispatch<T, 2>(g->d.bs, a, st);
+        e = stage_dispatch<T, 2>(g->d.bs, a, g->sched, st);
         break;
       case 2:
-        e = stage_dispatch<T, 3>(g->d.bs, a, st);
+        e = stage_dispatch<T, 3>(g->d.bs, a, g->sched, st);
         break;
       default:
-        e = stage_dispatch<T, 4>(g->d.bs, a, st);
+        e = stage_dispatch<T, 4>(g->d.bs, a, g->sched, st);
         break;
     }
     if (e != hipSuccess) return e;

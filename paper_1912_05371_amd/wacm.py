@@ -28,13 +28,22 @@ EXPORTS = ["wacm_last_error", "wacm_treecode_encode", "wacm_treecode_decode", "w
            "wacm_sync_ghosts", "wacm_rhs_acm", "wacm_compute_dt", "wacm_rk4_step",
            "wacm_diagnostics", "wacm_threshold_blocks", "wacm_adapt", "wacm_profile_enable",
            "wacm_profile_read", "wacm_adj_work_bytes", "wacm_sync_ghosts_adj",
-           "wacm_rhs_acm_adj", "wacm_force_adj", "wacm_rk4_step_adj"]
+           "wacm_rhs_acm_adj", "wacm_force_adj", "wacm_rk4_step_adj", "wacm_set_schedule",
+           "wacm_get_schedule"]
 
 
 class GridDesc(C.Structure):
     _fields_ = [("bs", C.c_int32), ("ng", C.c_int32), ("jmin", C.c_int32), ("jmax", C.c_int32),
                 ("dtype", C.c_int32), ("reserved", C.c_int32), ("capacity", C.c_int64),
                 ("L", C.c_double)]
+
+
+class Schedule(C.Structure):
+    _fields_ = [("wg_per_cu", C.c_int32), ("xcd_map", C.c_int32), ("prefetch", C.c_int32),
+                ("nontemporal", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class Params(C.Structure):
@@ -112,6 +121,8 @@ def lib():
         L.wacm_force_adj.argtypes = [vp, C.POINTER(Params), dbl, dbl, vp, vp, vp, vp, vp, vp]
         L.wacm_rk4_step_adj.argtypes = [vp, C.POINTER(Params), dbl, dbl, vp, vp, vp, vp, vp, vp,
                                         vp]
+        L.wacm_set_schedule.argtypes = [vp, C.POINTER(Schedule)]
+        L.wacm_get_schedule.argtypes = [vp, C.POINTER(Schedule)]
         L.wacm_profile_enable.argtypes = [vp, i32]
         L.wacm_profile_read.argtypes = [vp, vp, vp]
         _lib = L
@@ -296,6 +307,18 @@ class Grid:
             fptr = flags.ctypes.data_as(C.c_void_p)
         _check(lib().wacm_adapt(self._h, int(op), fptr, _ptr(U), C.byref(nb), _stream(stream)))
         return nb.value
+
+    def set_schedule(self, **kw):
+        s = Schedule()
+        _check(lib().wacm_get_schedule(self._h, C.byref(s)))
+        for k, v in kw.items():
+            setattr(s, k, int(v))
+        _check(lib().wacm_set_schedule(self._h, C.byref(s)))
+
+    def get_schedule(self) -> dict:
+        s = Schedule()
+        _check(lib().wacm_get_schedule(self._h, C.byref(s)))
+        return s.as_dict()
 
     def profile_enable(self, on: bool = True):
         _check(lib().wacm_profile_enable(self._h, int(bool(on))))

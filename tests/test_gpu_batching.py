@@ -1,0 +1,98 @@
+"""Batching: hipGraph capture of wacm_rk4_step, schedule independence and the
+autotuner, on a mixed-level octree (one persistent launch per stage over the
+whole block list of uneven per-level counts).
+
+Graph replays are checked bitwise against eager steps from the same state,
+several times, with eager work and synchronisation between replays.  Every
+stage-kernel schedule must give bitwise identical results (the schedule only
+maps blocks to workgroups; each block's arithmetic is the same).
+"""
+import numpy as np
+import pytest
+
+from paper_1912_05371_amd import autotune, cases, wacm
+
+from gpu_util import log, to_pool
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def octree():
+    return cases.random_octree(bs=24, ng=4, target=600, j0=2, jmax=5, seed=21)
+
+
+@pytest.mark.parametrize("prec", [wacm.F64, wacm.F32])
+def test_graph_replay_matches_eager(octree, prec):
+    log(f"graph replay, {octree.nb} blocks, dtype {prec}")
+    c = octree
+    g = wacm.Grid.from_case(c, dtype=prec)
+    U0 = to_pool(g, c.padded())
+    pool = U0.clone()
+    work = g.work()
+    t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    p = wacm.make_params(c.params)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        g.rk4_step(None, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_CFL, _p=p)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g.rk4_step(None, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_CFL, _p=p)
+    torch.cuda.synchronize()
+    state = U0.clone()
+    for rep in range(3):
+        # eager reference from `state`
+        ref = state.clone()
+        te = torch.zeros(1, dtype=torch.float64, device="cuda")
+        de = torch.zeros(1, dtype=torch.float64, device="cuda")
+        g.rk4_step(None, te, de, ref, work, dt_mode=wacm.DT_CFL, _p=p)
+        torch.cuda.synchronize()
+        # replay from the same state
+        pool.copy_(state)
+        t_dev.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(pool, ref), f"replay {rep} differs from eager"
+        assert float(t_dev.item()) == float(te.item()) == float(de.item())
+        state = ref  # next round starts one step later
+        _ = (state * 2.0).sum().item()  # unrelated eager work between replays
+
+
+def test_schedules_give_identical_results(octree):
+    c = octree
+    g = wacm.Grid.from_case(c, dtype=wacm.F64)
+    U0 = to_pool(g, c.padded())
+    work = g.work()
+    outs = []
+    for cand in autotune.CANDIDATES:
+        g.set_schedule(**cand)
+        U = U0.clone()
+        t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        g.rk4_step(c.params, t_dev, dt_dev, U, work, dt_mode=wacm.DT_CFL)
+        outs.append(U)
+    torch.cuda.synchronize()
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
+def test_autotuner_picks_a_candidate(octree, tmp_path, monkeypatch):
+    monkeypatch.setenv("WACM_CACHE_DIR", str(tmp_path))
+    c = octree
+    g = wacm.Grid.from_case(c, dtype=wacm.F32)
+    U0 = to_pool(g, c.padded())
+    before = U0.clone()
+    best, trials = autotune.tune(g, c.params, U0, steps=1, log=log)
+    assert best in autotune.CANDIDATES and g.get_schedule() == best
+    assert len(trials) == len(autotune.CANDIDATES)
+    assert torch.equal(U0, before)  # the caller's state is untouched
+    best2, _ = autotune.tune(g, c.params, U0)  # cache hit
+    assert best2 == best
+    with pytest.raises(wacm.WacmError):
+        g.set_schedule(prefetch=3)
