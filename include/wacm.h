@@ -91,12 +91,15 @@ typedef struct {
  * XCDs a contiguous run of the Morton-ordered blocks (shared faces meet in one
  * L2); prefetch: 1 loads U^n and the accumulator before a plane's barrier, 0
  * after the rhs, -1 default; nontemporal: 1 streams U^n and the accumulator
- * with non-temporal loads/stores.  Default {0, 1, -1, 1}. */
+ * with non-temporal loads/stores; tile_rows: 0 gives each workgroup a whole
+ * block (bs^2 threads), 8 a tile of 8 rows of the block's columns (8 bs
+ * threads, smaller workgroups, more of them per CU).  Default {0, 1, -1, 1, 0}. */
 typedef struct {
   int32_t wg_per_cu;
   int32_t xcd_map;
   int32_t prefetch;
   int32_t nontemporal;
+  int32_t tile_rows;
 } wacm_schedule;
 
 /* Parameters of the penalized ACM model (Sec. 2.1-2.3). */
@@ -154,7 +157,8 @@ int64_t wacm_grid_nb(const wacm_grid* grid);
 int wacm_grid_info(const wacm_grid* grid, int64_t* slots, uint64_t* treecodes, int8_t* levels);
 
 /* Set / read the stage-kernel schedule (values checked: wg_per_cu in [0, 16],
- * xcd_map and nontemporal in {0, 1}, prefetch in {-1, 0, 1}). */
+ * xcd_map and nontemporal in {0, 1}, prefetch in {-1, 0, 1}, tile_rows in
+ * {0, 8}). */
 int wacm_set_schedule(wacm_grid* grid, const wacm_schedule* s);
 int wacm_get_schedule(const wacm_grid* grid, wacm_schedule* s);
 

@@ -18,8 +18,8 @@ import numpy as np
 
 from . import wacm
 
-CANDIDATES = [dict(wg_per_cu=w, xcd_map=x, prefetch=p, nontemporal=n)
-              for w, x, p, n in itertools.product((0, 2), (0, 1), (0, 1), (0, 1))]
+CANDIDATES = [dict(wg_per_cu=w, xcd_map=x, prefetch=p, nontemporal=n, tile_rows=ty)
+              for ty, w, x, p, n in itertools.product((0, 8), (0, 2), (0, 1), (0, 1), (0, 1))]
 
 
 def cache_path() -> str:

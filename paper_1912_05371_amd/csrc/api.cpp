@@ -203,7 +203,8 @@ size_t wacm_work_bytes(const wacm_grid* g) { return g ? work_bytes(g) : 0; }
 int wacm_set_schedule(wacm_grid* g, const wacm_schedule* s) {
   if (!g || !s) return fail(WACM_E_INVAL, "NULL argument");
   if (s->wg_per_cu < 0 || s->wg_per_cu > 16 || (s->xcd_map != 0 && s->xcd_map != 1) ||
-      s->prefetch < -1 || s->prefetch > 1 || (s->nontemporal != 0 && s->nontemporal != 1))
+      s->prefetch < -1 || s->prefetch > 1 || (s->nontemporal != 0 && s->nontemporal != 1) ||
+      (s->tile_rows != 0 && s->tile_rows != 8))
     return fail(WACM_E_INVAL, "schedule value out of range");
   g->sched = *s;
   return WACM_OK;

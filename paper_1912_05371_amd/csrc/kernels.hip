@@ -180,19 +180,24 @@ __device__ __forceinline__ void ntstore(T v, T* p, int nt) {
 //   s3: acc += dt/3 k3,      out = U^n + dt k3
 //   s4: U^n = acc + dt/6 k4
 // PEN: penalization/sponge terms present.  PREF: load the epilogue operands
-// (U^n, acc) before the barrier instead of after the rhs.  One workgroup per block
-// (persistent), one thread per (x,y) column marching in z: z-neighbours in a
-// register queue, the x/y cross of the current plane in a double-buffered LDS
-// slab, the next plane's loads issued before the barrier.
-template <typename T, int BS, int MODE, bool PEN, bool PREF>
-__global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
-  constexpr int H = 3, W = BS + 2 * H, NH = 12 * BS;
+// (U^n, acc) before the barrier instead of after the rhs.  Work items are
+// tiles of TY rows of a block's (x,y) columns (TY = BS: the whole block), one
+// persistent workgroup per item at a time, one thread per column marching in
+// z: z-neighbours in a register queue, the x/y cross of the current plane in a
+// double-buffered LDS slab, the next plane's loads issued before the barrier.
+// Rows between tiles of one block are read from the block itself.
+template <typename T, int BS, int TY, int MODE, bool PEN, bool PREF>
+__global__ __launch_bounds__(BS* TY) __attribute__((amdgpu_waves_per_eu(TY == BS ? 1 : 3)))
+void stage_kernel(StageArgs<T> a) {
+  constexpr int H = 3, W = BS + 2 * H, WY = TY + 2 * H, NT = BS * TY;
+  constexpr int NTY = BS / TY, NH = 6 * TY + 6 * BS;
+  static_assert(NH <= NT || TY == BS, "halo points per plane exceed the threads");
   constexpr bool GH = (MODE == 0);
-  __shared__ T slab[2][4][W * W];
+  __shared__ T slab[2][4][W * WY];
   __shared__ FaceDesc<T> fds[6];
   __shared__ int32_t meta[5];
   const int tid = threadIdx.x;
-  const int x = tid % BS, y = tid / BS;
+  const int x = tid % BS, yl = tid / BS;
   const T a1 = T(TW1), a2 = T(TW2), a3 = T(TW3);
   const T c2a = T(D2A), c2b = T(D2B), c2c = T(D2C);
   double tc = a.t_host, dt = 0.0;
@@ -204,34 +209,47 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
   const T fA = T(MODE == 1 ? dt / 6.0 : (MODE == 4 ? dt / 6.0 : dt / 3.0));
   const T fB = T(MODE == 3 ? dt : 0.5 * dt);
   const int fin = (int)a.Lin.fstride, Pi = a.Lin.P;
-  const int cidx = (y + H) * W + (x + H);
-  // this thread's halo point of every plane (threads < NH): faces x-, x+, y-, y+
+  const int cidx = (yl + H) * W + (x + H);
+  // this thread's halo point of every plane (threads < NH): x-faces of the
+  // tile's rows, then the 3 rows below and above the tile
   const bool hthr = tid < NH;
-  int hf = 0, hd = 0, hs = 0, hli = 0;
+  int hkind = 0, hd = 0, hs = 0, hli = 0;  // hkind: 0..3 face x-,x+,below,above
   if (hthr) {
-    hf = tid / (3 * BS);
-    const int rem = tid - hf * 3 * BS;
-    hd = rem / BS;
-    hs = rem - hd * BS;
-    const int hx = hf == 0 ? -1 - hd : (hf == 1 ? BS + hd : hs);
-    const int hy = hf == 2 ? -1 - hd : (hf == 3 ? BS + hd : hs);
-    hli = (hy + H) * W + (hx + H);
+    if (tid < 6 * TY) {
+      hkind = tid / (3 * TY);
+      const int rem = tid - hkind * 3 * TY;
+      hd = rem / TY;
+      hs = rem - hd * TY;
+      const int hx = hkind == 0 ? -1 - hd : BS + hd;
+      hli = (hs + H) * W + (hx + H);
+    } else {
+      const int q = tid - 6 * TY;
+      hkind = 2 + q / (3 * BS);
+      const int rem = q - (hkind - 2) * 3 * BS;
+      hd = rem / BS;
+      hs = rem - hd * BS;
+      const int hyl = hkind == 2 ? -1 - hd : TY + hd;
+      hli = (hyl + H) * W + (hs + H);
+    }
   }
-  // offsets of this thread's column in the input, accumulator and U^n
-  const int col = (a.Lin.ng * Pi + (y + a.Lin.ng)) * Pi + (x + a.Lin.ng);
   const int zs = Pi * Pi;
-  const int acol = (a.Lacc.ng * a.Lacc.P + (y + a.Lacc.ng)) * a.Lacc.P + (x + a.Lacc.ng);
   const int azs = a.Lacc.P * a.Lacc.P, afs = (int)a.Lacc.fstride;
-  const int ucol = (a.Lun.ng * a.Lun.P + (y + a.Lun.ng)) * a.Lun.P + (x + a.Lun.ng);
   const int uzs = a.Lun.P * a.Lun.P, ufs = (int)a.Lun.fstride;
-  const int ocol = (a.Lout.ng * a.Lout.P + (y + a.Lout.ng)) * a.Lout.P + (x + a.Lout.ng);
   const int ozs = a.Lout.P * a.Lout.P, ofs = (int)a.Lout.fstride;
 
-  for (BlockIter it(a.nb, a.xcd_map); it.ib < it.end; it.ib += it.step) {
+  for (BlockIter it(a.nb * NTY, a.xcd_map); it.ib < it.end; it.ib += it.step) {
+    const int64_t ibk = it.ib / NTY;
+    const int y0 = (int)(it.ib - ibk * NTY) * TY;
+    const int y = y0 + yl;
     lds_barrier();
-    if (tid < 6) fds[tid] = face_desc<T, BS, GH>(a.tab[it.ib], a, tid);
-    if (tid < 5) meta[tid] = a.tab[it.ib].meta[tid];
+    if (tid < 6) fds[tid] = face_desc<T, BS, GH>(a.tab[ibk], a, tid);
+    if (tid < 5) meta[tid] = a.tab[ibk].meta[tid];
     lds_barrier();
+    // offsets of this thread's column in the input, accumulator and U^n
+    const int col = (a.Lin.ng * Pi + (y + a.Lin.ng)) * Pi + (x + a.Lin.ng);
+    const int acol = (a.Lacc.ng * a.Lacc.P + (y + a.Lacc.ng)) * a.Lacc.P + (x + a.Lacc.ng);
+    const int ucol = (a.Lun.ng * a.Lun.P + (y + a.Lun.ng)) * a.Lun.P + (x + a.Lun.ng);
+    const int ocol = (a.Lout.ng * a.Lout.P + (y + a.Lout.ng)) * a.Lout.P + (x + a.Lout.ng);
     const int slot = meta[0], J = meta[1];
     const double hdd = a.L / (double(int64_t(1) << J) * BS);
     const T ih = T(1.0 / hdd), ih2 = T(1.0 / (hdd * hdd));
@@ -240,8 +258,30 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
     T* unb = a.un + (int64_t)slot * a.Lun.bstride + ucol;
     T* outb = a.out + (int64_t)slot * a.Lout.bstride + ocol;
     const FaceDesc<T> fzl = fds[4], fzh = fds[5];
-    FaceDesc<T> fh;
-    if (hthr) fh = fds[hf];
+    // this thread's halo point as an affine map in z: hp[c hfs + z hzs]
+    const T* hp = nullptr;
+    int hfs = 0, hzs = 0;
+    if (hthr) {
+      if (hkind < 2) {
+        const FaceDesc<T>& fh = fds[hkind];
+        hp = fh.ptr + hd * fh.sd + (y0 + hs) * fh.s0;
+        hfs = fh.fs;
+        hzs = fh.s1;
+      } else {
+        const int hy = hkind == 2 ? y0 - 1 - hd : y0 + TY + hd;
+        if (hy < 0 || hy >= BS) {
+          const FaceDesc<T>& fh = fds[hy < 0 ? 2 : 3];
+          hp = fh.ptr + (hy < 0 ? -1 - hy : hy - BS) * fh.sd + hs * fh.s0;
+          hfs = fh.fs;
+          hzs = fh.s1;
+        } else {
+          hp = a.in + (int64_t)slot * a.Lin.bstride +
+               (a.Lin.ng * Pi + (hy + a.Lin.ng)) * Pi + (hs + a.Lin.ng);
+          hfs = fin;
+          hzs = zs;
+        }
+      }
+    }
 
     T q[4][7];
 #pragma unroll
@@ -257,11 +297,11 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
     for (int c = 0; c < 4; ++c) slab[0][c][cidx] = q[c][3];
     if (hthr) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) slab[0][c][hli] = fh.ptr[c * fh.fs + hd * fh.sd + hs * fh.s0];
+      for (int c = 0; c < 4; ++c) slab[0][c][hli] = hp[c * hfs];
     }
 
     for (int z = 0; z < BS; ++z) {
-      T(*sb)[W * W] = slab[z & 1];
+      T(*sb)[W * WY] = slab[z & 1];
       // loads for the next plane: column value at z+4 and this thread's halo point
       T nq[4], hnx[4];
       if (z + 1 < BS) {
@@ -272,8 +312,7 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
                           : fzh.ptr[c * fzh.fs + (zz - BS) * fzh.sd + x * fzh.s0 + y * fzh.s1];
         if (hthr) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c)
-            hnx[c] = fh.ptr[c * fh.fs + hd * fh.sd + hs * fh.s0 + (z + 1) * fh.s1];
+          for (int c = 0; c < 4; ++c) hnx[c] = hp[c * hfs + (z + 1) * hzs];
         }
       }
       // epilogue operands of this point, loaded early if PREF
@@ -386,7 +425,7 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
       if (z + 1 < BS) {
         // plane z+1 into the other slab: it was last read before this
         // plane's barrier, which every thread has passed
-        T(*nb_)[W * W] = slab[(z + 1) & 1];
+        T(*nb_)[W * WY] = slab[(z + 1) & 1];
 #pragma unroll
         for (int c = 0; c < 4; ++c) nb_[c][cidx] = q[c][4];
         if (hthr) {
@@ -407,24 +446,23 @@ __global__ __launch_bounds__(BS* BS) void stage_kernel(StageArgs<T> a) {
 // Faces next to a coarser or finer leaf: the depth-3 face halo of the stage
 // input into the halo buffer the stage kernel reads.  A finer neighbour gives
 // its coincident point (decimation, Sec. 3.1).  A coarser neighbour gives the
-// tensor-product DD4 prediction (Sec. 3.1), computed separably: the coarse
-// lattice box around the face (even local indices, read from whichever leaves
-// hold them) is gathered into LDS once, then predicted along the normal and
-// the two tangential axes in turn.
+// tensor-product DD4 prediction (Sec. 3.1), evaluated separably: each thread
+// takes one column of the coarse lattice box around the face (a tangential
+// position on the coarse lattice, even local indices), reads its points along
+// the normal from whichever leaves hold them and predicts the 3 halo depths
+// along the normal into LDS; then every halo point is predicted from LDS along
+// both tangential axes.  All 4 fields in one pass.
 constexpr int NLF_MAXS = 32 / 2 + 3;  // coarse points per tangential axis, bs <= 32
-constexpr int NLF_MAXN = 5;           // coarse points along the normal
 template <typename T>
 __global__ __launch_bounds__(NT_GEN) void nlface_kernel(const Tab* __restrict__ tab,
                                                         const int32_t* __restrict__ cf, int64_t n,
                                                         const T* __restrict__ in, Layout Lin,
                                                         T* __restrict__ hb, int bs) {
   __shared__ Tab st;
-  __shared__ int64_t soff[NLF_MAXN * NLF_MAXS * NLF_MAXS];
-  __shared__ T src[NLF_MAXN * NLF_MAXS * NLF_MAXS];
-  __shared__ T pa[3 * NLF_MAXS * NLF_MAXS];
-  __shared__ T pb[3 * NLF_MAXS * 32];
+  __shared__ T pa[4][3][NLF_MAXS * NLF_MAXS];
   const int S = bs / 2 + 3;  // tangential coarse positions -2, 0, ..., bs+2
   const T w0 = T(DDW0), w1 = T(DDW1);
+  const int64_t fs = Lin.fstride;
   for (int64_t wk = blockIdx.x; wk < n; wk += gridDim.x) {
     const int32_t ib = cf[2 * wk], f = cf[2 * wk + 1];
     __syncthreads();
@@ -436,83 +474,92 @@ __global__ __launch_bounds__(NT_GEN) void nlface_kernel(const Tab* __restrict__ 
     const int r = (axis == 0 ? 2 * side : 1) + 3 * (axis == 1 ? 2 * side : 1) +
                   9 * (axis == 2 ? 2 * side : 1);
     T* hbf = hb + ((int64_t)slot * 6 + f) * 12 * bs * bs;
+    const int b2 = bs * bs;
     if (st.kind[r] > 0) {
       // finer neighbour: every halo point is a point of a finer leaf
-      for (int p = threadIdx.x; p < 3 * bs * bs; p += blockDim.x) {
-        const int d = p / (bs * bs), qq = p - d * bs * bs;
+      for (int p = threadIdx.x; p < 3 * b2; p += blockDim.x) {
+        const int d = p / b2, qq = p - d * b2;
         int li[3];
         li[axis] = side ? bs + d : -1 - d;
         li[ua] = qq % bs;
         li[ub] = qq / bs;
         const int64_t o = point_offset(st, bs, Lin, li[0], li[1], li[2]);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) hbf[(int64_t)(c * 3) * bs * bs + p] = in[o + c * Lin.fstride];
+        for (int c = 0; c < 4; ++c) hbf[(int64_t)(c * 3) * b2 + p] = in[o + c * fs];
       }
       continue;
     }
-    // coarser neighbour.  normal ghost positions g_d = bs + d (side 1) or
-    // -1 - d (side 0); the even positions their stencils use run from n0 in
-    // steps of 2: side 1 [bs-2, bs+4] (4 points), side 0 [-6, 2] (5 points)
+    // coarser neighbour.  Halo depth d sits at g = bs + d (side 1) or -1 - d
+    // (side 0); the even normal positions the three depths use start at n0:
+    // side 1 [bs-2, bs+4] (4 points), side 0 [-6, 2] (5 points).
     const int n0 = side ? bs - 2 : -6;
     const int NN = side ? 4 : 5;
-    const int nsrc = NN * S * S;
-    for (int p = threadIdx.x; p < nsrc; p += blockDim.x) {
-      const int m = p / (S * S), qq = p - m * S * S;
-      int li[3];
-      li[axis] = n0 + 2 * m;
-      li[ua] = 2 * (qq % S) - 2;
-      li[ub] = 2 * (qq / S) - 2;
-      soff[p] = point_offset(st, bs, Lin, li[0], li[1], li[2]);
-    }
-    __syncthreads();
-    for (int c = 0; c < 4; ++c) {
-      for (int p = threadIdx.x; p < nsrc; p += blockDim.x) src[p] = in[soff[p] + c * Lin.fstride];
-      __syncthreads();
-      // along the normal: pa[d][t1'][t0']
-      for (int p = threadIdx.x; p < 3 * S * S; p += blockDim.x) {
-        const int d = p / (S * S), qq = p - d * S * S;
+    for (int col = threadIdx.x; col < S * S; col += blockDim.x) {
+      const int t0c = col % S, t1c = col / S;
+      T v[5][4];
+      for (int m = 0; m < NN; ++m) {
+        int li[3];
+        li[axis] = n0 + 2 * m;
+        li[ua] = 2 * t0c - 2;
+        li[ub] = 2 * t1c - 2;
+        const int64_t o = point_offset(st, bs, Lin, li[0], li[1], li[2]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[m][c] = in[o + c * fs];
+      }
+      for (int d = 0; d < 3; ++d) {
         const int g = side ? bs + d : -1 - d;
-        T v;
         if ((g & 1) == 0) {
-          v = src[((g - n0) / 2) * S * S + qq];
+          const int m = (g - n0) / 2;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) pa[c][d][col] = v[m][c];
         } else {
           const int m = (g - 3 - n0) / 2;  // taps g-3, g-1, g+1, g+3
-          v = w0 * src[m * S * S + qq] + w1 * src[(m + 1) * S * S + qq] +
-              w1 * src[(m + 2) * S * S + qq] + w0 * src[(m + 3) * S * S + qq];
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            pa[c][d][col] = w0 * v[m][c] + w1 * v[m + 1][c] + w1 * v[m + 2][c] + w0 * v[m + 3][c];
         }
-        pa[p] = v;
       }
-      __syncthreads();
-      // along t0: pb[d][t1'][t0], t0 in [0, bs)
-      for (int p = threadIdx.x; p < 3 * S * bs; p += blockDim.x) {
-        const int t0 = p % bs, rest = p / bs;  // rest = d * S + t1'
-        const T* row = pa + rest * S;
-        T v;
-        if ((t0 & 1) == 0) {
-          v = row[t0 / 2 + 1];
-        } else {
-          const int m = (t0 - 3) / 2 + 1;  // coarse index of t0-3
-          v = w0 * row[m] + w1 * row[m + 1] + w1 * row[m + 2] + w0 * row[m + 3];
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < 3 * b2; p += blockDim.x) {
+      const int d = p / b2, qq = p - d * b2;
+      const int t0 = qq % bs, t1 = qq / bs;
+      int i0[4], i1[4];
+      T x0[4], x1[4];
+      int n0t, n1t;
+      if ((t0 & 1) == 0) {
+        i0[0] = t0 / 2 + 1;
+        x0[0] = T(1);
+        n0t = 1;
+      } else {
+        const int m = (t0 - 3) / 2 + 1;
+        i0[0] = m, i0[1] = m + 1, i0[2] = m + 2, i0[3] = m + 3;
+        x0[0] = w0, x0[1] = w1, x0[2] = w1, x0[3] = w0;
+        n0t = 4;
+      }
+      if ((t1 & 1) == 0) {
+        i1[0] = t1 / 2 + 1;
+        x1[0] = T(1);
+        n1t = 1;
+      } else {
+        const int m = (t1 - 3) / 2 + 1;
+        i1[0] = m, i1[1] = m + 1, i1[2] = m + 2, i1[3] = m + 3;
+        x1[0] = w0, x1[1] = w1, x1[2] = w1, x1[3] = w0;
+        n1t = 4;
+      }
+      T acc[4] = {T(0), T(0), T(0), T(0)};
+      for (int b = 0; b < n1t; ++b) {
+        T row[4] = {T(0), T(0), T(0), T(0)};
+        for (int e = 0; e < n0t; ++e) {
+          const int q = i1[b] * S + i0[e];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) row[c] += x0[e] * pa[c][d][q];
         }
-        pb[p] = v;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] += x1[b] * row[c];
       }
-      __syncthreads();
-      // along t1: out[d][t1][t0]
-      for (int p = threadIdx.x; p < 3 * bs * bs; p += blockDim.x) {
-        const int d = p / (bs * bs), qq = p - d * bs * bs;
-        const int t0 = qq % bs, t1 = qq / bs;
-        const T* colp = pb + d * S * bs + t0;
-        T v;
-        if ((t1 & 1) == 0) {
-          v = colp[(t1 / 2 + 1) * bs];
-        } else {
-          const int m = (t1 - 3) / 2 + 1;
-          v = w0 * colp[m * bs] + w1 * colp[(m + 1) * bs] + w1 * colp[(m + 2) * bs] +
-              w0 * colp[(m + 3) * bs];
-        }
-        hbf[(int64_t)(c * 3) * bs * bs + p] = v;
-      }
-      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < 4; ++c) hbf[(int64_t)(c * 3) * b2 + p] = acc[c];
     }
   }
 }
@@ -1006,15 +1053,29 @@ static int resident_per_cu(K kernel, int threads) {
   return n;
 }
 
-template <typename T, int BS, int MODE, bool PEN, bool PREF>
-static hipError_t stage_launch_pp(const StageArgs<T>& a, int wg_per_cu, hipStream_t st) {
-  static const int resident = resident_per_cu(stage_kernel<T, BS, MODE, PEN, PREF>, BS * BS);
+template <typename T, int BS, int TY, int MODE, bool PEN, bool PREF>
+static hipError_t stage_launch_t(const StageArgs<T>& a, int wg_per_cu, hipStream_t st) {
+  static const int resident =
+      resident_per_cu(stage_kernel<T, BS, TY, MODE, PEN, PREF>, BS * TY);
   const int per_cu = wg_per_cu > 0 ? wg_per_cu : resident;
+  const int64_t items = a.nb * (BS / TY);
   int64_t grid = (int64_t)per_cu * num_cus();
-  if (grid > a.nb) grid = a.nb;
+  if (grid > items) grid = items;
   if (grid < 1) grid = 1;
-  stage_kernel<T, BS, MODE, PEN, PREF><<<(unsigned)grid, BS * BS, 0, st>>>(a);
+  stage_kernel<T, BS, TY, MODE, PEN, PREF><<<(unsigned)grid, BS * TY, 0, st>>>(a);
   return hipGetLastError();
+}
+
+// tile_rows 0: whole-block work items; 8: tiles of 8 rows (bs >= 24, where the
+// halo of a tile plane fits in one point per thread; smaller blocks use whole
+// blocks)
+template <typename T, int BS, int MODE, bool PEN, bool PREF>
+static hipError_t stage_launch_pp(const StageArgs<T>& a, const wacm_schedule& s,
+                                  hipStream_t st) {
+  if constexpr (BS >= 24) {
+    if (s.tile_rows == 8) return stage_launch_t<T, BS, 8, MODE, PEN, PREF>(a, s.wg_per_cu, st);
+  }
+  return stage_launch_t<T, BS, BS, MODE, PEN, PREF>(a, s.wg_per_cu, st);
 }
 
 // Schedule knobs: prefetch = 1 issues the epilogue loads before the plane's
@@ -1026,10 +1087,10 @@ static hipError_t stage_launch(const StageArgs<T>& a, const wacm_schedule& s, hi
   const bool pen = a.p.mask || a.p.sponge || a.dus;
   const bool pref = s.prefetch < 0 ? sizeof(T) == 4 : s.prefetch != 0;
   if (pen)
-    return pref ? stage_launch_pp<T, BS, MODE, true, true>(a, s.wg_per_cu, st)
-                : stage_launch_pp<T, BS, MODE, true, false>(a, s.wg_per_cu, st);
-  return pref ? stage_launch_pp<T, BS, MODE, false, true>(a, s.wg_per_cu, st)
-              : stage_launch_pp<T, BS, MODE, false, false>(a, s.wg_per_cu, st);
+    return pref ? stage_launch_pp<T, BS, MODE, true, true>(a, s, st)
+                : stage_launch_pp<T, BS, MODE, true, false>(a, s, st);
+  return pref ? stage_launch_pp<T, BS, MODE, false, true>(a, s, st)
+              : stage_launch_pp<T, BS, MODE, false, false>(a, s, st);
 }
 
 template <typename T, int MODE>

@@ -92,7 +92,7 @@ struct wacm_grid {
   int jfine = 0;                 // finest active level
   mutable wacm::Profiler prof;   // kernel timing, off by default
   std::vector<wacm::Tab> h_tab;  // host copy of the tables
-  wacm_schedule sched{0, 1, -1, 1};  // launch schedule of the stage kernel
+  wacm_schedule sched{0, 1, -1, 1, 0};  // launch schedule of the stage kernel
   wacm::AdjPlan plan[2];         // ghost-fill transposes: all layers / face star
 };
 
