@@ -6,8 +6,9 @@ Workload: a fixed, seeded random 2:1-balanced periodic octree on [0, 2 pi]^3
 smooth random-Fourier velocity and pressure (16 modes per field, |k| <= 8),
 nu 1e-2, C0 20, C_gamma 1, no mask, CFL 0.5 (time step recomputed on the GPU
 every step).  A step is one classical RK4 step: 4 x (ghost synchronisation +
-fused rhs/RK stage) plus the CFL reduction.  Inputs are resident in HBM
-before the timed region.
+fused rhs/RK stage) plus the CFL time step.  The K timed steps are one
+wacm_rk4_steps call (each step's CFL maximum is formed by the previous step's
+last stage).  Inputs are resident in HBM before the timed region.
 
 Metric: RK4 block-point updates/s = interior points x 4 stages / s.  The
 primary line is the FP64 path; the FP32 path is reported beside it with its
@@ -46,7 +47,8 @@ def build_case(target: int, seed: int):
                                with_fields=False)
 
 
-def run_gpu(case, dtype_code: int, steps: int, warmup: int, use_graph: bool, tune: bool):
+def run_gpu(case, dtype_code: int, steps: int, warmup: int, use_graph: bool, tune: bool,
+            schedule=None):
     import torch
 
     from paper_1912_05371_amd import inputs, wacm
@@ -63,13 +65,15 @@ def run_gpu(case, dtype_code: int, steps: int, warmup: int, use_graph: bool, tun
     dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
     p = wacm.make_params(case.params)
     stream = torch.cuda.current_stream()
-    schedule, trials = g.get_schedule(), []
-    if tune:
+    trials = []
+    if schedule:
+        g.set_schedule(**schedule)
+    elif tune:
         from paper_1912_05371_amd import autotune
         schedule, trials = autotune.tune(g, case.params, pool, steps=2, use_cache=False)
         log(f"  autotuned schedule {schedule} (best of {len(trials)})")
-    for _ in range(warmup):
-        g.rk4_step(None, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_CFL, _p=p)
+    schedule = g.get_schedule()
+    g.rk4_steps(None, t_dev, dt_dev, pool, work, warmup, dt_mode=wacm.DT_CFL, _p=p)
     torch.cuda.synchronize()
 
     # timed region: K steps, kernel classes timed with events on the stream
@@ -79,8 +83,7 @@ def run_gpu(case, dtype_code: int, steps: int, warmup: int, use_graph: bool, tun
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(steps):
-        g.rk4_step(None, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_CFL, _p=p)
+    g.rk4_steps(None, t_dev, dt_dev, pool, work, steps, dt_mode=wacm.DT_CFL, _p=p)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -96,16 +99,15 @@ def run_gpu(case, dtype_code: int, steps: int, warmup: int, use_graph: bool, tun
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            g.rk4_step(None, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_CFL, _p=p)
+            g.rk4_steps(None, t_dev, dt_dev, pool, work, 1, dt_mode=wacm.DT_CFL, _p=p)
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         with torch.cuda.graph(graph):
-            g.rk4_step(None, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_CFL, _p=p)
+            g.rk4_steps(None, t_dev, dt_dev, pool, work, steps, dt_mode=wacm.DT_CFL, _p=p)
         graph.replay()
         torch.cuda.synchronize()
         ev0.record()
-        for _ in range(steps):
-            graph.replay()
+        graph.replay()
         ev1.record()
         torch.cuda.synchronize()
         res["graph_ms_per_step"] = ev0.elapsed_time(ev1) / steps
@@ -211,6 +213,9 @@ def main():
     ap.add_argument("--dtype", choices=["both", "f64", "f32"], default="both")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default schedule")
+    ap.add_argument("--schedule", default="",
+                    help="fixed stage-kernel schedule instead of tuning, e.g. "
+                         "tile_rows=8,wg_per_cu=2,xcd_map=0,prefetch=0,nontemporal=1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=2.0,
                     help="GiB per buffer of a plain device copy timed for the achievable "
@@ -243,7 +248,10 @@ def main():
         if args.dtype not in ("both", name):
             continue
         log(f"running {name}: warmup {args.warmup}, steps {args.steps}")
-        r = run_gpu(case, code, args.steps, args.warmup, not args.no_graph, not args.no_tune)
+        sched = dict((k, int(v)) for k, v in (kv.split("=") for kv in args.schedule.split(",")
+                                               if kv)) or None
+        r = run_gpu(case, code, args.steps, args.warmup, not args.no_graph, not args.no_tune,
+                    sched)
         r["value"] = npts * 4 / (r["ms_per_step"] * 1e-3)
         r["roofline"] = roofline(r, npts, es)
         log(f"  {name}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4e} updates/s, stage kernel "
@@ -294,7 +302,7 @@ def main():
         }
     line["kernel_ms_per_step"] = {
         k: round(v / args.steps, 4)
-        for k, v in zip(["dt", "sync", "stage", "time"], R["kernel_ms"])}
+        for k, v in zip(["dt", "face_halo", "stage", "time"], R["kernel_ms"])}
     if copy:
         line["copy_probe"] = copy
         line["roofline"]["frac_of_copy"] = round(R["roofline"]["achieved"] / copy["GBps"], 4)

@@ -206,11 +206,28 @@ int wacm_compute_dt(wacm_grid* grid, const wacm_params* prm, const void* U, doub
  * WACM_DT_CFL dt is first computed from U (as wacm_compute_dt) and stored in
  * *dt_dev, with WACM_DT_FIXED it is read from *dt_dev.  *t_dev is advanced by
  * dt.  work: device buffer of wacm_work_bytes().  dus: as in wacm_rhs_acm.
+ * Only the interiors of U are defined on return: the stages read neighbour
+ * values directly, not U's ghost layers, and those layers are left with
+ * unspecified values (call wacm_sync_ghosts before a call that reads them).
  * No host synchronisation and no allocation: the call may be captured in a
  * HIP graph as long as the grid is not changed.
  */
 int wacm_rk4_step(wacm_grid* grid, const wacm_params* prm, double* t_dev, double* dt_dev,
                   void* U, void* work, const void* dus, int32_t dt_mode, void* stream);
+
+/*
+ * wacm_rk4_steps -- nsteps consecutive wacm_rk4_step calls in one call, with
+ * the same results bit for bit.  With WACM_DT_CFL every step takes its dt
+ * from the state it starts from, as in wacm_rk4_step; from the second step on,
+ * the velocity maximum that rule needs is formed by the previous step's last
+ * stage while it writes U, instead of by a separate pass over U.  *dt_dev
+ * holds the last step's dt on return.  nsteps >= 0 (WACM_E_INVAL otherwise);
+ * 0 does nothing.  Same buffers, synchronisation and graph-capture rules as
+ * wacm_rk4_step.
+ */
+int wacm_rk4_steps(wacm_grid* grid, const wacm_params* prm, double* t_dev, double* dt_dev,
+                   void* U, void* work, const void* dus, int32_t dt_mode, int64_t nsteps,
+                   void* stream);
 
 /*
  * wacm_diagnostics -- FP64 reductions over interiors at time t:

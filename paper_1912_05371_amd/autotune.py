@@ -68,11 +68,10 @@ def tune(grid: wacm.Grid, params: dict, pool, dus=None, steps: int = 3, candidat
     trials = []
     for cand in candidates or CANDIDATES:
         grid.set_schedule(**cand)
-        grid.rk4_step(None, t_dev, dt_dev, U, work, dus, dt_mode=wacm.DT_CFL, _p=p)
+        grid.rk4_steps(None, t_dev, dt_dev, U, work, 1, dus, dt_mode=wacm.DT_CFL, _p=p)
         torch.cuda.synchronize()
         e0.record(stream)
-        for _ in range(steps):
-            grid.rk4_step(None, t_dev, dt_dev, U, work, dus, dt_mode=wacm.DT_CFL, _p=p)
+        grid.rk4_steps(None, t_dev, dt_dev, U, work, steps, dus, dt_mode=wacm.DT_CFL, _p=p)
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps

@@ -238,15 +238,28 @@ int wacm_compute_dt(wacm_grid* g, const wacm_params* p, const void* U, double* d
   return e == hipSuccess ? WACM_OK : hipfail(e, "compute_dt launch");
 }
 
-int wacm_rk4_step(wacm_grid* g, const wacm_params* p, double* t_dev, double* dt_dev, void* U,
-                  void* work, const void* dus, int32_t dt_mode, void* stream) {
+static int rk4_common(wacm_grid* g, const wacm_params* p, double* t_dev, double* dt_dev, void* U,
+                      void* work, const void* dus, int32_t dt_mode, int64_t nsteps,
+                      void* stream, const char* what) {
   if (!elem_ok(g) || !U || !work || !t_dev || !dt_dev)
     return fail(WACM_E_INVAL, "NULL argument");
   if (dt_mode != WACM_DT_FIXED && dt_mode != WACM_DT_CFL) return fail(WACM_E_INVAL, "dt_mode");
+  if (nsteps < 0) return fail(WACM_E_INVAL, "nsteps must be >= 0");
   if (reinterpret_cast<uintptr_t>(work) % 256) return fail(WACM_E_INVAL, "work not 256-aligned");
   if (int rc = check_params(p)) return rc;
-  hipError_t e = launch_rk4(g, p, t_dev, dt_dev, U, work, dus, dt_mode, S(stream));
-  return e == hipSuccess ? WACM_OK : hipfail(e, "rk4_step launch");
+  hipError_t e = launch_rk4(g, p, t_dev, dt_dev, U, work, dus, dt_mode, nsteps, S(stream));
+  return e == hipSuccess ? WACM_OK : hipfail(e, what);
+}
+
+int wacm_rk4_step(wacm_grid* g, const wacm_params* p, double* t_dev, double* dt_dev, void* U,
+                  void* work, const void* dus, int32_t dt_mode, void* stream) {
+  return rk4_common(g, p, t_dev, dt_dev, U, work, dus, dt_mode, 1, stream, "rk4_step launch");
+}
+
+int wacm_rk4_steps(wacm_grid* g, const wacm_params* p, double* t_dev, double* dt_dev, void* U,
+                   void* work, const void* dus, int32_t dt_mode, int64_t nsteps, void* stream) {
+  return rk4_common(g, p, t_dev, dt_dev, U, work, dus, dt_mode, nsteps, stream,
+                    "rk4_steps launch");
 }
 
 int wacm_diagnostics(wacm_grid* g, const wacm_params* p, double t, const void* U,

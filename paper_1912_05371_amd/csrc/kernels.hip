@@ -23,6 +23,11 @@ __device__ __forceinline__ T wave_max(T v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
+// |u|^2 in FP64 with one fixed operation order: the maximum fused into the
+// last RK4 stage and the stand-alone reduction agree bit for bit.
+__device__ __forceinline__ double speed2(double u, double v, double w) {
+  return __builtin_fma(w, w, __builtin_fma(v, v, u * u));
+}
 template <typename T>
 __device__ __forceinline__ T wave_min(T v) {
   for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
@@ -82,6 +87,7 @@ struct StageArgs {
   const T* dus;  // extra solid velocity [slot][3][bs^3] or null
   const double* t_dev;
   const double* dt_dev;
+  double* umax_part;  // stage 4: per work item max |u|^2 of the new U^n, or null
   double t_host;
   double L;
   int xcd_map;  // 1: give each XCD a contiguous run of blocks
@@ -196,6 +202,7 @@ void stage_kernel(StageArgs<T> a) {
   __shared__ T slab[2][4][W * WY];
   __shared__ FaceDesc<T> fds[6];
   __shared__ int32_t meta[5];
+  __shared__ double red[NT / 64];
   const int tid = threadIdx.x;
   const int x = tid % BS, yl = tid / BS;
   const T a1 = T(TW1), a2 = T(TW2), a3 = T(TW3);
@@ -283,6 +290,7 @@ void stage_kernel(StageArgs<T> a) {
       }
     }
 
+    double m2 = 0.0;  // stage 4: max |u|^2 of this thread's new points
     T q[4][7];
 #pragma unroll
     for (int mm = 0; mm < 7; ++mm) {
@@ -410,8 +418,22 @@ void stage_kernel(StageArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) outb[c * ofs + z * ozs] = r[c];
       } else if (MODE == 4) {
+        T nv[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) ntstore(acv[c] + fA * r[c], unb + c * ufs + z * uzs, a.nt);
+        for (int c = 0; c < 4; ++c) {
+          nv[c] = acv[c] + fA * r[c];
+          ntstore(nv[c], unb + c * ufs + z * uzs, a.nt);
+        }
+        // The x-ghost columns of the row are cleared too, so that every cache
+        // line of the padded row is written whole: rows of partly written lines
+        // store far slower.  Ghost layers carry no state between steps.
+        const int gx = a.Lun.ng;
+        if (x < gx || x >= BS - gx) {
+          const int off = x < gx ? -gx : gx;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) ntstore(T(0), unb + c * ufs + z * uzs + off, a.nt);
+        }
+        if (a.umax_part) m2 = fmax(m2, speed2(double(nv[0]), double(nv[1]), double(nv[2])));
       } else {
         const T val[4] = {u, v, w, pr};
 #pragma unroll
@@ -440,29 +462,43 @@ void stage_kernel(StageArgs<T> a) {
         }
       }
     }
+    if (MODE == 4 && a.umax_part) {
+      // the work item's maximum, reduced in the workgroup; red is free again
+      // by the next item's writes (several barriers later)
+      m2 = wave_max(m2);
+      if ((tid & 63) == 0) red[tid >> 6] = m2;
+      lds_barrier();
+      if (tid == 0) {
+        double mx = red[0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) mx = fmax(mx, red[w]);
+        a.umax_part[it.ib] = mx;
+      }
+    }
   }
 }
 
 // Faces next to a coarser or finer leaf: the depth-3 face halo of the stage
 // input into the halo buffer the stage kernel reads.  A finer neighbour gives
 // its coincident point (decimation, Sec. 3.1).  A coarser neighbour gives the
-// tensor-product DD4 prediction (Sec. 3.1), evaluated separably: each thread
-// takes one column of the coarse lattice box around the face (a tangential
-// position on the coarse lattice, even local indices), reads its points along
-// the normal from whichever leaves hold them and predicts the 3 halo depths
-// along the normal into LDS; then every halo point is predicted from LDS along
-// both tangential axes.  All 4 fields in one pass.
+// tensor-product DD4 prediction (Sec. 3.1), computed separably: the coarse
+// lattice box around the face (even local indices, read from whichever leaves
+// hold them) is gathered into LDS once, then predicted along the normal and
+// the two tangential axes in turn.
 constexpr int NLF_MAXS = 32 / 2 + 3;  // coarse points per tangential axis, bs <= 32
+constexpr int NLF_MAXN = 5;           // coarse points along the normal
 template <typename T>
 __global__ __launch_bounds__(NT_GEN) void nlface_kernel(const Tab* __restrict__ tab,
                                                         const int32_t* __restrict__ cf, int64_t n,
                                                         const T* __restrict__ in, Layout Lin,
                                                         T* __restrict__ hb, int bs) {
   __shared__ Tab st;
-  __shared__ T pa[4][3][NLF_MAXS * NLF_MAXS];
+  __shared__ int64_t soff[NLF_MAXN * NLF_MAXS * NLF_MAXS];
+  __shared__ T src[NLF_MAXN * NLF_MAXS * NLF_MAXS];
+  __shared__ T pa[3 * NLF_MAXS * NLF_MAXS];
+  __shared__ T pb[3 * NLF_MAXS * 32];
   const int S = bs / 2 + 3;  // tangential coarse positions -2, 0, ..., bs+2
   const T w0 = T(DDW0), w1 = T(DDW1);
-  const int64_t fs = Lin.fstride;
   for (int64_t wk = blockIdx.x; wk < n; wk += gridDim.x) {
     const int32_t ib = cf[2 * wk], f = cf[2 * wk + 1];
     __syncthreads();
@@ -474,92 +510,83 @@ __global__ __launch_bounds__(NT_GEN) void nlface_kernel(const Tab* __restrict__ 
     const int r = (axis == 0 ? 2 * side : 1) + 3 * (axis == 1 ? 2 * side : 1) +
                   9 * (axis == 2 ? 2 * side : 1);
     T* hbf = hb + ((int64_t)slot * 6 + f) * 12 * bs * bs;
-    const int b2 = bs * bs;
     if (st.kind[r] > 0) {
       // finer neighbour: every halo point is a point of a finer leaf
-      for (int p = threadIdx.x; p < 3 * b2; p += blockDim.x) {
-        const int d = p / b2, qq = p - d * b2;
+      for (int p = threadIdx.x; p < 3 * bs * bs; p += blockDim.x) {
+        const int d = p / (bs * bs), qq = p - d * bs * bs;
         int li[3];
         li[axis] = side ? bs + d : -1 - d;
         li[ua] = qq % bs;
         li[ub] = qq / bs;
         const int64_t o = point_offset(st, bs, Lin, li[0], li[1], li[2]);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) hbf[(int64_t)(c * 3) * b2 + p] = in[o + c * fs];
+        for (int c = 0; c < 4; ++c) hbf[(int64_t)(c * 3) * bs * bs + p] = in[o + c * Lin.fstride];
       }
       continue;
     }
-    // coarser neighbour.  Halo depth d sits at g = bs + d (side 1) or -1 - d
-    // (side 0); the even normal positions the three depths use start at n0:
-    // side 1 [bs-2, bs+4] (4 points), side 0 [-6, 2] (5 points).
+    // coarser neighbour.  normal ghost positions g_d = bs + d (side 1) or
+    // -1 - d (side 0); the even positions their stencils use run from n0 in
+    // steps of 2: side 1 [bs-2, bs+4] (4 points), side 0 [-6, 2] (5 points)
     const int n0 = side ? bs - 2 : -6;
     const int NN = side ? 4 : 5;
-    for (int col = threadIdx.x; col < S * S; col += blockDim.x) {
-      const int t0c = col % S, t1c = col / S;
-      T v[5][4];
-      for (int m = 0; m < NN; ++m) {
-        int li[3];
-        li[axis] = n0 + 2 * m;
-        li[ua] = 2 * t0c - 2;
-        li[ub] = 2 * t1c - 2;
-        const int64_t o = point_offset(st, bs, Lin, li[0], li[1], li[2]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) v[m][c] = in[o + c * fs];
-      }
-      for (int d = 0; d < 3; ++d) {
-        const int g = side ? bs + d : -1 - d;
-        if ((g & 1) == 0) {
-          const int m = (g - n0) / 2;
-#pragma unroll
-          for (int c = 0; c < 4; ++c) pa[c][d][col] = v[m][c];
-        } else {
-          const int m = (g - 3 - n0) / 2;  // taps g-3, g-1, g+1, g+3
-#pragma unroll
-          for (int c = 0; c < 4; ++c)
-            pa[c][d][col] = w0 * v[m][c] + w1 * v[m + 1][c] + w1 * v[m + 2][c] + w0 * v[m + 3][c];
-        }
-      }
+    const int nsrc = NN * S * S;
+    for (int p = threadIdx.x; p < nsrc; p += blockDim.x) {
+      const int m = p / (S * S), qq = p - m * S * S;
+      int li[3];
+      li[axis] = n0 + 2 * m;
+      li[ua] = 2 * (qq % S) - 2;
+      li[ub] = 2 * (qq / S) - 2;
+      soff[p] = point_offset(st, bs, Lin, li[0], li[1], li[2]);
     }
     __syncthreads();
-    for (int p = threadIdx.x; p < 3 * b2; p += blockDim.x) {
-      const int d = p / b2, qq = p - d * b2;
-      const int t0 = qq % bs, t1 = qq / bs;
-      int i0[4], i1[4];
-      T x0[4], x1[4];
-      int n0t, n1t;
-      if ((t0 & 1) == 0) {
-        i0[0] = t0 / 2 + 1;
-        x0[0] = T(1);
-        n0t = 1;
-      } else {
-        const int m = (t0 - 3) / 2 + 1;
-        i0[0] = m, i0[1] = m + 1, i0[2] = m + 2, i0[3] = m + 3;
-        x0[0] = w0, x0[1] = w1, x0[2] = w1, x0[3] = w0;
-        n0t = 4;
-      }
-      if ((t1 & 1) == 0) {
-        i1[0] = t1 / 2 + 1;
-        x1[0] = T(1);
-        n1t = 1;
-      } else {
-        const int m = (t1 - 3) / 2 + 1;
-        i1[0] = m, i1[1] = m + 1, i1[2] = m + 2, i1[3] = m + 3;
-        x1[0] = w0, x1[1] = w1, x1[2] = w1, x1[3] = w0;
-        n1t = 4;
-      }
-      T acc[4] = {T(0), T(0), T(0), T(0)};
-      for (int b = 0; b < n1t; ++b) {
-        T row[4] = {T(0), T(0), T(0), T(0)};
-        for (int e = 0; e < n0t; ++e) {
-          const int q = i1[b] * S + i0[e];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) row[c] += x0[e] * pa[c][d][q];
+    for (int c = 0; c < 4; ++c) {
+      for (int p = threadIdx.x; p < nsrc; p += blockDim.x) src[p] = in[soff[p] + c * Lin.fstride];
+      __syncthreads();
+      // along the normal: pa[d][t1'][t0']
+      for (int p = threadIdx.x; p < 3 * S * S; p += blockDim.x) {
+        const int d = p / (S * S), qq = p - d * S * S;
+        const int g = side ? bs + d : -1 - d;
+        T v;
+        if ((g & 1) == 0) {
+          v = src[((g - n0) / 2) * S * S + qq];
+        } else {
+          const int m = (g - 3 - n0) / 2;  // taps g-3, g-1, g+1, g+3
+          v = w0 * src[m * S * S + qq] + w1 * src[(m + 1) * S * S + qq] +
+              w1 * src[(m + 2) * S * S + qq] + w0 * src[(m + 3) * S * S + qq];
         }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] += x1[b] * row[c];
+        pa[p] = v;
       }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) hbf[(int64_t)(c * 3) * b2 + p] = acc[c];
+      __syncthreads();
+      // along t0: pb[d][t1'][t0], t0 in [0, bs)
+      for (int p = threadIdx.x; p < 3 * S * bs; p += blockDim.x) {
+        const int t0 = p % bs, rest = p / bs;  // rest = d * S + t1'
+        const T* row = pa + rest * S;
+        T v;
+        if ((t0 & 1) == 0) {
+          v = row[t0 / 2 + 1];
+        } else {
+          const int m = (t0 - 3) / 2 + 1;  // coarse index of t0-3
+          v = w0 * row[m] + w1 * row[m + 1] + w1 * row[m + 2] + w0 * row[m + 3];
+        }
+        pb[p] = v;
+      }
+      __syncthreads();
+      // along t1: out[d][t1][t0]
+      for (int p = threadIdx.x; p < 3 * bs * bs; p += blockDim.x) {
+        const int d = p / (bs * bs), qq = p - d * bs * bs;
+        const int t0 = qq % bs, t1 = qq / bs;
+        const T* colp = pb + d * S * bs + t0;
+        T v;
+        if ((t1 & 1) == 0) {
+          v = colp[(t1 / 2 + 1) * bs];
+        } else {
+          const int m = (t1 - 3) / 2 + 1;
+          v = w0 * colp[m * bs] + w1 * colp[(m + 1) * bs] + w1 * colp[(m + 2) * bs] +
+              w0 * colp[(m + 3) * bs];
+        }
+        hbf[(int64_t)(c * 3) * bs * bs + p] = v;
+      }
+      __syncthreads();
     }
   }
 }
@@ -581,7 +608,7 @@ __global__ __launch_bounds__(NT_GEN) void maxu_kernel(const Tab* __restrict__ ta
       const int i = q % bs, j = (q / bs) % bs, k = q / (bs * bs);
       const int64_t o = ((int64_t)(k + L.ng) * L.P + (j + L.ng)) * L.P + (i + L.ng);
       const double u = b[o], v = b[o + L.fstride], w = b[o + 2 * L.fstride];
-      m = fmax(m, u * u + v * v + w * w);
+      m = fmax(m, speed2(u, v, w));
     }
     m = wave_max(m);
     __syncthreads();
@@ -1162,15 +1189,21 @@ hipError_t launch_dt(const wacm_grid* g, const wacm_params* p, const void* U, do
                                 : dt_t(g, p, (const float*)U, dt_dev, st);
 }
 
+// stage work items of the current schedule (whole blocks or tiles of 8 rows)
+static int64_t stage_items(const wacm_grid* g) {
+  const int bs = g->d.bs;
+  return g->nb * ((g->sched.tile_rows == 8 && bs >= 24) ? bs / 8 : 1);
+}
+
+// nsteps classical RK4 steps.  With the CFL rule, the first step's dt comes
+// from a reduction over U; every later step's from the maximum the previous
+// step's last stage formed while writing U (the same value, bit for bit).
 template <typename T>
 static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev, double* dt_dev,
-                        T* U, void* work, const T* dus, int dt_mode, hipStream_t st) {
+                        T* U, void* work, const T* dus, int dt_mode, int64_t nsteps,
+                        hipStream_t st) {
   if (g->nb == 0) return hipSuccess;
   hipError_t e;
-  if (dt_mode == WACM_DT_CFL) {
-    ProfScope ps(g, 0, st);
-    if ((e = dt_t<T>(g, p, U, dt_dev, st)) != hipSuccess) return e;
-  }
   const WorkParts wp = work_parts(g);
   char* w = (char*)work;
   T* acc = (T*)(w + wp.acc);
@@ -1189,44 +1222,61 @@ static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
   const Layout Lp = pool_layout(g), Lc = compact_layout(g);
   T* ins[4] = {U, ping, pong, ping};
   T* outs[4] = {ping, pong, ping, U};
-  for (int s = 0; s < 4; ++s) {
-    a.in = ins[s];
-    a.Lin = s == 0 ? Lp : Lc;
-    a.out = outs[s];
-    a.Lout = s == 3 ? Lp : Lc;
-    if (g->n_cface > 0) {
-      ProfScope ps(g, 1, st);
-      nlface_kernel<T><<<grid_for(g->n_cface, 8), NT_GEN, 0, st>>>(
-          g->d_tab, g->d_cface, g->n_cface, a.in, a.Lin, hb, g->d.bs);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
+  const double hmin = g->d.L / (double(int64_t(1) << g->jfine) * g->d.bs);
+  const int64_t items = stage_items(g);
+  for (int64_t k = 0; k < nsteps; ++k) {
+    if (dt_mode == WACM_DT_CFL) {
+      ProfScope ps(g, 0, st);
+      if (k == 0) {
+        if ((e = dt_t<T>(g, p, U, dt_dev, st)) != hipSuccess) return e;
+      } else {
+        dt_finalize<<<1, NT_GEN, 0, st>>>(g->d_part, items, *p, hmin, dt_dev);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
     }
-    ProfScope ps(g, 2, st);
-    switch (s) {
-      case 0:
-        e = stage_dispatch<T, 1>(g->d.bs, a, g->sched, st);
-        break;
-      case 1:
-        e = stage_dispatch<T, 2>(g->d.bs, a, g->sched, st);
-        break;
-      case 2:
-        e = stage_dispatch<T, 3>(g->d.bs, a, g->sched, st);
-        break;
-      default:
-        e = stage_dispatch<T, 4>(g->d.bs, a, g->sched, st);
-        break;
+    for (int s = 0; s < 4; ++s) {
+      a.in = ins[s];
+      a.Lin = s == 0 ? Lp : Lc;
+      a.out = outs[s];
+      a.Lout = s == 3 ? Lp : Lc;
+      a.umax_part = (s == 3 && dt_mode == WACM_DT_CFL && k + 1 < nsteps) ? g->d_part : nullptr;
+      if (g->n_cface > 0) {
+        ProfScope ps(g, 1, st);
+        nlface_kernel<T><<<grid_for(g->n_cface, 8), NT_GEN, 0, st>>>(
+            g->d_tab, g->d_cface, g->n_cface, a.in, a.Lin, hb, g->d.bs);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+      ProfScope ps(g, 2, st);
+      switch (s) {
+        case 0:
+          e = stage_dispatch<T, 1>(g->d.bs, a, g->sched, st);
+          break;
+        case 1:
+          e = stage_dispatch<T, 2>(g->d.bs, a, g->sched, st);
+          break;
+        case 2:
+          e = stage_dispatch<T, 3>(g->d.bs, a, g->sched, st);
+          break;
+        default:
+          e = stage_dispatch<T, 4>(g->d.bs, a, g->sched, st);
+          break;
+      }
+      if (e != hipSuccess) return e;
     }
-    if (e != hipSuccess) return e;
+    ProfScope ps(g, 3, st);
+    advance_time<<<1, 64, 0, st>>>(t_dev, dt_dev);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  ProfScope ps(g, 3, st);
-  advance_time<<<1, 64, 0, st>>>(t_dev, dt_dev);
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t launch_rk4(const wacm_grid* g, const wacm_params* p, double* t_dev, double* dt_dev,
-                      void* U, void* work, const void* dus, int dt_mode, hipStream_t st) {
-  return g->d.dtype == WACM_F64
-             ? rk4_t(g, p, t_dev, dt_dev, (double*)U, work, (const double*)dus, dt_mode, st)
-             : rk4_t(g, p, t_dev, dt_dev, (float*)U, work, (const float*)dus, dt_mode, st);
+                      void* U, void* work, const void* dus, int dt_mode, int64_t nsteps,
+                      hipStream_t st) {
+  return g->d.dtype == WACM_F64 ? rk4_t(g, p, t_dev, dt_dev, (double*)U, work,
+                                        (const double*)dus, dt_mode, nsteps, st)
+                                : rk4_t(g, p, t_dev, dt_dev, (float*)U, work, (const float*)dus,
+                                        dt_mode, nsteps, st);
 }
 
 template <typename T>

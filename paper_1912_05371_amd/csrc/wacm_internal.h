@@ -123,7 +123,8 @@ hipError_t launch_rhs(const wacm_grid* g, const wacm_params* p, double t, const 
 hipError_t launch_dt(const wacm_grid* g, const wacm_params* p, const void* U, double* dt_dev,
                      hipStream_t st);
 hipError_t launch_rk4(const wacm_grid* g, const wacm_params* p, double* t_dev, double* dt_dev,
-                      void* U, void* work, const void* dus, int dt_mode, hipStream_t st);
+                      void* U, void* work, const void* dus, int dt_mode, int64_t nsteps,
+                      hipStream_t st);
 hipError_t launch_diag(const wacm_grid* g, const wacm_params* p, double t, const void* U,
                        const void* dus, double* out, hipStream_t st);
 hipError_t launch_threshold(const wacm_grid* g, const wacm_params* p, double t, const void* U,

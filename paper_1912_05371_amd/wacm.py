@@ -25,7 +25,7 @@ MASK_NONE, MASK_SPHERE, MASK_PLATE = 0, 1, 2
 
 EXPORTS = ["wacm_last_error", "wacm_treecode_encode", "wacm_treecode_decode", "wacm_grid_create",
            "wacm_grid_destroy", "wacm_grid_nb", "wacm_grid_info", "wacm_work_bytes",
-           "wacm_sync_ghosts", "wacm_rhs_acm", "wacm_compute_dt", "wacm_rk4_step",
+           "wacm_sync_ghosts", "wacm_rhs_acm", "wacm_compute_dt", "wacm_rk4_step", "wacm_rk4_steps",
            "wacm_diagnostics", "wacm_threshold_blocks", "wacm_adapt", "wacm_profile_enable",
            "wacm_profile_read", "wacm_adj_work_bytes", "wacm_sync_ghosts_adj",
            "wacm_rhs_acm_adj", "wacm_force_adj", "wacm_rk4_step_adj", "wacm_set_schedule",
@@ -110,6 +110,7 @@ def lib():
         L.wacm_rhs_acm.argtypes = [vp, C.POINTER(Params), dbl, vp, vp, vp, vp]
         L.wacm_compute_dt.argtypes = [vp, C.POINTER(Params), vp, vp, vp]
         L.wacm_rk4_step.argtypes = [vp, C.POINTER(Params), vp, vp, vp, vp, vp, i32, vp]
+        L.wacm_rk4_steps.argtypes = [vp, C.POINTER(Params), vp, vp, vp, vp, vp, i32, i64, vp]
         L.wacm_diagnostics.argtypes = [vp, C.POINTER(Params), dbl, vp, vp, vp, vp]
         L.wacm_threshold_blocks.argtypes = [vp, C.POINTER(Params), dbl, vp, dbl, i32, vp, vp, vp,
                                             vp]
@@ -275,6 +276,19 @@ class Grid:
         p = _p if _p is not None else make_params(params)
         _check(lib().wacm_rk4_step(self._h, C.byref(p), _ptr(t_dev), _ptr(dt_dev), _ptr(U),
                                    _ptr(work), _ptr(dus), int(dt_mode), _stream(stream)))
+
+    def rk4_steps(self, params: dict, t_dev, dt_dev, U, work, nsteps: int, dus=None,
+                  dt_mode=DT_CFL, stream=None, _p=None):
+        self._chk_pool(U)
+        self._chk_dus(dus)
+        self._chk_vec(t_dev, 1, "f64", "t_dev")
+        self._chk_vec(dt_dev, 1, "f64", "dt_dev")
+        if not work.is_cuda or work.numel() * work.element_size() < self.work_bytes():
+            raise ValueError("work buffer too small")
+        p = _p if _p is not None else make_params(params)
+        _check(lib().wacm_rk4_steps(self._h, C.byref(p), _ptr(t_dev), _ptr(dt_dev), _ptr(U),
+                                    _ptr(work), _ptr(dus), int(dt_mode), int(nsteps),
+                                    _stream(stream)))
 
     def diagnostics(self, params: dict, t: float, U, out, dus=None, stream=None):
         self._chk_pool(U)

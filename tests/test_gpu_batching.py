@@ -96,3 +96,51 @@ def test_autotuner_picks_a_candidate(octree, tmp_path, monkeypatch):
     assert best2 == best
     with pytest.raises(wacm.WacmError):
         g.set_schedule(prefetch=3)
+
+
+def _steps_vs_step(g, params, U0, n, dt_mode, dt0=0.0):
+    work = g.work()
+    A, B = U0.clone(), U0.clone()
+    tA = torch.zeros(1, dtype=torch.float64, device="cuda")
+    tB = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dA = torch.full((1,), dt0, dtype=torch.float64, device="cuda")
+    dB = dA.clone()
+    for _ in range(n):
+        g.rk4_step(params, tA, dA, A, work, dt_mode=dt_mode)
+    g.rk4_steps(params, tB, dB, B, work, n, dt_mode=dt_mode)
+    torch.cuda.synchronize()
+    return A, B, (tA.item(), dA.item()), (tB.item(), dB.item())
+
+
+@pytest.mark.parametrize("prec", [wacm.F64, wacm.F32])
+@pytest.mark.parametrize("tile_rows", [0, 8])
+def test_multi_step_call_matches_single_steps(octree, prec, tile_rows):
+    """wacm_rk4_steps(n) = n wacm_rk4_step calls bit for bit: the CFL maximum
+    fused into the last stage equals the stand-alone reduction."""
+    c = octree
+    g = wacm.Grid.from_case(c, dtype=prec)
+    g.set_schedule(tile_rows=tile_rows)
+    log(f"rk4_steps vs rk4_step, dtype {prec}, tile_rows {tile_rows}")
+    U0 = to_pool(g, c.padded())
+    A, B, ta, tb = _steps_vs_step(g, c.params, U0, 4, wacm.DT_CFL)
+    assert torch.equal(A, B)
+    assert ta == tb
+
+
+def test_multi_step_call_penalized_and_fixed_dt(orc):
+    c = cases.sphere_two_level()
+    g = wacm.Grid.from_case(c, dtype=wacm.F64)
+    U0 = to_pool(g, c.padded())
+    for mode in (wacm.DT_CFL, wacm.DT_FIXED):
+        A, B, ta, tb = _steps_vs_step(g, c.params, U0, 3, mode, dt0=1e-4)
+        assert torch.equal(A, B) and ta == tb, f"dt_mode {mode}"
+    # nsteps = 0 leaves everything untouched; a negative count is rejected
+    work = g.work()
+    U = U0.clone()
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    d = torch.full((1,), 7.0, dtype=torch.float64, device="cuda")
+    g.rk4_steps(c.params, t, d, U, work, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(U, U0) and t.item() == 0.0 and d.item() == 7.0
+    with pytest.raises(wacm.WacmError):
+        g.rk4_steps(c.params, t, d, U, work, -1)
