@@ -182,7 +182,9 @@ __device__ __forceinline__ void ntstore(T v, T* p, int nt) {
 // MODE 0: dU = rhs(U) with U's own ghost layers.  MODE s = 1..4: classical
 // RK4 stage s with registers U^n, acc and the stage inputs:
 //   s1: acc = U^n + dt/6 k1, out = U^n + dt/2 k1   (input = U^n)
-//   s2: acc += dt/3 k2,      out = U^n + dt/2 k2
+//   s2: acc += dt/3 k2,      out = U^n + dt/2 k2, U^n = (3 acc - Y2)/2 with the
+//       stage input Y2 = U^n + dt/2 k1 (one register read fewer; the recovered
+//       value, rounded differently, enters only the input of stage 3)
 //   s3: acc += dt/3 k3,      out = U^n + dt k3
 //   s4: U^n = acc + dt/6 k4
 // PEN: penalization/sponge terms present.  PREF: load the epilogue operands
@@ -193,7 +195,7 @@ __device__ __forceinline__ void ntstore(T v, T* p, int nt) {
 // double-buffered LDS slab, the next plane's loads issued before the barrier.
 // Rows between tiles of one block are read from the block itself.
 template <typename T, int BS, int TY, int MODE, bool PEN, bool PREF>
-__global__ __launch_bounds__(BS* TY) __attribute__((amdgpu_waves_per_eu(TY == BS ? 1 : 3)))
+__global__ __launch_bounds__(BS* TY) __attribute__((amdgpu_waves_per_eu(TY == BS ? 1 : (sizeof(T) == 8 ? 2 : 3))))
 void stage_kernel(StageArgs<T> a) {
   constexpr int H = 3, W = BS + 2 * H, WY = TY + 2 * H, NT = BS * TY;
   constexpr int NTY = BS / TY, NH = 6 * TY + 6 * BS;
@@ -326,13 +328,13 @@ void stage_kernel(StageArgs<T> a) {
       // epilogue operands of this point, loaded early if PREF
       T unv[4], acv[4];
       if (PREF) {
-        if (MODE == 2 || MODE == 3) {
+        if (MODE == 3) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             unv[c] = ntload(unb + c * ufs + z * uzs, a.nt);
             acv[c] = ntload(accb + c * afs + z * azs, a.nt);
           }
-        } else if (MODE == 4) {
+        } else if (MODE == 2 || MODE == 4) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) acv[c] = ntload(accb + c * afs + z * azs, a.nt);
         }
@@ -403,13 +405,13 @@ void stage_kernel(StageArgs<T> a) {
       }
 
       if (!PREF) {
-        if (MODE == 2 || MODE == 3) {
+        if (MODE == 3) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             unv[c] = ntload(unb + c * ufs + z * uzs, a.nt);
             acv[c] = ntload(accb + c * afs + z * azs, a.nt);
           }
-        } else if (MODE == 4) {
+        } else if (MODE == 2 || MODE == 4) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) acv[c] = ntload(accb + c * afs + z * azs, a.nt);
         }
@@ -438,7 +440,10 @@ void stage_kernel(StageArgs<T> a) {
         const T val[4] = {u, v, w, pr};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const T u0 = MODE == 1 ? val[c] : unv[c];
+          // stage 2 recovers U^n from its input Y2 = U^n + dt/2 k1 and the
+          // accumulator U^n + dt/6 k1 instead of reading it
+          const T u0 = MODE == 1 ? val[c]
+                                 : (MODE == 2 ? T(1.5) * acv[c] - T(0.5) * val[c] : unv[c]);
           const T ac = MODE == 1 ? u0 : acv[c];
           ntstore(ac + fA * r[c], accb + c * afs + z * azs, a.nt);
           outb[c * ofs + z * ozs] = u0 + fB * r[c];
