@@ -129,6 +129,36 @@ def case_seed(case):
     return case.extra.get("seed", 12345)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_traffic_random_octree_bs24.md")
+
+
+def counter_traffic(dtype: str, schedule: dict):
+    """HBM bytes per stage-kernel launch (FETCH_SIZE + WRITE_SIZE, scaled by
+    the copy probe) from the committed counter summary, if it was taken with
+    the current stage-kernel sources and this schedule; else None."""
+    from paper_1912_05371_amd import profile_summary
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    key = ",".join(f"{k}={schedule[k]}" for k in sorted(schedule))
+    sha, found = None, None
+    inside = False
+    for ln in lines:
+        f = ln.split()
+        if ln.strip() == "traffic-data":
+            inside = True
+        elif ln.strip() == "end-traffic-data":
+            inside = False
+        elif inside and f and f[0] == "source_sha1":
+            sha = f[1]
+        elif inside and len(f) == 6 and f[0] == dtype and f[1] == key:
+            found = float(f[3]) + float(f[5])
+    if found is None or sha != profile_summary.stage_source_sha1():
+        return None
+    return found
+
+
 def roofline(res, npts: int, es: int):
     stage_ms = res["kernel_ms"][2] / max(res["kernel_launches"][2], 1)
     bytes_per_launch = 15 * es * npts  # mean over the 4 stages (12, 16, 20, 12 values)
@@ -140,7 +170,7 @@ def roofline(res, npts: int, es: int):
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": None,  # filled from the counter summary when it applies
         "kernel": "stage_kernel (fused rhs + RK4 stage)",
         "kernel_avg_ms": round(stage_ms, 4),
         "bytes_per_launch": bytes_per_launch,
@@ -256,6 +286,12 @@ def main():
                     sched)
         r["value"] = npts * 4 / (r["ms_per_step"] * 1e-3)
         r["roofline"] = roofline(r, npts, es)
+        tb = counter_traffic(name, r["schedule"])
+        if tb is not None:
+            # bytes per launch, like bytes_per_launch
+            r["roofline"]["traffic"] = int(round(tb))
+            r["roofline"]["traffic_over_algorithmic"] = round(
+                tb / r["roofline"]["bytes_per_launch"], 3)
         log(f"  {name}: {r['ms_per_step']:.3f} ms/step, {r['value']:.4e} updates/s, stage kernel "
             f"{r['roofline']['kernel_avg_ms']:.3f} ms = {r['roofline']['achieved']:.0f} GB/s "
             f"({100 * r['roofline']['frac']:.1f} %), graph {r.get('graph_ms_per_step', 0):.3f} "

@@ -122,14 +122,17 @@ struct BlockIter {
 // ptr[c fs + d sd + t0 s0 + t1 s1].  Same-level neighbours are read in place
 // (their interior next to the face); faces next to a coarser or finer leaf
 // point into the halo buffer filled by nlface_kernel; the rhs-only mode reads
-// the block's own synchronised ghost layers.
+// the block's own synchronised ghost layers.  With an x-split input the
+// x faces stay affine (the neighbour's side columns); for the y and z faces
+// mode = 1 and ptr is the neighbour's origin: each thread addresses its own
+// column with xsplit_offset.
 template <typename T>
 struct FaceDesc {
   const T* ptr;
-  int32_t fs, sd, s0, s1;
+  int32_t fs, sd, s0, s1, mode;
 };
 
-template <typename T, int BS, bool GHOSTS>
+template <typename T, int BS, bool GHOSTS, bool XIN>
 __device__ __forceinline__ FaceDesc<T> face_desc(const Tab& tb, const StageArgs<T>& a, int f) {
   const int axis = f >> 1, side = f & 1;
   const Layout& L = a.Lin;
@@ -138,6 +141,7 @@ __device__ __forceinline__ FaceDesc<T> face_desc(const Tab& tb, const StageArgs<
   const int slot = tb.meta[0];
   const int64_t org = ((int64_t)L.ng * L.P + L.ng) * L.P + L.ng;  // local (0,0,0)
   FaceDesc<T> fd;
+  fd.mode = 0;
   if (GHOSTS) {
     fd.ptr = a.in + (int64_t)slot * L.bstride + org + (int64_t)(side ? BS : -1) * sa;
     fd.fs = (int)L.fstride;
@@ -148,7 +152,22 @@ __device__ __forceinline__ FaceDesc<T> face_desc(const Tab& tb, const StageArgs<
   }
   const int r = (axis == 0 ? 2 * side : 1) + 3 * (axis == 1 ? 2 * side : 1) +
                 9 * (axis == 2 ? 2 * side : 1);
-  if (tb.kind[r] == 0) {
+  if (tb.kind[r] == 0 && XIN) {
+    const T* nb = a.in + (int64_t)tb.slot[r][0] * L.bstride;
+    fd.fs = (int)L.fstride;
+    if (axis == 0) {
+      // side 0 reads the neighbour's last columns from the top, side 1 its
+      // first ones
+      fd.ptr = nb + (side ? BS * BS * (BS - 2 * XS_H) : BS * BS * (BS - XS_H) + XS_H - 1);
+      fd.sd = side ? 1 : -1;
+      fd.s0 = XS_H;
+      fd.s1 = XS_H * BS;
+    } else {
+      fd.ptr = nb;
+      fd.sd = fd.s0 = fd.s1 = 0;
+      fd.mode = 1;
+    }
+  } else if (tb.kind[r] == 0) {
     fd.ptr = a.in + (int64_t)tb.slot[r][0] * L.bstride + org + (int64_t)(side ? 0 : BS - 1) * sa;
     fd.fs = (int)L.fstride;
     fd.sd = side ? sa : -sa;
@@ -201,6 +220,9 @@ void stage_kernel(StageArgs<T> a) {
   constexpr int NTY = BS / TY, NH = 6 * TY + 6 * BS;
   static_assert(NH <= NT || TY == BS, "halo points per plane exceed the threads");
   constexpr bool GH = (MODE == 0);
+  // the stage registers between stages are x-split (stage 1 reads and stage
+  // 4 writes the pool)
+  constexpr bool XIN = MODE >= 2, XOUT = MODE >= 1 && MODE <= 3;
   __shared__ T slab[2][4][W * WY];
   __shared__ FaceDesc<T> fds[6];
   __shared__ int32_t meta[5];
@@ -216,6 +238,9 @@ void stage_kernel(StageArgs<T> a) {
   }
   const T nu = T(a.p.nu), c0sq = T(a.p.c0 * a.p.c0), cg = T(a.p.c_gamma);
   const T fA = T(MODE == 1 ? dt / 6.0 : (MODE == 4 ? dt / 6.0 : dt / 3.0));
+  // the stage time and what of the mask depends on it alone
+  const double ts = tc + (MODE == 2 || MODE == 3 ? 0.5 * dt : (MODE == 4 ? dt : 0.0));
+  const MaskTime mt = PEN && a.p.mask ? mask_time(a.p, ts) : MaskTime{1.0, 0.0, 0.0};
   const T fB = T(MODE == 3 ? dt : 0.5 * dt);
   const int fin = (int)a.Lin.fstride, Pi = a.Lin.P;
   const int cidx = (yl + H) * W + (x + H);
@@ -241,32 +266,44 @@ void stage_kernel(StageArgs<T> a) {
       hli = (hyl + H) * W + (hs + H);
     }
   }
-  const int zs = Pi * Pi;
+  // plane steps of this thread's column
+  const int zs = XIN ? xsplit_zstride(BS, x) : Pi * Pi;
   const int azs = a.Lacc.P * a.Lacc.P, afs = (int)a.Lacc.fstride;
   const int uzs = a.Lun.P * a.Lun.P, ufs = (int)a.Lun.fstride;
-  const int ozs = a.Lout.P * a.Lout.P, ofs = (int)a.Lout.fstride;
+  const int ozs = XOUT ? xsplit_zstride(BS, x) : a.Lout.P * a.Lout.P;
+  const int ofs = (int)a.Lout.fstride;
 
   for (BlockIter it(a.nb * NTY, a.xcd_map); it.ib < it.end; it.ib += it.step) {
     const int64_t ibk = it.ib / NTY;
     const int y0 = (int)(it.ib - ibk * NTY) * TY;
     const int y = y0 + yl;
     lds_barrier();
-    if (tid < 6) fds[tid] = face_desc<T, BS, GH>(a.tab[ibk], a, tid);
+    if (tid < 6) fds[tid] = face_desc<T, BS, GH, XIN>(a.tab[ibk], a, tid);
     if (tid < 5) meta[tid] = a.tab[ibk].meta[tid];
     lds_barrier();
     // offsets of this thread's column in the input, accumulator and U^n
-    const int col = (a.Lin.ng * Pi + (y + a.Lin.ng)) * Pi + (x + a.Lin.ng);
+    const int col = XIN ? xsplit_offset(BS, x, y, 0)
+                        : (a.Lin.ng * Pi + (y + a.Lin.ng)) * Pi + (x + a.Lin.ng);
     const int acol = (a.Lacc.ng * a.Lacc.P + (y + a.Lacc.ng)) * a.Lacc.P + (x + a.Lacc.ng);
     const int ucol = (a.Lun.ng * a.Lun.P + (y + a.Lun.ng)) * a.Lun.P + (x + a.Lun.ng);
-    const int ocol = (a.Lout.ng * a.Lout.P + (y + a.Lout.ng)) * a.Lout.P + (x + a.Lout.ng);
-    const int slot = meta[0], J = meta[1];
+    const int ocol = XOUT ? xsplit_offset(BS, x, y, 0)
+                          : (a.Lout.ng * a.Lout.P + (y + a.Lout.ng)) * a.Lout.P + (x + a.Lout.ng);
+    // uniform over the workgroup: scalar registers
+    const int slot = __builtin_amdgcn_readfirstlane(meta[0]);
+    const int J = __builtin_amdgcn_readfirstlane(meta[1]);
     const double hdd = a.L / (double(int64_t(1) << J) * BS);
     const T ih = T(1.0 / hdd), ih2 = T(1.0 / (hdd * hdd));
     const T* __restrict__ inb = a.in + (int64_t)slot * a.Lin.bstride + col;
     T* accb = a.acc + (int64_t)slot * a.Lacc.bstride + acol;
     T* unb = a.un + (int64_t)slot * a.Lun.bstride + ucol;
     T* outb = a.out + (int64_t)slot * a.Lout.bstride + ocol;
-    const FaceDesc<T> fzl = fds[4], fzh = fds[5];
+    // field c of this thread's column at depth d below (f = 4) or above
+    // (f = 5) the block; the descriptor is re-read from LDS at each use
+    auto zface = [&](int f, int d, int c) -> T {
+      const FaceDesc<T>& fz = fds[f];
+      if (XIN && fz.mode == 1) return fz.ptr[c * fin + col + (f == 4 ? BS - 1 - d : d) * zs];
+      return fz.ptr[c * fz.fs + d * fz.sd + x * fz.s0 + y * fz.s1];
+    };
     // this thread's halo point as an affine map in z: hp[c hfs + z hzs]
     const T* hp = nullptr;
     int hfs = 0, hzs = 0;
@@ -280,27 +317,54 @@ void stage_kernel(StageArgs<T> a) {
         const int hy = hkind == 2 ? y0 - 1 - hd : y0 + TY + hd;
         if (hy < 0 || hy >= BS) {
           const FaceDesc<T>& fh = fds[hy < 0 ? 2 : 3];
-          hp = fh.ptr + (hy < 0 ? -1 - hy : hy - BS) * fh.sd + hs * fh.s0;
-          hfs = fh.fs;
-          hzs = fh.s1;
+          if (XIN && fh.mode == 1) {
+            hp = fh.ptr + xsplit_offset(BS, hs, hy < 0 ? BS + hy : hy - BS, 0);
+            hfs = fin;
+            hzs = xsplit_zstride(BS, hs);
+          } else {
+            hp = fh.ptr + (hy < 0 ? -1 - hy : hy - BS) * fh.sd + hs * fh.s0;
+            hfs = fh.fs;
+            hzs = fh.s1;
+          }
+        } else if (XIN) {
+          hp = a.in + (int64_t)slot * a.Lin.bstride + xsplit_offset(BS, hs, hy, 0);
+          hfs = fin;
+          hzs = xsplit_zstride(BS, hs);
         } else {
           hp = a.in + (int64_t)slot * a.Lin.bstride +
                (a.Lin.ng * Pi + (hy + a.Lin.ng)) * Pi + (hs + a.Lin.ng);
           hfs = fin;
-          hzs = zs;
+          hzs = Pi * Pi;
         }
       }
     }
 
     double m2 = 0.0;  // stage 4: max |u|^2 of this thread's new points
+    // mask, solid velocity and sponge of this thread's point of the next
+    // plane, evaluated at the end of the previous plane where fewer values
+    // are live
+    T pchi = T(0), psp = T(0), pus[3] = {T(0), T(0), T(0)};
+    auto pen_at = [&](int zz) {
+      const double xg = (double)(meta[2] * BS + x) * hdd, yg = (double)(meta[3] * BS + y) * hdd,
+                   zg = (double)(meta[4] * BS + zz) * hdd;
+      if (a.p.mask) {
+        double cd, u3[3];
+        mask_point(a.p, mt, xg, yg, zg, cd, u3);
+        pchi = T(cd);
+        pus[0] = T(u3[0]);
+        pus[1] = T(u3[1]);
+        pus[2] = T(u3[2]);
+      }
+      if (a.p.sponge) psp = T(sponge_eval(a.p, a.L, xg, yg, zg));
+    };
+    if (PEN) pen_at(0);
     T q[4][7];
 #pragma unroll
     for (int mm = 0; mm < 7; ++mm) {
       const int z = mm - 3;
 #pragma unroll
       for (int c = 0; c < 4; ++c)
-        q[c][mm] = z < 0 ? fzl.ptr[c * fzl.fs + (-1 - z) * fzl.sd + x * fzl.s0 + y * fzl.s1]
-                         : inb[c * fin + z * zs];
+        q[c][mm] = z < 0 ? zface(4, -1 - z, c) : inb[c * fin + z * zs];
     }
     // plane 0 into slab 0
 #pragma unroll
@@ -318,8 +382,7 @@ void stage_kernel(StageArgs<T> a) {
         const int zz = z + 4;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-          nq[c] = zz < BS ? inb[c * fin + zz * zs]
-                          : fzh.ptr[c * fzh.fs + (zz - BS) * fzh.sd + x * fzh.s0 + y * fzh.s1];
+          nq[c] = zz < BS ? inb[c * fin + zz * zs] : zface(5, zz - BS, c);
         if (hthr) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) hnx[c] = hp[c * hfs + (z + 1) * hzs];
@@ -375,19 +438,7 @@ void stage_kernel(StageArgs<T> a) {
       r[3] = -c0sq * div - cg * pr;
       if (PEN) {
         const wacm_params& p = a.p;
-        const double ts = tc + (MODE == 2 || MODE == 3 ? 0.5 * dt : (MODE == 4 ? dt : 0.0));
-        T chi = T(0), sp = T(0), us[3] = {T(0), T(0), T(0)};
-        const double xg = (double)(meta[2] * BS + x) * hdd, yg = (double)(meta[3] * BS + y) * hdd,
-                     zg = (double)(meta[4] * BS + z) * hdd;
-        if (p.mask) {
-          double cd, u3[3];
-          mask_eval(p, ts, xg, yg, zg, cd, u3);
-          chi = T(cd);
-          us[0] = T(u3[0]);
-          us[1] = T(u3[1]);
-          us[2] = T(u3[2]);
-        }
-        if (p.sponge) sp = T(sponge_eval(p, a.L, xg, yg, zg));
+        T chi = pchi, sp = psp, us[3] = {pus[0], pus[1], pus[2]};
         if (a.dus) {
           const T* du = a.dus + (int64_t)slot * 3 * BS * BS * BS + (z * BS + y) * BS + x;
           us[0] += du[0];
@@ -465,6 +516,7 @@ void stage_kernel(StageArgs<T> a) {
           for (int mm = 0; mm < 6; ++mm) q[c][mm] = q[c][mm + 1];
           q[c][6] = nq[c];
         }
+        if (PEN) pen_at(z + 1);
       }
     }
     if (MODE == 4 && a.umax_part) {
@@ -1037,6 +1089,13 @@ static Layout compact_layout(const wacm_grid* g) {
   return L;
 }
 
+// the stage inputs between stages: compact, x-split
+static Layout split_layout(const wacm_grid* g) {
+  Layout L = compact_layout(g);
+  L.xs = 1;
+  return L;
+}
+
 static unsigned grid_for(int64_t n, int per_cu) {
   int64_t cap = (int64_t)num_cus() * per_cu;
   return (unsigned)(n < cap ? (n > 0 ? n : 1) : cap);
@@ -1224,7 +1283,7 @@ static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
   a.dus = dus;
   a.t_dev = t_dev;
   a.dt_dev = dt_dev;
-  const Layout Lp = pool_layout(g), Lc = compact_layout(g);
+  const Layout Lp = pool_layout(g), Ls = split_layout(g);
   T* ins[4] = {U, ping, pong, ping};
   T* outs[4] = {ping, pong, ping, U};
   const double hmin = g->d.L / (double(int64_t(1) << g->jfine) * g->d.bs);
@@ -1241,9 +1300,9 @@ static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
     }
     for (int s = 0; s < 4; ++s) {
       a.in = ins[s];
-      a.Lin = s == 0 ? Lp : Lc;
+      a.Lin = s == 0 ? Lp : Ls;
       a.out = outs[s];
-      a.Lout = s == 3 ? Lp : Lc;
+      a.Lout = s == 3 ? Lp : Ls;
       a.umax_part = (s == 3 && dt_mode == WACM_DT_CFL && k + 1 < nsteps) ? g->d_part : nullptr;
       if (g->n_cface > 0) {
         ProfScope ps(g, 1, st);

@@ -62,6 +62,7 @@ WACM_HD inline int64_t point_offset(const Tab& t, int bs, const Layout& L, int i
 #if defined(WACM_HOST_CHECK) && !defined(__HIP_DEVICE_COMPILE__)
   wacm_host_check(slot, li, lj, lk, bs);
 #endif
+  if (L.xs) return (int64_t)slot * L.bstride + xsplit_offset(bs, li, lj, lk);
   return (int64_t)slot * L.bstride +
          ((int64_t)(lk + L.ng) * L.P + (lj + L.ng)) * L.P + (li + L.ng);
 }
@@ -160,9 +161,28 @@ WACM_HD inline void ghost_taps(const Tab& t, int bs, const Layout& L, int i, int
 
 // Mask chi and solid velocity u_s at a point and time (Sec. 2.2): a sphere
 // with a tanh layer, or a thin box pitching about an axis through x_le
-// parallel to y with alpha(t) = amp sin(2 pi freq t + phase).
-WACM_HD inline void mask_eval(const wacm_params& p, double t, double x, double y,
-                                          double z, double& chi, double us[3]) {
+// parallel to y with alpha(t) = amp sin(2 pi freq t + phase).  mask_time holds
+// what depends on t only (the pitch angle's cosine and sine and its rate), so
+// that a kernel evaluates it once; mask_eval = mask_point(mask_time(t)).
+struct MaskTime {
+  double ca, sa, ad;
+};
+
+WACM_HD inline MaskTime mask_time(const wacm_params& p, double t) {
+  MaskTime m{1.0, 0.0, 0.0};
+  if (p.mask == WACM_MASK_PLATE) {
+    const double twopi = 6.283185307179586476925286766559;
+    const double ph = twopi * p.freq * t + p.phase;
+    const double al = p.amp * sin(ph);
+    m.ad = p.amp * twopi * p.freq * cos(ph);
+    m.ca = cos(al);
+    m.sa = sin(al);
+  }
+  return m;
+}
+
+WACM_HD inline void mask_point(const wacm_params& p, const MaskTime& m, double x, double y,
+                               double z, double& chi, double us[3]) {
   us[0] = us[1] = us[2] = 0.0;
   chi = 0.0;
   if (p.mask == WACM_MASK_SPHERE) {
@@ -170,20 +190,20 @@ WACM_HD inline void mask_eval(const wacm_params& p, double t, double x, double y
     const double d = sqrt(dx * dx + dy * dy + dz * dz) - p.sph_r;
     chi = 0.5 * (1.0 - tanh(d / p.w));
   } else if (p.mask == WACM_MASK_PLATE) {
-    const double twopi = 6.283185307179586476925286766559;
-    const double ph = twopi * p.freq * t + p.phase;
-    const double al = p.amp * sin(ph);
-    const double ad = p.amp * twopi * p.freq * cos(ph);
     const double rx = x - p.x_le[0], ry = y - p.x_le[1], rz = z - p.x_le[2];
-    const double ca = cos(al), sa = sin(al);
-    const double b0 = ca * rx - sa * rz, b1 = ry, b2 = sa * rx + ca * rz;  // R_y(al)^T r
+    const double b0 = m.ca * rx - m.sa * rz, b1 = ry, b2 = m.sa * rx + m.ca * rz;  // R^T r
     chi = 0.5 * (tanh((b0 - p.lo[0]) / p.w) - tanh((b0 - p.hi[0]) / p.w));
     chi *= 0.5 * (tanh((b1 - p.lo[1]) / p.w) - tanh((b1 - p.hi[1]) / p.w));
     chi *= 0.5 * (tanh((b2 - p.lo[2]) / p.w) - tanh((b2 - p.hi[2]) / p.w));
-    us[0] = ad * rz;  // alpha_dot e_y x r
-    us[2] = -ad * rx;
+    us[0] = m.ad * rz;  // alpha_dot e_y x r
+    us[2] = -m.ad * rx;
   }
   if (p.clip && chi < 1e-8) chi = 0.0;
+}
+
+WACM_HD inline void mask_eval(const wacm_params& p, double t, double x, double y,
+                                          double z, double& chi, double us[3]) {
+  mask_point(p, mask_time(p, t), x, y, z, chi, us);
 }
 
 // Plate mask with its derivative in the pitch angle, and the solid velocity

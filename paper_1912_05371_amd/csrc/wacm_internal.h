@@ -35,7 +35,26 @@ struct Layout {
   int64_t fstride;  // elements per field
   int32_t P;        // edge of the stored cube
   int32_t ng;       // ghost layers stored
+  int32_t xs = 0;   // 1: compact x-split order (xsplit_offset), ng = 0
 };
+
+// Compact x-split order of a block's field (bs^3 values): the XS_H columns
+// next to each x face are stored apart from the middle columns, each part
+// [z][y][x] with x fastest.  A neighbour's x-face halo (the 3 columns next to
+// the face) is then read from a run of short rows instead of a few values per
+// cache line.  XS_H = 4 rather than 3 keeps every part's rows of a tile of 8
+// rows on whole 128-byte lines (FP64), so tiles never share a line.
+constexpr int XS_H = 4;
+__host__ __device__ inline int xsplit_offset(int bs, int i, int j, int k) {
+  const int row = k * bs + j;
+  if (i < XS_H) return bs * bs * (bs - 2 * XS_H) + row * XS_H + i;
+  if (i >= bs - XS_H) return bs * bs * (bs - XS_H) + row * XS_H + (i - (bs - XS_H));
+  return row * (bs - 2 * XS_H) + (i - XS_H);
+}
+// step of xsplit_offset from plane k to k+1 of column i
+__host__ __device__ inline int xsplit_zstride(int bs, int i) {
+  return (i < XS_H || i >= bs - XS_H ? XS_H : bs - 2 * XS_H) * bs;
+}
 
 struct Leaf {
   int32_t J;

@@ -32,7 +32,26 @@ void wacm_host_check(int slot, int li, int lj, int lk, int bs) {
 
 using namespace wacm;
 
+// The x-split order of the stage registers must be a bijection of [0, bs)^3
+// onto [0, bs^3), affine in z along every column with xsplit_zstride.
+static bool xsplit_ok(int bs) {
+  std::vector<int> hit(bs * bs * bs, 0);
+  for (int k = 0; k < bs; ++k)
+    for (int j = 0; j < bs; ++j)
+      for (int i = 0; i < bs; ++i) {
+        const int o = xsplit_offset(bs, i, j, k);
+        if (o < 0 || o >= bs * bs * bs || hit[o]++) return false;
+        if (o != xsplit_offset(bs, i, j, 0) + k * xsplit_zstride(bs, i)) return false;
+      }
+  return true;
+}
+
 int main(int argc, char** argv) {
+  for (int bs : {16, 24, 32})
+    if (!xsplit_ok(bs)) {
+      std::fprintf(stderr, "x-split order of bs %d is not a bijection\n", bs);
+      return 7;
+    }
   if (argc != 4) return 2;
   FILE* f = std::fopen(argv[1], "r");
   if (!f) return 2;

@@ -65,12 +65,24 @@ def test_graph_replay_matches_eager(octree, prec):
 
 
 def test_schedules_give_identical_results(octree):
-    c = octree
-    g = wacm.Grid.from_case(c, dtype=wacm.F64)
+    _schedules_identical(octree, autotune.CANDIDATES)
+
+
+@pytest.mark.parametrize("prec", [wacm.F64, wacm.F32])
+def test_schedules_identical_bs32(prec):
+    c = cases.random_octree(bs=32, ng=4, target=100, j0=1, jmax=3, seed=11)
+    cands = [dict(tile_rows=t, prefetch=p, wg_per_cu=w) for t in (0, 8) for p in (0, 1)
+             for w in (0, 2)]
+    _schedules_identical(c, cands, prec)
+
+
+def _schedules_identical(c, candidates, prec=wacm.F64):
+    log(f"schedules bs {c.bs}, {c.nb} blocks, dtype {prec}")
+    g = wacm.Grid.from_case(c, dtype=prec)
     U0 = to_pool(g, c.padded())
     work = g.work()
     outs = []
-    for cand in autotune.CANDIDATES:
+    for cand in candidates:
         g.set_schedule(**cand)
         U = U0.clone()
         t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")

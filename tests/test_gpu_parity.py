@@ -30,6 +30,14 @@ CASES = {
     "taylor_green": cases.taylor_green,
     "sphere_two_level": cases.sphere_two_level,
     "octree_bs24": small_octree,
+    # the largest block size and the smallest ghost width the ABI accepts
+    "octree_bs32": lambda: cases.random_octree(bs=32, ng=4, target=100, j0=1, jmax=3, seed=11),
+    "octree_bs16_ng3": lambda: cases.random_octree(bs=16, ng=3, target=300, j0=2, jmax=4,
+                                                   seed=5),
+    # degenerate periodic grids: one block that is its own neighbour on every
+    # side, and 8 blocks whose two x (y, z) neighbours are the same block
+    "single_block": lambda: cases.random_octree(bs=16, ng=4, target=1, j0=0, jmax=0, seed=3),
+    "level1_uniform": lambda: cases.random_octree(bs=16, ng=4, target=1, j0=1, jmax=1, seed=3),
 }
 _cache = {}
 
