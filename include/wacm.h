@@ -162,8 +162,10 @@ int wacm_grid_info(const wacm_grid* grid, int64_t* slots, uint64_t* treecodes, i
 int wacm_set_schedule(wacm_grid* grid, const wacm_schedule* s);
 int wacm_get_schedule(const wacm_grid* grid, wacm_schedule* s);
 
-/* Bytes of the `work` buffer wacm_rk4_step needs (3 RK registers for every
- * pool slot), 256-byte aligned by the caller. */
+/* Bytes of the `work` buffer wacm_rk4_step / wacm_rk4_steps need (4 compact
+ * registers of bs^3 points x 4 fields for every pool slot: accumulator, two
+ * stage inputs and the state between the steps of one wacm_rk4_steps call;
+ * plus the depth-3 halo of the 6 faces), 256-byte aligned by the caller. */
 size_t wacm_work_bytes(const wacm_grid* grid);
 
 /*

@@ -132,8 +132,9 @@ struct FaceDesc {
   int32_t fs, sd, s0, s1, mode;
 };
 
-template <typename T, int BS, bool GHOSTS, bool XIN>
-__device__ __forceinline__ FaceDesc<T> face_desc(const Tab& tb, const StageArgs<T>& a, int f) {
+template <typename T, int BS, bool GHOSTS>
+__device__ __forceinline__ FaceDesc<T> face_desc(const Tab& tb, const StageArgs<T>& a, int f,
+                                                 bool xin) {
   const int axis = f >> 1, side = f & 1;
   const Layout& L = a.Lin;
   const int sx[3] = {1, L.P, L.P * L.P};
@@ -152,7 +153,7 @@ __device__ __forceinline__ FaceDesc<T> face_desc(const Tab& tb, const StageArgs<
   }
   const int r = (axis == 0 ? 2 * side : 1) + 3 * (axis == 1 ? 2 * side : 1) +
                 9 * (axis == 2 ? 2 * side : 1);
-  if (tb.kind[r] == 0 && XIN) {
+  if (tb.kind[r] == 0 && xin) {
     const T* nb = a.in + (int64_t)tb.slot[r][0] * L.bstride;
     fd.fs = (int)L.fstride;
     if (axis == 0) {
@@ -220,9 +221,11 @@ void stage_kernel(StageArgs<T> a) {
   constexpr int NTY = BS / TY, NH = 6 * TY + 6 * BS;
   static_assert(NH <= NT || TY == BS, "halo points per plane exceed the threads");
   constexpr bool GH = (MODE == 0);
-  // the stage registers between stages are x-split (stage 1 reads and stage
-  // 4 writes the pool)
-  constexpr bool XIN = MODE >= 2, XOUT = MODE >= 1 && MODE <= 3;
+  // the stage registers between stages are x-split; U^n is the pool or, from
+  // the second step of a multi-step call on, an x-split register too
+  const bool xin = MODE >= 2 || (MODE == 1 && a.Lin.xs != 0);
+  const bool xun = (MODE == 3 || MODE == 4) && a.Lun.xs != 0;
+  constexpr bool XOUT = MODE >= 1 && MODE <= 3;
   __shared__ T slab[2][4][W * WY];
   __shared__ FaceDesc<T> fds[6];
   __shared__ int32_t meta[5];
@@ -267,9 +270,9 @@ void stage_kernel(StageArgs<T> a) {
     }
   }
   // plane steps of this thread's column
-  const int zs = XIN ? xsplit_zstride(BS, x) : Pi * Pi;
+  const int zs = xin ? xsplit_zstride(BS, x) : Pi * Pi;
   const int azs = a.Lacc.P * a.Lacc.P, afs = (int)a.Lacc.fstride;
-  const int uzs = a.Lun.P * a.Lun.P, ufs = (int)a.Lun.fstride;
+  const int uzs = xun ? xsplit_zstride(BS, x) : a.Lun.P * a.Lun.P, ufs = (int)a.Lun.fstride;
   const int ozs = XOUT ? xsplit_zstride(BS, x) : a.Lout.P * a.Lout.P;
   const int ofs = (int)a.Lout.fstride;
 
@@ -278,14 +281,15 @@ void stage_kernel(StageArgs<T> a) {
     const int y0 = (int)(it.ib - ibk * NTY) * TY;
     const int y = y0 + yl;
     lds_barrier();
-    if (tid < 6) fds[tid] = face_desc<T, BS, GH, XIN>(a.tab[ibk], a, tid);
+    if (tid < 6) fds[tid] = face_desc<T, BS, GH>(a.tab[ibk], a, tid, xin);
     if (tid < 5) meta[tid] = a.tab[ibk].meta[tid];
     lds_barrier();
     // offsets of this thread's column in the input, accumulator and U^n
-    const int col = XIN ? xsplit_offset(BS, x, y, 0)
+    const int col = xin ? xsplit_offset(BS, x, y, 0)
                         : (a.Lin.ng * Pi + (y + a.Lin.ng)) * Pi + (x + a.Lin.ng);
     const int acol = (a.Lacc.ng * a.Lacc.P + (y + a.Lacc.ng)) * a.Lacc.P + (x + a.Lacc.ng);
-    const int ucol = (a.Lun.ng * a.Lun.P + (y + a.Lun.ng)) * a.Lun.P + (x + a.Lun.ng);
+    const int ucol = xun ? xsplit_offset(BS, x, y, 0)
+                         : (a.Lun.ng * a.Lun.P + (y + a.Lun.ng)) * a.Lun.P + (x + a.Lun.ng);
     const int ocol = XOUT ? xsplit_offset(BS, x, y, 0)
                           : (a.Lout.ng * a.Lout.P + (y + a.Lout.ng)) * a.Lout.P + (x + a.Lout.ng);
     // uniform over the workgroup: scalar registers
@@ -301,7 +305,7 @@ void stage_kernel(StageArgs<T> a) {
     // (f = 5) the block; the descriptor is re-read from LDS at each use
     auto zface = [&](int f, int d, int c) -> T {
       const FaceDesc<T>& fz = fds[f];
-      if (XIN && fz.mode == 1) return fz.ptr[c * fin + col + (f == 4 ? BS - 1 - d : d) * zs];
+      if (xin && fz.mode == 1) return fz.ptr[c * fin + col + (f == 4 ? BS - 1 - d : d) * zs];
       return fz.ptr[c * fz.fs + d * fz.sd + x * fz.s0 + y * fz.s1];
     };
     // this thread's halo point as an affine map in z: hp[c hfs + z hzs]
@@ -317,7 +321,7 @@ void stage_kernel(StageArgs<T> a) {
         const int hy = hkind == 2 ? y0 - 1 - hd : y0 + TY + hd;
         if (hy < 0 || hy >= BS) {
           const FaceDesc<T>& fh = fds[hy < 0 ? 2 : 3];
-          if (XIN && fh.mode == 1) {
+          if (xin && fh.mode == 1) {
             hp = fh.ptr + xsplit_offset(BS, hs, hy < 0 ? BS + hy : hy - BS, 0);
             hfs = fin;
             hzs = xsplit_zstride(BS, hs);
@@ -326,7 +330,7 @@ void stage_kernel(StageArgs<T> a) {
             hfs = fh.fs;
             hzs = fh.s1;
           }
-        } else if (XIN) {
+        } else if (xin) {
           hp = a.in + (int64_t)slot * a.Lin.bstride + xsplit_offset(BS, hs, hy, 0);
           hfs = fin;
           hzs = xsplit_zstride(BS, hs);
@@ -481,7 +485,7 @@ void stage_kernel(StageArgs<T> a) {
         // line of the padded row is written whole: rows of partly written lines
         // store far slower.  Ghost layers carry no state between steps.
         const int gx = a.Lun.ng;
-        if (x < gx || x >= BS - gx) {
+        if (!xun && (x < gx || x >= BS - gx)) {
           const int off = x < gx ? -gx : gx;
 #pragma unroll
           for (int c = 0; c < 4; ++c) ntstore(T(0), unb + c * ufs + z * uzs + off, a.nt);
@@ -1104,7 +1108,7 @@ static unsigned grid_for(int64_t n, int per_cu) {
 // work buffer: acc, ping, pong (compact, bs^3 per field) and the coarse-face
 // halo buffer (6 faces x 4 fields x 3 x bs^2 per slot), 256-byte aligned parts
 struct WorkParts {
-  size_t acc, ping, pong, hb, total;
+  size_t acc, ping, pong, uc, hb, total;
 };
 static WorkParts work_parts(const wacm_grid* g) {
   const size_t es = g->d.dtype == WACM_F64 ? 8 : 4;
@@ -1115,7 +1119,8 @@ static WorkParts work_parts(const wacm_grid* g) {
   w.acc = 0;
   w.ping = up(cap * 4 * b3 * es);
   w.pong = w.ping + up(cap * 4 * b3 * es);
-  w.hb = w.pong + up(cap * 4 * b3 * es);
+  w.uc = w.pong + up(cap * 4 * b3 * es);
+  w.hb = w.uc + up(cap * 4 * b3 * es);
   w.total = w.hb + up(cap * 6 * 4 * 3 * b2 * es);
   return w;
 }
@@ -1262,6 +1267,8 @@ static int64_t stage_items(const wacm_grid* g) {
 // nsteps classical RK4 steps.  With the CFL rule, the first step's dt comes
 // from a reduction over U; every later step's from the maximum the previous
 // step's last stage formed while writing U (the same value, bit for bit).
+// Between the steps of one call the state stays in the x-split register uc:
+// only the first step reads the pool and only the last one writes it.
 template <typename T>
 static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev, double* dt_dev,
                         T* U, void* work, const T* dus, int dt_mode, int64_t nsteps,
@@ -1273,10 +1280,9 @@ static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
   T* acc = (T*)(w + wp.acc);
   T* ping = (T*)(w + wp.ping);
   T* pong = (T*)(w + wp.pong);
+  T* uc = (T*)(w + wp.uc);
   T* hb = (T*)(w + wp.hb);
   StageArgs<T> a = base_args<T>(g, p);
-  a.un = U;
-  a.Lun = pool_layout(g);
   a.acc = acc;
   a.Lacc = compact_layout(g);
   a.hb = hb;
@@ -1286,6 +1292,7 @@ static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
   const Layout Lp = pool_layout(g), Ls = split_layout(g);
   T* ins[4] = {U, ping, pong, ping};
   T* outs[4] = {ping, pong, ping, U};
+  Layout lins[4] = {Lp, Ls, Ls, Ls};
   const double hmin = g->d.L / (double(int64_t(1) << g->jfine) * g->d.bs);
   const int64_t items = stage_items(g);
   for (int64_t k = 0; k < nsteps; ++k) {
@@ -1298,11 +1305,20 @@ static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
     }
+    // U^n of this step and U^{n+1}: the pool at the ends of the call, uc between
+    T* un = k == 0 ? U : uc;
+    const Layout Lun = k == 0 ? Lp : Ls;
+    T* unext = k + 1 == nsteps ? U : uc;
+    const Layout Lnext = k + 1 == nsteps ? Lp : Ls;
+    ins[0] = un;
+    lins[0] = Lun;
     for (int s = 0; s < 4; ++s) {
       a.in = ins[s];
-      a.Lin = s == 0 ? Lp : Ls;
-      a.out = outs[s];
-      a.Lout = s == 3 ? Lp : Ls;
+      a.Lin = lins[s];
+      a.out = s == 3 ? unext : outs[s];
+      a.Lout = s == 3 ? Lnext : Ls;
+      a.un = s == 3 ? unext : un;
+      a.Lun = s == 3 ? Lnext : Lun;
       a.umax_part = (s == 3 && dt_mode == WACM_DT_CFL && k + 1 < nsteps) ? g->d_part : nullptr;
       if (g->n_cface > 0) {
         ProfScope ps(g, 1, st);
