@@ -10,12 +10,13 @@ library's kernels.
         (a torch.neg kernel that reads and writes G GiB once each)
     python -m paper_1912_05371_amd.profile_summary dispatches DB [--match stage_kernel]
         one line per matching dispatch: kernel and counter values, in order
-    python -m paper_1912_05371_amd.profile_summary schedules DBFETCH DBWRITE --copy-gib G
-        --dtype f64 --warmup W --steps K
-        HBM traffic per stage-kernel launch for every schedule the autotuner
-        tried in a `bench.py --no-graph --dtype D` run under rocprofv3 --pmc
-        (FETCH_SIZE in one run, WRITE_SIZE in another), as the machine-readable
-        block bench.py reads back.
+    python -m paper_1912_05371_amd.profile_summary traffic DBFETCH DBWRITE --copy-gib G
+        --dtype D --schedule KEY --last N
+        HBM bytes per stage-kernel launch, the mean over the last N stage
+        launches (the timed steps) of a `bench.py --no-graph --dtype D
+        --schedule KEY` run under rocprofv3 --pmc (FETCH_SIZE in one run,
+        WRITE_SIZE in another), each counter scaled by the copy probe, as the
+        machine-readable block bench.py reads back.
 """
 from __future__ import annotations
 
@@ -125,39 +126,32 @@ def counter_table(dbs, match: str, copy_gib: float) -> str:
     return "\n".join(lines)
 
 
-def schedule_traffic(db_fetch: str, db_write: str, copy_gib: float, warmup: int, steps: int):
-    """Per-schedule HBM bytes per stage-kernel launch of an autotuned bench run.
-
-    The tuner runs each candidate schedule for 1 + 2 RK4 steps (4 stage
-    launches each) in the order of autotune.CANDIDATES; the bench then runs
-    warmup + steps steps with the chosen schedule."""
-    from . import autotune
-    per = 12
-    res = {}
-    fac = {}
+def stage_traffic(db_fetch: str, db_write: str, copy_gib: float, last: int):
+    """Mean scaled FETCH_SIZE and WRITE_SIZE bytes over the last `last`
+    stage-kernel launches, and the scale factors."""
+    out, fac = {}, {}
     for cn, db in (("FETCH_SIZE", db_fetch), ("WRITE_SIZE", db_write)):
         disp = dispatch_counters(db, "stage_kernel")
-        fac[cn] = copy_factors(disp, copy_gib)[cn]
+        f = copy_factors(disp, copy_gib)
+        if cn not in f:
+            raise SystemExit(f"{db}: no copy-probe dispatch with {cn}")
+        fac[cn] = f[cn]
         st = [d[cn] for n, d in disp if "stage_kernel" in n]
-        need = per * len(autotune.CANDIDATES) + 4 * (warmup + steps)
-        if len(st) != need:
-            raise SystemExit(f"{db}: {len(st)} stage launches, expected {need}")
-        for i, cand in enumerate(autotune.CANDIDATES):
-            chunk = st[i * per:(i + 1) * per]
-            key = ",".join(f"{k}={cand[k]}" for k in sorted(cand))
-            res.setdefault(key, {})[cn] = sum(chunk) / per * fac[cn] * 1024
-    return res, fac
+        if len(st) < last:
+            raise SystemExit(f"{db}: {len(st)} stage launches, fewer than {last}")
+        out[cn] = sum(st[-last:]) / last * fac[cn] * 1024
+    return out, fac
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("mode", choices=["trace", "counters", "dispatches", "schedules"])
+    ap.add_argument("mode", choices=["trace", "counters", "dispatches", "traffic"])
     ap.add_argument("dbs", nargs="+")
     ap.add_argument("--match", default="wacm")
     ap.add_argument("--copy-gib", type=float, default=0.0)
     ap.add_argument("--dtype", default="f64")
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--schedule", default="")
+    ap.add_argument("--last", type=int, default=0)
     a = ap.parse_args(argv)
     if a.mode == "trace":
         for db in a.dbs:
@@ -170,15 +164,15 @@ def main(argv=None):
                 print(f"{i:5d} {n[:60]:60s} " +
                       " ".join(f"{k}={v:.0f}" for k, v in sorted(d.items())))
     else:
-        if len(a.dbs) != 2 or not a.copy_gib:
-            raise SystemExit("schedules needs DBFETCH DBWRITE and --copy-gib")
-        res, fac = schedule_traffic(a.dbs[0], a.dbs[1], a.copy_gib, a.warmup, a.steps)
+        if len(a.dbs) != 2 or not a.copy_gib or not a.schedule or a.last <= 0:
+            raise SystemExit("traffic needs DBFETCH DBWRITE, --copy-gib, --schedule, --last")
+        v, fac = stage_traffic(a.dbs[0], a.dbs[1], a.copy_gib, a.last)
+        key = ",".join(sorted(a.schedule.split(",")))
         print(f"copy-probe scale factors: FETCH_SIZE x{fac['FETCH_SIZE']:.4f}, "
               f"WRITE_SIZE x{fac['WRITE_SIZE']:.4f}")
         print("traffic-data")
         print(f"source_sha1 {stage_source_sha1()}")
-        for key, v in res.items():
-            print(f"{a.dtype} {key} fetch {v['FETCH_SIZE']:.0f} write {v['WRITE_SIZE']:.0f}")
+        print(f"{a.dtype} {key} fetch {v['FETCH_SIZE']:.0f} write {v['WRITE_SIZE']:.0f}")
         print("end-traffic-data")
     return 0
 
