@@ -89,7 +89,7 @@ typedef struct {
  * only: results do not depend on it).  wg_per_cu: persistent workgroups per
  * compute unit (0: as many as are resident); xcd_map: 1 gives each of the 8
  * XCDs a contiguous run of the Morton-ordered blocks (shared faces meet in one
- * L2); prefetch: 1 loads U^n and the accumulator before a plane's barrier, 0
+ * L2), 0 deals the work items round-robin; prefetch: 1 loads U^n and the accumulator before a plane's barrier, 0
  * after the rhs, -1 default; nontemporal: 1 streams U^n and the accumulator
  * with non-temporal loads/stores; tile_rows: 0 gives each workgroup a whole
  * block (bs^2 threads), 8 a tile of 8 rows of the block's columns (8 bs

@@ -90,28 +90,29 @@ struct StageArgs {
   double* umax_part;  // stage 4: per work item max |u|^2 of the new U^n, or null
   double t_host;
   double L;
-  int xcd_map;  // 1: give each XCD a contiguous run of blocks
+  int xcd_map;  // 1: give each XCD a contiguous run of work items
   int nt;       // 1: non-temporal loads/stores of the streaming operands
   wacm_params p;
 };
 
-// Persistent block loop.  With xcd_map, workgroup w (dispatched to XCD w % 8)
-// walks a contiguous eighth of the Morton-ordered block list, so blocks that
-// share faces are processed close in time on the same L2.
+// Persistent loop over the work items (block b, tile t) = item b nty + t of
+// the Morton-ordered block list.  With xcd_map, workgroup w (dispatched to XCD
+// w % 8) walks a contiguous eighth of the items, so blocks that share faces
+// are processed close in time on the same L2; otherwise items go round-robin.
 struct BlockIter {
   int64_t ib, end, step;
-  __device__ BlockIter(int64_t nb, int xcd_map) {
+  __device__ BlockIter(int64_t n, int xcd_map) {
     const int64_t G = gridDim.x, w = blockIdx.x;
-    if (xcd_map && G % 8 == 0 && nb >= G) {
+    if (xcd_map && G % 8 == 0 && n >= G) {
       const int64_t per = G / 8, xcd = w % 8, lw = w / 8;
-      const int64_t chunk = (nb + 7) / 8;
+      const int64_t chunk = (n + 7) / 8;
       const int64_t start = xcd * chunk;
-      end = start + chunk < nb ? start + chunk : nb;
+      end = start + chunk < n ? start + chunk : n;
       ib = start + lw;
       step = per;
     } else {
       ib = w;
-      end = nb;
+      end = n;
       step = G;
     }
   }
@@ -277,8 +278,9 @@ void stage_kernel(StageArgs<T> a) {
   const int ofs = (int)a.Lout.fstride;
 
   for (BlockIter it(a.nb * NTY, a.xcd_map); it.ib < it.end; it.ib += it.step) {
-    const int64_t ibk = it.ib / NTY;
-    const int y0 = (int)(it.ib - ibk * NTY) * TY;
+    const int64_t item = it.ib;
+    const int64_t ibk = item / NTY;
+    const int y0 = (int)(item - ibk * NTY) * TY;
     const int y = y0 + yl;
     lds_barrier();
     if (tid < 6) fds[tid] = face_desc<T, BS, GH>(a.tab[ibk], a, tid, xin);
@@ -533,7 +535,7 @@ void stage_kernel(StageArgs<T> a) {
         double mx = red[0];
 #pragma unroll
         for (int w = 1; w < NT / 64; ++w) mx = fmax(mx, red[w]);
-        a.umax_part[it.ib] = mx;
+        a.umax_part[item] = mx;
       }
     }
   }
@@ -544,22 +546,27 @@ void stage_kernel(StageArgs<T> a) {
 // its coincident point (decimation, Sec. 3.1).  A coarser neighbour gives the
 // tensor-product DD4 prediction (Sec. 3.1), computed separably: the coarse
 // lattice box around the face (even local indices, read from whichever leaves
-// hold them) is gathered into LDS once, then predicted along the normal and
-// the two tangential axes in turn.
-constexpr int NLF_MAXS = 32 / 2 + 3;  // coarse points per tangential axis, bs <= 32
-constexpr int NLF_MAXN = 5;           // coarse points along the normal
-template <typename T>
+// hold them) is gathered once, then predicted along the normal and the two
+// tangential axes in turn, one field at a time through LDS.  The loads of all
+// 4 fields are issued together into registers before the first field's
+// passes, so one memory latency per face is exposed instead of four.
+template <typename T, int BS>
 __global__ __launch_bounds__(NT_GEN) void nlface_kernel(const Tab* __restrict__ tab,
                                                         const int32_t* __restrict__ cf, int64_t n,
                                                         const T* __restrict__ in, Layout Lin,
-                                                        T* __restrict__ hb, int bs) {
+                                                        T* __restrict__ hb) {
+  constexpr int S = BS / 2 + 3;   // tangential coarse positions -2, 0, ..., bs+2
+  constexpr int NSRC = 5 * S * S;  // at most 5 coarse points along the normal
+  constexpr int PER = (NSRC + NT_GEN - 1) / NT_GEN;
+  constexpr int B2 = BS * BS;
+  constexpr int NFINE = (3 * B2 + NT_GEN - 1) / NT_GEN;
   __shared__ Tab st;
-  __shared__ int64_t soff[NLF_MAXN * NLF_MAXS * NLF_MAXS];
-  __shared__ T src[NLF_MAXN * NLF_MAXS * NLF_MAXS];
-  __shared__ T pa[3 * NLF_MAXS * NLF_MAXS];
-  __shared__ T pb[3 * NLF_MAXS * 32];
-  const int S = bs / 2 + 3;  // tangential coarse positions -2, 0, ..., bs+2
+  __shared__ T src[NSRC];
+  __shared__ T pa[3 * S * S];
+  __shared__ T pb[3 * S * BS];
   const T w0 = T(DDW0), w1 = T(DDW1);
+  const int64_t fs = Lin.fstride;
+  const int tid = threadIdx.x;
   for (int64_t wk = blockIdx.x; wk < n; wk += gridDim.x) {
     const int32_t ib = cf[2 * wk], f = cf[2 * wk + 1];
     __syncthreads();
@@ -570,82 +577,107 @@ __global__ __launch_bounds__(NT_GEN) void nlface_kernel(const Tab* __restrict__ 
     const int ua = axis == 0 ? 1 : 0, ub = axis == 2 ? 1 : 2;  // tangential axes t0, t1
     const int r = (axis == 0 ? 2 * side : 1) + 3 * (axis == 1 ? 2 * side : 1) +
                   9 * (axis == 2 ? 2 * side : 1);
-    T* hbf = hb + ((int64_t)slot * 6 + f) * 12 * bs * bs;
+    T* hbf = hb + ((int64_t)slot * 6 + f) * 12 * B2;
     if (st.kind[r] > 0) {
-      // finer neighbour: every halo point is a point of a finer leaf
-      for (int p = threadIdx.x; p < 3 * bs * bs; p += blockDim.x) {
-        const int d = p / (bs * bs), qq = p - d * bs * bs;
-        int li[3];
-        li[axis] = side ? bs + d : -1 - d;
-        li[ua] = qq % bs;
-        li[ub] = qq / bs;
-        const int64_t o = point_offset(st, bs, Lin, li[0], li[1], li[2]);
+      // finer neighbour: every halo point is a point of a finer leaf; all
+      // loads of this thread's points first, then the stores
+      T v[NFINE][4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) hbf[(int64_t)(c * 3) * bs * bs + p] = in[o + c * Lin.fstride];
+      for (int k = 0; k < NFINE; ++k) {
+        const int p = tid + k * NT_GEN;
+        if (p < 3 * B2) {
+          const int d = p / B2, qq = p - d * B2;
+          int li[3];
+          li[axis] = side ? BS + d : -1 - d;
+          li[ua] = qq % BS;
+          li[ub] = qq / BS;
+          const int64_t o = point_offset(st, BS, Lin, li[0], li[1], li[2]);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) v[k][c] = in[o + c * fs];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NFINE; ++k) {
+        const int p = tid + k * NT_GEN;
+        if (p < 3 * B2) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) hbf[(int64_t)(c * 3) * B2 + p] = v[k][c];
+        }
       }
       continue;
     }
-    // coarser neighbour.  normal ghost positions g_d = bs + d (side 1) or
+    // coarser neighbour.  Normal ghost positions g_d = bs + d (side 1) or
     // -1 - d (side 0); the even positions their stencils use run from n0 in
     // steps of 2: side 1 [bs-2, bs+4] (4 points), side 0 [-6, 2] (5 points)
-    const int n0 = side ? bs - 2 : -6;
+    const int n0 = side ? BS - 2 : -6;
     const int NN = side ? 4 : 5;
     const int nsrc = NN * S * S;
-    for (int p = threadIdx.x; p < nsrc; p += blockDim.x) {
-      const int m = p / (S * S), qq = p - m * S * S;
-      int li[3];
-      li[axis] = n0 + 2 * m;
-      li[ua] = 2 * (qq % S) - 2;
-      li[ub] = 2 * (qq / S) - 2;
-      soff[p] = point_offset(st, bs, Lin, li[0], li[1], li[2]);
+    T v[PER][4];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int p = tid + k * NT_GEN;
+      if (p < nsrc) {
+        const int m = p / (S * S), qq = p - m * S * S;
+        int li[3];
+        li[axis] = n0 + 2 * m;
+        li[ua] = 2 * (qq % S) - 2;
+        li[ub] = 2 * (qq / S) - 2;
+        const int64_t o = point_offset(st, BS, Lin, li[0], li[1], li[2]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[k][c] = in[o + c * fs];
+      }
     }
-    __syncthreads();
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
-      for (int p = threadIdx.x; p < nsrc; p += blockDim.x) src[p] = in[soff[p] + c * Lin.fstride];
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int p = tid + k * NT_GEN;
+        if (p < nsrc) src[p] = v[k][c];
+      }
       __syncthreads();
       // along the normal: pa[d][t1'][t0']
-      for (int p = threadIdx.x; p < 3 * S * S; p += blockDim.x) {
+      for (int p = tid; p < 3 * S * S; p += NT_GEN) {
         const int d = p / (S * S), qq = p - d * S * S;
-        const int g = side ? bs + d : -1 - d;
-        T v;
+        const int g = side ? BS + d : -1 - d;
+        T val;
         if ((g & 1) == 0) {
-          v = src[((g - n0) / 2) * S * S + qq];
+          val = src[((g - n0) / 2) * S * S + qq];
         } else {
           const int m = (g - 3 - n0) / 2;  // taps g-3, g-1, g+1, g+3
-          v = w0 * src[m * S * S + qq] + w1 * src[(m + 1) * S * S + qq] +
-              w1 * src[(m + 2) * S * S + qq] + w0 * src[(m + 3) * S * S + qq];
+          val = w0 * src[m * S * S + qq] + w1 * src[(m + 1) * S * S + qq] +
+                w1 * src[(m + 2) * S * S + qq] + w0 * src[(m + 3) * S * S + qq];
         }
-        pa[p] = v;
+        pa[p] = val;
       }
       __syncthreads();
       // along t0: pb[d][t1'][t0], t0 in [0, bs)
-      for (int p = threadIdx.x; p < 3 * S * bs; p += blockDim.x) {
-        const int t0 = p % bs, rest = p / bs;  // rest = d * S + t1'
+      for (int p = tid; p < 3 * S * BS; p += NT_GEN) {
+        const int t0 = p % BS, rest = p / BS;  // rest = d * S + t1'
         const T* row = pa + rest * S;
-        T v;
+        T val;
         if ((t0 & 1) == 0) {
-          v = row[t0 / 2 + 1];
+          val = row[t0 / 2 + 1];
         } else {
           const int m = (t0 - 3) / 2 + 1;  // coarse index of t0-3
-          v = w0 * row[m] + w1 * row[m + 1] + w1 * row[m + 2] + w0 * row[m + 3];
+          val = w0 * row[m] + w1 * row[m + 1] + w1 * row[m + 2] + w0 * row[m + 3];
         }
-        pb[p] = v;
+        pb[p] = val;
       }
       __syncthreads();
       // along t1: out[d][t1][t0]
-      for (int p = threadIdx.x; p < 3 * bs * bs; p += blockDim.x) {
-        const int d = p / (bs * bs), qq = p - d * bs * bs;
-        const int t0 = qq % bs, t1 = qq / bs;
-        const T* colp = pb + d * S * bs + t0;
-        T v;
+      for (int p = tid; p < 3 * B2; p += NT_GEN) {
+        const int d = p / B2, qq = p - d * B2;
+        const int t0 = qq % BS, t1 = qq / BS;
+        const T* colp = pb + d * S * BS + t0;
+        T val;
         if ((t1 & 1) == 0) {
-          v = colp[(t1 / 2 + 1) * bs];
+          val = colp[(t1 / 2 + 1) * BS];
         } else {
           const int m = (t1 - 3) / 2 + 1;
-          v = w0 * colp[m * bs] + w1 * colp[(m + 1) * bs] + w1 * colp[(m + 2) * bs] +
-              w0 * colp[(m + 3) * bs];
+          val = w0 * colp[m * BS] + w1 * colp[(m + 1) * BS] + w1 * colp[(m + 2) * BS] +
+                w0 * colp[(m + 3) * BS];
         }
-        hbf[(int64_t)(c * 3) * bs * bs + p] = v;
+        hbf[(int64_t)(c * 3) * B2 + p] = val;
       }
       __syncthreads();
     }
@@ -1105,6 +1137,26 @@ static unsigned grid_for(int64_t n, int per_cu) {
   return (unsigned)(n < cap ? (n > 0 ? n : 1) : cap);
 }
 
+template <typename T>
+static hipError_t nlface_launch(const wacm_grid* g, const T* in, const Layout& Lin, T* hb,
+                                hipStream_t st) {
+  const unsigned grid = grid_for(g->n_cface, 8);
+  switch (g->d.bs) {
+    case 16:
+      nlface_kernel<T, 16><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->d_cface, g->n_cface, in, Lin, hb);
+      break;
+    case 24:
+      nlface_kernel<T, 24><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->d_cface, g->n_cface, in, Lin, hb);
+      break;
+    case 32:
+      nlface_kernel<T, 32><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->d_cface, g->n_cface, in, Lin, hb);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // work buffer: acc, ping, pong (compact, bs^3 per field) and the coarse-face
 // halo buffer (6 faces x 4 fields x 3 x bs^2 per slot), 256-byte aligned parts
 struct WorkParts {
@@ -1322,9 +1374,7 @@ static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
       a.umax_part = (s == 3 && dt_mode == WACM_DT_CFL && k + 1 < nsteps) ? g->d_part : nullptr;
       if (g->n_cface > 0) {
         ProfScope ps(g, 1, st);
-        nlface_kernel<T><<<grid_for(g->n_cface, 8), NT_GEN, 0, st>>>(
-            g->d_tab, g->d_cface, g->n_cface, a.in, a.Lin, hb, g->d.bs);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = nlface_launch<T>(g, a.in, a.Lin, hb, st)) != hipSuccess) return e;
       }
       ProfScope ps(g, 2, st);
       switch (s) {
