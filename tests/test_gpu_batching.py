@@ -100,11 +100,11 @@ def test_autotuner_picks_a_candidate(octree, tmp_path, monkeypatch):
     g = wacm.Grid.from_case(c, dtype=wacm.F32)
     U0 = to_pool(g, c.padded())
     before = U0.clone()
-    best, trials = autotune.tune(g, c.params, U0, steps=1, log=log)
+    best, trials = autotune.tune(g, c.params, U0, steps=1, log=log, shipped=False)
     assert best in autotune.CANDIDATES and g.get_schedule() == best
     assert len(trials) == len(autotune.CANDIDATES)
     assert torch.equal(U0, before)  # the caller's state is untouched
-    best2, _ = autotune.tune(g, c.params, U0)  # cache hit
+    best2, _ = autotune.tune(g, c.params, U0, shipped=False)  # cache hit
     assert best2 == best
     with pytest.raises(wacm.WacmError):
         g.set_schedule(prefetch=3)
