@@ -14,11 +14,12 @@ Metric: RK4 block-point updates/s = interior points x 4 stages / s.  The
 primary line is the FP64 path; the FP32 path is reported beside it with its
 speed-up.  The roofline object refers to the fused rhs + RK stage kernel: its
 algorithmic bytes (values per interior point: stage 1 reads U^n and writes
-the accumulator and the next stage input, 12; stage 2 reads its input and
-the accumulator and writes both registers, 16 (U^n is recovered from those
-two); stage 3 also reads U^n, 20; stage 4 reads its input and the
-accumulator and writes U^{n+1}, 12; mean 15) divided by its average duration,
-measured with HIP events on the launch stream inside the timed region.
+the next stage input, 8; stage 2 reads its input and U^n and writes the
+accumulator and the next input, 16; stage 3 reads its input, U^n and the
+accumulator and writes both registers, 20; stage 4 reads its input and the
+accumulator and writes U^{n+1}, 12; mean 14) divided by its average
+duration, measured with HIP events on the launch stream inside the timed
+region.
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 5]
 """
@@ -174,9 +175,9 @@ def counter_traffic(dtype: str, schedule: dict):
 
 def roofline(res, npts: int, es: int):
     stage_ms = res["kernel_ms"][2] / max(res["kernel_launches"][2], 1)
-    bytes_per_launch = 15 * es * npts  # mean over the 4 stages (12, 16, 20, 12 values)
+    bytes_per_launch = 14 * es * npts  # mean over the 4 stages (8, 16, 20, 12 values)
     achieved = bytes_per_launch / (stage_ms * 1e-3) / 1e9
-    step_bytes = 60 * es * npts
+    step_bytes = 56 * es * npts
     return {
         "bound": "hbm",
         "achieved": round(achieved, 1),

@@ -202,12 +202,12 @@ __device__ __forceinline__ void ntstore(T v, T* p, int nt) {
 
 // MODE 0: dU = rhs(U) with U's own ghost layers.  MODE s = 1..4: classical
 // RK4 stage s with registers U^n, acc and the stage inputs:
-//   s1: acc = U^n + dt/6 k1, out = U^n + dt/2 k1   (input = U^n)
-//   s2: acc += dt/3 k2,      out = U^n + dt/2 k2, U^n = (3 acc - Y2)/2 with the
-//       stage input Y2 = U^n + dt/2 k1 (one register read fewer; the recovered
-//       value, rounded differently, enters only the input of stage 3)
+//   s1: out = Y2 = U^n + dt/2 k1                    (input = U^n)
+//   s2: acc = U^n + (Y2 - U^n)/3 + dt/3 k2, out = U^n + dt/2 k2: U^n + dt/6 k1
+//       is formed from the input Y2 and U^n, so stage 1 writes one register
+//       instead of two (same value up to rounding of U^n's size)
 //   s3: acc += dt/3 k3,      out = U^n + dt k3
-//   s4: U^n = acc + dt/6 k4
+//   s4: U^{n+1} = acc + dt/6 k4
 // PEN: penalization/sponge terms present.  PREF: load the epilogue operands
 // (U^n, acc) before the barrier instead of after the rhs.  Work items are
 // tiles of TY rows of a block's (x,y) columns (TY = BS: the whole block), one
@@ -225,7 +225,7 @@ void stage_kernel(StageArgs<T> a) {
   // the stage registers between stages are x-split; U^n is the pool or, from
   // the second step of a multi-step call on, an x-split register too
   const bool xin = MODE >= 2 || (MODE == 1 && a.Lin.xs != 0);
-  const bool xun = (MODE == 3 || MODE == 4) && a.Lun.xs != 0;
+  const bool xun = MODE >= 2 && a.Lun.xs != 0;
   constexpr bool XOUT = MODE >= 1 && MODE <= 3;
   __shared__ T slab[2][4][W * WY];
   __shared__ FaceDesc<T> fds[6];
@@ -241,7 +241,7 @@ void stage_kernel(StageArgs<T> a) {
     dt = *a.dt_dev;
   }
   const T nu = T(a.p.nu), c0sq = T(a.p.c0 * a.p.c0), cg = T(a.p.c_gamma);
-  const T fA = T(MODE == 1 ? dt / 6.0 : (MODE == 4 ? dt / 6.0 : dt / 3.0));
+  const T fA = T(MODE == 4 ? dt / 6.0 : dt / 3.0);
   // the stage time and what of the mask depends on it alone
   const double ts = tc + (MODE == 2 || MODE == 3 ? 0.5 * dt : (MODE == 4 ? dt : 0.0));
   const MaskTime mt = PEN && a.p.mask ? mask_time(a.p, ts) : MaskTime{1.0, 0.0, 0.0};
@@ -397,15 +397,10 @@ void stage_kernel(StageArgs<T> a) {
       // epilogue operands of this point, loaded early if PREF
       T unv[4], acv[4];
       if (PREF) {
-        if (MODE == 3) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            unv[c] = ntload(unb + c * ufs + z * uzs, a.nt);
-            acv[c] = ntload(accb + c * afs + z * azs, a.nt);
-          }
-        } else if (MODE == 2 || MODE == 4) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acv[c] = ntload(accb + c * afs + z * azs, a.nt);
+        for (int c = 0; c < 4; ++c) {
+          if (MODE == 2 || MODE == 3) unv[c] = ntload(unb + c * ufs + z * uzs, a.nt);
+          if (MODE == 3 || MODE == 4) acv[c] = ntload(accb + c * afs + z * azs, a.nt);
         }
       }
       lds_barrier();
@@ -462,15 +457,10 @@ void stage_kernel(StageArgs<T> a) {
       }
 
       if (!PREF) {
-        if (MODE == 3) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            unv[c] = ntload(unb + c * ufs + z * uzs, a.nt);
-            acv[c] = ntload(accb + c * afs + z * azs, a.nt);
-          }
-        } else if (MODE == 2 || MODE == 4) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acv[c] = ntload(accb + c * afs + z * azs, a.nt);
+        for (int c = 0; c < 4; ++c) {
+          if (MODE == 2 || MODE == 3) unv[c] = ntload(unb + c * ufs + z * uzs, a.nt);
+          if (MODE == 3 || MODE == 4) acv[c] = ntload(accb + c * afs + z * azs, a.nt);
         }
       }
       if (MODE == 0) {
@@ -497,12 +487,12 @@ void stage_kernel(StageArgs<T> a) {
         const T val[4] = {u, v, w, pr};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          // stage 2 recovers U^n from its input Y2 = U^n + dt/2 k1 and the
-          // accumulator U^n + dt/6 k1 instead of reading it
-          const T u0 = MODE == 1 ? val[c]
-                                 : (MODE == 2 ? T(1.5) * acv[c] - T(0.5) * val[c] : unv[c]);
-          const T ac = MODE == 1 ? u0 : acv[c];
-          ntstore(ac + fA * r[c], accb + c * afs + z * azs, a.nt);
+          const T u0 = MODE == 1 ? val[c] : unv[c];
+          if (MODE != 1) {
+            // stage 2 forms U^n + dt/6 k1 from its input Y2 = U^n + dt/2 k1
+            const T ac = MODE == 2 ? u0 + (val[c] - u0) * T(1.0 / 3.0) : acv[c];
+            ntstore(ac + fA * r[c], accb + c * afs + z * azs, a.nt);
+          }
           outb[c * ofs + z * ozs] = u0 + fB * r[c];
         }
       }
