@@ -858,83 +858,107 @@ __global__ __launch_bounds__(NT_GEN) void norm_finalize(const double* __restrict
   }
 }
 
-template <typename T>
+// Wavelet details (Sec. 3.1) of one block: d = u - P R u at every interior
+// point, P R u the tensor-product DD4 prediction from the block's even
+// lattice (ghost-synchronised pool), evaluated separably and z-marching: for
+// each coarse plane k' the x pass gives X(i, j', k') on the coarse rows j',
+// the y pass Y(i, j, k') on the whole plane (a ring of the last 4 coarse
+// planes in LDS), and the z pass the prediction of the fine plane k' (even)
+// and k' - 3 (odd).  Per block: max over fields of max |d| / ||u_c||,
+// the mask range and the coarsening flag (Sec. 3.3-3.5).
+template <typename T, int BS>
 __global__ __launch_bounds__(NT_GEN) void detail_kernel(
-    const Tab* __restrict__ tab, int64_t nb, const T* __restrict__ U, Layout L, int bs,
+    const Tab* __restrict__ tab, int64_t nb, const T* __restrict__ U, Layout L,
     const double* __restrict__ norm, double Ldom, wacm_params p, double t, double eps,
     int dealias, int jmin, int jmax, double* __restrict__ dmax, double* __restrict__ mrange,
     int8_t* __restrict__ flags) {
+  constexpr int S = BS / 2 + 3;  // even positions -2, 0, ..., bs+2
+  constexpr int B2 = BS * BS;
+  __shared__ T xp[S * BS];       // X(i, j') of the current coarse plane
+  __shared__ T yr[4][B2];        // Y(i, j) of the last 4 coarse planes
   __shared__ double red[3][NT_GEN / 64];
-  const int n3 = bs * bs * bs;
-  double inv[4];
-  for (int c = 0; c < 4; ++c) inv[c] = 1.0 / norm[c];
+  const T w0 = T(DDW0), w1 = T(DDW1);
+  const int tid = threadIdx.x;
+  const int P = L.P, ng = L.ng;
+  const MaskTime mt = p.mask ? mask_time(p, t) : MaskTime{1.0, 0.0, 0.0};
   for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
     const int32_t* m = tab[ib].meta;
     const int slot = m[0], J = m[1];
-    const double h = Ldom / (double(int64_t(1) << J) * bs);
+    const double h = Ldom / (double(int64_t(1) << J) * BS);
     const T* b = U + (int64_t)slot * L.bstride;
+    // element of local point (i, j, k)
+    auto at = [&](int c, int i, int j, int k) -> T {
+      return b[c * L.fstride + ((int64_t)(k + ng) * P + (j + ng)) * P + (i + ng)];
+    };
     double dm = 0.0, cmin = 1e300, cmax = -1e300;
-    for (int q = threadIdx.x; q < n3; q += blockDim.x) {
-      const int i = q % bs, j = (q / bs) % bs, k = q / (bs * bs);
-      if (p.mask) {
+    if (p.mask) {
+      for (int q = tid; q < B2 * BS; q += NT_GEN) {
+        const int i = q % BS, j = (q / BS) % BS, k = q / B2;
         double chi, us[3];
-        mask_eval(p, t, (double)(m[2] * bs + i) * h, (double)(m[3] * bs + j) * h,
-                  (double)(m[4] * bs + k) * h, chi, us);
+        mask_point(p, mt, (double)(m[2] * BS + i) * h, (double)(m[3] * BS + j) * h,
+                   (double)(m[4] * BS + k) * h, chi, us);
         cmin = fmin(cmin, chi);
         cmax = fmax(cmax, chi);
       }
-      if (((i | j | k) & 1) == 0) continue;
-      int tx[4], ty[4], tz[4];
-      T wx[4], wy[4], wz[4];
-      int nx, ny, nz;
-      auto taps = [](int q2, int* tq, T* wq, int& n) {
-        if ((q2 & 1) == 0) {
-          tq[0] = q2;
-          wq[0] = T(1);
-          n = 1;
-        } else {
-          tq[0] = q2 - 3;
-          tq[1] = q2 - 1;
-          tq[2] = q2 + 1;
-          tq[3] = q2 + 3;
-          wq[0] = T(DDW0);
-          wq[1] = T(DDW1);
-          wq[2] = T(DDW1);
-          wq[3] = T(DDW0);
-          n = 4;
+    }
+    for (int c = 0; c < 4; ++c) {
+      const double inv = 1.0 / norm[c];
+      for (int mm = 0; mm < S; ++mm) {
+        const int kc = 2 * mm - 2;  // coarse plane
+        __syncthreads();            // xp and the ring slot are free again
+        // x pass on the coarse rows j' = 2 jj - 2 of plane kc
+        for (int q = tid; q < S * BS; q += NT_GEN) {
+          const int jj = q / BS, i = q - jj * BS, jc = 2 * jj - 2;
+          T v;
+          if ((i & 1) == 0)
+            v = at(c, i, jc, kc);
+          else
+            v = w0 * at(c, i - 3, jc, kc) + w1 * at(c, i - 1, jc, kc) +
+                w1 * at(c, i + 1, jc, kc) + w0 * at(c, i + 3, jc, kc);
+          xp[q] = v;
         }
-      };
-      taps(i, tx, wx, nx);
-      taps(j, ty, wy, ny);
-      taps(k, tz, wz, nz);
-      T pred[4] = {T(0), T(0), T(0), T(0)};
-      for (int aa = 0; aa < nz; ++aa)
-        for (int bb = 0; bb < ny; ++bb) {
-          const T wzy = wz[aa] * wy[bb];
-          for (int e = 0; e < nx; ++e) {
-            const T w = wzy * wx[e];
-            const int64_t o = ((int64_t)(tz[aa] + L.ng) * L.P + (ty[bb] + L.ng)) * L.P +
-                              (tx[e] + L.ng);
-            for (int c = 0; c < 4; ++c) pred[c] += w * b[o + c * L.fstride];
+        __syncthreads();
+        // y pass: Y(i, j) of plane kc into ring slot mm % 4
+        T* yo = yr[mm & 3];
+        for (int q = tid; q < B2; q += NT_GEN) {
+          const int j = q / BS, i = q - j * BS;
+          T v;
+          if ((j & 1) == 0) {
+            v = xp[(j / 2 + 1) * BS + i];
+          } else {
+            const int jj = (j - 3) / 2 + 1;  // coarse row of j - 3
+            v = w0 * xp[jj * BS + i] + w1 * xp[(jj + 1) * BS + i] + w1 * xp[(jj + 2) * BS + i] +
+                w0 * xp[(jj + 3) * BS + i];
+          }
+          yo[q] = v;
+        }
+        __syncthreads();
+        // z pass: the even fine plane kc and the odd fine plane kc - 3
+        for (int q = tid; q < B2; q += NT_GEN) {
+          const int j = q / BS, i = q - j * BS;
+          if (kc >= 0 && kc < BS && ((i | j) & 1))
+            dm = fmax(dm, fabs((double)(at(c, i, j, kc) - yo[q])) * inv);
+          const int ko = kc - 3;
+          if (ko >= 0 && ko < BS) {
+            // taps ko-3, ko-1, ko+1, ko+3 = coarse planes mm-3 .. mm
+            const T pr = w0 * yr[(mm + 1) & 3][q] + w1 * yr[(mm + 2) & 3][q] +
+                         w1 * yr[(mm + 3) & 3][q] + w0 * yo[q];
+            dm = fmax(dm, fabs((double)(at(c, i, j, ko) - pr)) * inv);
           }
         }
-      const int64_t o = ((int64_t)(k + L.ng) * L.P + (j + L.ng)) * L.P + (i + L.ng);
-      for (int c = 0; c < 4; ++c) {
-        const T d = b[o + c * L.fstride] - pred[c];
-        dm = fmax(dm, fabs((double)d) * inv[c]);
       }
     }
     dm = wave_max(dm);
     cmin = wave_min(cmin);
     cmax = wave_max(cmax);
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
-      red[0][threadIdx.x >> 6] = dm;
-      red[1][threadIdx.x >> 6] = cmin;
-      red[2][threadIdx.x >> 6] = cmax;
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = dm;
+      red[1][tid >> 6] = cmin;
+      red[2][tid >> 6] = cmax;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       double r0 = red[0][0], r1 = red[1][0], r2 = red[2][0];
       for (int w = 1; w < NT_GEN / 64; ++w) {
         r0 = fmax(r0, red[0][w]);
@@ -1424,9 +1448,22 @@ static hipError_t thr_t(const wacm_grid* g, const wacm_params* p, double t, cons
   norm_kernel<T><<<grid_for(g->nb, 8), NT_GEN, 0, st>>>(g->d_tab, g->nb, U, pool_layout(g),
                                                         g->d.bs, g->d_part);
   norm_finalize<<<1, NT_GEN, 0, st>>>(g->d_part, g->nb, g->d_norm);
-  detail_kernel<T><<<grid_for(g->nb, 8), NT_GEN, 0, st>>>(
-      g->d_tab, g->nb, U, pool_layout(g), g->d.bs, g->d_norm, g->d.L, *p, t, eps, dealias,
-      g->d.jmin, g->d.jmax, dmax, mrange, flags);
+  const unsigned grid = grid_for(g->nb, 8);
+  const Layout L = pool_layout(g);
+  switch (g->d.bs) {
+#define WACM_DETAIL(BSV)                                                                    \
+  case BSV:                                                                                 \
+    detail_kernel<T, BSV><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, L, g->d_norm, g->d.L, \
+                                                   *p, t, eps, dealias, g->d.jmin, g->d.jmax, \
+                                                   dmax, mrange, flags);                    \
+    break;
+    WACM_DETAIL(16)
+    WACM_DETAIL(24)
+    WACM_DETAIL(32)
+#undef WACM_DETAIL
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
