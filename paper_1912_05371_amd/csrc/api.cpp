@@ -44,7 +44,9 @@ void free_dev(wacm_grid* g) {
   if (g->d_norm) (void)hipFree(g->d_norm);
   if (g->d_list) (void)hipFree(g->d_list);
   if (g->d_cface) (void)hipFree(g->d_cface);
+  if (g->d_cregion) (void)hipFree(g->d_cregion);
   g->d_cface = nullptr;
+  g->d_cregion = nullptr;
   g->d_tab = nullptr;
   g->d_part = nullptr;
   g->d_norm = nullptr;
@@ -163,7 +165,8 @@ int wacm_grid_create(const wacm_grid_desc* d, int64_t nleaves, const uint64_t* t
       (e = hipMalloc(&g->d_part, sizeof(double) * 16 * (d->capacity + 1024))) != hipSuccess ||
       (e = hipMalloc(&g->d_norm, sizeof(double) * 16)) != hipSuccess ||
       (e = hipMalloc(&g->d_list, sizeof(int32_t) * 10 * d->capacity)) != hipSuccess ||
-      (e = hipMalloc(&g->d_cface, sizeof(int32_t) * 12 * d->capacity)) != hipSuccess) {
+      (e = hipMalloc(&g->d_cface, sizeof(int32_t) * 12 * d->capacity)) != hipSuccess ||
+      (e = hipMalloc(&g->d_cregion, sizeof(int32_t) * 52 * d->capacity)) != hipSuccess) {
     free_dev(g);
     delete g;
     return hipfail(e, "hipMalloc of grid tables");

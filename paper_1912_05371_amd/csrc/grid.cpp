@@ -132,6 +132,17 @@ std::vector<int32_t> coarse_faces(const std::vector<Tab>& tabs) {
   return cf;
 }
 
+std::vector<int32_t> coarser_regions(const std::vector<Tab>& tabs) {
+  std::vector<int32_t> cr;
+  for (size_t i = 0; i < tabs.size(); ++i)
+    for (int r = 0; r < 27; ++r)
+      if (r != 13 && tabs[i].kind[r] < 0) {
+        cr.push_back((int32_t)i);
+        cr.push_back(r);
+      }
+  return cr;
+}
+
 int upload_tables(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
   if (tabs.empty()) return WACM_OK;
   hipError_t e = hipMemcpy(g->d_tab, tabs.data(), sizeof(Tab) * tabs.size(),
@@ -139,11 +150,15 @@ int upload_tables(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) 
   std::vector<int32_t> cf = coarse_faces(tabs);
   if (e == hipSuccess && !cf.empty())
     e = hipMemcpy(g->d_cface, cf.data(), sizeof(int32_t) * cf.size(), hipMemcpyHostToDevice);
+  std::vector<int32_t> cr = coarser_regions(tabs);
+  if (e == hipSuccess && !cr.empty())
+    e = hipMemcpy(g->d_cregion, cr.data(), sizeof(int32_t) * cr.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     err = std::string("hipMemcpy tables: ") + hipGetErrorString(e);
     return WACM_E_HIP;
   }
   g->n_cface = (int64_t)cf.size() / 2;
+  g->n_cregion = (int64_t)cr.size() / 2;
   g->h_tab = tabs;
   return WACM_OK;
 }

@@ -37,10 +37,14 @@ __device__ __forceinline__ T wave_min(T v) {
 // --------------------------------------------------------------------------
 // ghost synchronisation
 // --------------------------------------------------------------------------
+// Point-wise ghost fill: mode 0 every ghost point of all ng layers, mode 1 the
+// depth-3 face star (the points the rhs stencils read).  With skip_coarser,
+// points of regions that lie in a coarser leaf are left to
+// sync_coarser_kernel.
 template <typename T>
 __global__ __launch_bounds__(NT_GEN) void sync_kernel(const Tab* __restrict__ tab, int64_t nb,
                                                       T* __restrict__ U, Layout L, int bs,
-                                                      int mode) {
+                                                      int mode, int skip_coarser) {
   __shared__ Tab st;
   const int npts = mode == 1 ? 18 * bs * bs : L.P * L.P * L.P - bs * bs * bs;
   for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
@@ -51,11 +55,134 @@ __global__ __launch_bounds__(NT_GEN) void sync_kernel(const Tab* __restrict__ ta
     for (int p = threadIdx.x; p < npts; p += blockDim.x) {
       int i, j, k;
       shell_point(p, bs, L.ng, L.P, mode, i, j, k);
+      if (skip_coarser &&
+          st.kind[region_of(i, bs) + 3 * region_of(j, bs) + 9 * region_of(k, bs)] < 0)
+        continue;
       T v[4];
       ghost_value<T>(st, bs, L, U, i, j, k, v);
       const int64_t o = ((int64_t)(k + L.ng) * L.P + (j + L.ng)) * L.P + (i + L.ng);
 #pragma unroll
       for (int c = 0; c < 4; ++c) dst[o + c * L.fstride] = v[c];
+    }
+  }
+}
+
+// Ghost regions that lie in a coarser leaf (Sec. 3.1 prediction, Sec. 4.2):
+// one work item per (block, region).  The region's box of ghost points is
+// predicted separably: the even lattice box around it (read from whichever
+// leaves hold it) is gathered for all 4 fields at once into registers, then,
+// one field at a time through LDS, predicted along x, y and z and written.
+// The same tensor-product DD4 values as the point-wise fill, summed in
+// another order.  Requires ng <= SC_MAXG (checked by the launcher).
+constexpr int SC_MAXG = 6;
+template <int BS>
+struct SyncCoarseDims {
+  static constexpr int S = BS / 2 + 3;       // lattice points along an interior axis
+  static constexpr int MG = SC_MAXG;         // lattice points along a ghost axis, ng <= 6
+  static constexpr int NSRC = MG * S * S;    // largest lattice box (a face region)
+  static constexpr int NA = MG * S * BS;     // largest x-pass box
+  static constexpr int NB = MG * BS * BS;    // largest y-pass box
+};
+template <typename T, int BS>
+__global__ __launch_bounds__(NT_GEN) void sync_coarser_kernel(const Tab* __restrict__ tab,
+                                                              const int32_t* __restrict__ cr,
+                                                              int64_t n, T* __restrict__ U,
+                                                              Layout L) {
+  using D = SyncCoarseDims<BS>;
+  constexpr int PER = (D::NSRC + NT_GEN - 1) / NT_GEN;
+  __shared__ Tab st;
+  __shared__ T buf0[D::NSRC > D::NB ? D::NSRC : D::NB];  // lattice, then the y pass
+  __shared__ T buf1[D::NA];                               // x pass
+  const T w0 = T(DDW0), w1 = T(DDW1);
+  const int tid = threadIdx.x, ng = L.ng, P = L.P;
+  const int64_t fs = L.fstride;
+  for (int64_t wk = blockIdx.x; wk < n; wk += gridDim.x) {
+    const int32_t ib = cr[2 * wk], r = cr[2 * wk + 1];
+    __syncthreads();
+    load_tab(tab + ib, st);
+    __syncthreads();
+    T* dst = U + (int64_t)st.meta[0] * L.bstride;
+    // box lo..lo+n-1 per axis, and its even lattice e0, e0+2, ... (m points)
+    int lo[3], nn[3], e0[3], m[3];
+    const int rd[3] = {r % 3, (r / 3) % 3, r / 9};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = rd[d] == 0 ? -ng : (rd[d] == 1 ? 0 : BS);
+      nn[d] = rd[d] == 1 ? BS : ng;
+      const int hi = lo[d] + nn[d] - 1;
+      e0[d] = (lo[d] & ~1) - 2;
+      m[d] = (hi + ((hi & 1) ? 3 : 2) - e0[d]) / 2 + 1;
+    }
+    const int nsrc = m[0] * m[1] * m[2];
+    T v[PER][4];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int p = tid + q * NT_GEN;
+      if (p < nsrc) {
+        const int ax = p % m[0], rest = p / m[0], ay = rest % m[1], az = rest / m[1];
+        const int64_t o = point_offset(st, BS, L, e0[0] + 2 * ax, e0[1] + 2 * ay, e0[2] + 2 * az);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[q][c] = U[o + c * fs];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int p = tid + q * NT_GEN;
+        if (p < nsrc) buf0[p] = v[q][c];
+      }
+      __syncthreads();
+      // x pass: buf1[az][ay][i], i over the box
+      for (int p = tid; p < m[2] * m[1] * nn[0]; p += NT_GEN) {
+        const int ii = p % nn[0], row = p / nn[0];
+        const int i = lo[0] + ii;
+        const T* s = buf0 + row * m[0];
+        T val;
+        if ((i & 1) == 0) {
+          val = s[(i - e0[0]) / 2];
+        } else {
+          const int a = (i - 3 - e0[0]) / 2;
+          val = w0 * s[a] + w1 * s[a + 1] + w1 * s[a + 2] + w0 * s[a + 3];
+        }
+        buf1[p] = val;
+      }
+      __syncthreads();
+      // y pass: buf0[az][j][i]
+      for (int p = tid; p < m[2] * nn[1] * nn[0]; p += NT_GEN) {
+        const int ii = p % nn[0], rest = p / nn[0], jj = rest % nn[1], az = rest / nn[1];
+        const int j = lo[1] + jj;
+        const T* s = buf1 + az * m[1] * nn[0] + ii;
+        T val;
+        if ((j & 1) == 0) {
+          val = s[((j - e0[1]) / 2) * nn[0]];
+        } else {
+          const int a = (j - 3 - e0[1]) / 2;
+          val = w0 * s[a * nn[0]] + w1 * s[(a + 1) * nn[0]] + w1 * s[(a + 2) * nn[0]] +
+                w0 * s[(a + 3) * nn[0]];
+        }
+        buf0[p] = val;
+      }
+      __syncthreads();
+      // z pass into the ghost points
+      const int plane = nn[1] * nn[0];
+      for (int p = tid; p < nn[2] * plane; p += NT_GEN) {
+        const int kk = p / plane, q2 = p - kk * plane;
+        const int k = lo[2] + kk;
+        const T* s = buf0 + q2;
+        T val;
+        if ((k & 1) == 0) {
+          val = s[((k - e0[2]) / 2) * plane];
+        } else {
+          const int a = (k - 3 - e0[2]) / 2;
+          val = w0 * s[a * plane] + w1 * s[(a + 1) * plane] + w1 * s[(a + 2) * plane] +
+                w0 * s[(a + 3) * plane];
+        }
+        const int jj = q2 / nn[0], ii = q2 - jj * nn[0];
+        const int64_t o = ((int64_t)(k + ng) * P + (lo[1] + jj + ng)) * P + (lo[0] + ii + ng);
+        dst[o + c * fs] = val;
+      }
+      __syncthreads();
     }
   }
 }
@@ -1193,11 +1320,36 @@ static WorkParts work_parts(const wacm_grid* g) {
 
 size_t work_bytes(const wacm_grid* g) { return work_parts(g).total; }
 
+template <typename T, int BS>
+static void sync_coarser_launch(const wacm_grid* g, T* U, hipStream_t st) {
+  sync_coarser_kernel<T, BS><<<grid_for(g->n_cregion, 8), NT_GEN, 0, st>>>(
+      g->d_tab, g->d_cregion, g->n_cregion, U, pool_layout(g));
+}
+
+// Full ghost fill (mode 0): point-wise for same-level and finer regions, and
+// the separable region kernel for regions in a coarser leaf; the face star
+// (mode 1) point-wise.
 template <typename T>
 static hipError_t sync_t(const wacm_grid* g, T* U, int mode, hipStream_t st) {
   if (g->nb == 0) return hipSuccess;
+  const bool split = mode == 0 && g->d.ng <= SC_MAXG && g->n_cregion > 0;
   sync_kernel<T><<<grid_for(g->nb, 8), NT_GEN, 0, st>>>(g->d_tab, g->nb, U, pool_layout(g),
-                                                        g->d.bs, mode);
+                                                        g->d.bs, mode, split ? 1 : 0);
+  if (split) {
+    switch (g->d.bs) {
+      case 16:
+        sync_coarser_launch<T, 16>(g, U, st);
+        break;
+      case 24:
+        sync_coarser_launch<T, 24>(g, U, st);
+        break;
+      case 32:
+        sync_coarser_launch<T, 32>(g, U, st);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
   return hipGetLastError();
 }
 

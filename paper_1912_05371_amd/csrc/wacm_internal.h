@@ -108,6 +108,8 @@ struct wacm_grid {
   int32_t* d_list = nullptr;     // adaptation work lists: capacity * 10 int32
   int32_t* d_cface = nullptr;    // (active index, face) of faces next to another level
   int64_t n_cface = 0;
+  int32_t* d_cregion = nullptr;  // (active index, region) of ghost regions in a coarser leaf
+  int64_t n_cregion = 0;
   int jfine = 0;                 // finest active level
   mutable wacm::Profiler prof;   // kernel timing, off by default
   std::vector<wacm::Tab> h_tab;  // host copy of the tables
@@ -122,6 +124,7 @@ void reorder_leaves(wacm_grid* g);  // Morton order, key index, finest level
 int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err);
 int upload_tables(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err);
 std::vector<int32_t> coarse_faces(const std::vector<Tab>& tabs);  // non-same-level faces
+std::vector<int32_t> coarser_regions(const std::vector<Tab>& tabs);  // regions in coarser leaves
 uint64_t morton_key(const Leaf& l);
 void set_error(const std::string& s);
 

@@ -2,9 +2,9 @@
 
 Tolerances (relative max-norm over the interiors of the 4-component state,
 after one step from bit-identical inputs): FP64 1e-12, FP32 1e-5 (the FP32
-input is the FP64 state rounded to FP32).  Ghost values of the FP64 path are
-copies or 4-64 term sums with weights exact in binary, so they must agree to
-a few ulps.  The FP32 rhs alone is compared against a bound derived from the
+input is the FP64 state rounded to FP32).  Ghost values are copies or
+tensor-product DD4 predictions with weights exact in binary, evaluated as
+three 4-term passes (< 16 ulp of the field's max).  The FP32 rhs alone is compared against a bound derived from the
 size of its largest terms (C0^2 |u| sum|a_m| / h), since the pressure
 equation amplifies rounding by C0^2 / h.
 """
@@ -70,7 +70,10 @@ def test_sync_matches_oracle(orc, name, prec):
     Ug = from_pool(pool, np.arange(og.nb))
     assert not np.isnan(Ug).any()
     scale = np.max(np.abs(Uo))
-    tol = 8 * np.finfo(np.float64 if prec == "f64" else np.float32).eps * scale
+    # regions in a coarser leaf are predicted separably: three passes of
+    # 4-term sums with weight sums 1.25 per axis bound the rounding by
+    # 3 eps (1.25 + 1.25^2 + 1.25^3) max|u| < 16 eps max|u|
+    tol = 16 * np.finfo(np.float64 if prec == "f64" else np.float32).eps * scale
     err = np.max(np.abs(Ug - Uo))
     log(f"  max ghost diff {err:.3e} (tol {tol:.1e})")
     assert err <= tol
