@@ -327,12 +327,14 @@ int wacm_rk4_step_adj(wacm_grid* grid, const wacm_params* prm, double t, double 
 
 /*
  * Measurement support (not part of the method).  wacm_profile_enable(g, 1)
- * makes wacm_rk4_step record a HIP event pair around each group of kernels it
- * launches on its stream; do not enable it while the stream is being captured
- * into a graph.  wacm_profile_read waits for the recorded events and returns,
- * per kernel class [0 time-step reduction, 1 ghost synchronisation, 2 fused
- * rhs + RK stage, 3 time update], the summed milliseconds and the number of
- * timed launches since the last read (host arrays of 4), then resets them.
+ * makes wacm_rk4_step / wacm_rk4_steps record a HIP event pair around each
+ * group of kernels they launch on their stream; do not enable it while the
+ * stream is being captured into a graph.  wacm_profile_read waits for the
+ * recorded events and returns, per kernel class [0 time-step reduction,
+ * 1 face halo of faces next to another level (the stage's ghost values that
+ * are not read in place), 2 fused rhs + RK stage, 3 time update], the summed
+ * milliseconds and the number of timed launches since the last read (host
+ * arrays of 4), then resets them.
  */
 int wacm_profile_enable(wacm_grid* grid, int32_t on);
 int wacm_profile_read(wacm_grid* grid, double* ms, int64_t* launches);

@@ -219,3 +219,35 @@ def test_adaptive_plate_replay(orc, prec):
             assert disagree == 0
         og, U, t = og_n, U_n, t + dt
         del gg
+
+
+def test_adaptive_driver_matches_oracle(orc):
+    """adaptive.adaptive_step (the ABI calls of Sec. 3.5 in sequence, with the
+    GPU's own coarsening flags) against the oracle's adaptive step, 2 steps of
+    the rotating plate in FP64: same leaves and states to 1e-12."""
+    from paper_1912_05371_amd.adaptive import adaptive_step
+    c = plate_small()
+    eps, dealias = c.extra["eps"], c.extra["dealias"]
+    log(f"adaptive driver, plate {c.nb} blocks")
+    og = orc.Grid(c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix, c.iy, c.iz)
+    U = c.padded()
+    gg = wacm.Grid.from_case(c, dtype=wacm.F64, capacity=12 * c.nb + 64)
+    pool = put(gg, og, U)
+    work = gg.work()
+    t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t = 0.0
+    for step in range(2):
+        og, U, dt, passes = adaptive_step_oracle(og, U, c.params, t, eps, dealias)
+        t += dt
+        timings = {}
+        merged = adaptive_step(gg, c.params, pool, work, t_dev, dt_dev, eps, dealias,
+                               timings=timings)["merged_passes"]
+        assert same_leaves(gg, og)
+        e = rel_err(from_pool(pool, slot_map(gg, og)), U, c.bs, c.ng)
+        log(f"  step {step}: {og.nb} blocks, {merged} merging passes (oracle {len(passes)}), "
+            f"state rel err {e:.2e}, dt {float(dt_dev.item()):.6e} vs {dt:.6e}; "
+            f"{ {k: round(v, 2) for k, v in timings.items()} } ms")
+        assert merged == len(passes)
+        assert e < 1e-12
+        assert abs(float(t_dev.item()) - t) <= 1e-12 * t
