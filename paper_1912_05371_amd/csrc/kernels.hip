@@ -1110,52 +1110,77 @@ __global__ __launch_bounds__(NT_GEN) void detail_kernel(
 // --------------------------------------------------------------------------
 // refinement (prediction into 8 children) and coarsening (decimation)
 // --------------------------------------------------------------------------
-template <typename T>
+// Refinement (Sec. 3.1 prediction, Sec. 3.5): child octant oct of a
+// ghost-synchronised parent.  Child point (i, j, k) is the parent's fine-grid
+// point Q = off + (i, j, k), off = octant offset (0 or bs per axis); even Q
+// copy the parent point Q/2, odd Q use the DD4 taps (Q-3)/2 .. (Q+3)/2 (the
+// parent's ghost layers included).  Separable and z-marching as in
+// detail_kernel: for each parent plane an x pass on the parent rows and a y
+// pass into a ring of 4 planes in LDS, then the z pass writes the child
+// planes the ring completes.
+template <typename T, int BS>
 __global__ __launch_bounds__(NT_GEN) void prolong_kernel(const int32_t* __restrict__ list,
-                                                         int64_t n, T* __restrict__ U, Layout L,
-                                                         int bs) {
-  const int n3 = bs * bs * bs;
+                                                         int64_t n, T* __restrict__ U, Layout L) {
+  constexpr int S = BS / 2 + 4;  // parent points per axis: off/2 - 2 .. off/2 + bs/2 + 1
+  constexpr int B2 = BS * BS;
+  __shared__ T xp[S * BS];
+  __shared__ T yr[4][B2];
+  const T w0 = T(DDW0), w1 = T(DDW1);
+  const int tid = threadIdx.x, P = L.P, ng = L.ng;
   for (int64_t w = blockIdx.x; w < n; w += gridDim.x) {
     const int32_t ps = list[3 * w], cs = list[3 * w + 1], oct = list[3 * w + 2];
-    const int off[3] = {(oct & 1) * bs, ((oct >> 1) & 1) * bs, ((oct >> 2) & 1) * bs};
+    const int h0 = (oct & 1) * (BS / 2) - 2, h1 = ((oct >> 1) & 1) * (BS / 2) - 2,
+              h2 = ((oct >> 2) & 1) * (BS / 2) - 2;  // first parent index per axis
     const T* par = U + (int64_t)ps * L.bstride;
     T* ch = U + (int64_t)cs * L.bstride;
-    for (int q = threadIdx.x; q < n3; q += blockDim.x) {
-      const int i = q % bs, j = (q / bs) % bs, k = q / (bs * bs);
-      const int Q[3] = {off[0] + i, off[1] + j, off[2] + k};
-      int tq[3][4];
-      T wq[3][4];
-      int nq[3];
-      for (int d = 0; d < 3; ++d) {
-        if ((Q[d] & 1) == 0) {
-          tq[d][0] = Q[d] >> 1;
-          wq[d][0] = T(1);
-          nq[d] = 1;
-        } else {
-          tq[d][0] = (Q[d] - 3) >> 1;
-          tq[d][1] = (Q[d] - 1) >> 1;
-          tq[d][2] = (Q[d] + 1) >> 1;
-          tq[d][3] = (Q[d] + 3) >> 1;
-          wq[d][0] = T(DDW0);
-          wq[d][1] = T(DDW1);
-          wq[d][2] = T(DDW1);
-          wq[d][3] = T(DDW0);
-          nq[d] = 4;
+    auto pidx = [&](int i, int j, int k) -> int64_t {
+      return ((int64_t)(k + ng) * P + (j + ng)) * P + (i + ng);
+    };
+    for (int c = 0; c < 4; ++c) {
+      const T* pc = par + c * L.fstride;
+      T* cc = ch + c * L.fstride;
+      for (int mm = 0; mm < S; ++mm) {
+        const int kz = h2 + mm;  // parent plane
+        __syncthreads();
+        // x pass: xp[jj][i] for the parent rows j = h1 + jj; child i has
+        // Q = 2 (h0 + 2) + i, even -> parent point Q/2, odd -> taps
+        for (int q = tid; q < S * BS; q += NT_GEN) {
+          const int jj = q / BS, i = q - jj * BS;
+          const int64_t row = pidx(0, h1 + jj, kz);
+          const int base = h0 + 2 + (i >> 1);  // parent index of Q/2 (even Q)
+          T v;
+          if ((i & 1) == 0)
+            v = pc[row + base];
+          else  // taps (Q-3)/2 .. (Q+3)/2 = base-1 .. base+2
+            v = w0 * pc[row + base - 1] + w1 * pc[row + base] + w1 * pc[row + base + 1] +
+                w0 * pc[row + base + 2];
+          xp[q] = v;
+        }
+        __syncthreads();
+        T* yo = yr[mm & 3];
+        for (int q = tid; q < B2; q += NT_GEN) {
+          const int j = q / BS, i = q - j * BS;
+          const int jj = 2 + (j >> 1);  // row of Q/2 in xp
+          T v;
+          if ((j & 1) == 0)
+            v = xp[jj * BS + i];
+          else
+            v = w0 * xp[(jj - 1) * BS + i] + w1 * xp[jj * BS + i] + w1 * xp[(jj + 1) * BS + i] +
+                w0 * xp[(jj + 2) * BS + i];
+          yo[q] = v;
+        }
+        __syncthreads();
+        // z pass: child plane k even uses plane mm = 2 + k/2; k odd uses
+        // planes 1 + (k-1)/2 .. 4 + (k-1)/2, complete when mm = 4 + (k-1)/2
+        const int ke = 2 * (mm - 2), ko = 2 * (mm - 4) + 1;
+        for (int q = tid; q < B2; q += NT_GEN) {
+          const int j = q / BS, i = q - j * BS;
+          if (ke >= 0 && ke < BS) cc[pidx(i, j, ke)] = yo[q];
+          if (ko >= 0 && ko < BS)
+            cc[pidx(i, j, ko)] = w0 * yr[(mm + 1) & 3][q] + w1 * yr[(mm + 2) & 3][q] +
+                                 w1 * yr[(mm + 3) & 3][q] + w0 * yo[q];
         }
       }
-      T acc[4] = {T(0), T(0), T(0), T(0)};
-      for (int a = 0; a < nq[2]; ++a)
-        for (int b = 0; b < nq[1]; ++b) {
-          const T wzy = wq[2][a] * wq[1][b];
-          for (int e = 0; e < nq[0]; ++e) {
-            const T wgt = wzy * wq[0][e];
-            const int64_t o = ((int64_t)(tq[2][a] + L.ng) * L.P + (tq[1][b] + L.ng)) * L.P +
-                              (tq[0][e] + L.ng);
-            for (int c = 0; c < 4; ++c) acc[c] += wgt * par[o + c * L.fstride];
-          }
-        }
-      const int64_t o = ((int64_t)(k + L.ng) * L.P + (j + L.ng)) * L.P + (i + L.ng);
-      for (int c = 0; c < 4; ++c) ch[o + c * L.fstride] = acc[c];
     }
   }
 }
@@ -1627,15 +1652,29 @@ hipError_t launch_threshold(const wacm_grid* g, const wacm_params* p, double t, 
              : thr_t(g, p, t, (const float*)U, eps, dealias, dmax, mrange, flags, st);
 }
 
+template <typename T>
+static hipError_t prolong_t(const wacm_grid* g, T* U, int64_t n, hipStream_t st) {
+  const unsigned grid = grid_for(n, 8);
+  switch (g->d.bs) {
+    case 16:
+      prolong_kernel<T, 16><<<grid, NT_GEN, 0, st>>>(g->d_list, n, U, pool_layout(g));
+      break;
+    case 24:
+      prolong_kernel<T, 24><<<grid, NT_GEN, 0, st>>>(g->d_list, n, U, pool_layout(g));
+      break;
+    case 32:
+      prolong_kernel<T, 32><<<grid, NT_GEN, 0, st>>>(g->d_list, n, U, pool_layout(g));
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_prolong(const wacm_grid* g, void* U, int64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  if (g->d.dtype == WACM_F64)
-    prolong_kernel<double><<<grid_for(n, 8), NT_GEN, 0, st>>>(g->d_list, n, (double*)U,
-                                                             pool_layout(g), g->d.bs);
-  else
-    prolong_kernel<float><<<grid_for(n, 8), NT_GEN, 0, st>>>(g->d_list, n, (float*)U,
-                                                            pool_layout(g), g->d.bs);
-  return hipGetLastError();
+  return g->d.dtype == WACM_F64 ? prolong_t(g, (double*)U, n, st)
+                                : prolong_t(g, (float*)U, n, st);
 }
 
 hipError_t launch_decimate(const wacm_grid* g, void* U, int64_t n, hipStream_t st) {
