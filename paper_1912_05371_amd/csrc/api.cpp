@@ -336,13 +336,13 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
       int64_t px = l.x >> 1, py = l.y >> 1, pz = l.z >> 1;
       if (merge) {
         for (int c = 0; c < 8 && merge; ++c) {
-          auto it = g->index.find(
+          const int32_t si = g->index.find(
               leaf_key(l.J, 2 * px + (c & 1), 2 * py + ((c >> 1) & 1), 2 * pz + ((c >> 2) & 1)));
-          if (it == g->index.end() || !flags[it->second]) {
+          if (si < 0 || !flags[si]) {
             merge = false;
           } else {
-            sidx[c] = it->second;
-            sis[c] = g->slots[it->second];
+            sidx[c] = si;
+            sis[c] = g->slots[si];
           }
         }
       }
@@ -363,7 +363,7 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
               bool covered = false;
               for (int K = l.J; K >= g->d.jmin && !covered; --K) {
                 int s = l.J + 1 - K;
-                covered = g->index.count(leaf_key(K, bx >> s, by >> s, bz >> s)) > 0;
+                covered = g->index.find(leaf_key(K, bx >> s, by >> s, bz >> s)) >= 0;
               }
               if (!covered) merge = false;
             }

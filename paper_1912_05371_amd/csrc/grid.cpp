@@ -29,9 +29,8 @@ static inline int64_t wrapi(int64_t a, int64_t n) {
 // Slot of the active leaf (J, x, y, z), or -1.
 static int32_t find_slot(const wacm_grid* g, int J, int64_t x, int64_t y, int64_t z) {
   if (J < 0) return -1;
-  auto it = g->index.find(leaf_key(J, x, y, z));
-  if (it == g->index.end()) return -1;
-  return g->slots[it->second];
+  const int32_t i = g->index.find(leaf_key(J, x, y, z));
+  return i < 0 ? -1 : g->slots[i];
 }
 
 // Sort active blocks into Morton order and rebuild the key index.
@@ -50,12 +49,11 @@ void reorder_leaves(wacm_grid* g) {
   g->leaves.swap(L);
   g->slots.swap(S);
   g->nb = (int64_t)g->leaves.size();
-  g->index.clear();
-  g->index.reserve(g->leaves.size() * 2);
+  g->index.build(g->leaves.size());
   g->jfine = g->d.jmin;
   for (int64_t i = 0; i < g->nb; ++i) {
     const Leaf& l = g->leaves[i];
-    g->index[leaf_key(l.J, l.x, l.y, l.z)] = (int32_t)i;
+    g->index.insert(leaf_key(l.J, l.x, l.y, l.z), (int32_t)i);
     g->jfine = std::max(g->jfine, l.J);
   }
 }
@@ -67,7 +65,6 @@ int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err) {
   for (int64_t i = 0; i < nb; ++i) {
     const Leaf& b = g->leaves[i];
     Tab& t = tabs[i];
-    std::memset(&t, 0, sizeof(Tab));
     t.meta[0] = g->slots[i];
     t.meta[1] = b.J;
     t.meta[2] = (int32_t)b.x;

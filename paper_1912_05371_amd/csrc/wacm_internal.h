@@ -65,6 +65,53 @@ inline uint64_t leaf_key(int J, int64_t x, int64_t y, int64_t z) {
   return (uint64_t(J) << 57) | (uint64_t(x) << 38) | (uint64_t(y) << 19) | uint64_t(z);
 }
 
+// Leaf key -> active index: open addressing with linear probing in a
+// power-of-two table at most half full (the table building does ~30 lookups
+// per block, so this is the host-side cost of every adaptation).
+class LeafIndex {
+ public:
+  void build(size_t n) {
+    size_t cap = 16;
+    int bits = 4;
+    while (cap < 2 * n) {
+      cap <<= 1;
+      ++bits;
+    }
+    keys_.assign(cap, kEmpty);
+    vals_.assign(cap, -1);
+    mask_ = cap - 1;
+    shift_ = 64 - bits;
+  }
+  void insert(uint64_t k, int32_t v) {
+    size_t h = slot(k);
+    while (keys_[h] != kEmpty && keys_[h] != k) h = (h + 1) & mask_;
+    keys_[h] = k;
+    vals_[h] = v;
+  }
+  int32_t find(uint64_t k) const {
+    if (keys_.empty()) return -1;
+    for (size_t h = slot(k);; h = (h + 1) & mask_) {
+      if (keys_[h] == k) return vals_[h];
+      if (keys_[h] == kEmpty) return -1;
+    }
+  }
+  void swap(LeafIndex& o) {
+    keys_.swap(o.keys_);
+    vals_.swap(o.vals_);
+    std::swap(mask_, o.mask_);
+    std::swap(shift_, o.shift_);
+  }
+
+ private:
+  static constexpr uint64_t kEmpty = ~uint64_t(0);  // no leaf key has all bits set
+  // Fibonacci hashing: the top bits of the product mix every key bit
+  size_t slot(uint64_t k) const { return (size_t)((k * 0x9E3779B97F4A7C15ull) >> shift_); }
+  std::vector<uint64_t> keys_;
+  std::vector<int32_t> vals_;
+  size_t mask_ = 0;
+  int shift_ = 60;
+};
+
 // Event-based timing of the kernels rk4_step launches (measurement only).
 struct Profiler {
   struct Rec {
@@ -99,7 +146,7 @@ struct wacm_grid {
   int64_t nb = 0;
   std::vector<wacm::Leaf> leaves;      // active, Morton order
   std::vector<int32_t> slots;          // pool slot of each active block
-  std::unordered_map<uint64_t, int32_t> index;  // leaf key -> active index
+  wacm::LeafIndex index;               // leaf key -> active index
   std::vector<int32_t> free_slots;     // unused pool slots (stack)
   // device tables, sized for `capacity` blocks
   wacm::Tab* d_tab = nullptr;
