@@ -19,10 +19,10 @@ compulsory interior traffic of classical RK4 with 3 + 1 registers, 16 values
 per interior point and stage (stage 1 reads U^n and writes the accumulator
 and the next input, 12; stages 2 and 3 read the input, U^n and the
 accumulator and write two registers, 20; stage 4 reads the input and the
-accumulator and writes U^{n+1}, 12).  The implementation itself moves 14
-(stage 1 writes only the next input, stage 2 forms the first accumulator from
-U^n and its input); `moved_min_bytes_per_launch` states that figure, and
-`traffic` the bytes the hardware counters saw.
+accumulator and writes U^{n+1}, 12).  The implementation itself moves 12
+(8, 16, 12, 12 for stages 1-4: only stage 2 writes a second register, which
+with the stage-4 input gives U^{n+1}); `moved_min_bytes_per_launch` states
+that figure, and `traffic` the bytes the hardware counters saw.
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 5]
 """
@@ -192,7 +192,7 @@ def roofline(res, npts: int, es: int):
         "kernel_avg_ms": round(stage_ms, 4),
         "bytes_per_launch": bytes_per_launch,
         # interior bytes the implementation itself moves per launch (8, 16, 20, 12 values)
-        "moved_min_bytes_per_launch": 14 * es * npts,
+        "moved_min_bytes_per_launch": 12 * es * npts,
         "whole_step_frac": round(step_bytes / (res["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                  4),
     }

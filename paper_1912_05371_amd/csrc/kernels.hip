@@ -328,13 +328,16 @@ __device__ __forceinline__ void ntstore(T v, T* p, int nt) {
 }
 
 // MODE 0: dU = rhs(U) with U's own ghost layers.  MODE s = 1..4: classical
-// RK4 stage s with registers U^n, acc and the stage inputs:
+// RK4 stage s with registers U^n, W and the stage inputs Y_s:
 //   s1: out = Y2 = U^n + dt/2 k1                    (input = U^n)
-//   s2: acc = U^n + (Y2 - U^n)/3 + dt/3 k2, out = U^n + dt/2 k2: U^n + dt/6 k1
-//       is formed from the input Y2 and U^n, so stage 1 writes one register
-//       instead of two (same value up to rounding of U^n's size)
-//   s3: acc += dt/3 k3,      out = U^n + dt k3
-//   s4: U^{n+1} = acc + dt/6 k4
+//   s2: out = Y3 = U^n + dt/2 k2,  W = (U^n + Y2)/3 + dt/3 k2
+//   s3: out = Y4 = U^n + dt k3
+//   s4: U^{n+1} = W + Y4/3 + dt/6 k4
+// Since dt k1 = 2 (Y2 - U^n) and dt k3 = Y4 - U^n, the update
+// U^n + dt/6 (k1 + 2 k2 + 2 k3 + k4) equals W + Y4/3 + dt/6 k4 with
+// W = 2/3 U^n + dt/6 k1 + dt/3 k2: only stage 2 writes a second register and
+// stages 3 and 4 read one besides their input (same values up to rounding of
+// U^n's size).
 // PEN: penalization/sponge terms present.  PREF: load the epilogue operands
 // (U^n, acc) before the barrier instead of after the rhs.  Work items are
 // tiles of TY rows of a block's (x,y) columns (TY = BS: the whole block), one
@@ -368,7 +371,7 @@ void stage_kernel(StageArgs<T> a) {
     dt = *a.dt_dev;
   }
   const T nu = T(a.p.nu), c0sq = T(a.p.c0 * a.p.c0), cg = T(a.p.c_gamma);
-  const T fA = T(MODE == 4 ? dt / 6.0 : dt / 3.0);
+  const T fA = T(MODE == 4 ? dt / 6.0 : dt / 3.0);  // k weight of W (s2) and of U^{n+1} (s4)
   // the stage time and what of the mask depends on it alone
   const double ts = tc + (MODE == 2 || MODE == 3 ? 0.5 * dt : (MODE == 4 ? dt : 0.0));
   const MaskTime mt = PEN && a.p.mask ? mask_time(a.p, ts) : MaskTime{1.0, 0.0, 0.0};
@@ -527,7 +530,7 @@ void stage_kernel(StageArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           if (MODE == 2 || MODE == 3) unv[c] = ntload(unb + c * ufs + z * uzs, a.nt);
-          if (MODE == 3 || MODE == 4) acv[c] = ntload(accb + c * afs + z * azs, a.nt);
+          if (MODE == 4) acv[c] = ntload(accb + c * afs + z * azs, a.nt);
         }
       }
       lds_barrier();
@@ -587,17 +590,18 @@ void stage_kernel(StageArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           if (MODE == 2 || MODE == 3) unv[c] = ntload(unb + c * ufs + z * uzs, a.nt);
-          if (MODE == 3 || MODE == 4) acv[c] = ntload(accb + c * afs + z * azs, a.nt);
+          if (MODE == 4) acv[c] = ntload(accb + c * afs + z * azs, a.nt);
         }
       }
       if (MODE == 0) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) outb[c * ofs + z * ozs] = r[c];
       } else if (MODE == 4) {
+        const T val[4] = {u, v, w, pr};
         T nv[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          nv[c] = acv[c] + fA * r[c];
+          nv[c] = acv[c] + val[c] * T(1.0 / 3.0) + fA * r[c];
           ntstore(nv[c], unb + c * ufs + z * uzs, a.nt);
         }
         // The x-ghost columns of the row are cleared too, so that every cache
@@ -615,11 +619,8 @@ void stage_kernel(StageArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const T u0 = MODE == 1 ? val[c] : unv[c];
-          if (MODE != 1) {
-            // stage 2 forms U^n + dt/6 k1 from its input Y2 = U^n + dt/2 k1
-            const T ac = MODE == 2 ? u0 + (val[c] - u0) * T(1.0 / 3.0) : acv[c];
-            ntstore(ac + fA * r[c], accb + c * afs + z * azs, a.nt);
-          }
+          // (U^n + Y2)/3 = 2/3 U^n + dt/6 k1, from the input Y2 = U^n + dt/2 k1
+          if (MODE == 2) ntstore((u0 + val[c]) * T(1.0 / 3.0) + fA * r[c], accb + c * afs + z * azs, a.nt);
           outb[c * ofs + z * ozs] = u0 + fB * r[c];
         }
       }
