@@ -89,7 +89,10 @@ typedef struct {
  * only: results do not depend on it).  wg_per_cu: persistent workgroups per
  * compute unit (0: as many as are resident); xcd_map: 1 gives each of the 8
  * XCDs a contiguous run of the Morton-ordered blocks (shared faces meet in one
- * L2), 0 deals the work items round-robin; prefetch: 1 loads U^n and the accumulator before a plane's barrier, 0
+ * L2), 2 does the same through per-XCD work counters from which each
+ * workgroup takes its next item, moving on to the other XCDs' runs when its
+ * own is empty (calls on one grid must then not overlap in time: they share
+ * the counters), 0 deals the work items round-robin; prefetch: 1 loads U^n and the accumulator before a plane's barrier, 0
  * after the rhs, -1 default; nontemporal: 1 streams U^n and the accumulator
  * with non-temporal loads/stores; tile_rows: 0 gives each workgroup a whole
  * block (bs^2 threads), 8 a tile of 8 rows of the block's columns (8 bs
@@ -157,7 +160,7 @@ int64_t wacm_grid_nb(const wacm_grid* grid);
 int wacm_grid_info(const wacm_grid* grid, int64_t* slots, uint64_t* treecodes, int8_t* levels);
 
 /* Set / read the stage-kernel schedule (values checked: wg_per_cu in [0, 16],
- * xcd_map and nontemporal in {0, 1}, prefetch in {-1, 0, 1}, tile_rows in
+ * xcd_map in {0, 1, 2}, nontemporal in {0, 1}, prefetch in {-1, 0, 1}, tile_rows in
  * {0, 8}). */
 int wacm_set_schedule(wacm_grid* grid, const wacm_schedule* s);
 int wacm_get_schedule(const wacm_grid* grid, wacm_schedule* s);

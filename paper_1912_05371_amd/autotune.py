@@ -21,7 +21,7 @@ import numpy as np
 from . import wacm
 
 CANDIDATES = [dict(wg_per_cu=w, xcd_map=x, prefetch=p, nontemporal=n, tile_rows=ty)
-              for ty, w, x, p, n in itertools.product((0, 8), (0, 2), (0, 1), (0, 1), (0, 1))]
+              for ty, w, x, p, n in itertools.product((0, 8), (0, 2), (0, 1, 2), (0, 1), (0, 1))]
 
 
 SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_schedules.json")

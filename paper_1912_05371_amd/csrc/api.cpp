@@ -42,6 +42,7 @@ void free_dev(wacm_grid* g) {
   if (g->d_tab) (void)hipFree(g->d_tab);
   if (g->d_part) (void)hipFree(g->d_part);
   if (g->d_norm) (void)hipFree(g->d_norm);
+  if (g->d_queue) (void)hipFree(g->d_queue);
   if (g->d_list) (void)hipFree(g->d_list);
   if (g->d_cface) (void)hipFree(g->d_cface);
   if (g->d_cregion) (void)hipFree(g->d_cregion);
@@ -50,6 +51,7 @@ void free_dev(wacm_grid* g) {
   g->d_tab = nullptr;
   g->d_part = nullptr;
   g->d_norm = nullptr;
+  g->d_queue = nullptr;
   g->d_list = nullptr;
 }
 
@@ -164,6 +166,7 @@ int wacm_grid_create(const wacm_grid_desc* d, int64_t nleaves, const uint64_t* t
   if ((e = hipMalloc(&g->d_tab, sizeof(Tab) * d->capacity)) != hipSuccess ||
       (e = hipMalloc(&g->d_part, sizeof(double) * 16 * (d->capacity + 1024))) != hipSuccess ||
       (e = hipMalloc(&g->d_norm, sizeof(double) * 16)) != hipSuccess ||
+      (e = hipMalloc(&g->d_queue, sizeof(int32_t) * 256)) != hipSuccess ||
       (e = hipMalloc(&g->d_list, sizeof(int32_t) * 10 * d->capacity)) != hipSuccess ||
       (e = hipMalloc(&g->d_cface, sizeof(int32_t) * 12 * d->capacity)) != hipSuccess ||
       (e = hipMalloc(&g->d_cregion, sizeof(int32_t) * 52 * d->capacity)) != hipSuccess) {
@@ -205,7 +208,7 @@ size_t wacm_work_bytes(const wacm_grid* g) { return g ? work_bytes(g) : 0; }
 
 int wacm_set_schedule(wacm_grid* g, const wacm_schedule* s) {
   if (!g || !s) return fail(WACM_E_INVAL, "NULL argument");
-  if (s->wg_per_cu < 0 || s->wg_per_cu > 16 || (s->xcd_map != 0 && s->xcd_map != 1) ||
+  if (s->wg_per_cu < 0 || s->wg_per_cu > 16 || s->xcd_map < 0 || s->xcd_map > 2 ||
       s->prefetch < -1 || s->prefetch > 1 || (s->nontemporal != 0 && s->nontemporal != 1) ||
       (s->tile_rows != 0 && s->tile_rows != 8))
     return fail(WACM_E_INVAL, "schedule value out of range");

@@ -194,6 +194,9 @@ __global__ __launch_bounds__(NT_GEN) void sync_coarser_kernel(const Tab* __restr
 // flight (they are the next plane's prefetch).
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  // s_waitcnt lgkmcnt(0): this wave's LDS writes have completed before it
+  // arrives (the fence alone need not wait for them)
+  __builtin_amdgcn_s_waitcnt(0xC07F);
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
@@ -218,6 +221,7 @@ struct StageArgs {
   double t_host;
   double L;
   int xcd_map;  // 1: give each XCD a contiguous run of work items
+  int* queue;   // xcd_map 2: per-XCD work counters (QSTRIDE apart), zero at launch
   int nt;       // 1: non-temporal loads/stores of the streaming operands
   wacm_params p;
 };
@@ -244,6 +248,30 @@ struct BlockIter {
     }
   }
 };
+
+// Dynamic per-XCD work queues (xcd_map 2): the Morton-ordered items are cut
+// into 8 contiguous chunks, one per XCD; workgroup w (on XCD w % 8) takes the
+// next item of its own chunk from that chunk's counter, so the tiles of one
+// block and neighbouring blocks run together on one L2, and when its chunk is
+// empty it takes items from the following chunks, so no XCD idles while
+// another still has work.  Each counter increment that finds a chunk empty
+// moves on to the next chunk: at most 8 misses per workgroup, so every
+// workgroup ends.  Thread 0 only.
+constexpr int QSTRIDE = 32;  // ints between counters: one 128-byte line each
+__device__ __forceinline__ int queue_take(int* ctr, int& q, int chunk, int n, int v) {
+  for (int miss = 0;;) {
+    const int lo = q * chunk;
+    const int hi = lo + chunk < n ? lo + chunk : n;
+    if (lo + v < hi) return lo + v;
+    if (++miss == 8) return n;
+    q = (q + 1) & 7;
+    v = atomicAdd(ctr + q * QSTRIDE, 1);
+  }
+}
+
+__global__ void queue_clear(int* ctr) {
+  if (threadIdx.x < 8 * QSTRIDE) ctr[threadIdx.x] = 0;
+}
 
 // Where the depth-3 halo of one face of the current block lives: element
 // (field c, depth d away from the face, tangential t0 < t1 by axis order) is
@@ -361,6 +389,7 @@ void stage_kernel(StageArgs<T> a) {
   __shared__ FaceDesc<T> fds[6];
   __shared__ int32_t meta[5];
   __shared__ double red[NT / 64];
+  __shared__ int qitem;
   const int tid = threadIdx.x;
   const int x = tid % BS, yl = tid / BS;
   const T a1 = T(TW1), a2 = T(TW2), a3 = T(TW3);
@@ -407,15 +436,28 @@ void stage_kernel(StageArgs<T> a) {
   const int ozs = XOUT ? xsplit_zstride(BS, x) : a.Lout.P * a.Lout.P;
   const int ofs = (int)a.Lout.fstride;
 
-  for (BlockIter it(a.nb * NTY, a.xcd_map); it.ib < it.end; it.ib += it.step) {
-    const int64_t item = it.ib;
+  // work items: static (round-robin or contiguous per XCD) or from the
+  // per-XCD queues, whose next item thread 0 requests while the current one
+  // is processed and publishes in qitem before the loop's first barrier
+  const int64_t nitems = a.nb * NTY;
+  const bool dyn = a.queue != nullptr;
+  BlockIter it(nitems, a.xcd_map);
+  int qh = blockIdx.x & 7, qpend = 0;
+  const int qchunk = (int)((nitems + 7) / 8);
+  if (dyn && tid == 0) qitem = queue_take(a.queue, qh, qchunk, (int)nitems,
+                                          atomicAdd(a.queue + qh * QSTRIDE, 1));
+  for (;;) {
+    lds_barrier();
+    const int64_t item = dyn ? (int64_t)__builtin_amdgcn_readfirstlane(qitem) : it.ib;
+    if (item >= (dyn ? nitems : it.end)) break;
+    if (!dyn) it.ib += it.step;
     const int64_t ibk = item / NTY;
     const int y0 = (int)(item - ibk * NTY) * TY;
     const int y = y0 + yl;
-    lds_barrier();
     if (tid < 6) fds[tid] = face_desc<T, BS, GH>(a.tab[ibk], a, tid, xin);
     if (tid < 5) meta[tid] = a.tab[ibk].meta[tid];
     lds_barrier();
+    if (dyn && tid == 0) qpend = atomicAdd(a.queue + qh * QSTRIDE, 1);
     // offsets of this thread's column in the input, accumulator and U^n
     const int col = xin ? xsplit_offset(BS, x, y, 0)
                         : (a.Lin.ng * Pi + (y + a.Lin.ng)) * Pi + (x + a.Lin.ng);
@@ -656,6 +698,7 @@ void stage_kernel(StageArgs<T> a) {
         a.umax_part[item] = mx;
       }
     }
+    if (dyn && tid == 0) qitem = queue_take(a.queue, qh, qchunk, (int)nitems, qpend);
   }
 }
 
@@ -1402,6 +1445,11 @@ static hipError_t stage_launch_t(const StageArgs<T>& a, int wg_per_cu, hipStream
   int64_t grid = (int64_t)per_cu * num_cus();
   if (grid > items) grid = items;
   if (grid < 1) grid = 1;
+  if (a.queue) {
+    queue_clear<<<1, 8 * QSTRIDE, 0, st>>>(a.queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   stage_kernel<T, BS, TY, MODE, PEN, PREF><<<(unsigned)grid, BS * TY, 0, st>>>(a);
   return hipGetLastError();
 }
@@ -1455,6 +1503,7 @@ static StageArgs<T> base_args(const wacm_grid* g, const wacm_params* p) {
   a.nb = g->nb;
   a.L = g->d.L;
   a.xcd_map = g->sched.xcd_map;
+  a.queue = g->sched.xcd_map == 2 ? g->d_queue : nullptr;
   a.nt = g->sched.nontemporal;
   a.p = *p;
   return a;

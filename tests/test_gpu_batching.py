@@ -108,6 +108,8 @@ def test_autotuner_picks_a_candidate(octree, tmp_path, monkeypatch):
     assert best2 == best
     with pytest.raises(wacm.WacmError):
         g.set_schedule(prefetch=3)
+    with pytest.raises(wacm.WacmError):
+        g.set_schedule(xcd_map=3)
 
 
 def _steps_vs_step(g, params, U0, n, dt_mode, dt0=0.0):

@@ -117,7 +117,8 @@ def test_fullsize_multi_step_call_and_schedules_bitwise(full):
     t, dt = scalars()
     g.rk4_steps(c.params, t, dt, A, work, 2, dt_mode=wacm.DT_CFL)
     for sched in (dict(BENCH_SCHEDULE), dict(tile_rows=0, wg_per_cu=0, xcd_map=1, prefetch=0,
-                                              nontemporal=0)):
+                                              nontemporal=0),
+                  dict(tile_rows=8, wg_per_cu=0, xcd_map=2, prefetch=0, nontemporal=1)):
         g.set_schedule(**sched)
         B = U0.clone()
         t2, dt2 = scalars()
