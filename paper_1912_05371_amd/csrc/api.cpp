@@ -166,7 +166,7 @@ int wacm_grid_create(const wacm_grid_desc* d, int64_t nleaves, const uint64_t* t
   if ((e = hipMalloc(&g->d_tab, sizeof(Tab) * d->capacity)) != hipSuccess ||
       (e = hipMalloc(&g->d_part, sizeof(double) * 16 * (d->capacity + 1024))) != hipSuccess ||
       (e = hipMalloc(&g->d_norm, sizeof(double) * 16)) != hipSuccess ||
-      (e = hipMalloc(&g->d_queue, sizeof(int32_t) * 256)) != hipSuccess ||
+      (e = hipMalloc(&g->d_queue, sizeof(int32_t) * 512)) != hipSuccess ||
       (e = hipMalloc(&g->d_list, sizeof(int32_t) * 10 * d->capacity)) != hipSuccess ||
       (e = hipMalloc(&g->d_cface, sizeof(int32_t) * 12 * d->capacity)) != hipSuccess ||
       (e = hipMalloc(&g->d_cregion, sizeof(int32_t) * 52 * d->capacity)) != hipSuccess) {

@@ -710,12 +710,15 @@ void stage_kernel(StageArgs<T> a) {
 // hold them) is gathered once, then predicted along the normal and the two
 // tangential axes in turn, one field at a time through LDS.  The loads of all
 // 4 fields are issued together into registers before the first field's
-// passes, so one memory latency per face is exposed instead of four.
+// passes, so one memory latency per face is exposed instead of four.  With
+// `queue` (schedule xcd_map 2) the faces, listed in the blocks' Morton order,
+// are taken from per-XCD work counters like the stage kernel's items, so the
+// faces of sister blocks, which read the same coarse data, meet in one L2.
 template <typename T, int BS>
 __global__ __launch_bounds__(NT_GEN) void nlface_kernel(const Tab* __restrict__ tab,
                                                         const int32_t* __restrict__ cf, int64_t n,
                                                         const T* __restrict__ in, Layout Lin,
-                                                        T* __restrict__ hb) {
+                                                        T* __restrict__ hb, int* queue) {
   constexpr int S = BS / 2 + 3;   // tangential coarse positions -2, 0, ..., bs+2
   constexpr int NSRC = 5 * S * S;  // at most 5 coarse points along the normal
   constexpr int PER = (NSRC + NT_GEN - 1) / NT_GEN;
@@ -725,14 +728,24 @@ __global__ __launch_bounds__(NT_GEN) void nlface_kernel(const Tab* __restrict__ 
   __shared__ T src[NSRC];
   __shared__ T pa[3 * S * S];
   __shared__ T pb[3 * S * BS];
+  __shared__ int qitem;
   const T w0 = T(DDW0), w1 = T(DDW1);
   const int64_t fs = Lin.fstride;
   const int tid = threadIdx.x;
-  for (int64_t wk = blockIdx.x; wk < n; wk += gridDim.x) {
-    const int32_t ib = cf[2 * wk], f = cf[2 * wk + 1];
+  const bool dyn = queue != nullptr;
+  int qh = blockIdx.x & 7, qpend = 0;
+  const int qchunk = (int)((n + 7) / 8);
+  if (dyn && tid == 0) qitem = queue_take(queue, qh, qchunk, (int)n, atomicAdd(queue + qh * QSTRIDE, 1));
+  int64_t wnext = blockIdx.x;
+  for (;;) {
     __syncthreads();
+    const int64_t wk = dyn ? (int64_t)__builtin_amdgcn_readfirstlane(qitem) : wnext;
+    if (wk >= n) break;
+    wnext += gridDim.x;
+    const int32_t ib = cf[2 * wk], f = cf[2 * wk + 1];
     load_tab(tab + ib, st);
     __syncthreads();
+    if (dyn && tid == 0) qpend = atomicAdd(queue + qh * QSTRIDE, 1);
     const int slot = st.meta[0];
     const int axis = f >> 1, side = f & 1;
     const int ua = axis == 0 ? 1 : 0, ub = axis == 2 ? 1 : 2;  // tangential axes t0, t1
@@ -765,6 +778,7 @@ __global__ __launch_bounds__(NT_GEN) void nlface_kernel(const Tab* __restrict__ 
           for (int c = 0; c < 4; ++c) hbf[(int64_t)(c * 3) * B2 + p] = v[k][c];
         }
       }
+      if (dyn && tid == 0) qitem = queue_take(queue, qh, qchunk, (int)n, qpend);
       continue;
     }
     // coarser neighbour.  Normal ghost positions g_d = bs + d (side 1) or
@@ -842,6 +856,7 @@ __global__ __launch_bounds__(NT_GEN) void nlface_kernel(const Tab* __restrict__ 
       }
       __syncthreads();
     }
+    if (dyn && tid == 0) qitem = queue_take(queue, qh, qchunk, (int)n, qpend);
   }
 }
 
@@ -1347,19 +1362,27 @@ static unsigned grid_for(int64_t n, int per_cu) {
   return (unsigned)(n < cap ? (n > 0 ? n : 1) : cap);
 }
 
+// The face-halo kernel follows the stage kernel's XCD mapping: with xcd_map
+// 2 it takes its faces from the second set of work counters.
 template <typename T>
 static hipError_t nlface_launch(const wacm_grid* g, const T* in, const Layout& Lin, T* hb,
                                 hipStream_t st) {
   const unsigned grid = grid_for(g->n_cface, 8);
+  int* q = g->sched.xcd_map == 2 ? g->d_queue + 8 * QSTRIDE : nullptr;
+  if (q) {
+    queue_clear<<<1, 8 * QSTRIDE, 0, st>>>(q);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   switch (g->d.bs) {
     case 16:
-      nlface_kernel<T, 16><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->d_cface, g->n_cface, in, Lin, hb);
+      nlface_kernel<T, 16><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->d_cface, g->n_cface, in, Lin, hb, q);
       break;
     case 24:
-      nlface_kernel<T, 24><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->d_cface, g->n_cface, in, Lin, hb);
+      nlface_kernel<T, 24><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->d_cface, g->n_cface, in, Lin, hb, q);
       break;
     case 32:
-      nlface_kernel<T, 32><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->d_cface, g->n_cface, in, Lin, hb);
+      nlface_kernel<T, 32><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->d_cface, g->n_cface, in, Lin, hb, q);
       break;
     default:
       return hipErrorInvalidValue;

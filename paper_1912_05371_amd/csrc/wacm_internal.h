@@ -151,7 +151,7 @@ struct wacm_grid {
   // device tables, sized for `capacity` blocks
   wacm::Tab* d_tab = nullptr;
   double* d_part = nullptr;      // reduction partials: capacity * 16 doubles
-  int32_t* d_queue = nullptr;    // stage-kernel work counters (schedule xcd_map 2)
+  int32_t* d_queue = nullptr;    // work counters (schedule xcd_map 2): stage kernel, face halo
   double* d_norm = nullptr;      // 8 doubles
   int32_t* d_list = nullptr;     // adaptation work lists: capacity * 10 int32
   int32_t* d_cface = nullptr;    // (active index, face) of faces next to another level
