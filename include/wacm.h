@@ -258,6 +258,19 @@ int wacm_threshold_blocks(wacm_grid* grid, const wacm_params* prm, double t, con
                           int8_t* flags, void* stream);
 
 /*
+ * wacm_filter_blocks -- wavelet filtering (Sec. 3.1 details; the filtering at
+ * the finest level of the results section's equidistant runs) of a
+ * ghost-synchronised pool U, in place: in every active block of level
+ * `level` (every block if level < 0) each interior point with an odd local
+ * index is replaced by P R u, the tensor-product DD4 prediction from the
+ * block's even-index points (ghost layers included), which removes the
+ * block's details; points whose three indices are even, ghost layers and
+ * other blocks are not changed.  Ghost layers are stale afterwards (sync
+ * again before the next use).  Asynchronous on `stream`.
+ */
+int wacm_filter_blocks(wacm_grid* grid, void* U, int32_t level, void* stream);
+
+/*
  * wacm_adapt -- change the grid (Sec. 3.5).  Synchronous.
  * WACM_REFINE_ALL: ghosts of U are synchronised, then every active block below
  *   jmax is replaced by its 8 children (even child points copy the parent,

@@ -98,6 +98,7 @@ def lib():
         L.orc_diagnostics.argtypes = [vp, C.POINTER(OrcParams), C.c_double, vp, vp, vp]
         L.orc_details.argtypes = [vp, C.POINTER(OrcParams), C.c_double, vp, vp, vp]
         L.orc_flags.argtypes = [vp, vp, vp, C.c_double, C.c_int, vp]
+        L.orc_filter.argtypes = [vp, C.c_int, vp]
         L.orc_refine_count.restype = C.c_int64
         L.orc_refine_count.argtypes = [vp]
         L.orc_refine_all.restype = vp
@@ -234,6 +235,11 @@ class Grid:
             p = make_params(params)
             lib().orc_details(self._h, C.byref(p), t, _ptr(U), _ptr(dmax), _ptr(mr))
         return dmax, mr
+
+    def filter(self, level: int, U: np.ndarray) -> None:
+        """Remove the details of the blocks of `level` (all if < 0) in place;
+        U ghost-synced."""
+        lib().orc_filter(self._h, int(level), _ptr(U))
 
     def flags(self, dmax, mrange, eps: float, dealias: bool) -> np.ndarray:
         f = np.zeros(self.nb, np.int8)

@@ -684,6 +684,39 @@ void orc_diagnostics(const orc_grid* g, const orc_params* p, double t, const dou
 }
 
 /* ------------------------------------------------------------------------ */
+/* P R u of a block at its own level (Sec. 3.1): at a block-local point, the   */
+/* tensor-product DD4 prediction from the block's even-index points (interior */
+/* or ghost): weight 1 on each axis where the index is even, the 4 taps at    */
+/* offsets -3, -1, +1, +3 where it is odd.  Summed z outer, then y, then x.    */
+/* ------------------------------------------------------------------------ */
+static double block_prediction(const orc_grid* g, const double* f, int64_t i, int64_t j,
+                               int64_t k) {
+  int64_t L[3] = {i, j, k};
+  int64_t T[3][4];
+  double W[3][4];
+  int N[3];
+  for (int d = 0; d < 3; ++d) {
+    if (L[d] % 2 == 0) {
+      T[d][0] = L[d];
+      W[d][0] = 1.0;
+      N[d] = 1;
+    } else {
+      for (int m = 0; m < 4; ++m) {
+        T[d][m] = L[d] + DD4O[m];
+        W[d][m] = DD4W[m];
+      }
+      N[d] = 4;
+    }
+  }
+  double pred = 0.0;
+  for (int a = 0; a < N[2]; ++a)
+    for (int e = 0; e < N[1]; ++e)
+      for (int x = 0; x < N[0]; ++x)
+        pred += ((W[2][a] * W[1][e]) * W[0][x]) * f[pidx(g, T[0][x], T[1][e], T[2][a])];
+  return pred;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Details (Sec. 3.1): d = u - P R u at points with an odd local index, where */
 /* R keeps the even points and P is the tensor-product DD4 prediction.         */
 /* Normalised per component by the global Linf norm (Sec. 3.4).               */
@@ -713,29 +746,7 @@ void orc_details(const orc_grid* g, const orc_params* p, double t, const double*
         for (int64_t j = 0; j < bs; ++j)
           for (int64_t i = 0; i < bs; ++i) {
             if (i % 2 == 0 && j % 2 == 0 && k % 2 == 0) continue;
-            int64_t L[3] = {i, j, k};
-            int64_t T[3][4];
-            double W[3][4];
-            int N[3];
-            for (int d = 0; d < 3; ++d) {
-              if (L[d] % 2 == 0) {
-                T[d][0] = L[d];
-                W[d][0] = 1.0;
-                N[d] = 1;
-              } else {
-                for (int m = 0; m < 4; ++m) {
-                  T[d][m] = L[d] + DD4O[m];
-                  W[d][m] = DD4W[m];
-                }
-                N[d] = 4;
-              }
-            }
-            double pred = 0.0;
-            for (int a = 0; a < N[2]; ++a)
-              for (int e = 0; e < N[1]; ++e)
-                for (int x = 0; x < N[0]; ++x)
-                  pred += ((W[2][a] * W[1][e]) * W[0][x]) * f[pidx(g, T[0][x], T[1][e], T[2][a])];
-            double d = fabs(f[pidx(g, i, j, k)] - pred) / norm[c];
+            double d = fabs(f[pidx(g, i, j, k)] - block_prediction(g, f, i, j, k)) / norm[c];
             if (d > dm) dm = d;
           }
     }
@@ -756,6 +767,37 @@ void orc_details(const orc_grid* g, const orc_params* p, double t, const double*
     } else {
       mrange[b] = 0.0;
     }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Wavelet filtering of blocks at their own level: removing the details      */
+/* (Sec. 3.1) sets every interior point with an odd local index to P R u; the */
+/* even points are kept.  With level >= 0 only blocks of that level are       */
+/* filtered (filtering at the finest level, as in the equidistant runs of the */
+/* results section); level < 0 filters every block.  U must be ghost-synced.  */
+/* ------------------------------------------------------------------------ */
+void orc_filter(const orc_grid* g, int level, double* U) {
+  const int bs = g->bs;
+  const int64_t n3 = (int64_t)bs * bs * bs;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t b = 0; b < g->nb; ++b) {
+    if (level >= 0 && g->lev[b] != level) continue;
+    double* pred = (double*)malloc(sizeof(double) * n3);
+    for (int c = 0; c < 4; ++c) {
+      double* f = fld(g, U, b, c);
+      /* all predictions from the unfiltered block first, then the writes */
+      for (int64_t k = 0; k < bs; ++k)
+        for (int64_t j = 0; j < bs; ++j)
+          for (int64_t i = 0; i < bs; ++i)
+            pred[(k * bs + j) * bs + i] = block_prediction(g, f, i, j, k);
+      for (int64_t k = 0; k < bs; ++k)
+        for (int64_t j = 0; j < bs; ++j)
+          for (int64_t i = 0; i < bs; ++i)
+            if (i % 2 != 0 || j % 2 != 0 || k % 2 != 0)
+              f[pidx(g, i, j, k)] = pred[(k * bs + j) * bs + i];
+    }
+    free(pred);
   }
 }
 

@@ -103,6 +103,8 @@ void orc_diagnostics(const orc_grid* g, const orc_params* p, double t, const dou
  * mask range max(chi)-min(chi) over the interior (p may be NULL: range 0). */
 void orc_details(const orc_grid* g, const orc_params* p, double t, const double* U,
                  double* dmax, double* mrange);
+/* wavelet filtering (details removed) of the blocks of one level (all if < 0) */
+void orc_filter(const orc_grid* g, int level, double* U);
 /* Coarsening flags (Sec. 3.3, 3.5). */
 void orc_flags(const orc_grid* g, const double* dmax, const double* mrange, double eps,
                int dealias, int8_t* flags);

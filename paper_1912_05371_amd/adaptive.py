@@ -55,3 +55,17 @@ def adaptive_step(grid: wacm.Grid, params: dict, U, work, t_dev, dt_dev, eps: fl
             break
         merged += 1
     return {"refined": refined, "merged_passes": merged, "blocks": grid.nb}
+
+
+def filtered_steps(grid: wacm.Grid, params: dict, U, work, t_dev, dt_dev, nsteps: int,
+                   level: int = -1, dt_mode: int = wacm.DT_CFL) -> None:
+    """`nsteps` RK4 steps on a fixed grid, each followed by wavelet filtering:
+    ghost synchronisation, then the details of the blocks of `level` (every
+    block if < 0) are removed (the results section's filtering at the finest
+    level, which stabilises equidistant runs).  All arithmetic runs in
+    libwacm."""
+    p = wacm.make_params(params)
+    for _ in range(nsteps):
+        grid.rk4_step(None, t_dev, dt_dev, U, work, dt_mode=dt_mode, _p=p)
+        grid.sync_ghosts(U)
+        grid.filter_blocks(U, level)

@@ -286,6 +286,12 @@ int wacm_threshold_blocks(wacm_grid* g, const wacm_params* p, double t, const vo
   return e == hipSuccess ? WACM_OK : hipfail(e, "threshold_blocks launch");
 }
 
+int wacm_filter_blocks(wacm_grid* g, void* U, int32_t level, void* stream) {
+  if (!elem_ok(g) || !U) return fail(WACM_E_INVAL, "NULL argument");
+  hipError_t e = launch_filter(g, U, level, S(stream));
+  return e == hipSuccess ? WACM_OK : hipfail(e, "filter_blocks launch");
+}
+
 int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* nb_out,
                void* stream) {
   if (!elem_ok(g) || !U) return fail(WACM_E_INVAL, "NULL argument");

@@ -1166,6 +1166,93 @@ __global__ __launch_bounds__(NT_GEN) void detail_kernel(
   }
 }
 
+// Wavelet filtering of a block at its own level: removing its details (Sec.
+// 3.1) sets every interior point with an odd local index to P R u, the
+// tensor-product DD4 prediction from the block's even lattice (ghost layers
+// included); the even points are kept.  Only blocks of level `level` are
+// filtered (every block if level < 0).  Same separable, z-marching passes as
+// detail_kernel.  In place: the passes read only points whose three local
+// indices are even, and the writes change only points with an odd index
+// (all-even points are rewritten with their own value).
+template <typename T, int BS>
+__global__ __launch_bounds__(NT_GEN) void filter_kernel(const Tab* __restrict__ tab, int64_t nb,
+                                                        T* U, Layout L, int level) {
+  constexpr int S = BS / 2 + 3;  // even positions -2, 0, ..., bs+2
+  constexpr int B2 = BS * BS;
+  constexpr int NX = S * BS;                             // x-pass values per field and plane
+  constexpr int KX = (4 * NX + NT_GEN - 1) / NT_GEN;     // x-pass values per thread
+  constexpr int KQ = (B2 + NT_GEN - 1) / NT_GEN;         // (i, j) columns per thread
+  __shared__ T xp[4 * NX];  // X(i, j', k') of the current coarse plane, 4 fields
+  const T w0 = T(DDW0), w1 = T(DDW1);
+  const int tid = threadIdx.x;
+  const int P = L.P, ng = L.ng;
+  for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
+    const int32_t* m = tab[ib].meta;
+    const int slot = m[0], J = m[1];
+    if (level >= 0 && J != level) continue;  // uniform over the workgroup
+    T* b = U + (int64_t)slot * L.bstride;
+    auto ix = [&](int c, int i, int j, int k) -> int64_t {
+      return c * L.fstride + ((int64_t)(k + ng) * P + (j + ng)) * P + (i + ng);
+    };
+    // Y(i, j, k') of this thread's columns for the last 4 coarse planes
+    // (oldest first), all 4 fields, in registers
+    T ring[KQ][4][4] = {};
+    for (int mm = 0; mm < S; ++mm) {
+      const int kc = 2 * mm - 2;  // coarse plane
+      __syncthreads();            // xp is free again
+      // x pass on the coarse rows j' = 2 jj - 2 of plane kc, 4 fields
+#pragma unroll 2
+      for (int kx = 0; kx < KX; ++kx) {
+        const int it = tid + kx * NT_GEN;
+        if (it < 4 * NX) {
+          const int c = it / NX, q = it - c * NX;
+          const int jj = q / BS, i = q - jj * BS, jc = 2 * jj - 2;
+          T v;
+          if ((i & 1) == 0)
+            v = b[ix(c, i, jc, kc)];
+          else
+            v = w0 * b[ix(c, i - 3, jc, kc)] + w1 * b[ix(c, i - 1, jc, kc)] +
+                w1 * b[ix(c, i + 1, jc, kc)] + w0 * b[ix(c, i + 3, jc, kc)];
+          xp[it] = v;
+        }
+      }
+      __syncthreads();
+      // y pass into the ring, z pass: the even fine plane kc (the whole plane
+      // is stored, so that its rows are written as whole lines: at points
+      // with i and j even Y is the point itself, copied through both passes
+      // without arithmetic) and the odd fine plane kc - 3
+#pragma unroll
+      for (int kq = 0; kq < KQ; ++kq) {
+        const int q = tid + kq * NT_GEN;
+        if (q < B2) {
+          const int j = q / BS, i = q - j * BS;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const T* xc = xp + c * NX;
+            T y;
+            if ((j & 1) == 0) {
+              y = xc[(j / 2 + 1) * BS + i];
+            } else {
+              const int jj = (j - 3) / 2 + 1;  // coarse row of j - 3
+              y = w0 * xc[jj * BS + i] + w1 * xc[(jj + 1) * BS + i] + w1 * xc[(jj + 2) * BS + i] +
+                  w0 * xc[(jj + 3) * BS + i];
+            }
+            if (kc >= 0 && kc < BS) b[ix(c, i, j, kc)] = y;
+            const int ko = kc - 3;
+            if (ko >= 0 && ko < BS)
+              b[ix(c, i, j, ko)] = w0 * ring[kq][c][1] + w1 * ring[kq][c][2] +
+                                   w1 * ring[kq][c][3] + w0 * y;
+            ring[kq][c][0] = ring[kq][c][1];
+            ring[kq][c][1] = ring[kq][c][2];
+            ring[kq][c][2] = ring[kq][c][3];
+            ring[kq][c][3] = y;
+          }
+        }
+      }
+    }
+  }
+}
+
 // --------------------------------------------------------------------------
 // refinement (prediction into 8 children) and coarsening (decimation)
 // --------------------------------------------------------------------------
@@ -1723,6 +1810,32 @@ hipError_t launch_threshold(const wacm_grid* g, const wacm_params* p, double t, 
   return g->d.dtype == WACM_F64
              ? thr_t(g, p, t, (const double*)U, eps, dealias, dmax, mrange, flags, st)
              : thr_t(g, p, t, (const float*)U, eps, dealias, dmax, mrange, flags, st);
+}
+
+template <typename T>
+static hipError_t filter_t(const wacm_grid* g, T* U, int level, hipStream_t st) {
+  if (g->nb == 0) return hipSuccess;
+  const unsigned grid = grid_for(g->nb, 8);
+  const Layout L = pool_layout(g);
+  switch (g->d.bs) {
+    case 16:
+      filter_kernel<T, 16><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, L, level);
+      break;
+    case 24:
+      filter_kernel<T, 24><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, L, level);
+      break;
+    case 32:
+      filter_kernel<T, 32><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, L, level);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_filter(const wacm_grid* g, void* U, int level, hipStream_t st) {
+  return g->d.dtype == WACM_F64 ? filter_t(g, (double*)U, level, st)
+                                : filter_t(g, (float*)U, level, st);
 }
 
 template <typename T>

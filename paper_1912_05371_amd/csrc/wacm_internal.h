@@ -200,6 +200,7 @@ hipError_t launch_diag(const wacm_grid* g, const wacm_params* p, double t, const
 hipError_t launch_threshold(const wacm_grid* g, const wacm_params* p, double t, const void* U,
                             double eps, int dealias, double* dmax, double* mrange,
                             int8_t* flags, hipStream_t st);
+hipError_t launch_filter(const wacm_grid* g, void* U, int level, hipStream_t st);
 // refine: n entries of (parent slot, child slot, octant); decimate: n entries
 // of (parent slot, 8 child slots); lists already on the device in d_list.
 hipError_t launch_prolong(const wacm_grid* g, void* U, int64_t n, hipStream_t st);

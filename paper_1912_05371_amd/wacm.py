@@ -26,8 +26,8 @@ MASK_NONE, MASK_SPHERE, MASK_PLATE = 0, 1, 2
 EXPORTS = ["wacm_last_error", "wacm_treecode_encode", "wacm_treecode_decode", "wacm_grid_create",
            "wacm_grid_destroy", "wacm_grid_nb", "wacm_grid_info", "wacm_work_bytes",
            "wacm_sync_ghosts", "wacm_rhs_acm", "wacm_compute_dt", "wacm_rk4_step", "wacm_rk4_steps",
-           "wacm_diagnostics", "wacm_threshold_blocks", "wacm_adapt", "wacm_profile_enable",
-           "wacm_profile_read", "wacm_adj_work_bytes", "wacm_sync_ghosts_adj",
+           "wacm_diagnostics", "wacm_threshold_blocks", "wacm_filter_blocks", "wacm_adapt",
+           "wacm_profile_enable", "wacm_profile_read", "wacm_adj_work_bytes", "wacm_sync_ghosts_adj",
            "wacm_rhs_acm_adj", "wacm_force_adj", "wacm_rk4_step_adj", "wacm_set_schedule",
            "wacm_get_schedule"]
 
@@ -114,6 +114,7 @@ def lib():
         L.wacm_diagnostics.argtypes = [vp, C.POINTER(Params), dbl, vp, vp, vp, vp]
         L.wacm_threshold_blocks.argtypes = [vp, C.POINTER(Params), dbl, vp, dbl, i32, vp, vp, vp,
                                             vp]
+        L.wacm_filter_blocks.argtypes = [vp, vp, i32, vp]
         L.wacm_adapt.argtypes = [vp, i32, vp, vp, vp, vp]
         L.wacm_adj_work_bytes.restype = C.c_size_t
         L.wacm_adj_work_bytes.argtypes = [vp]
@@ -309,6 +310,12 @@ class Grid:
         _check(lib().wacm_threshold_blocks(self._h, C.byref(p), float(t), _ptr(U), float(eps),
                                            int(bool(dealias)), _ptr(dmax), _ptr(mrange),
                                            _ptr(flags), _stream(stream)))
+
+    def filter_blocks(self, U, level: int = -1, stream=None):
+        """Remove the details of the blocks of `level` (all if < 0) in place;
+        U ghost-synced."""
+        self._chk_pool(U)
+        _check(lib().wacm_filter_blocks(self._h, _ptr(U), int(level), _stream(stream)))
 
     def adapt(self, op: int, U, flags=None, stream=None) -> int:
         self._chk_pool(U)

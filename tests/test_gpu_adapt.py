@@ -100,6 +100,30 @@ def test_threshold_matches_oracle(orc, name):
 
 
 @pytest.mark.parametrize("name", ["octree16", "plate"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_filter_matches_oracle(orc, name, prec):
+    c = CASES[name]()
+    og, gg = build(orc, c, wacm.F64 if prec == "f64" else wacm.F32)
+    U = c.padded()
+    og.sync(U)
+    J = int(np.max(og.lev))
+    for level in (-1, J):
+        log(f"filter {name} {prec} level {level}")
+        pool = put(gg, og, U)
+        gg.filter_blocks(pool, level)
+        Uo = U.copy()
+        og.filter(level, Uo)
+        Ug = from_pool(pool, slot_map(gg, og))
+        e = rel_err(Ug, Uo, c.bs, c.ng)
+        log(f"  interior rel err {e:.2e}")
+        # FP64: separable vs tensor-sum rounding; FP32: the input's rounding
+        assert e < (1e-14 if prec == "f64" else 1e-6)
+        if prec == "f64" and level == J:
+            keep = np.asarray(og.lev) != J
+            assert np.array_equal(Ug[keep], U[keep])
+
+
+@pytest.mark.parametrize("name", ["octree16", "plate"])
 def test_refine_all_matches_oracle(orc, name):
     log(f"refine_all {name}")
     c = CASES[name]()

@@ -184,6 +184,36 @@ def test_taylor_green_ten_steps(orc, prec):
     assert drift < (1e-11 if prec == "f64" else 1e-4)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_filtered_taylor_green_steps(orc, prec):
+    """An equidistant run with wavelet filtering after every step (RK4 step,
+    ghost sync, details of every block removed), gated per step from the
+    oracle's state like the plain run above."""
+    from paper_1912_05371_amd.adaptive import filtered_steps
+    log(f"filtered taylor green {prec}")
+    c = get_case("taylor_green")
+    og, gg = make_pair(orc, c, DT[prec])
+    U = c.padded()
+    work = gg.work()
+    t = 0.0
+    worst = 0.0
+    for n in range(3):
+        dt = og.dt(c.params, U)
+        pool = to_pool(gg, U.astype(np.float32).astype(np.float64) if prec == "f32" else U)
+        t_dev = torch.tensor([t], dtype=torch.float64, device="cuda")
+        dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
+        filtered_steps(gg, c.params, pool, work, t_dev, dt_dev, 1, -1, dt_mode=wacm.DT_FIXED)
+        og.rk4_step(c.params, t, dt, U)
+        og.sync(U)
+        og.filter(-1, U)
+        torch.cuda.synchronize()
+        e = rel_err(from_pool(pool, np.arange(og.nb)), U, c.bs, c.ng)
+        worst = max(worst, e)
+        t += dt
+    log(f"  worst per-step rel err {worst:.3e}")
+    assert worst < (1e-12 if prec == "f64" else 1e-5)
+
+
 @pytest.mark.parametrize("name", ["sphere_two_level", "octree_bs24"])
 def test_diagnostics_match_oracle(orc, name):
     log(f"diagnostics {name}")

@@ -497,6 +497,59 @@ def test_details_quartic_is_9h4(orc):
     assert np.allclose(dmax, 9 * h ** 4 / norm, rtol=1e-9, atol=0)
 
 
+# ---------------------------------------------------------------- filtering
+def test_filter_quartic_closed_form(orc):
+    # Removing the details of u = x^4 subtracts the cubic interpolation error
+    # (x+3h)(x+h)(x-h)(x-3h) at x = 0, i.e. 9 h^4, at every point whose x
+    # index is odd, whatever the parity in y and z; points with an even x
+    # index keep their value.  A cubic is reproduced, zeros stay zero.
+    lev, ix, iy, iz = inputs.uniform_leaves(1)
+    g = orc.Grid(16, 4, 1.0, 1, 1, lev, ix, iy, iz)
+    h = 1.0 / 32
+    U = _fill_poly(g, lambda c, x, y, z: x ** 4 if c == 0 else
+                   ((y ** 3 - 2 * z * x * y + x ** 2) if c == 1 else 0 * x))
+    F = U.copy()
+    g.filter(-1, F)
+    I = slice(g.ng, g.ng + g.bs)
+    odd_x = (np.arange(g.bs) % 2 == 1)[None, None, :]
+    d0 = (U[:, 0, I, I, I] - F[:, 0, I, I, I])
+    assert np.max(np.abs(np.where(odd_x, d0 - 9 * h ** 4, d0))) < 1e-14
+    assert np.max(np.abs(U[:, 1, I, I, I] - F[:, 1, I, I, I])) < 1e-14
+    assert np.all(F[:, 2:] == 0.0)
+
+
+def test_filter_keeps_even_points_is_idempotent_and_selects_level(orc):
+    lev, ix, iy, iz = inputs.random_balanced_leaves(11, 1, 3, 60)
+    g = orc.Grid(16, 4, 1.0, 1, 3, lev, ix, iy, iz)
+    rng = np.random.default_rng(5)
+    U = rng.standard_normal((g.nb, 4, g.P, g.P, g.P))
+    g.sync(U)
+    F = U.copy()
+    g.filter(-1, F)
+    ng, bs = g.ng, g.bs
+    I = slice(ng, ng + bs)
+    E = slice(ng, ng + bs, 2)
+    # points with three even indices and every ghost point are untouched
+    assert np.array_equal(F[:, :, E, E, E], U[:, :, E, E, E])
+    ghost = np.ones((g.P, g.P, g.P), bool)
+    ghost[I, I, I] = False
+    assert np.array_equal(F[:, :, ghost], U[:, :, ghost])
+    # odd points did change (random data has details)
+    assert np.max(np.abs(F[:, :, I, I, I] - U[:, :, I, I, I])) > 1e-3
+    # the predictions read only even points: a second pass changes nothing
+    F2 = F.copy()
+    g.filter(-1, F2)
+    assert np.array_equal(F2, F)
+    # one level only: those blocks as in the full pass, the others untouched
+    J = int(g.lev.max())
+    FJ = U.copy()
+    g.filter(J, FJ)
+    sel = np.asarray(g.lev) == J
+    assert 0 < sel.sum() < g.nb
+    assert np.array_equal(FJ[sel], F[sel])
+    assert np.array_equal(FJ[~sel], U[~sel])
+
+
 def test_flags_rules(orc):
     lev, ix, iy, iz = inputs.random_balanced_leaves(11, 1, 3, 60)
     g = orc.Grid(16, 4, 1.0, 1, 3, lev, ix, iy, iz)
