@@ -373,8 +373,12 @@ __device__ __forceinline__ void ntstore(T v, T* p, int nt) {
 // z: z-neighbours in a register queue, the x/y cross of the current plane in a
 // double-buffered LDS slab, the next plane's loads issued before the barrier.
 // Rows between tiles of one block are read from the block itself.
+// Occupancy: FP64 tiles are held to 2 waves per SIMD, FP32 tiles to 3; a
+// whole bs-16 block (4 waves) to 2 per SIMD, which keeps two workgroups per
+// CU for the penalized FP64 variant at the cost of a few spills (measured
+// faster than one workgroup per CU without spills).
 template <typename T, int BS, int TY, int MODE, bool PEN, bool PREF>
-__global__ __launch_bounds__(BS* TY) __attribute__((amdgpu_waves_per_eu(TY == BS ? 1 : (sizeof(T) == 8 ? 2 : 3))))
+__global__ __launch_bounds__(BS* TY) __attribute__((amdgpu_waves_per_eu(TY == BS ? (BS == 16 ? 2 : 1) : (sizeof(T) == 8 ? 2 : 3))))
 void stage_kernel(StageArgs<T> a) {
   constexpr int H = 3, W = BS + 2 * H, WY = TY + 2 * H, NT = BS * TY;
   constexpr int NTY = BS / TY, NH = 6 * TY + 6 * BS;
