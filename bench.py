@@ -202,7 +202,8 @@ def aux_timings(case):
     """Timings of the other hot-path calls, outside the timed region (FP64):
     on the benchmark grid the stand-alone ghost synchronisation, wavelet
     thresholding, diagnostics, time step and wavelet filtering of every
-    block; on the adaptive plate case one
+    block, each with its compulsory bytes and the fraction of the HBM peak
+    they imply; on the adaptive plate case one
     full adaptive step (refine all, one RK4 step, coarsening passes until no
     block merges), by phase."""
     import torch
@@ -231,7 +232,21 @@ def aux_timings(case):
         # same loads and stores each time
         "filter_blocks": lambda: g.filter_blocks(pool, -1),
     }
+    # compulsory bytes per call (FP64): the ghost shell written once and its
+    # sources read once; interiors read by the norm and detail passes; 4
+    # values read per point; 3 velocity values read per point; every interior
+    # value written plus the even lattice (a quarter of the padded rows of
+    # every other plane) read
+    es = 8
+    npts = case.nb * case.bs ** 3
+    P = case.bs + 2 * case.ng
+    shell = case.nb * (P ** 3 - case.bs ** 3)
+    even = case.nb * (case.bs // 2 + 3) ** 2 * P
+    algo = {"sync_ghosts": 2 * shell * 4 * es, "threshold_blocks": 8 * npts * es,
+            "diagnostics": 4 * npts * es, "compute_dt": 3 * npts * es,
+            "filter_blocks": (4 * npts + 4 * even) * es}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    roof = {}
     for name, fn in calls.items():
         fn()
         torch.cuda.synchronize()
@@ -240,7 +255,12 @@ def aux_timings(case):
             fn()
         e1.record()
         torch.cuda.synchronize()
-        out[name + "_ms"] = round(e0.elapsed_time(e1) / 3, 4)
+        ms = e0.elapsed_time(e1) / 3
+        out[name + "_ms"] = round(ms, 4)
+        gbs = algo[name] / (ms * 1e-3) / 1e9
+        roof[name] = {"bytes": algo[name], "GBps": round(gbs, 1),
+                      "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out["roofline"] = roof
     del pool
     g.close()
     torch.cuda.empty_cache()

@@ -99,6 +99,9 @@ def lib():
         L.orc_details.argtypes = [vp, C.POINTER(OrcParams), C.c_double, vp, vp, vp]
         L.orc_flags.argtypes = [vp, vp, vp, C.c_double, C.c_int, vp]
         L.orc_filter.argtypes = [vp, C.c_int, vp]
+        L.orc_set_wavelet.restype = C.c_int
+        L.orc_set_wavelet.argtypes = [vp, C.c_int]
+        L.orc_lift_lowpass.argtypes = [C.c_int, vp]
         L.orc_refine_count.restype = C.c_int64
         L.orc_refine_count.argtypes = [vp]
         L.orc_refine_all.restype = vp
@@ -130,6 +133,13 @@ def tam_webb() -> np.ndarray:
     a = (C.c_double * 3)()
     lib().orc_tam_webb(a)
     return np.array(list(a))
+
+
+def lift_lowpass(order: int) -> np.ndarray:
+    """Taps at offsets -6..6 of the lifted low-pass (order 4: CDF 4/4, 2: CDF 2/2)."""
+    t = np.zeros(13)
+    lib().orc_lift_lowpass(int(order), _ptr(t))
+    return t
 
 
 def treecode_encode(level: int, ix: int, iy: int, iz: int) -> int:
@@ -235,6 +245,11 @@ class Grid:
             p = make_params(params)
             lib().orc_details(self._h, C.byref(p), t, _ptr(U), _ptr(dmax), _ptr(mr))
         return dmax, mr
+
+    def set_wavelet(self, wavelet: int) -> None:
+        """0: CDF 4/0 (decimation), 1: CDF 4/4 (lifted restriction, ng >= 6)."""
+        if lib().orc_set_wavelet(self._h, int(wavelet)) != 0:
+            raise ValueError("invalid wavelet for this grid")
 
     def filter(self, level: int, U: np.ndarray) -> None:
         """Remove the details of the blocks of `level` (all if < 0) in place;

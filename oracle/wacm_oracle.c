@@ -33,6 +33,7 @@
 
 struct orc_grid {
   int bs, ng, P, jmin, jmax;
+  int wavelet; /* 0: CDF 4/0 (restriction = decimation), 1: CDF 4/4 (lifted) */
   double L;
   int64_t nb;
   int32_t* lev;
@@ -396,6 +397,70 @@ static double lattice_value(const orc_grid* g, const double* U, int J, int c, in
   return v;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Lifted restriction (Sec. 3.2, CDF 4/4).  Lifting the interpolating wavelet  */
+/* of CDF 4/0 gives the primal wavelet 4 vanishing moments; the dual scaling   */
+/* function changes with it, so restriction is no longer decimation.  Along   */
+/* one axis, with u the fine values around an even point (offset 0):          */
+/*   predict (the details of Sec. 3.1): d_m = u_m - P u at the odd offsets    */
+/*            m = -3, -1, 1, 3, P the DD4 prediction from m-3, m-1, m+1, m+3;  */
+/*   update:  c = u_0 + sum_m U_m d_m,  U = (-1, 9, 9, -1)/32 on m = -3..3,   */
+/* the update of the interpolating family, half its predict filter, which    */
+/* makes the low-pass keep the first 4 moments.  The linear analogue (predict */
+/* (1/2, 1/2) at -1, 1, update 1/4 at -1, 1) is the CDF 2/2 case the paper    */
+/* spells out.  A coarse value needs the fine values at offsets -6..6; in 3D  */
+/* the axis restriction runs along x, then y, then z.                         */
+/* ------------------------------------------------------------------------ */
+static const double LIFTU[4] = {-1.0 / 32.0, 9.0 / 32.0, 9.0 / 32.0, -1.0 / 32.0};
+
+static double lift_1d(int order, const double v[13]) {
+  double c = v[6];
+  if (order == 2) {
+    for (int m = -1; m <= 1; m += 2) {
+      double d = v[6 + m] - 0.5 * (v[6 + m - 1] + v[6 + m + 1]);
+      c += 0.25 * d;
+    }
+    return c;
+  }
+  for (int k = 0; k < 4; ++k) {
+    int m = 6 + DD4O[k];
+    double pred = 0.0;
+    for (int t = 0; t < 4; ++t) pred += DD4W[t] * v[m + DD4O[t]];
+    c += LIFTU[k] * (v[m] - pred);
+  }
+  return c;
+}
+
+void orc_lift_lowpass(int order, double taps[13]) {
+  for (int n = 0; n < 13; ++n) {
+    double v[13] = {0};
+    v[n] = 1.0;
+    taps[n] = lift_1d(order, v);
+  }
+}
+
+/* Lifted restriction at the even local point (i,j,k) of the padded field f. */
+static double lift_restrict_3d(const orc_grid* g, const double* f, int64_t i, int64_t j,
+                               int64_t k) {
+  double ax[13][13];
+  for (int z = 0; z < 13; ++z)
+    for (int y = 0; y < 13; ++y) {
+      double line[13];
+      for (int x = 0; x < 13; ++x) line[x] = f[pidx(g, i - 6 + x, j - 6 + y, k - 6 + z)];
+      ax[z][y] = lift_1d(4, line);
+    }
+  double ay[13];
+  for (int z = 0; z < 13; ++z) ay[z] = lift_1d(4, ax[z]);
+  return lift_1d(4, ay);
+}
+
+int orc_set_wavelet(orc_grid* g, int wavelet) {
+  if (wavelet != 0 && wavelet != 1) return -1;
+  if (wavelet == 1 && g->ng < 6) return -1; /* the lifted stencil reaches 6 fine points */
+  g->wavelet = wavelet;
+  return 0;
+}
+
 void orc_sync(const orc_grid* g, double* U) {
   const int bs = g->bs, ng = g->ng;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -413,6 +478,31 @@ void orc_sync(const orc_grid* g, double* U) {
           }
     }
   }
+  if (g->wavelet != 1) return;
+  /* CDF 4/4: every ghost point whose owner is finer takes the lifted
+   * restriction of the owner's level-(J+1) lattice around it, read from the
+   * owner's padded array as synchronised above (CDF 4/0 values in its ghost
+   * layers, which are 6 deep). */
+  const int64_t n = g->nb * 4 * (int64_t)g->P * g->P * g->P;
+  double* S = (double*)malloc(sizeof(double) * n);
+  memcpy(S, U, sizeof(double) * n);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t b = 0; b < g->nb; ++b) {
+    int J = g->lev[b];
+    int64_t ox = g->ix[b] * bs, oy = g->iy[b] * bs, oz = g->iz[b] * bs;
+    for (int64_t k = -ng; k < bs + ng; ++k)
+      for (int64_t j = -ng; j < bs + ng; ++j)
+        for (int64_t i = -ng; i < bs + ng; ++i) {
+          int inside = (i >= 0 && i < bs && j >= 0 && j < bs && k >= 0 && k < bs);
+          if (inside) continue;
+          int64_t li, lj, lk;
+          int64_t o = orc_owner(g, J, ox + i, oy + j, oz + k, &li, &lj, &lk);
+          if (o < 0 || g->lev[o] != J + 1) continue;
+          for (int c = 0; c < 4; ++c)
+            fld(g, U, b, c)[pidx(g, i, j, k)] = lift_restrict_3d(g, cfld(g, S, o, c), li, lj, lk);
+        }
+  }
+  free(S);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -845,6 +935,7 @@ int64_t orc_refine_count(const orc_grid* g) {
 static orc_grid* grid_from_newleaves(const orc_grid* g, newleaf* nl, int64_t n) {
   qsort(nl, n, sizeof(newleaf), cmp_newleaf);
   orc_grid* h = grid_alloc(g->bs, g->ng, g->L, g->jmin, g->jmax, n);
+  h->wavelet = g->wavelet;
   for (int64_t b = 0; b < n; ++b) {
     h->lev[b] = nl[b].lev;
     h->ix[b] = nl[b].x;
@@ -1034,7 +1125,12 @@ orc_grid* orc_coarsen(const orc_grid* g, const int8_t* flags, const double* U, d
               Lc[d] = Q[d] - C[d] * bs;
             }
             int64_t child = hfind(g, J, 2 * q->x + C[0], 2 * q->y + C[1], 2 * q->z + C[2]);
-            o[pidx(h, i, j, k)] = cfld(g, U, child, c)[pidx(g, Lc[0], Lc[1], Lc[2])];
+            /* CDF 4/4: the lifted restriction over the child's synchronised
+             * padded array (its 6-deep ghost layers hold the sisters' and
+             * neighbours' values) */
+            o[pidx(h, i, j, k)] =
+                g->wavelet == 1 ? lift_restrict_3d(g, cfld(g, U, child, c), Lc[0], Lc[1], Lc[2])
+                                : cfld(g, U, child, c)[pidx(g, Lc[0], Lc[1], Lc[2])];
           }
     }
   }

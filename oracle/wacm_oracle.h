@@ -75,8 +75,18 @@ int orc_is_balanced(const orc_grid* g);
 int64_t orc_owner(const orc_grid* g, int J, int64_t gx, int64_t gy, int64_t gz,
                   int64_t* li, int64_t* lj, int64_t* lk);
 
-/* Ghost-node synchronisation (Sec. 4.2, Sec. 3.1 prediction/decimation). */
+/* Ghost-node synchronisation (Sec. 4.2, Sec. 3.1 prediction/decimation).
+ * With the CDF 4/4 wavelet, ghost points whose owner is finer then take the
+ * lifted restriction (Sec. 3.2) of the owner's synchronised padded array. */
 void orc_sync(const orc_grid* g, double* U);
+
+/* Wavelet of restriction: 0 CDF 4/0 (decimation, default), 1 CDF 4/4 (lifted;
+ * needs ng >= 6).  Returns 0, or -1 for an invalid choice.  Grids made by
+ * refinement or coarsening inherit it. */
+int orc_set_wavelet(orc_grid* g, int wavelet);
+/* Taps (offsets -6..6) of the lifted low-pass along one axis: order 4 (CDF
+ * 4/4) or 2 (CDF 2/2), from the lifting steps applied to unit impulses. */
+void orc_lift_lowpass(int order, double taps[13]);
 
 /* Mask and solid velocity at interior points, at time t. chi: [nb][bs^3], us: [nb][3][bs^3]. */
 void orc_mask(const orc_grid* g, const orc_params* p, double t, double* chi, double* us);

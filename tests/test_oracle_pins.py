@@ -550,6 +550,125 @@ def test_filter_keeps_even_points_is_idempotent_and_selects_level(orc):
     assert np.array_equal(FJ[~sel], U[~sel])
 
 
+# ---------------------------------------------------------------- CDF 4/4 lifting
+def test_lifted_lowpass_taps(orc):
+    # CDF 2/2: the paper's lifted low-pass for linear interpolation (Sec. 3.2,
+    # printed with garbled signs; read as the 5-tap filter whose taps sum to 1)
+    t2 = orc.lift_lowpass(2)
+    assert np.array_equal(t2, np.array([0, 0, 0, 0, -1, 2, 6, 2, -1, 0, 0, 0, 0]) / 8)
+    # CDF 4/4: the lifting steps expanded by hand (predict (-1, 9, 9, -1)/16,
+    # update (-1, 9, 9, -1)/32)
+    t4 = orc.lift_lowpass(4)
+    assert np.array_equal(t4, np.array([-1, 0, 18, -16, -63, 144, 348, 144, -63, -16, 18, 0,
+                                        -1]) / 512)
+    # M vanishing moments of the lifted primal wavelet <=> the low-pass keeps
+    # the mean and has an M-fold zero at the Nyquist frequency:
+    # sum (-1)^n n^p h_n = 0 for p < M, and not for p = M
+    n = np.arange(-6, 7)
+    for t, M in ((t2, 2), (t4, 4)):
+        assert abs(t.sum() - 1.0) < 1e-15
+        for p in range(M):
+            assert abs(np.sum((-1.0) ** n * n ** p * t)) < 1e-13
+        assert abs(np.sum((-1.0) ** n * n ** M * t)) > 1e-3
+
+
+def _one_refined_block(bs=24, ng=6):
+    """Uniform level 1 with block (0,0,0) split into its 8 children."""
+    leaves = [(1, x, y, z) for z in range(2) for y in range(2) for x in range(2) if (x, y, z) != (0, 0, 0)]
+    leaves += [(2, x, y, z) for z in range(2) for y in range(2) for x in range(2)]
+    lev = np.array([l[0] for l in leaves], np.int32)
+    ix, iy, iz = (np.array([l[d] for l in leaves], np.int64) for d in (1, 2, 3))
+    return lev, ix, iy, iz
+
+
+def test_cdf44_sync_quartic_closed_form(orc):
+    # u = x^4: the details along x are 9 h^4 at every odd point, so the lifted
+    # restriction adds (-1 + 9 + 9 - 1)/32 * 9 h^4 = 4.5 h^4 (h the fine
+    # spacing) to the decimated value; the y and z passes see a function
+    # constant along them.  Checked at ghost points of the coarse block next
+    # to the children whose 13-point stencils stay inside a child's interior.
+    lev, ix, iy, iz = _one_refined_block()
+    g4 = orc.Grid(24, 6, 1.0, 1, 2, lev, ix, iy, iz)
+    g0 = orc.Grid(24, 6, 1.0, 1, 2, lev, ix, iy, iz)
+    g4.set_wavelet(1)
+    U = _fill_poly(g4, lambda c, x, y, z: x ** 4 if c == 0 else 0 * x)
+    U0 = U.copy()
+    g4.sync(U)
+    g0.sync(U0)
+    b = [i for i in range(g4.nb) if (g4.lev[i], g4.ix[i], g4.iy[i], g4.iz[i]) == (1, 1, 0, 0)][0]
+    ng, bs = 6, 24
+    hf = 1.0 / 96
+    js = [j for j in range(bs) if 3 <= j <= 8 or 15 <= j <= 20]
+    n = 0
+    for d in range(4, 7):
+        x = 0.5 - d / 48
+        for j in js:
+            for k in js:
+                v4 = U[b, 0, k + ng, j + ng, -d + ng]
+                v0 = U0[b, 0, k + ng, j + ng, -d + ng]
+                assert abs(v0 - x ** 4) < 1e-16
+                assert abs(v4 - (x ** 4 + 4.5 * hf ** 4)) < 1e-15
+                n += 1
+    assert n == 3 * len(js) ** 2
+    # other ghost points whose owner is not finer are untouched by the lifting
+    assert np.array_equal(U[[i for i in range(g4.nb) if g4.lev[i] == 2]],
+                          U0[[i for i in range(g4.nb) if g4.lev[i] == 2]])
+
+
+def test_cdf44_sync_cubic_equals_decimation(orc):
+    lev, ix, iy, iz = _one_refined_block()
+    g4 = orc.Grid(24, 6, 1.0, 1, 2, lev, ix, iy, iz)
+    g0 = orc.Grid(24, 6, 1.0, 1, 2, lev, ix, iy, iz)
+    g4.set_wavelet(1)
+    f = lambda c, x, y, z: 1 + (c + 1) * x ** 3 - y ** 2 * z + 0.5 * x * y * z ** 2
+    U = _fill_poly(g4, f)
+    U0 = U.copy()
+    g4.sync(U)
+    g0.sync(U0)
+    # the -x ghost layers of the coarse block next to the children, at
+    # tangential positions whose stencils stay off the periodic wrap (where a
+    # polynomial jumps); every depth 1..6
+    b = [i for i in range(g4.nb) if (g4.lev[i], g4.ix[i], g4.iy[i], g4.iz[i]) == (1, 1, 0, 0)][0]
+    js = np.array([j for j in range(24) if 3 <= j <= 8 or 15 <= j <= 20]) + 6
+    G4 = U[b][:, js][:, :, js][:, :, :, 0:6]
+    G0 = U0[b][:, js][:, :, js][:, :, :, 0:6]
+    assert np.max(np.abs(G4 - G0)) < 1e-14
+    with pytest.raises(ValueError):
+        orc.Grid(24, 4, 1.0, 1, 2, lev, ix, iy, iz).set_wavelet(1)
+
+
+def test_cdf44_coarsen_quartic_closed_form(orc):
+    lev, ix, iy, iz = _one_refined_block()
+    g = orc.Grid(24, 6, 1.0, 1, 2, lev, ix, iy, iz)
+    g.set_wavelet(1)
+    U = _fill_poly(g, lambda c, x, y, z: x ** 4 if c == 0 else 0 * x)  # analytic ghosts
+    flags = (np.asarray(g.lev) == 2).astype(np.int8)
+    g2, U2 = g.coarsen(flags, U)
+    assert g2.nb == 8
+    p = [i for i in range(g2.nb) if (g2.ix[i], g2.iy[i], g2.iz[i]) == (0, 0, 0)][0]
+    x = (np.arange(24) / 48.0)[None, None, :]
+    I = slice(6, 30)
+    assert np.max(np.abs(U2[p, 0, I, I, I] - (x ** 4 + 4.5 / 96 ** 4))) < 1e-15
+    assert np.all(U2[p, 1:, I, I, I] == 0.0)
+
+
+def test_cdf44_refine_then_coarsen_is_identity(orc):
+    # the lifted restriction inverts the DD4 prediction: all details of a
+    # predicted field vanish, so the update adds nothing
+    lev, ix, iy, iz = inputs.uniform_leaves(1)
+    g = orc.Grid(24, 6, 1.0, 1, 2, lev, ix, iy, iz)
+    g.set_wavelet(1)
+    rng = np.random.default_rng(8)
+    U = rng.standard_normal((g.nb, 4, g.P, g.P, g.P))
+    g.sync(U)
+    g2, U2 = g.refine_all(U)
+    g2.sync(U2)
+    g3, U3 = g2.coarsen(np.ones(g2.nb, np.int8), U2)
+    assert g3.nb == g.nb
+    I = slice(6, 30)
+    assert np.max(np.abs(U3[:, :, I, I, I] - U[:, :, I, I, I])) < 1e-13
+
+
 def test_flags_rules(orc):
     lev, ix, iy, iz = inputs.random_balanced_leaves(11, 1, 3, 60)
     g = orc.Grid(16, 4, 1.0, 1, 3, lev, ix, iy, iz)
