@@ -59,6 +59,10 @@ extern "C" {
 #define WACM_E_NONFINITE (-6)  /* NaN or Inf found in the state                */
 #define WACM_E_TILING (-7)     /* leaves overlap, repeat or leave gaps          */
 
+/* restriction wavelet (wacm_set_wavelet) */
+#define WACM_CDF40 0
+#define WACM_CDF44 1
+
 #define WACM_F32 1
 #define WACM_F64 2
 
@@ -158,6 +162,25 @@ int64_t wacm_grid_nb(const wacm_grid* grid);
  * receives nb entries: pool slot, treecode, level.
  */
 int wacm_grid_info(const wacm_grid* grid, int64_t* slots, uint64_t* treecodes, int8_t* levels);
+
+/* Restriction wavelet of the grid (Sec. 3.2).  WACM_CDF40 (default):
+ * restriction is decimation.  WACM_CDF44: the interpolating wavelet lifted to
+ * 4 vanishing moments; restriction becomes the lifted low-pass (13 taps
+ * (-1, 0, 18, -16, -63, 144, 348, 144, -63, -16, 18, 0, -1)/512 along each
+ * axis, x then y then z) over the finer leaf's level-(J+1) lattice as held in
+ * its padded array after the CDF 4/0 ghost fill.  It applies wherever the
+ * method restricts: in wacm_sync_ghosts to every ghost point whose owner is
+ * finer (a second phase after the CDF 4/0 fill; the first phase's values are
+ * staged so no lifted value reads another), in wacm_adapt(REFINE_ALL)'s own
+ * sync, and in wacm_adapt(COARSEN) to the parents (then U must be
+ * ghost-synchronised, as it is after thresholding).  Details, prediction and
+ * refinement are unchanged.  CDF 4/4 needs ng >= 6 (else WACM_E_INVAL) and
+ * device buffers for its ghost phase, which the grid allocates here and on
+ * every adaptation (WACM_E_NOMEM if that fails).  Not available with CDF 4/4:
+ * wacm_rk4_step(s), wacm_filter_blocks and the adjoint (WACM_E_INVAL).
+ * wacm_get_wavelet returns the current choice. */
+int wacm_set_wavelet(wacm_grid* grid, int32_t wavelet);
+int wacm_get_wavelet(const wacm_grid* grid);
 
 /* Set / read the stage-kernel schedule (values checked: wg_per_cu in [0, 16],
  * xcd_map in {0, 1, 2}, nontemporal in {0, 1}, prefetch in {-1, 0, 1}, tile_rows in

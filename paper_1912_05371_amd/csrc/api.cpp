@@ -46,6 +46,12 @@ void free_dev(wacm_grid* g) {
   if (g->d_list) (void)hipFree(g->d_list);
   if (g->d_cface) (void)hipFree(g->d_cface);
   if (g->d_cregion) (void)hipFree(g->d_cregion);
+  if (g->d_lift) (void)hipFree(g->d_lift);
+  if (g->d_lift_tmp) (void)hipFree(g->d_lift_tmp);
+  g->d_lift = nullptr;
+  g->d_lift_tmp = nullptr;
+  g->lift_items_cap = g->lift_tmp_cap = 0;
+  g->n_lift = 0;
   g->d_cface = nullptr;
   g->d_cregion = nullptr;
   g->d_tab = nullptr;
@@ -222,11 +228,37 @@ int wacm_get_schedule(const wacm_grid* g, wacm_schedule* s) {
   return WACM_OK;
 }
 
+// Full ghost fill with the grid's wavelet: the CDF 4/0 fill, then with CDF
+// 4/4 the lifted values of ghost points whose owner is finer.
+static hipError_t full_sync(const wacm_grid* g, void* U, hipStream_t st) {
+  hipError_t e = launch_sync(g, U, 0, st);
+  if (e == hipSuccess && g->wavelet == WACM_CDF44) e = launch_lift_sync(g, U, st);
+  return e;
+}
+
 int wacm_sync_ghosts(wacm_grid* g, void* U, void* stream) {
   if (!elem_ok(g) || !U) return fail(WACM_E_INVAL, "NULL argument");
-  hipError_t e = launch_sync(g, U, 0, S(stream));
+  hipError_t e = full_sync(g, U, S(stream));
   return e == hipSuccess ? WACM_OK : hipfail(e, "sync_ghosts launch");
 }
+
+int wacm_set_wavelet(wacm_grid* g, int32_t wavelet) {
+  if (!elem_ok(g)) return fail(WACM_E_INVAL, "NULL argument");
+  if (wavelet != WACM_CDF40 && wavelet != WACM_CDF44) return fail(WACM_E_INVAL, "wavelet");
+  if (wavelet == WACM_CDF44 && g->d.ng < 6)
+    return fail(WACM_E_INVAL, "CDF 4/4 needs ng >= 6 (the lifted stencil reaches 6 fine points)");
+  const int old = g->wavelet;
+  g->wavelet = wavelet;
+  std::string err;
+  if (int rc = build_lift(g, g->h_tab, err)) {
+    g->wavelet = old;
+    build_lift(g, g->h_tab, err);
+    return fail(rc, err);
+  }
+  return WACM_OK;
+}
+
+int wacm_get_wavelet(const wacm_grid* g) { return g ? g->wavelet : WACM_E_INVAL; }
 
 int wacm_rhs_acm(wacm_grid* g, const wacm_params* p, double t, const void* U, void* dU,
                  const void* dus, void* stream) {
@@ -253,6 +285,7 @@ static int rk4_common(wacm_grid* g, const wacm_params* p, double* t_dev, double*
   if (nsteps < 0) return fail(WACM_E_INVAL, "nsteps must be >= 0");
   if (reinterpret_cast<uintptr_t>(work) % 256) return fail(WACM_E_INVAL, "work not 256-aligned");
   if (int rc = check_params(p)) return rc;
+  if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "RK4 with CDF 4/4 is not available");
   hipError_t e = launch_rk4(g, p, t_dev, dt_dev, U, work, dus, dt_mode, nsteps, S(stream));
   return e == hipSuccess ? WACM_OK : hipfail(e, what);
 }
@@ -288,6 +321,7 @@ int wacm_threshold_blocks(wacm_grid* g, const wacm_params* p, double t, const vo
 
 int wacm_filter_blocks(wacm_grid* g, void* U, int32_t level, void* stream) {
   if (!elem_ok(g) || !U) return fail(WACM_E_INVAL, "NULL argument");
+  if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "filtering is CDF 4/0 only");
   hipError_t e = launch_filter(g, U, level, S(stream));
   return e == hipSuccess ? WACM_OK : hipfail(e, "filter_blocks launch");
 }
@@ -414,13 +448,17 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
   hipError_t e;
   if (nwork > 0) {
     if (op == WACM_REFINE_ALL) {
-      e = launch_sync(g, U, 0, st);
+      e = full_sync(g, U, st);
       if (e != hipSuccess) return hipfail(e, "adapt sync");
     }
     e = hipMemcpyAsync(g->d_list, list.data(), sizeof(int32_t) * list.size(),
                        hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hipfail(e, "adapt list upload");
-    e = op == WACM_REFINE_ALL ? launch_prolong(g, U, nwork, st) : launch_decimate(g, U, nwork, st);
+    if (op == WACM_REFINE_ALL)
+      e = launch_prolong(g, U, nwork, st);
+    else
+      e = g->wavelet == WACM_CDF44 ? launch_lift_coarsen(g, U, nwork, st)
+                                   : launch_decimate(g, U, nwork, st);
     if (e != hipSuccess) return hipfail(e, "adapt kernel");
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hipfail(e, "adapt synchronize");
@@ -443,6 +481,7 @@ size_t wacm_adj_work_bytes(const wacm_grid* g) { return g ? adj_work_bytes(g) : 
 
 int wacm_sync_ghosts_adj(wacm_grid* g, void* Ub, void* stream) {
   if (!elem_ok(g) || !Ub) return fail(WACM_E_INVAL, "NULL argument");
+  if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "the adjoint is CDF 4/0 only");
   std::string err;
   if (int rc = build_adj_plan(g, 0, err)) return fail(rc, err);
   hipError_t e = launch_sync_adj(g, Ub, 0, S(stream));
@@ -452,6 +491,7 @@ int wacm_sync_ghosts_adj(wacm_grid* g, void* Ub, void* stream) {
 int wacm_rhs_acm_adj(wacm_grid* g, const wacm_params* p, double t, const void* U, const void* V,
                      void* Ub, double* dtheta, double* dusbar, const void* dus, void* stream) {
   if (!elem_ok(g) || !U || !V || !Ub || !dtheta) return fail(WACM_E_INVAL, "NULL argument");
+  if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "the adjoint is CDF 4/0 only");
   if (int rc = check_params(p)) return rc;
   hipError_t e = launch_rhs_adj(g, p, t, U, V, Ub, dtheta, dusbar, dus, S(stream));
   return e == hipSuccess ? WACM_OK : hipfail(e, "rhs_acm_adj launch");
@@ -460,6 +500,7 @@ int wacm_rhs_acm_adj(wacm_grid* g, const wacm_params* p, double t, const void* U
 int wacm_force_adj(wacm_grid* g, const wacm_params* p, double t, double weight, const void* U,
                    void* Ub, double* dtheta, double* dusbar, const void* dus, void* stream) {
   if (!elem_ok(g) || !U || !Ub || !dtheta) return fail(WACM_E_INVAL, "NULL argument");
+  if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "the adjoint is CDF 4/0 only");
   if (int rc = check_params(p)) return rc;
   hipError_t e = launch_force_adj(g, p, t, weight, U, Ub, dtheta, dusbar, dus, S(stream));
   return e == hipSuccess ? WACM_OK : hipfail(e, "force_adj launch");
@@ -469,6 +510,7 @@ int wacm_rk4_step_adj(wacm_grid* g, const wacm_params* p, double t, double dt, c
                       void* lam, double* dtheta, double* dusbar, const void* dus, void* work,
                       void* stream) {
   if (!elem_ok(g) || !Un || !lam || !dtheta || !work) return fail(WACM_E_INVAL, "NULL argument");
+  if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "the adjoint is CDF 4/0 only");
   if (reinterpret_cast<uintptr_t>(work) % 256) return fail(WACM_E_INVAL, "work not 256-aligned");
   if (int rc = check_params(p)) return rc;
   std::string err;

@@ -140,6 +140,88 @@ std::vector<int32_t> coarser_regions(const std::vector<Tab>& tabs) {
   return cr;
 }
 
+// Lifted ghost phase (CDF 4/4): one item per (block, ghost region in a finer
+// leaf, child of that region next to the block).  Along an axis the region
+// is [-ng, 0) (children of the upper half), [bs, bs+ng) (lower half) or the
+// block's own range split into its two halves; an output at block-local
+// coarse index i is centred on the child's fine point 2 (i - (r-1) bs) - h bs,
+// whose 13-point stencil must lie in the child's padded array.
+int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
+  g->n_lift = 0;
+  if (g->wavelet != 1 || tabs.empty()) return WACM_OK;
+  const int bs = g->d.bs, ng = g->d.ng, hb = bs / 2;
+  std::vector<int32_t> it;
+  int64_t pts = 0;
+  for (size_t ib = 0; ib < tabs.size(); ++ib) {
+    const Tab& t = tabs[ib];
+    for (int r = 0; r < 27; ++r) {
+      if (r == 13 || t.kind[r] <= 0) continue;
+      const int rr[3] = {r % 3, (r / 3) % 3, r / 9};
+      int st[3][2], cnt[3][2], half[3][2], nseg[3];
+      for (int d = 0; d < 3; ++d) {
+        if (rr[d] == 0) {
+          nseg[d] = 1, st[d][0] = -ng, cnt[d][0] = ng, half[d][0] = 1;
+        } else if (rr[d] == 2) {
+          nseg[d] = 1, st[d][0] = bs, cnt[d][0] = ng, half[d][0] = 0;
+        } else {
+          nseg[d] = 2;
+          st[d][0] = 0, cnt[d][0] = hb, half[d][0] = 0;
+          st[d][1] = hb, cnt[d][1] = hb, half[d][1] = 1;
+        }
+      }
+      for (int c = 0; c < nseg[2]; ++c)
+        for (int b = 0; b < nseg[1]; ++b)
+          for (int a = 0; a < nseg[0]; ++a) {
+            const int sg[3] = {a, b, c};
+            int f0[3], n3[3], o0[3], oct = 0;
+            for (int d = 0; d < 3; ++d) {
+              o0[d] = st[d][sg[d]];
+              n3[d] = cnt[d][sg[d]];
+              f0[d] = 2 * (o0[d] - (rr[d] - 1) * bs) - half[d][sg[d]] * bs;
+              oct += half[d][sg[d]] << d;
+              if (f0[d] - 6 < -ng || f0[d] + 2 * (n3[d] - 1) + 6 > bs + ng - 1) {
+                err = "lifted restriction stencil leaves the child's ghost layers";
+                return WACM_E_INVAL;
+              }
+            }
+            const int32_t item[12] = {t.meta[0], o0[0], o0[1], o0[2], n3[0], n3[1], n3[2],
+                                      t.slot[r][oct], f0[0], f0[1], f0[2], (int32_t)pts};
+            it.insert(it.end(), item, item + 12);
+            pts += (int64_t)n3[0] * n3[1] * n3[2];
+          }
+    }
+  }
+  if (pts > (int64_t(1) << 30)) {
+    err = "too many lifted ghost points";
+    return WACM_E_CAPACITY;
+  }
+  const size_t es = g->d.dtype == WACM_F64 ? 8 : 4;
+  const size_t ibytes = it.size() * sizeof(int32_t), tbytes = (size_t)pts * 4 * es;
+  hipError_t e = hipSuccess;
+  if (ibytes > g->lift_items_cap) {
+    if (g->d_lift) (void)hipFree(g->d_lift);
+    g->d_lift = nullptr;
+    g->lift_items_cap = 0;
+    e = hipMalloc(&g->d_lift, ibytes);
+    if (e == hipSuccess) g->lift_items_cap = ibytes;
+  }
+  if (e == hipSuccess && tbytes > g->lift_tmp_cap) {
+    if (g->d_lift_tmp) (void)hipFree(g->d_lift_tmp);
+    g->d_lift_tmp = nullptr;
+    g->lift_tmp_cap = 0;
+    e = hipMalloc(&g->d_lift_tmp, tbytes);
+    if (e == hipSuccess) g->lift_tmp_cap = tbytes;
+  }
+  if (e == hipSuccess && ibytes > 0)
+    e = hipMemcpy(g->d_lift, it.data(), ibytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    err = std::string("lifted ghost items: ") + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? WACM_E_NOMEM : WACM_E_HIP;
+  }
+  g->n_lift = (int64_t)it.size() / 12;
+  return WACM_OK;
+}
+
 int upload_tables(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
   if (tabs.empty()) return WACM_OK;
   hipError_t e = hipMemcpy(g->d_tab, tabs.data(), sizeof(Tab) * tabs.size(),
@@ -157,7 +239,7 @@ int upload_tables(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) 
   g->n_cface = (int64_t)cf.size() / 2;
   g->n_cregion = (int64_t)cr.size() / 2;
   g->h_tab = tabs;
-  return WACM_OK;
+  return build_lift(g, tabs, err);
 }
 
 }  // namespace wacm

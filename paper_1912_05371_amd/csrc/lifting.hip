@@ -1,0 +1,197 @@
+// CDF 4/4 lifted restriction (Sec. 3.2) on the device: the second phase of
+// the ghost synchronisation (ghost points whose owner is finer) and the
+// parents of merged families.
+//
+// Lifting the interpolating CDF 4/0 wavelet to 4 vanishing moments turns
+// restriction from decimation into a low-pass filter.  Along one axis the
+// coarse value at an even fine point is
+//   c = u_0 + sum_m U_m (u_m - P u_m),  m = -3, -1, 1, 3,
+// P the DD4 prediction from the neighbours m-3, m-1, m+1, m+3 and
+// U = (-1, 9, 9, -1)/32; expanded, a 13-tap filter on the offsets -6..6
+// (zero at +-5).  In 3D it is applied along x, y and z.  The fine values are
+// read from the finer leaf's padded array after the CDF 4/0 ghost fill, whose
+// ghost layers must be at least 6 deep.
+#include <hip/hip_runtime.h>
+
+#include "resolve.h"
+#include "wacm_internal.h"
+
+namespace wacm {
+
+// Expanded lifted low-pass, offsets -6..6.
+constexpr double LIFT_TAP[13] = {-1.0 / 512,  0.0,         18.0 / 512,  -16.0 / 512, -63.0 / 512,
+                                 144.0 / 512, 348.0 / 512, 144.0 / 512, -63.0 / 512, -16.0 / 512,
+                                 18.0 / 512,  0.0,         -1.0 / 512};
+
+// One work item: a box of nx x ny x nz coarse outputs.  Source: the padded
+// array of pool slot `sslot`; the output (dx, dy, dz) is centred on the
+// source's fine point (fx0 + 2 dx, fy0 + 2 dy, fz0 + 2 dz).  Items of the
+// ghost phase write into a staging buffer (4 fields, [c][dz][dy][dx], at 4 *
+// base values), so that no item reads a ghost value another item rewrites;
+// items of a merge write the parent's interior directly (parent slots are
+// fresh).  Each output is a z-march over the 13 fine planes around it: for
+// every fine plane an x pass on the fine rows into LDS, a y pass per output
+// column into a register ring of the last 13 planes, and the z pass once the
+// ring holds an output's 13 planes.
+//
+// mode 0: `items` holds 12 int32 per item (dst slot, i0, j0, k0, nx, ny, nz,
+//         src slot, fx0, fy0, fz0, base); outputs to `out` at 4 * base.
+// mode 1: `items` is the merge list (10 int32 per parent: parent slot, 8
+//         child slots, unused); item w is octant w % 8 of parent w / 8, a box
+//         of (bs/2)^3 outputs at the octant's offset, centred on the child's
+//         even points from (0, 0, 0); outputs into U at the parent.
+template <typename T, int BS>
+__global__ __launch_bounds__(NT_GEN) void lift_box_kernel(const int32_t* __restrict__ items,
+                                                          int64_t n, const T* U, Layout L,
+                                                          T* out, int mode) {
+  constexpr int NM = BS / 2;           // largest box edge
+  constexpr int NROW = 2 * NM + 11;    // fine rows a box needs
+  __shared__ T xq[NROW * NM];
+  const int tid = threadIdx.x;
+  T h[13];
+#pragma unroll
+  for (int q = 0; q < 13; ++q) h[q] = T(LIFT_TAP[q]);
+  for (int64_t w = blockIdx.x; w < n; w += gridDim.x) {
+    int dslot, i0, j0, k0, nx, ny, nz, sslot, fx0, fy0, fz0;
+    int64_t base = 0;
+    if (mode == 0) {
+      const int32_t* e = items + 12 * w;
+      dslot = e[0], i0 = e[1], j0 = e[2], k0 = e[3], nx = e[4], ny = e[5], nz = e[6];
+      sslot = e[7], fx0 = e[8], fy0 = e[9], fz0 = e[10];
+      base = (int64_t)e[11] * 4;
+    } else {
+      const int32_t* e = items + 10 * (w >> 3);
+      const int oc = (int)(w & 7);
+      dslot = e[0];
+      sslot = e[1 + oc];
+      i0 = (oc & 1) * NM, j0 = ((oc >> 1) & 1) * NM, k0 = (oc >> 2) * NM;
+      nx = ny = nz = NM;
+      fx0 = fy0 = fz0 = 0;
+    }
+    const T* src = U + (int64_t)sslot * L.bstride;
+    const int nrow = 2 * ny + 11, nplane = 2 * nz + 11;
+    const bool own = tid < nx * ny;
+    const int dx = own ? tid % nx : 0, dy = own ? tid / nx : 0;
+    for (int c = 0; c < 4; ++c) {
+      const T* sc = src + c * L.fstride;
+      T ring[13];
+#pragma unroll
+      for (int q = 0; q < 13; ++q) ring[q] = T(0);
+      for (int zf = 0; zf < nplane; ++zf) {
+        const int z = fz0 - 6 + zf;
+        __syncthreads();  // xq is free again
+        for (int it = tid; it < nrow * nx; it += NT_GEN) {
+          const int yf = it / nx, ox = it - yf * nx;
+          const int y = fy0 - 6 + yf;
+          const T* row =
+              sc + ((int64_t)(z + L.ng) * L.P + (y + L.ng)) * L.P + (fx0 + 2 * ox - 6 + L.ng);
+          T v = T(0);
+#pragma unroll
+          for (int q = 0; q < 13; ++q)
+            if (q != 1 && q != 11) v += h[q] * row[q];
+          xq[yf * NM + ox] = v;
+        }
+        __syncthreads();
+        if (own) {
+          T v = T(0);
+#pragma unroll
+          for (int q = 0; q < 13; ++q)
+            if (q != 1 && q != 11) v += h[q] * xq[(2 * dy + q) * NM + dx];
+#pragma unroll
+          for (int q = 0; q < 12; ++q) ring[q] = ring[q + 1];
+          ring[12] = v;
+          if (zf >= 12 && ((zf - 12) & 1) == 0) {
+            const int k = (zf - 12) >> 1;
+            T o = T(0);
+#pragma unroll
+            for (int q = 0; q < 13; ++q)
+              if (q != 1 && q != 11) o += h[q] * ring[q];
+            if (mode == 0)
+              out[base + ((int64_t)(c * nz + k) * ny + dy) * nx + dx] = o;
+            else
+              out[(int64_t)dslot * L.bstride + c * L.fstride +
+                  ((int64_t)(k0 + k + L.ng) * L.P + (j0 + dy + L.ng)) * L.P + (i0 + dx + L.ng)] = o;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Staged ghost values (mode 0 items) into the ghost layers.
+template <typename T>
+__global__ __launch_bounds__(NT_GEN) void lift_scatter_kernel(const int32_t* __restrict__ items,
+                                                              int64_t n, const T* __restrict__ tmp,
+                                                              T* __restrict__ U, Layout L) {
+  for (int64_t w = blockIdx.x; w < n; w += gridDim.x) {
+    const int32_t* e = items + 12 * w;
+    const int dslot = e[0], i0 = e[1], j0 = e[2], k0 = e[3], nx = e[4], ny = e[5], nz = e[6];
+    const int64_t base = (int64_t)e[11] * 4;
+    const int np = nx * ny * nz;
+    T* dst = U + (int64_t)dslot * L.bstride;
+    for (int p = threadIdx.x; p < 4 * np; p += blockDim.x) {
+      const int c = p / np, q = p - c * np;
+      const int dx = q % nx, dy = (q / nx) % ny, dz = q / (nx * ny);
+      dst[c * L.fstride + ((int64_t)(k0 + dz + L.ng) * L.P + (j0 + dy + L.ng)) * L.P +
+          (i0 + dx + L.ng)] = tmp[base + p];
+    }
+  }
+}
+
+static Layout lift_layout(const wacm_grid* g) {
+  Layout L;
+  L.P = g->P;
+  L.ng = g->d.ng;
+  L.fstride = (int64_t)g->P * g->P * g->P;
+  L.bstride = 4 * L.fstride;
+  return L;
+}
+
+static unsigned lift_grid(int64_t n) {
+  const int64_t cap = 2048;
+  return (unsigned)(n < cap ? (n > 0 ? n : 1) : cap);
+}
+
+template <typename T, int BS>
+static hipError_t lift_box_t(const wacm_grid* g, const int32_t* items, int64_t n, T* U, T* out,
+                             int mode, hipStream_t st) {
+  lift_box_kernel<T, BS><<<lift_grid(n), NT_GEN, 0, st>>>(items, n, U, lift_layout(g), out, mode);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t lift_box(const wacm_grid* g, const int32_t* items, int64_t n, T* U, T* out,
+                           int mode, hipStream_t st) {
+  switch (g->d.bs) {
+    case 24:
+      return lift_box_t<T, 24>(g, items, n, U, out, mode, st);
+    case 32:
+      return lift_box_t<T, 32>(g, items, n, U, out, mode, st);
+    default:
+      return hipErrorInvalidValue;  // CDF 4/4 needs ng >= 6, hence bs >= 18
+  }
+}
+
+template <typename T>
+static hipError_t lift_sync_t(const wacm_grid* g, T* U, hipStream_t st) {
+  if (g->n_lift == 0) return hipSuccess;
+  T* tmp = (T*)g->d_lift_tmp;
+  hipError_t e = lift_box<T>(g, g->d_lift, g->n_lift, U, tmp, 0, st);
+  if (e != hipSuccess) return e;
+  lift_scatter_kernel<T><<<lift_grid(g->n_lift), NT_GEN, 0, st>>>(g->d_lift, g->n_lift, tmp, U,
+                                                                  lift_layout(g));
+  return hipGetLastError();
+}
+
+hipError_t launch_lift_sync(const wacm_grid* g, void* U, hipStream_t st) {
+  return g->d.dtype == WACM_F64 ? lift_sync_t(g, (double*)U, st) : lift_sync_t(g, (float*)U, st);
+}
+
+hipError_t launch_lift_coarsen(const wacm_grid* g, void* U, int64_t nparents, hipStream_t st) {
+  if (nparents == 0) return hipSuccess;
+  return g->d.dtype == WACM_F64
+             ? lift_box<double>(g, g->d_list, 8 * nparents, (double*)U, (double*)U, 1, st)
+             : lift_box<float>(g, g->d_list, 8 * nparents, (float*)U, (float*)U, 1, st);
+}
+
+}  // namespace wacm

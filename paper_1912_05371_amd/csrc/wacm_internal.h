@@ -163,6 +163,15 @@ struct wacm_grid {
   std::vector<wacm::Tab> h_tab;  // host copy of the tables
   wacm_schedule sched{0, 1, -1, 1, 0};  // launch schedule of the stage kernel
   wacm::AdjPlan plan[2];         // ghost-fill transposes: all layers / face star
+  // restriction wavelet: 0 CDF 4/0 (decimation), 1 CDF 4/4 (lifted); with
+  // CDF 4/4, the work items of the lifted ghost phase (12 int32 each) and
+  // their staging buffer (4 fields per output point)
+  int wavelet = 0;
+  int32_t* d_lift = nullptr;
+  int64_t n_lift = 0;
+  size_t lift_items_cap = 0;
+  void* d_lift_tmp = nullptr;
+  size_t lift_tmp_cap = 0;
 };
 
 namespace wacm {
@@ -173,6 +182,9 @@ int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err);
 int upload_tables(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err);
 std::vector<int32_t> coarse_faces(const std::vector<Tab>& tabs);  // non-same-level faces
 std::vector<int32_t> coarser_regions(const std::vector<Tab>& tabs);  // regions in coarser leaves
+// CDF 4/4: builds the lifted ghost-phase items of the current tables and
+// (re)allocates their device buffers; a no-op for CDF 4/0
+int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err);
 uint64_t morton_key(const Leaf& l);
 void set_error(const std::string& s);
 
@@ -201,6 +213,10 @@ hipError_t launch_threshold(const wacm_grid* g, const wacm_params* p, double t, 
                             double eps, int dealias, double* dmax, double* mrange,
                             int8_t* flags, hipStream_t st);
 hipError_t launch_filter(const wacm_grid* g, void* U, int level, hipStream_t st);
+// CDF 4/4 (lifting.hip): the lifted ghost phase after the CDF 4/0 fill, and
+// the parents of a merge list of n families (already in d_list)
+hipError_t launch_lift_sync(const wacm_grid* g, void* U, hipStream_t st);
+hipError_t launch_lift_coarsen(const wacm_grid* g, void* U, int64_t nparents, hipStream_t st);
 // refine: n entries of (parent slot, child slot, octant); decimate: n entries
 // of (parent slot, 8 child slots); lists already on the device in d_list.
 hipError_t launch_prolong(const wacm_grid* g, void* U, int64_t n, hipStream_t st);

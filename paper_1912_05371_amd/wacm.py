@@ -21,6 +21,7 @@ E_INVAL, E_NOMEM, E_CAPACITY, E_UNBALANCED, E_HIP, E_NONFINITE, E_TILING = -1, -
 F32, F64 = 1, 2
 DT_FIXED, DT_CFL = 0, 1
 REFINE_ALL, COARSEN = 1, 2
+CDF40, CDF44 = 0, 1
 MASK_NONE, MASK_SPHERE, MASK_PLATE = 0, 1, 2
 
 EXPORTS = ["wacm_last_error", "wacm_treecode_encode", "wacm_treecode_decode", "wacm_grid_create",
@@ -29,7 +30,7 @@ EXPORTS = ["wacm_last_error", "wacm_treecode_encode", "wacm_treecode_decode", "w
            "wacm_diagnostics", "wacm_threshold_blocks", "wacm_filter_blocks", "wacm_adapt",
            "wacm_profile_enable", "wacm_profile_read", "wacm_adj_work_bytes", "wacm_sync_ghosts_adj",
            "wacm_rhs_acm_adj", "wacm_force_adj", "wacm_rk4_step_adj", "wacm_set_schedule",
-           "wacm_get_schedule"]
+           "wacm_get_schedule", "wacm_set_wavelet", "wacm_get_wavelet"]
 
 
 class GridDesc(C.Structure):
@@ -115,6 +116,8 @@ def lib():
         L.wacm_threshold_blocks.argtypes = [vp, C.POINTER(Params), dbl, vp, dbl, i32, vp, vp, vp,
                                             vp]
         L.wacm_filter_blocks.argtypes = [vp, vp, i32, vp]
+        L.wacm_set_wavelet.argtypes = [vp, i32]
+        L.wacm_get_wavelet.argtypes = [vp]
         L.wacm_adapt.argtypes = [vp, i32, vp, vp, vp, vp]
         L.wacm_adj_work_bytes.restype = C.c_size_t
         L.wacm_adj_work_bytes.argtypes = [vp]
@@ -310,6 +313,13 @@ class Grid:
         _check(lib().wacm_threshold_blocks(self._h, C.byref(p), float(t), _ptr(U), float(eps),
                                            int(bool(dealias)), _ptr(dmax), _ptr(mrange),
                                            _ptr(flags), _stream(stream)))
+
+    def set_wavelet(self, wavelet: int):
+        """CDF40 (restriction = decimation) or CDF44 (lifted, needs ng >= 6)."""
+        _check(lib().wacm_set_wavelet(self._h, int(wavelet)))
+
+    def get_wavelet(self) -> int:
+        return int(lib().wacm_get_wavelet(self._h))
 
     def filter_blocks(self, U, level: int = -1, stream=None):
         """Remove the details of the blocks of `level` (all if < 0) in place;

@@ -1,0 +1,127 @@
+"""GPU parity of the CDF 4/4 lifted restriction (Sec. 3.2) against the FP64
+oracle through the C ABI: the two-phase ghost synchronisation (ghost layers
+included in the comparison), a coarsening pass whose parents are lifted
+restrictions of their children, and refine-all (whose own synchronisation
+uses the lifted ghost values).  Grid: a seeded random 2:1 octree with bs 24
+and 6 ghost layers (the lifted stencil reaches 6 fine points)."""
+import numpy as np
+import pytest
+
+from paper_1912_05371_amd import cases, wacm
+
+from gpu_util import from_pool, log, rel_err, slot_map
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def octree24():
+    return cases.random_octree(bs=24, ng=6, target=120, j0=1, jmax=3, seed=21)
+
+
+def build(orc, c, prec=wacm.F64):
+    og = orc.Grid(c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix, c.iy, c.iz)
+    og.set_wavelet(1)
+    gg = wacm.Grid.from_case(c, dtype=prec, capacity=9 * c.nb + 64)
+    gg.set_wavelet(wacm.CDF44)
+    assert gg.get_wavelet() == wacm.CDF44
+    return og, gg
+
+
+def put(gg, og, U):
+    pool = gg.pool()
+    slots = slot_map(gg, og)
+    pool[torch.as_tensor(slots, device="cuda")] = torch.from_numpy(U).to(
+        device="cuda", dtype=gg.torch_dtype())
+    return pool
+
+
+def active_index(gg, og):
+    slots, codes, levels = gg.info()
+    pos = {(int(l), int(c)): i for i, (c, l) in enumerate(zip(codes, levels))}
+    return np.array([pos[(int(og.lev[b]), wacm.treecode_encode(og.lev[b], og.ix[b], og.iy[b],
+                                                                og.iz[b]))]
+                     for b in range(og.nb)])
+
+
+def same_leaves(gg, og):
+    slots, codes, levels = gg.info()
+    a = sorted(zip(levels.tolist(), codes.tolist()))
+    b = sorted((int(l), wacm.treecode_encode(l, x, y, z))
+               for l, x, y, z in zip(og.lev, og.ix, og.iy, og.iz))
+    return a == b
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cdf44_sync_matches_oracle(orc, prec):
+    c = octree24()
+    log(f"CDF 4/4 sync, {c.nb} blocks, {prec}")
+    og, gg = build(orc, c, wacm.F64 if prec == "f64" else wacm.F32)
+    U = c.padded()
+    pool = put(gg, og, U)
+    gg.sync_ghosts(pool)
+    Uo = U.copy()
+    og.sync(Uo)
+    Ug = from_pool(pool, slot_map(gg, og))
+    e = float(np.max(np.abs(Ug - Uo)) / np.max(np.abs(Uo)))
+    # how many ghost values the lifting changed (so the test covers it)
+    U0 = U.copy()
+    orc.Grid(c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix, c.iy, c.iz).sync(U0)
+    nl = int(np.sum(np.abs(Uo - U0) > 1e-12))
+    log(f"  whole padded arrays rel err {e:.2e}; {nl} values differ from CDF 4/0")
+    assert nl > 1000
+    assert e < (1e-13 if prec == "f64" else 1e-5)
+
+
+def test_cdf44_coarsen_pass_matches_oracle(orc):
+    c = octree24()
+    og, gg = build(orc, c)
+    U = c.padded()
+    og.sync(U)
+    flags_o = (np.asarray(og.lev) == c.jmax).astype(np.int8)  # every finest family
+    og2, Uo2 = og.coarsen(flags_o, U)
+    pool = put(gg, og, U)
+    ai = active_index(gg, og)
+    flags_g = np.zeros(og.nb, np.int8)
+    flags_g[ai] = flags_o
+    nb_new = gg.adapt(wacm.COARSEN, pool, flags_g)
+    log(f"CDF 4/4 coarsen: {og.nb} -> {og2.nb} blocks")
+    assert og2.nb < og.nb
+    assert nb_new == og2.nb and same_leaves(gg, og2)
+    Ug = from_pool(pool, slot_map(gg, og2))
+    e = rel_err(Ug, Uo2, c.bs, c.ng)
+    log(f"  interior rel err {e:.2e}")
+    assert e < 1e-13
+
+
+def test_cdf44_refine_all_matches_oracle(orc):
+    c = octree24()
+    og, gg = build(orc, c)
+    U = c.padded()
+    pool = put(gg, og, U)
+    nb_new = gg.adapt(wacm.REFINE_ALL, pool)
+    Uo = U.copy()
+    og.sync(Uo)
+    og2, Uo2 = og.refine_all(Uo)
+    assert nb_new == og2.nb and same_leaves(gg, og2)
+    Ug = from_pool(pool, slot_map(gg, og2))
+    e = rel_err(Ug, Uo2, c.bs, c.ng)
+    log(f"CDF 4/4 refine_all: {og.nb} -> {og2.nb} blocks, interior rel err {e:.2e}")
+    assert e < 1e-13
+
+
+def test_cdf44_needs_six_ghost_layers_and_guards():
+    c = cases.random_octree(bs=24, ng=4, target=40, j0=1, jmax=2, seed=5)
+    g = wacm.Grid.from_case(c, dtype=wacm.F64)
+    with pytest.raises(wacm.WacmError):
+        g.set_wavelet(wacm.CDF44)
+    assert g.get_wavelet() == wacm.CDF40
+    c6 = octree24()
+    g6 = wacm.Grid.from_case(c6, dtype=wacm.F64)
+    g6.set_wavelet(wacm.CDF44)
+    pool = g6.pool()
+    with pytest.raises(wacm.WacmError):
+        g6.filter_blocks(pool, -1)
+    g6.set_wavelet(wacm.CDF40)
+    g6.filter_blocks(pool, -1)
