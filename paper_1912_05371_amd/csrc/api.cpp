@@ -210,7 +210,10 @@ int wacm_grid_info(const wacm_grid* g, int64_t* slots, uint64_t* treecodes, int8
   return WACM_OK;
 }
 
-size_t wacm_work_bytes(const wacm_grid* g) { return g ? work_bytes(g) : 0; }
+size_t wacm_work_bytes(const wacm_grid* g) {
+  if (!g) return 0;
+  return g->wavelet == WACM_CDF44 ? lift_work_bytes(g) : work_bytes(g);
+}
 
 int wacm_set_schedule(wacm_grid* g, const wacm_schedule* s) {
   if (!g || !s) return fail(WACM_E_INVAL, "NULL argument");
@@ -285,8 +288,10 @@ static int rk4_common(wacm_grid* g, const wacm_params* p, double* t_dev, double*
   if (nsteps < 0) return fail(WACM_E_INVAL, "nsteps must be >= 0");
   if (reinterpret_cast<uintptr_t>(work) % 256) return fail(WACM_E_INVAL, "work not 256-aligned");
   if (int rc = check_params(p)) return rc;
-  if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "RK4 with CDF 4/4 is not available");
-  hipError_t e = launch_rk4(g, p, t_dev, dt_dev, U, work, dus, dt_mode, nsteps, S(stream));
+  hipError_t e = g->wavelet == WACM_CDF44
+                     ? launch_rk4_lifted(g, p, t_dev, dt_dev, U, work, dus, dt_mode, nsteps,
+                                         S(stream))
+                     : launch_rk4(g, p, t_dev, dt_dev, U, work, dus, dt_mode, nsteps, S(stream));
   return e == hipSuccess ? WACM_OK : hipfail(e, what);
 }
 

@@ -194,4 +194,104 @@ hipError_t launch_lift_coarsen(const wacm_grid* g, void* U, int64_t nparents, hi
              : lift_box<float>(g, g->d_list, 8 * nparents, (float*)U, (float*)U, 1, st);
 }
 
+// --------------------------------------------------------------------------
+// Classical RK4 with CDF 4/4 ghosts.  The fused stage path reads same-level
+// halos in place and fills face halos next to other levels itself; with the
+// lifted restriction every stage input is instead synchronised in full (CDF
+// 4/0 fill, then the lifted phase) and the rhs read from its own ghost
+// layers: per stage a sync, the rhs and one combination kernel, registers Y,
+// K and the accumulator A in the padded pool layout in `work`.
+// --------------------------------------------------------------------------
+struct LiftWork {
+  size_t y, k, a, total;
+};
+static LiftWork lift_work(const wacm_grid* g) {
+  const size_t es = g->d.dtype == WACM_F64 ? 8 : 4;
+  const size_t reg = (size_t)g->d.capacity * 4 * (size_t)g->P * g->P * g->P * es;
+  const size_t up = (reg + 255) / 256 * 256;
+  return LiftWork{0, up, 2 * up, 3 * up};
+}
+
+size_t lift_work_bytes(const wacm_grid* g) { return lift_work(g).total; }
+
+// D = A + s B on the interiors of the active blocks (B null: D = A).
+template <typename T>
+__global__ __launch_bounds__(NT_GEN) void lin_kernel(const Tab* __restrict__ tab, int64_t nb,
+                                                     T* D, const T* A, const T* B, T s, Layout L,
+                                                     int bs) {
+  const int n3 = bs * bs * bs;
+  for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
+    const int64_t so = (int64_t)tab[ib].meta[0] * L.bstride;
+    for (int q = threadIdx.x; q < 4 * n3; q += blockDim.x) {
+      const int c = q / n3, r = q - c * n3;
+      const int i = r % bs, j = (r / bs) % bs, k = r / (bs * bs);
+      const int64_t o =
+          so + c * L.fstride + ((int64_t)(k + L.ng) * L.P + (j + L.ng)) * L.P + (i + L.ng);
+      D[o] = B ? A[o] + s * B[o] : A[o];
+    }
+  }
+}
+
+__global__ void lift_advance_time(double* t_dev, const double* dt_dev) {
+  if (threadIdx.x == 0) t_dev[0] += dt_dev[0];
+}
+
+template <typename T>
+static hipError_t rk4_lifted_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
+                               double* dt_dev, T* U, void* work, const void* dus, int dt_mode,
+                               int64_t nsteps, hipStream_t st) {
+  if (g->nb == 0) return hipSuccess;
+  const LiftWork wp = lift_work(g);
+  T* Y = (T*)((char*)work + wp.y);
+  T* K = (T*)((char*)work + wp.k);
+  T* A = (T*)((char*)work + wp.a);
+  const Layout L = lift_layout(g);
+  const unsigned grid = lift_grid(g->nb);
+  hipError_t e;
+  auto lin = [&](T* D, const T* X, const T* B, double s) {
+    lin_kernel<T><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, D, X, B, T(s), L, g->d.bs);
+    return hipGetLastError();
+  };
+  auto sync = [&](T* X) {
+    hipError_t r = launch_sync(g, X, 0, st);
+    return r == hipSuccess ? launch_lift_sync(g, X, st) : r;
+  };
+  for (int64_t n = 0; n < nsteps; ++n) {
+    if (dt_mode == WACM_DT_CFL && (e = launch_dt(g, p, U, dt_dev, st)) != hipSuccess) return e;
+    // the stage times enter the rhs as host values: read t and dt back once
+    // per step
+    double h[2];
+    if ((e = hipMemcpyAsync(&h[0], t_dev, sizeof(double), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(&h[1], dt_dev, sizeof(double), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      return e;
+    const double t = h[0], dt = h[1];
+    if ((e = lin(Y, U, nullptr, 0.0)) != hipSuccess || (e = sync(Y)) != hipSuccess ||
+        (e = launch_rhs(g, p, t, Y, K, dus, st)) != hipSuccess ||
+        (e = lin(A, U, K, dt / 6.0)) != hipSuccess || (e = lin(Y, U, K, 0.5 * dt)) != hipSuccess ||
+        (e = sync(Y)) != hipSuccess ||
+        (e = launch_rhs(g, p, t + 0.5 * dt, Y, K, dus, st)) != hipSuccess ||
+        (e = lin(A, A, K, dt / 3.0)) != hipSuccess || (e = lin(Y, U, K, 0.5 * dt)) != hipSuccess ||
+        (e = sync(Y)) != hipSuccess ||
+        (e = launch_rhs(g, p, t + 0.5 * dt, Y, K, dus, st)) != hipSuccess ||
+        (e = lin(A, A, K, dt / 3.0)) != hipSuccess || (e = lin(Y, U, K, dt)) != hipSuccess ||
+        (e = sync(Y)) != hipSuccess || (e = launch_rhs(g, p, t + dt, Y, K, dus, st)) != hipSuccess ||
+        (e = lin(U, A, K, dt / 6.0)) != hipSuccess)
+      return e;
+    lift_advance_time<<<1, 64, 0, st>>>(t_dev, dt_dev);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_rk4_lifted(const wacm_grid* g, const wacm_params* p, double* t_dev,
+                             double* dt_dev, void* U, void* work, const void* dus, int dt_mode,
+                             int64_t nsteps, hipStream_t st) {
+  return g->d.dtype == WACM_F64
+             ? rk4_lifted_t(g, p, t_dev, dt_dev, (double*)U, work, dus, dt_mode, nsteps, st)
+             : rk4_lifted_t(g, p, t_dev, dt_dev, (float*)U, work, dus, dt_mode, nsteps, st);
+}
+
 }  // namespace wacm

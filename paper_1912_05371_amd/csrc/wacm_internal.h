@@ -217,6 +217,12 @@ hipError_t launch_filter(const wacm_grid* g, void* U, int level, hipStream_t st)
 // the parents of a merge list of n families (already in d_list)
 hipError_t launch_lift_sync(const wacm_grid* g, void* U, hipStream_t st);
 hipError_t launch_lift_coarsen(const wacm_grid* g, void* U, int64_t nparents, hipStream_t st);
+// RK4 with CDF 4/4 ghosts: every stage input synchronised in full, the rhs
+// from its own ghost layers; work = 3 padded registers (lift_work_bytes)
+hipError_t launch_rk4_lifted(const wacm_grid* g, const wacm_params* p, double* t_dev,
+                             double* dt_dev, void* U, void* work, const void* dus, int dt_mode,
+                             int64_t nsteps, hipStream_t st);
+size_t lift_work_bytes(const wacm_grid* g);
 // refine: n entries of (parent slot, child slot, octant); decimate: n entries
 // of (parent slot, 8 child slots); lists already on the device in d_list.
 hipError_t launch_prolong(const wacm_grid* g, void* U, int64_t n, hipStream_t st);

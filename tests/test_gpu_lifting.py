@@ -125,3 +125,53 @@ def test_cdf44_needs_six_ghost_layers_and_guards():
         g6.filter_blocks(pool, -1)
     g6.set_wavelet(wacm.CDF40)
     g6.filter_blocks(pool, -1)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cdf44_rk4_step_matches_oracle(orc, prec):
+    """RK4 steps with the lifted ghosts: each step from the oracle's state with
+    the oracle's CFL time step (per-step gate), then two free-running steps
+    with the device's own CFL step against two oracle steps."""
+    c = octree24()
+    og, gg = build(orc, c, wacm.F64 if prec == "f64" else wacm.F32)
+    U = c.padded()
+    work = gg.work()
+    t = 0.0
+    worst = 0.0
+    for n in range(2):
+        dt = og.dt(c.params, U)
+        Uin = U.astype(np.float32).astype(np.float64) if prec == "f32" else U
+        pool = put(gg, og, Uin)
+        t_dev = torch.tensor([t], dtype=torch.float64, device="cuda")
+        dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
+        gg.rk4_step(c.params, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_FIXED)
+        og.rk4_step(c.params, t, dt, U)
+        torch.cuda.synchronize()
+        e = rel_err(from_pool(pool, slot_map(gg, og)), U, c.bs, c.ng)
+        worst = max(worst, e)
+        t += dt
+        assert abs(float(t_dev.item()) - t) <= 1e-15 * t
+    log(f"CDF 4/4 RK4 {prec}: worst per-step rel err {worst:.2e}")
+    assert worst < (1e-12 if prec == "f64" else 1e-5)
+    if prec == "f64":
+        # n steps in one call = n single calls, bitwise; CFL time step on the device
+        U0 = c.padded()
+        A = put(gg, og, U0)
+        B = A.clone()
+        ta, dta = (torch.zeros(1, dtype=torch.float64, device="cuda") for _ in range(2))
+        tb, dtb = (torch.zeros(1, dtype=torch.float64, device="cuda") for _ in range(2))
+        gg.rk4_steps(c.params, ta, dta, A, work, 2, dt_mode=wacm.DT_CFL)
+        for _ in range(2):
+            gg.rk4_step(c.params, tb, dtb, B, work, dt_mode=wacm.DT_CFL)
+        torch.cuda.synchronize()
+        I = slice(c.ng, c.ng + c.bs)
+        assert torch.equal(A[..., I, I, I], B[..., I, I, I]) and ta.item() == tb.item()
+        Uo = U0.copy()
+        to = 0.0
+        for _ in range(2):
+            dto = og.dt(c.params, Uo)
+            og.rk4_step(c.params, to, dto, Uo)
+            to += dto
+        e = rel_err(from_pool(A, slot_map(gg, og)), Uo, c.bs, c.ng)
+        log(f"  2 free CFL steps: rel err {e:.2e}, t {ta.item():.6e} vs {to:.6e}")
+        assert e < 1e-12 and abs(ta.item() - to) <= 1e-12 * to
