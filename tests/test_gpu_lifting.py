@@ -175,3 +175,35 @@ def test_cdf44_rk4_step_matches_oracle(orc, prec):
         e = rel_err(from_pool(A, slot_map(gg, og)), Uo, c.bs, c.ng)
         log(f"  2 free CFL steps: rel err {e:.2e}, t {ta.item():.6e} vs {to:.6e}")
         assert e < 1e-12 and abs(ta.item() - to) <= 1e-12 * to
+
+
+def test_cdf44_adaptive_driver_matches_oracle(orc):
+    """adaptive.adaptive_step on a CDF 4/4 grid (lifted ghosts in every sync,
+    lifted parents in every merge, the GPU's own flags) against the oracle's
+    adaptive step: same leaves, states to 1e-12, two steps."""
+    from paper_1912_05371_amd.adaptive import adaptive_step
+    from test_gpu_adapt import adaptive_step_oracle
+    c = octree24()
+    eps, dealias = 1e-2, True
+    og, gg = build(orc, c)
+    gg.close()
+    gg = wacm.Grid.from_case(c, dtype=wacm.F64, capacity=12 * c.nb + 64)
+    gg.set_wavelet(wacm.CDF44)
+    U = c.padded()
+    pool = put(gg, og, U)
+    work = gg.work()
+    t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t = 0.0
+    for step in range(2):
+        og, U, dt, passes = adaptive_step_oracle(og, U, c.params, t, eps, dealias)
+        t += dt
+        merged = adaptive_step(gg, c.params, pool, work, t_dev, dt_dev, eps, dealias)[
+            "merged_passes"]
+        assert same_leaves(gg, og)
+        e = rel_err(from_pool(pool, slot_map(gg, og)), U, c.bs, c.ng)
+        log(f"CDF 4/4 adaptive step {step}: {og.nb} blocks, {merged} merging passes "
+            f"(oracle {len(passes)}), state rel err {e:.2e}")
+        assert merged == len(passes) and merged > 0
+        assert e < 1e-12
+        assert abs(float(t_dev.item()) - t) <= 1e-12 * t
