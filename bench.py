@@ -265,6 +265,8 @@ def aux_timings(case):
     g.close()
     torch.cuda.empty_cache()
 
+    out["cdf44"] = lifting_timings(case_seed(case))
+
     # one adaptive step of the rotating plate (levels 2..6, bs 16)
     from paper_1912_05371_amd.adaptive import adaptive_step
     c = cases.plate_adaptive()
@@ -284,6 +286,48 @@ def aux_timings(case):
         "total_ms": round(sum(ph.values()), 3)}
     del U, work
     ga.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def lifting_timings(seed: int):
+    """CDF 4/4 (lifted restriction) on a random octree with 6 ghost layers
+    (bs 24, levels 3-6, ~4000 blocks, FP64): the full ghost sync with CDF 4/0
+    and with CDF 4/4 (the lifted phase on top), and one RK4 step on the lifted
+    path (4 full syncs, 4 rhs evaluations from the ghost layers)."""
+    import torch
+
+    from paper_1912_05371_amd import cases, inputs, wacm
+
+    c = cases.random_octree(bs=24, ng=6, target=4000, j0=3, jmax=6, seed=seed,
+                            with_fields=False)
+    g = wacm.Grid.from_case(c, dtype=wacm.F64)
+    pool = g.pool()
+    modes = inputs.fourier_modes(seed, 4, 16, 8, 1.0 / 16.0)
+    inputs.fourier_fill_device(pool, modes, c.bs, c.ng, c.L, c.lev, c.ix, c.iy, c.iz,
+                               np.arange(c.nb))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return round(e0.elapsed_time(e1) / reps, 3)
+
+    out = {"blocks": c.nb, "sync_cdf40_ms": timed(lambda: g.sync_ghosts(pool))}
+    g.set_wavelet(wacm.CDF44)
+    out["sync_cdf44_ms"] = timed(lambda: g.sync_ghosts(pool))
+    work = g.work()
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    out["rk4_step_cdf44_ms"] = timed(
+        lambda: g.rk4_step(c.params, t, dt, pool, work, dt_mode=wacm.DT_CFL), reps=2)
+    del work, pool
+    g.close()
     torch.cuda.empty_cache()
     return out
 
