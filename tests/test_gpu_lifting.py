@@ -53,10 +53,11 @@ def same_leaves(gg, og):
     return a == b
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_cdf44_sync_matches_oracle(orc, prec):
-    c = octree24()
-    log(f"CDF 4/4 sync, {c.nb} blocks, {prec}")
+@pytest.mark.parametrize("prec,bs", [("f64", 24), ("f32", 24), ("f64", 32)])
+def test_cdf44_sync_matches_oracle(orc, prec, bs):
+    c = octree24() if bs == 24 else cases.random_octree(bs=32, ng=6, target=60, j0=1, jmax=3,
+                                                         seed=23)
+    log(f"CDF 4/4 sync, bs {bs}, {c.nb} blocks, {prec}")
     og, gg = build(orc, c, wacm.F64 if prec == "f64" else wacm.F32)
     U = c.padded()
     pool = put(gg, og, U)
@@ -207,3 +208,20 @@ def test_cdf44_adaptive_driver_matches_oracle(orc):
         assert merged == len(passes) and merged > 0
         assert e < 1e-12
         assert abs(float(t_dev.item()) - t) <= 1e-12 * t
+
+
+def test_cdf44_uniform_grid_is_cdf40(orc):
+    """No ghost point has a finer owner on a uniform grid: the lifted phase has
+    no work and the sync equals the CDF 4/0 one bitwise."""
+    c = cases.random_octree(bs=24, ng=6, target=8, j0=1, jmax=1, seed=2)
+    assert c.nb == 8
+    g = wacm.Grid.from_case(c, dtype=wacm.F64)
+    U = c.padded()
+    A = g.pool()
+    A[: c.nb].copy_(torch.from_numpy(U))
+    B = A.clone()
+    g.sync_ghosts(A)
+    g.set_wavelet(wacm.CDF44)
+    g.sync_ghosts(B)
+    torch.cuda.synchronize()
+    assert torch.equal(A, B)
