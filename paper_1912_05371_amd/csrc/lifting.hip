@@ -214,20 +214,29 @@ static LiftWork lift_work(const wacm_grid* g) {
 
 size_t lift_work_bytes(const wacm_grid* g) { return lift_work(g).total; }
 
-// D = A + s B on the interiors of the active blocks (B null: D = A).
-template <typename T>
-__global__ __launch_bounds__(NT_GEN) void lin_kernel(const Tab* __restrict__ tab, int64_t nb,
-                                                     T* D, const T* A, const T* B, T s, Layout L,
-                                                     int bs) {
-  const int n3 = bs * bs * bs;
+// RK4 combinations on the interiors of the active blocks, after the rhs K of
+// a stage: mode 0 (stage 1) A = U + sa K, Y = U + sy K; mode 1 (stages 2, 3)
+// A += sa K, Y = U + sy K; mode 2 (stage 4) U = A + sa K.
+template <typename T, int BS>
+__global__ __launch_bounds__(NT_GEN) void rk_combine_kernel(const Tab* __restrict__ tab,
+                                                            int64_t nb, T* U, const T* K, T* A,
+                                                            T* Y, T sa, T sy, int mode, Layout L) {
+  constexpr int N3 = BS * BS * BS;
   for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
     const int64_t so = (int64_t)tab[ib].meta[0] * L.bstride;
-    for (int q = threadIdx.x; q < 4 * n3; q += blockDim.x) {
-      const int c = q / n3, r = q - c * n3;
-      const int i = r % bs, j = (r / bs) % bs, k = r / (bs * bs);
+    for (int q = threadIdx.x; q < 4 * N3; q += blockDim.x) {
+      const int c = q / N3, r = q - c * N3;
+      const int i = r % BS, j = (r / BS) % BS, k = r / (BS * BS);
       const int64_t o =
           so + c * L.fstride + ((int64_t)(k + L.ng) * L.P + (j + L.ng)) * L.P + (i + L.ng);
-      D[o] = B ? A[o] + s * B[o] : A[o];
+      const T kv = K[o];
+      if (mode == 2) {
+        U[o] = A[o] + sa * kv;
+      } else {
+        const T u = U[o];
+        A[o] = (mode == 0 ? u : A[o]) + sa * kv;
+        Y[o] = u + sy * kv;
+      }
     }
   }
 }
@@ -248,8 +257,19 @@ static hipError_t rk4_lifted_t(const wacm_grid* g, const wacm_params* p, double*
   const Layout L = lift_layout(g);
   const unsigned grid = lift_grid(g->nb);
   hipError_t e;
-  auto lin = [&](T* D, const T* X, const T* B, double s) {
-    lin_kernel<T><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, D, X, B, T(s), L, g->d.bs);
+  auto comb = [&](double sa, double sy, int mode) {
+    switch (g->d.bs) {
+      case 24:
+        rk_combine_kernel<T, 24><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, K, A, Y, T(sa),
+                                                          T(sy), mode, L);
+        break;
+      case 32:
+        rk_combine_kernel<T, 32><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, K, A, Y, T(sa),
+                                                          T(sy), mode, L);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   };
   auto sync = [&](T* X) {
@@ -268,17 +288,15 @@ static hipError_t rk4_lifted_t(const wacm_grid* g, const wacm_params* p, double*
         (e = hipStreamSynchronize(st)) != hipSuccess)
       return e;
     const double t = h[0], dt = h[1];
-    if ((e = lin(Y, U, nullptr, 0.0)) != hipSuccess || (e = sync(Y)) != hipSuccess ||
-        (e = launch_rhs(g, p, t, Y, K, dus, st)) != hipSuccess ||
-        (e = lin(A, U, K, dt / 6.0)) != hipSuccess || (e = lin(Y, U, K, 0.5 * dt)) != hipSuccess ||
-        (e = sync(Y)) != hipSuccess ||
+    // stage 1 reads U^n with its own ghost layers, synchronised in place
+    if ((e = sync(U)) != hipSuccess || (e = launch_rhs(g, p, t, U, K, dus, st)) != hipSuccess ||
+        (e = comb(dt / 6.0, 0.5 * dt, 0)) != hipSuccess || (e = sync(Y)) != hipSuccess ||
         (e = launch_rhs(g, p, t + 0.5 * dt, Y, K, dus, st)) != hipSuccess ||
-        (e = lin(A, A, K, dt / 3.0)) != hipSuccess || (e = lin(Y, U, K, 0.5 * dt)) != hipSuccess ||
-        (e = sync(Y)) != hipSuccess ||
+        (e = comb(dt / 3.0, 0.5 * dt, 1)) != hipSuccess || (e = sync(Y)) != hipSuccess ||
         (e = launch_rhs(g, p, t + 0.5 * dt, Y, K, dus, st)) != hipSuccess ||
-        (e = lin(A, A, K, dt / 3.0)) != hipSuccess || (e = lin(Y, U, K, dt)) != hipSuccess ||
-        (e = sync(Y)) != hipSuccess || (e = launch_rhs(g, p, t + dt, Y, K, dus, st)) != hipSuccess ||
-        (e = lin(U, A, K, dt / 6.0)) != hipSuccess)
+        (e = comb(dt / 3.0, dt, 1)) != hipSuccess || (e = sync(Y)) != hipSuccess ||
+        (e = launch_rhs(g, p, t + dt, Y, K, dus, st)) != hipSuccess ||
+        (e = comb(dt / 6.0, 0.0, 2)) != hipSuccess)
       return e;
     lift_advance_time<<<1, 64, 0, st>>>(t_dev, dt_dev);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -162,6 +162,9 @@ def test_cdf44_rk4_step_matches_oracle(orc, prec):
         ta, dta = (torch.zeros(1, dtype=torch.float64, device="cuda") for _ in range(2))
         tb, dtb = (torch.zeros(1, dtype=torch.float64, device="cuda") for _ in range(2))
         gg.rk4_steps(c.params, ta, dta, A, work, 2, dt_mode=wacm.DT_CFL)
+        # the rhs of this path follows the stage-kernel schedule: tiles of 8
+        # rows and the work counters give the same state bitwise
+        gg.set_schedule(tile_rows=8, wg_per_cu=2, xcd_map=2, prefetch=1, nontemporal=0)
         for _ in range(2):
             gg.rk4_step(c.params, tb, dtb, B, work, dt_mode=wacm.DT_CFL)
         torch.cuda.synchronize()
