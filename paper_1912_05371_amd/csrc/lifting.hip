@@ -32,7 +32,8 @@ constexpr double LIFT_TAP[13] = {-1.0 / 512,  0.0,         18.0 / 512,  -16.0 / 
 // fresh).  Each output is a z-march over the 13 fine planes around it: for
 // every fine plane an x pass on the fine rows into LDS, a y pass per output
 // column into a register ring of the last 13 planes, and the z pass once the
-// ring holds an output's 13 planes.
+// ring holds an output's 13 planes; the 4 fields go through each plane
+// together.
 //
 // mode 0: `items` holds 12 int32 per item (dst slot, i0, j0, k0, nx, ny, nz,
 //         src slot, fx0, fy0, fz0, base); outputs to `out` at 4 * base.
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(NT_GEN) void lift_box_kernel(const int32_t* __restr
                                                           T* out, int mode) {
   constexpr int NM = BS / 2;           // largest box edge
   constexpr int NROW = 2 * NM + 11;    // fine rows a box needs
-  __shared__ T xq[NROW * NM];
+  __shared__ T xq[4][NROW * NM];       // x pass of the current fine plane, 4 fields
   const int tid = threadIdx.x;
   T h[13];
 #pragma unroll
@@ -69,43 +70,47 @@ __global__ __launch_bounds__(NT_GEN) void lift_box_kernel(const int32_t* __restr
       fx0 = fy0 = fz0 = 0;
     }
     const T* src = U + (int64_t)sslot * L.bstride;
-    const int nrow = 2 * ny + 11, nplane = 2 * nz + 11;
+    const int nrow = 2 * ny + 11, nplane = 2 * nz + 11, nxp = nrow * nx;
     const bool own = tid < nx * ny;
     const int dx = own ? tid % nx : 0, dy = own ? tid / nx : 0;
-    for (int c = 0; c < 4; ++c) {
-      const T* sc = src + c * L.fstride;
-      T ring[13];
+    T ring[4][13];
 #pragma unroll
-      for (int q = 0; q < 13; ++q) ring[q] = T(0);
-      for (int zf = 0; zf < nplane; ++zf) {
-        const int z = fz0 - 6 + zf;
-        __syncthreads();  // xq is free again
-        for (int it = tid; it < nrow * nx; it += NT_GEN) {
-          const int yf = it / nx, ox = it - yf * nx;
-          const int y = fy0 - 6 + yf;
-          const T* row =
-              sc + ((int64_t)(z + L.ng) * L.P + (y + L.ng)) * L.P + (fx0 + 2 * ox - 6 + L.ng);
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int q = 0; q < 13; ++q) ring[c][q] = T(0);
+    for (int zf = 0; zf < nplane; ++zf) {
+      const int z = fz0 - 6 + zf;
+      __syncthreads();  // xq is free again
+      for (int it = tid; it < 4 * nxp; it += NT_GEN) {
+        const int c = it / nxp, rem = it - c * nxp;
+        const int yf = rem / nx, ox = rem - yf * nx;
+        const int y = fy0 - 6 + yf;
+        const T* row = src + c * L.fstride + ((int64_t)(z + L.ng) * L.P + (y + L.ng)) * L.P +
+                       (fx0 + 2 * ox - 6 + L.ng);
+        T v = T(0);
+#pragma unroll
+        for (int q = 0; q < 13; ++q)
+          if (q != 1 && q != 11) v += h[q] * row[q];
+        xq[c][yf * NM + ox] = v;
+      }
+      __syncthreads();
+      if (own) {
+        const bool emit = zf >= 12 && ((zf - 12) & 1) == 0;
+        const int k = (zf - 12) >> 1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
           T v = T(0);
 #pragma unroll
           for (int q = 0; q < 13; ++q)
-            if (q != 1 && q != 11) v += h[q] * row[q];
-          xq[yf * NM + ox] = v;
-        }
-        __syncthreads();
-        if (own) {
-          T v = T(0);
+            if (q != 1 && q != 11) v += h[q] * xq[c][(2 * dy + q) * NM + dx];
 #pragma unroll
-          for (int q = 0; q < 13; ++q)
-            if (q != 1 && q != 11) v += h[q] * xq[(2 * dy + q) * NM + dx];
-#pragma unroll
-          for (int q = 0; q < 12; ++q) ring[q] = ring[q + 1];
-          ring[12] = v;
-          if (zf >= 12 && ((zf - 12) & 1) == 0) {
-            const int k = (zf - 12) >> 1;
+          for (int q = 0; q < 12; ++q) ring[c][q] = ring[c][q + 1];
+          ring[c][12] = v;
+          if (emit) {
             T o = T(0);
 #pragma unroll
             for (int q = 0; q < 13; ++q)
-              if (q != 1 && q != 11) o += h[q] * ring[q];
+              if (q != 1 && q != 11) o += h[q] * ring[c][q];
             if (mode == 0)
               out[base + ((int64_t)(c * nz + k) * ny + dy) * nx + dx] = o;
             else
