@@ -146,12 +146,13 @@ std::vector<int32_t> coarser_regions(const std::vector<Tab>& tabs) {
 // block's own range split into its two halves; an output at block-local
 // coarse index i is centred on the child's fine point 2 (i - (r-1) bs) - h bs,
 // whose 13-point stencil must lie in the child's padded array.
-int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
-  g->n_lift = 0;
-  if (g->wavelet != 1 || tabs.empty()) return WACM_OK;
+// The items of the tables (12 int32 each, pts = output points); also used
+// by the host harness that checks them against the point resolver.
+int lift_items(const wacm_grid* g, const std::vector<Tab>& tabs, std::vector<int32_t>& it,
+               int64_t& pts, std::string& err) {
   const int bs = g->d.bs, ng = g->d.ng, hb = bs / 2;
-  std::vector<int32_t> it;
-  int64_t pts = 0;
+  it.clear();
+  pts = 0;
   for (size_t ib = 0; ib < tabs.size(); ++ib) {
     const Tab& t = tabs[ib];
     for (int r = 0; r < 27; ++r) {
@@ -191,6 +192,15 @@ int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
           }
     }
   }
+  return WACM_OK;
+}
+
+int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
+  g->n_lift = 0;
+  if (g->wavelet != 1 || tabs.empty()) return WACM_OK;
+  std::vector<int32_t> it;
+  int64_t pts = 0;
+  if (int rc = lift_items(g, tabs, it, pts, err)) return rc;
   if (pts > (int64_t(1) << 30)) {
     err = "too many lifted ghost points";
     return WACM_E_CAPACITY;

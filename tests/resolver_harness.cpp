@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <set>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -18,6 +19,77 @@
 #include "wacm_internal.h"
 
 static int g_cap = 0;
+
+namespace wacm {
+int lift_items(const wacm_grid* g, const std::vector<Tab>& tabs, std::vector<int32_t>& it,
+               int64_t& pts, std::string& err);
+}
+
+// The CDF 4/4 lifted ghost-phase items: every ghost point whose owner is finer
+// is the output of exactly one item, no other point is, every output is
+// centred on the point the resolver gives for that ghost point (the finer
+// owner's coincident fine point), and every 13-point stencil stays inside the
+// source's padded array.
+static int check_lift(const wacm_grid& g, const std::vector<wacm::Tab>& tabs) {
+  using namespace wacm;
+  const int bs = g.d.bs, ng = g.d.ng, P = g.P;
+  Layout L;
+  L.P = P;
+  L.ng = ng;
+  L.fstride = (int64_t)P * P * P;
+  L.bstride = 4 * L.fstride;
+  std::vector<int32_t> it;
+  int64_t pts = 0;
+  std::string err;
+  if (lift_items(&g, tabs, it, pts, err)) {
+    std::fprintf(stderr, "lift items: %s\n", err.c_str());
+    return 10;
+  }
+  std::vector<int> tab_of(g_cap, -1);
+  for (size_t ib = 0; ib < tabs.size(); ++ib) tab_of[tabs[ib].meta[0]] = (int)ib;
+  std::set<std::tuple<int, int, int, int>> covered;
+  int64_t npts = 0;
+  for (size_t w = 0; w < it.size() / 12; ++w) {
+    const int32_t* e = &it[12 * w];
+    if (e[0] < 0 || e[0] >= g_cap || tab_of[e[0]] < 0 || e[7] < 0 || e[7] >= g_cap) return 11;
+    if (e[11] != npts) return 12;
+    const Tab& t = tabs[tab_of[e[0]]];
+    for (int dz = 0; dz < e[6]; ++dz)
+      for (int dy = 0; dy < e[5]; ++dy)
+        for (int dx = 0; dx < e[4]; ++dx) {
+          const int i = e[1] + dx, j = e[2] + dy, k = e[3] + dz;
+          const int r = region_of(i, bs) + 3 * region_of(j, bs) + 9 * region_of(k, bs);
+          if (r == 13 || t.kind[r] <= 0 || i < -ng || i >= bs + ng || j < -ng || j >= bs + ng ||
+              k < -ng || k >= bs + ng)
+            return 13;
+          if (!covered.insert({e[0], i, j, k}).second) return 14;
+          const int c[3] = {e[8] + 2 * dx, e[9] + 2 * dy, e[10] + 2 * dz};
+          for (int d = 0; d < 3; ++d)
+            if (c[d] - 6 < -ng || c[d] + 6 > bs + ng - 1) return 15;
+          const int64_t want = point_offset(t, bs, L, i, j, k);
+          const int64_t got = (int64_t)e[7] * L.bstride +
+                              ((int64_t)(c[2] + ng) * P + (c[1] + ng)) * P + (c[0] + ng);
+          if (want != got) {
+            std::fprintf(stderr, "lift item %zu: centre %lld, resolver %lld\n", w, (long long)got,
+                         (long long)want);
+            return 16;
+          }
+          ++npts;
+        }
+  }
+  if (npts != pts) return 17;
+  // every ghost point with a finer owner is covered
+  for (size_t ib = 0; ib < tabs.size(); ++ib)
+    for (int k = -ng; k < bs + ng; ++k)
+      for (int j = -ng; j < bs + ng; ++j)
+        for (int i = -ng; i < bs + ng; ++i) {
+          const int r = region_of(i, bs) + 3 * region_of(j, bs) + 9 * region_of(k, bs);
+          if (r == 13 || tabs[ib].kind[r] <= 0) continue;
+          if (!covered.count({tabs[ib].meta[0], i, j, k})) return 18;
+        }
+  std::printf("lift items %zu, points %lld\n", it.size() / 12, (long long)pts);
+  return 0;
+}
 
 namespace wacm {
 void wacm_host_check(int slot, int li, int lj, int lk, int bs) {
@@ -52,7 +124,7 @@ int main(int argc, char** argv) {
       std::fprintf(stderr, "x-split order of bs %d is not a bijection\n", bs);
       return 7;
     }
-  if (argc != 4) return 2;
+  if (argc != 4 && !(argc == 3 && std::string(argv[2]) == "lift")) return 2;
   FILE* f = std::fopen(argv[1], "r");
   if (!f) return 2;
   wacm_grid g;
@@ -83,6 +155,7 @@ int main(int argc, char** argv) {
     std::fprintf(stderr, "tables: %s\n", err.c_str());
     return 3;
   }
+  if (argc == 3) return check_lift(g, tabs);
   const int bs = g.d.bs, ng = g.d.ng, P = g.P;
   Layout L;
   L.P = P;

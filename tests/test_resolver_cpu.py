@@ -92,3 +92,21 @@ def test_unbalanced_tables_rejected(orc, harness, tmp_path):
     r = subprocess.run([harness, str(lf), str(tmp_path / "in.bin"), str(tmp_path / "out.bin")],
                        capture_output=True, text=True)
     assert r.returncode == 3 and "balanced" in r.stderr
+
+
+@pytest.mark.parametrize("bs", [24, 32])
+def test_lift_items_match_resolver(harness, tmp_path, bs):
+    """CDF 4/4 lifted ghost items (host side): exactly the ghost points whose
+    owner is finer, each centred on the resolver's coincident fine point, with
+    every stencil inside the source's 6 ghost layers."""
+    for seed in range(2):
+        lev, ix, iy, iz = inputs.random_balanced_leaves(70 + seed, 1, 4, 150)
+        lf = tmp_path / "leaves.txt"
+        with open(lf, "w") as f:
+            f.write(f"{bs} 6 1.0 1 4 {len(lev)} {len(lev)}\n")
+            for l, x, y, z in zip(lev, ix, iy, iz):
+                f.write(f"{l} {x} {y} {z}\n")
+        r = subprocess.run([harness, str(lf), "lift"], capture_output=True, text=True)
+        assert r.returncode == 0, (r.returncode, r.stderr)
+        n = int(r.stdout.split()[2].rstrip(","))
+        assert n > 0
