@@ -200,8 +200,12 @@ int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
   if (g->wavelet != 1 || tabs.empty()) return WACM_OK;
   std::vector<int32_t> it;
   int64_t pts = 0;
-  if (int rc = lift_items(g, tabs, it, pts, err)) return rc;
+  if (int rc = lift_items(g, tabs, it, pts, err)) {
+    g->n_lift = -1;
+    return rc;
+  }
   if (pts > (int64_t(1) << 30)) {
+    g->n_lift = -1;
     err = "too many lifted ghost points";
     return WACM_E_CAPACITY;
   }
@@ -225,6 +229,8 @@ int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
   if (e == hipSuccess && ibytes > 0)
     e = hipMemcpy(g->d_lift, it.data(), ibytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
+    // no usable items: the lifted phase refuses to run until a rebuild works
+    g->n_lift = -1;
     err = std::string("lifted ghost items: ") + hipGetErrorString(e);
     return e == hipErrorOutOfMemory ? WACM_E_NOMEM : WACM_E_HIP;
   }

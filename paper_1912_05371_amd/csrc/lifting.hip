@@ -179,6 +179,7 @@ static hipError_t lift_box(const wacm_grid* g, const int32_t* items, int64_t n, 
 
 template <typename T>
 static hipError_t lift_sync_t(const wacm_grid* g, T* U, hipStream_t st) {
+  if (g->n_lift < 0) return hipErrorOutOfMemory;  // the last item build failed
   if (g->n_lift == 0) return hipSuccess;
   T* tmp = (T*)g->d_lift_tmp;
   hipError_t e = lift_box<T>(g, g->d_lift, g->n_lift, U, tmp, 0, st);
