@@ -237,8 +237,13 @@ int wacm_compute_dt(wacm_grid* grid, const wacm_params* prm, const void* U, doub
  * Only the interiors of U are defined on return: the stages read neighbour
  * values directly, not U's ghost layers, and those layers are left with
  * unspecified values (call wacm_sync_ghosts before a call that reads them).
- * No host synchronisation and no allocation: the call may be captured in a
- * HIP graph as long as the grid is not changed.
+ * With the CDF 4/0 wavelet: no host synchronisation and no allocation, so the
+ * call may be captured in a HIP graph as long as the grid is not changed.
+ * With CDF 4/4 (wacm_set_wavelet): each step first synchronises U's ghost
+ * layers in place (on return they hold the ghosts of the state the last step
+ * started from, not of the result), the work buffer is 3 padded registers
+ * (wacm_work_bytes), and each step copies t and dt back to the host and
+ * synchronises the stream once, so the call is not graph-capturable.
  */
 int wacm_rk4_step(wacm_grid* grid, const wacm_params* prm, double* t_dev, double* dt_dev,
                   void* U, void* work, const void* dus, int32_t dt_mode, void* stream);
