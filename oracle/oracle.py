@@ -102,6 +102,8 @@ def lib():
         L.orc_set_wavelet.restype = C.c_int
         L.orc_set_wavelet.argtypes = [vp, C.c_int]
         L.orc_lift_lowpass.argtypes = [C.c_int, vp]
+        L.orc_mr_forward.argtypes = [C.c_int64, C.c_int, C.c_int, C.c_int, vp]
+        L.orc_mr_inverse.argtypes = [C.c_int64, C.c_int, C.c_int, C.c_int, vp]
         L.orc_refine_count.restype = C.c_int64
         L.orc_refine_count.argtypes = [vp]
         L.orc_refine_all.restype = vp
@@ -140,6 +142,29 @@ def lift_lowpass(order: int) -> np.ndarray:
     t = np.zeros(13)
     lib().orc_lift_lowpass(int(order), _ptr(t))
     return t
+
+
+def _mr(fn, u: np.ndarray, nlev: int, wavelet: int) -> np.ndarray:
+    a = np.ascontiguousarray(u, dtype=np.float64).copy()
+    squeeze = a.ndim == 3
+    if squeeze:
+        a = a[None]
+    if a.ndim != 4 or not (a.shape[1] == a.shape[2] == a.shape[3]):
+        raise ValueError("mr transform: expected [nf, n, n, n] or [n, n, n]")
+    if fn(a.shape[1], a.shape[0], nlev, wavelet, _ptr(a)) != 0:
+        raise ValueError("mr transform: invalid size, level count or wavelet")
+    return a[0] if squeeze else a
+
+
+def mr_forward(u: np.ndarray, nlev: int, wavelet: int = 0) -> np.ndarray:
+    """Multiresolution transform (Sec. 3.1, 3.2) of periodic fields, a new
+    array ([nf, n, n, n] or [n, n, n]); wavelet 0 CDF 4/0, 1 CDF 4/4."""
+    return _mr(lib().orc_mr_forward, u, nlev, wavelet)
+
+
+def mr_inverse(w: np.ndarray, nlev: int, wavelet: int = 0) -> np.ndarray:
+    """Inverse of :func:`mr_forward`."""
+    return _mr(lib().orc_mr_inverse, w, nlev, wavelet)
 
 
 def treecode_encode(level: int, ix: int, iy: int, iz: int) -> int:

@@ -1452,3 +1452,138 @@ void orc_rk4_step_adj(const orc_grid* g, const orc_params* p, double t, double d
   }
   free(K);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Multiresolution transform (Sec. 3.1; lifted coarse values of Sec. 3.2) of */
+/* nf periodic fields of n^3 points each (x fastest), in place.  The level-m */
+/* step works on the lattice of stride s = 2^m: a point of it is even when   */
+/* all three of its coordinates are multiples of 2s, odd otherwise.          */
+/*   forward, m = 0 .. nlev-1: every odd point takes its detail, the value   */
+/*     minus the tensor DD4 prediction from the even points; with CDF 4/4    */
+/*     every even point takes the lifted restriction of the stride-s values  */
+/*     (the x, y, z lifting of lift_1d at stride s), with CDF 4/0 it keeps   */
+/*     its value (decimation).  Both from the values before the step.        */
+/*   inverse, m = nlev-1 .. 0: with CDF 4/4 the even values are recovered    */
+/*     as c - L(delta), delta the stride-s lattice with the details at the   */
+/*     odd points and zeros at the even ones, L the lifted restriction       */
+/*     (L is linear and returns e when applied to e extended by prediction,  */
+/*     so c = L(u) = e + L(delta)); then every odd point becomes its detail   */
+/*     plus the prediction from the even values.                             */
+/* After a forward transform the stride-2^nlev lattice holds the coarse       */
+/* approximation and a point whose coordinates are all multiples of 2^m but  */
+/* not all of 2^(m+1) holds its level-m detail.  n must be a multiple of     */
+/* 2^nlev with n / 2^nlev >= 4.                                              */
+/* ------------------------------------------------------------------------ */
+static int mr_is_odd(int64_t x, int64_t y, int64_t z, int64_t s) {
+  return (x / s) % 2 != 0 || (y / s) % 2 != 0 || (z / s) % 2 != 0;
+}
+
+/* tensor DD4 prediction at the stride-s lattice point G from the stride-2s
+ * lattice of f */
+static double mr_prediction(const double* f, int64_t n, int64_t s, int64_t gx, int64_t gy,
+                            int64_t gz) {
+  int64_t T[3][4];
+  double W[3][4];
+  int N[3];
+  const int64_t G[3] = {gx, gy, gz};
+  for (int d = 0; d < 3; ++d) {
+    if ((G[d] / s) % 2 == 0) {
+      T[d][0] = G[d];
+      W[d][0] = 1.0;
+      N[d] = 1;
+    } else {
+      for (int m = 0; m < 4; ++m) {
+        T[d][m] = wrap(G[d] + DD4O[m] * s, n);
+        W[d][m] = DD4W[m];
+      }
+      N[d] = 4;
+    }
+  }
+  double v = 0.0;
+  for (int a = 0; a < N[2]; ++a)
+    for (int b = 0; b < N[1]; ++b)
+      for (int e = 0; e < N[0]; ++e) {
+        double w = (W[2][a] * W[1][b]) * W[0][e];
+        v += w * f[(T[2][a] * n + T[1][b]) * n + T[0][e]];
+      }
+  return v;
+}
+
+/* lifted restriction at the stride-2s point G from the stride-s lattice of f */
+static double mr_lifted(const double* f, int64_t n, int64_t s, int64_t gx, int64_t gy,
+                        int64_t gz) {
+  double ax[13][13];
+  for (int z = 0; z < 13; ++z)
+    for (int y = 0; y < 13; ++y) {
+      double line[13];
+      int64_t zz = wrap(gz + (z - 6) * s, n), yy = wrap(gy + (y - 6) * s, n);
+      for (int x = 0; x < 13; ++x) line[x] = f[(zz * n + yy) * n + wrap(gx + (x - 6) * s, n)];
+      ax[z][y] = lift_1d(4, line);
+    }
+  double ay[13];
+  for (int z = 0; z < 13; ++z) ay[z] = lift_1d(4, ax[z]);
+  return lift_1d(4, ay);
+}
+
+static int mr_valid(int64_t n, int nf, int nlev, int wavelet) {
+  if (n < 4 || nf < 1 || nlev < 0 || nlev > 20 || (wavelet != 0 && wavelet != 1)) return 0;
+  if (n % ((int64_t)1 << nlev) != 0 || (n >> nlev) < 4) return 0;
+  return 1;
+}
+
+int orc_mr_forward(int64_t n, int nf, int nlev, int wavelet, double* u) {
+  if (!mr_valid(n, nf, nlev, wavelet)) return -1;
+  const int64_t n3 = n * n * n;
+  double* f0 = (double*)malloc(sizeof(double) * n3);
+  for (int c = 0; c < nf; ++c) {
+    double* f = u + c * n3;
+    for (int m = 0; m < nlev; ++m) {
+      const int64_t s = (int64_t)1 << m;
+      memcpy(f0, f, sizeof(double) * n3);
+#pragma omp parallel for schedule(static)
+      for (int64_t z = 0; z < n; z += s)
+        for (int64_t y = 0; y < n; y += s)
+          for (int64_t x = 0; x < n; x += s) {
+            if (mr_is_odd(x, y, z, s))
+              f[(z * n + y) * n + x] = f0[(z * n + y) * n + x] - mr_prediction(f0, n, s, x, y, z);
+            else if (wavelet == 1)
+              f[(z * n + y) * n + x] = mr_lifted(f0, n, s, x, y, z);
+          }
+    }
+  }
+  free(f0);
+  return 0;
+}
+
+int orc_mr_inverse(int64_t n, int nf, int nlev, int wavelet, double* u) {
+  if (!mr_valid(n, nf, nlev, wavelet)) return -1;
+  const int64_t n3 = n * n * n;
+  double* f0 = (double*)malloc(sizeof(double) * n3);
+  for (int c = 0; c < nf; ++c) {
+    double* f = u + c * n3;
+    for (int m = nlev - 1; m >= 0; --m) {
+      const int64_t s = (int64_t)1 << m;
+      if (wavelet == 1) {
+        /* delta: details at the odd points, zeros at the even ones */
+        memcpy(f0, f, sizeof(double) * n3);
+        for (int64_t z = 0; z < n; z += 2 * s)
+          for (int64_t y = 0; y < n; y += 2 * s)
+            for (int64_t x = 0; x < n; x += 2 * s) f0[(z * n + y) * n + x] = 0.0;
+#pragma omp parallel for schedule(static)
+        for (int64_t z = 0; z < n; z += 2 * s)
+          for (int64_t y = 0; y < n; y += 2 * s)
+            for (int64_t x = 0; x < n; x += 2 * s)
+              f[(z * n + y) * n + x] -= mr_lifted(f0, n, s, x, y, z);
+      }
+      memcpy(f0, f, sizeof(double) * n3);
+#pragma omp parallel for schedule(static)
+      for (int64_t z = 0; z < n; z += s)
+        for (int64_t y = 0; y < n; y += s)
+          for (int64_t x = 0; x < n; x += s)
+            if (mr_is_odd(x, y, z, s))
+              f[(z * n + y) * n + x] = f0[(z * n + y) * n + x] + mr_prediction(f0, n, s, x, y, z);
+    }
+  }
+  free(f0);
+  return 0;
+}

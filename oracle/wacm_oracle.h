@@ -88,6 +88,16 @@ int orc_set_wavelet(orc_grid* g, int wavelet);
  * 4/4) or 2 (CDF 2/2), from the lifting steps applied to unit impulses. */
 void orc_lift_lowpass(int order, double taps[13]);
 
+/* Multiresolution transform (Sec. 3.1, 3.2), in place, of nf periodic fields
+ * of n^3 points (x fastest): nlev forward steps, finest first, or their
+ * inverse.  wavelet 0: CDF 4/0 (coarse values by decimation), 1: CDF 4/4
+ * (lifted coarse values).  The stride-2^nlev lattice then holds the coarse
+ * approximation; a point whose coordinates are all multiples of 2^m but not
+ * all of 2^(m+1) holds its level-m detail.  Returns -1 unless n is a
+ * multiple of 2^nlev with n / 2^nlev >= 4, nf >= 1, 0 <= nlev <= 20. */
+int orc_mr_forward(int64_t n, int nf, int nlev, int wavelet, double* u);
+int orc_mr_inverse(int64_t n, int nf, int nlev, int wavelet, double* u);
+
 /* Mask and solid velocity at interior points, at time t. chi: [nb][bs^3], us: [nb][3][bs^3]. */
 void orc_mask(const orc_grid* g, const orc_params* p, double t, double* chi, double* us);
 
