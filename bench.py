@@ -266,6 +266,7 @@ def aux_timings(case):
     torch.cuda.empty_cache()
 
     out["cdf44"] = lifting_timings(case_seed(case))
+    out["mr_transform"] = mr_timings(case_seed(case))
 
     # one adaptive step of the rotating plate (levels 2..6, bs 16)
     from paper_1912_05371_amd.adaptive import adaptive_step
@@ -328,6 +329,44 @@ def lifting_timings(seed: int):
         lambda: g.rk4_step(c.params, t, dt, pool, work, dt_mode=wacm.DT_CFL), reps=2)
     del work, pool
     g.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def mr_timings(seed: int, n: int = 256, nf: int = 4, nlev: int = 5):
+    """Multiresolution transform of the equidistant lattice (n^3 points, nf
+    fields, nlev levels, FP64, periodic): forward and inverse with CDF 4/0
+    and CDF 4/4, each with the compulsory bytes (every lattice value of a
+    level read once and its changed values written once: 7/8 of them with
+    CDF 4/0, all with CDF 4/4) and the fraction of the HBM peak they imply."""
+    import torch
+
+    from paper_1912_05371_amd import wacm
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    u = torch.randn((nf, n, n, n), dtype=torch.float64, device="cuda", generator=g)
+    work = wacm.mr_work(u)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pts = sum((n >> m) ** 3 for m in range(nlev)) * nf
+    out = {"n": n, "fields": nf, "levels": nlev, "dtype": "f64"}
+    for wname, wav, wfrac in (("cdf40", wacm.CDF40, 7 / 8), ("cdf44", wacm.CDF44, 1.0)):
+        nbytes = int(pts * (1 + wfrac) * 8)
+        for dname, fn in (("forward", wacm.mr_forward), ("inverse", wacm.mr_inverse)):
+            fn(u, nlev, wav, work)
+            torch.cuda.synchronize()
+            e0.record()
+            reps = 5
+            for _ in range(reps):
+                fn(u, nlev, wav, work)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            gbs = nbytes / (ms * 1e-3) / 1e9
+            out[f"{wname}_{dname}"] = {"ms": round(ms, 4), "bytes": nbytes,
+                                       "GBps": round(gbs, 1),
+                                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del u, work
     torch.cuda.empty_cache()
     return out
 
@@ -418,6 +457,9 @@ def main():
     ap.add_argument("--copy-probe", type=float, default=2.0,
                     help="GiB per buffer of a plain device copy timed for the achievable "
                          "bandwidth (0: skip)")
+    ap.add_argument("--mr-only", action="store_true",
+                    help="time only the multiresolution transform (256^3 x 4, 5 levels) and "
+                         "print its figures")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -430,6 +472,9 @@ def main():
     from paper_1912_05371_amd import wacm
 
     wacm.lib()
+    if args.mr_only:
+        print(json.dumps({"mr_transform": mr_timings(args.seed)}), flush=True)
+        return
     t0 = time.perf_counter()
     case = build_case(args.target, args.seed)
     case.extra["seed"] = args.seed

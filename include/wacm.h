@@ -299,6 +299,34 @@ int wacm_threshold_blocks(wacm_grid* grid, const wacm_params* prm, double t, con
 int wacm_filter_blocks(wacm_grid* grid, void* U, int32_t level, void* stream);
 
 /*
+ * wacm_mr_forward / wacm_mr_inverse -- the multiresolution transform (Sec.
+ * 3.1: details u - P R u iterated from the finest level down; Sec. 3.2:
+ * lifted coarse values for CDF 4/4) of nfields periodic fields on the
+ * equidistant lattice, in place.  No grid handle: u holds nfields arrays of
+ * n^3 values of `dtype` (WACM_F32 / WACM_F64), x fastest, contiguous, on the
+ * device.  Step m (m = 0 .. nlev-1, finest first; the inverse runs them in
+ * reverse) works on the lattice of stride 2^m: its odd points (not all
+ * coordinates multiples of 2^(m+1)) take their detail, the value minus the
+ * tensor-product DD4 prediction from the even points; with WACM_CDF44 the
+ * even points then take the lifted restriction of the stride-2^m values
+ * (x, y, z), with WACM_CDF40 they keep their values (decimation).  Afterwards
+ * the stride-2^nlev lattice holds the coarse approximation and a point whose
+ * coordinates are all multiples of 2^m but not all of 2^(m+1) holds its
+ * level-m detail.  wacm_mr_inverse reconstructs u up to rounding.
+ * Requirements (WACM_E_INVAL otherwise): 4 <= n <= 1024, n a multiple of
+ * 2^nlev with n / 2^nlev >= 4, 0 <= nlev <= 9, 1 <= nfields <= 65535, u not
+ * NULL; with WACM_CDF44 and nlev > 0, work: a device buffer of
+ * wacm_mr_work_bytes(n, nfields, dtype) bytes (may be NULL for WACM_CDF40).
+ * The caller owns u and work.  No allocation, no host synchronisation:
+ * asynchronous on `stream` and graph-capturable.
+ */
+size_t wacm_mr_work_bytes(int64_t n, int32_t nfields, int32_t dtype);
+int wacm_mr_forward(int64_t n, int32_t nfields, int32_t dtype, int32_t wavelet, int32_t nlev,
+                    void* u, void* work, void* stream);
+int wacm_mr_inverse(int64_t n, int32_t nfields, int32_t dtype, int32_t wavelet, int32_t nlev,
+                    void* u, void* work, void* stream);
+
+/*
  * wacm_adapt -- change the grid (Sec. 3.5).  Synchronous.
  * WACM_REFINE_ALL: ghosts of U are synchronised, then every active block below
  *   jmax is replaced by its 8 children (even child points copy the parent,

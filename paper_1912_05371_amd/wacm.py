@@ -30,7 +30,8 @@ EXPORTS = ["wacm_last_error", "wacm_treecode_encode", "wacm_treecode_decode", "w
            "wacm_diagnostics", "wacm_threshold_blocks", "wacm_filter_blocks", "wacm_adapt",
            "wacm_profile_enable", "wacm_profile_read", "wacm_adj_work_bytes", "wacm_sync_ghosts_adj",
            "wacm_rhs_acm_adj", "wacm_force_adj", "wacm_rk4_step_adj", "wacm_set_schedule",
-           "wacm_get_schedule", "wacm_set_wavelet", "wacm_get_wavelet"]
+           "wacm_get_schedule", "wacm_set_wavelet", "wacm_get_wavelet", "wacm_mr_work_bytes",
+           "wacm_mr_forward", "wacm_mr_inverse"]
 
 
 class GridDesc(C.Structure):
@@ -117,6 +118,10 @@ def lib():
                                             vp]
         L.wacm_filter_blocks.argtypes = [vp, vp, i32, vp]
         L.wacm_set_wavelet.argtypes = [vp, i32]
+        L.wacm_mr_work_bytes.restype = C.c_size_t
+        L.wacm_mr_work_bytes.argtypes = [i64, i32, i32]
+        L.wacm_mr_forward.argtypes = [i64, i32, i32, i32, i32, vp, vp, vp]
+        L.wacm_mr_inverse.argtypes = [i64, i32, i32, i32, i32, vp, vp, vp]
         L.wacm_get_wavelet.argtypes = [vp]
         L.wacm_adapt.argtypes = [vp, i32, vp, vp, vp, vp]
         L.wacm_adj_work_bytes.restype = C.c_size_t
@@ -160,6 +165,42 @@ def _ptr(t):
     if t is None:
         return None
     return C.c_void_p(t.data_ptr())
+
+
+def _mr_args(u):
+    import torch
+    if u.dim() == 3:
+        u = u.unsqueeze(0)
+    if (u.dim() != 4 or not u.is_cuda or not u.is_contiguous()
+            or not (u.shape[1] == u.shape[2] == u.shape[3])):
+        raise ValueError("mr transform: expected a contiguous cuda tensor [nf, n, n, n]")
+    dt = {torch.float64: F64, torch.float32: F32}.get(u.dtype)
+    if dt is None:
+        raise ValueError("mr transform: float32 or float64 only")
+    return u.shape[1], u.shape[0], dt
+
+
+def mr_work(u):
+    """Work buffer (uint8 cuda tensor) for mr_forward / mr_inverse on u."""
+    import torch
+    n, nf, dt = _mr_args(u)
+    nbytes = int(lib().wacm_mr_work_bytes(n, nf, dt))
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=u.device)
+
+
+def mr_forward(u, nlev: int, wavelet: int = CDF40, work=None, stream=None):
+    """Multiresolution transform of the periodic fields u ([nf, n, n, n] or
+    [n, n, n], contiguous, cuda), in place."""
+    n, nf, dt = _mr_args(u)
+    _check(lib().wacm_mr_forward(n, nf, dt, int(wavelet), int(nlev), _ptr(u), _ptr(work),
+                                 _stream(stream)))
+
+
+def mr_inverse(u, nlev: int, wavelet: int = CDF40, work=None, stream=None):
+    """Inverse of :func:`mr_forward`, in place."""
+    n, nf, dt = _mr_args(u)
+    _check(lib().wacm_mr_inverse(n, nf, dt, int(wavelet), int(nlev), _ptr(u), _ptr(work),
+                                 _stream(stream)))
 
 
 class Grid:
