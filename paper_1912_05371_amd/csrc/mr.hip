@@ -14,9 +14,9 @@
 // odd = detail + prediction.  A prediction reads only even points and the
 // update only odd ones, so both run in place without hazards.
 //
-// Kernels per step: mr_predict_kernel (one thread per coarse cell: its 4^3
-// even neighbours, interpolated along x, y, z, give the 7 odd points of the
-// cell) and, for CDF 4/4, three separable low-pass passes through a work
+// Kernels per step: mr_predict_kernel (the 7 odd points of each coarse cell
+// from its 4^3 even neighbours, interpolated along x, y, then z, marching
+// along z) and, for CDF 4/4, three separable low-pass passes through a work
 // buffer (x into tx, y into ty, z added into the even points).
 #include <hip/hip_runtime.h>
 
@@ -25,7 +25,7 @@
 #include "wacm_internal.h"
 
 namespace wacm {
-namespace {
+namespace mr {
 
 constexpr int MR_NT = 256;
 
@@ -38,129 +38,204 @@ __device__ constexpr double MR_LIFT[13] = {-1.0 / 512,  0.0,         18.0 / 512,
                                           -63.0 / 512, -16.0 / 512, 18.0 / 512,  0.0,
                                           -1.0 / 512};
 
+// A value the compiler cannot see through (an empty asm that claims to
+// change its register), so that storing a just-loaded value back to its own
+// address is not removed as a no-op.
+template <typename T>
+__device__ inline T opaque(T x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin in linear order, each
+// XCD with its own L2.  Renumber them so that every XCD runs one contiguous
+// range of the logical order (neighbouring (X, Y) columns, which share even
+// rows, then meet in one L2).  Returns the logical linear index.
+__device__ inline uint32_t xcd_contiguous(uint32_t l, uint32_t G) {
+  const uint32_t x = l % 8, q = G / 8, r = G % 8;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l / 8;
+}
+
 // Odd points of the stride-s lattice: u += sign * P(even).  Cell (X, Y, Z)
 // of the stride-2s lattice (nc per axis) owns the odd points (2X + a, 2Y + b,
-// 2Z + c) s, (a, b, c) in {0,1}^3 minus (0,0,0); field blockIdx.y.
+// 2Z + c) s, (a, b, c) in {0,1}^3 minus (0,0,0).  One thread per (X, Y) and
+// run of lz cells along Z (field blockIdx.y): per coarse plane it reads the
+// 4 x 4 even points around (X, Y), interpolates them along x then y (the
+// four (a, b) types of that plane), and keeps the last 4 planes in
+// registers; the z interpolation of the odd plane then needs no new loads.
+template <typename T>
+__device__ inline void mr_plane(const T* __restrict__ plane, const int64_t (&xo)[4],
+                                const int64_t (&yo)[4], T (&v)[4]) {
+  T ex[4], ox[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const T* row = plane + yo[j];
+    const T a0 = row[xo[0]], a1 = row[xo[1]], a2 = row[xo[2]], a3 = row[xo[3]];
+    ex[j] = a1;
+    ox[j] = T(MR_DD4[0]) * a0 + T(MR_DD4[1]) * a1 + T(MR_DD4[2]) * a2 + T(MR_DD4[3]) * a3;
+  }
+  v[0] = ex[1];  // (a, b) = (0, 0)
+  v[1] = ox[1];  // (1, 0)
+  v[2] = T(MR_DD4[0]) * ex[0] + T(MR_DD4[1]) * ex[1] + T(MR_DD4[2]) * ex[2] +
+         T(MR_DD4[3]) * ex[3];  // (0, 1)
+  v[3] = T(MR_DD4[0]) * ox[0] + T(MR_DD4[1]) * ox[1] + T(MR_DD4[2]) * ox[2] +
+         T(MR_DD4[3]) * ox[3];  // (1, 1)
+}
+
 template <typename T>
 __global__ __launch_bounds__(MR_NT) void mr_predict_kernel(T* __restrict__ u, int64_t n, int s,
-                                                           uint32_t nc, T sign) {
-  const uint32_t cell = blockIdx.x * MR_NT + threadIdx.x;
-  if (cell >= nc * nc * nc) return;
-  T* f = u + (int64_t)blockIdx.y * n * n * n;
-  const uint32_t X = cell % nc, Y = (cell / nc) % nc, Z = cell / (nc * nc);
-  const int64_t s2 = 2 * (int64_t)s;
-  int64_t xo[4], yo[4], zo[4];
+                                                           uint32_t nc, uint32_t lz, T sign) {
+  const uint32_t nrun = (nc + lz - 1) / lz;
+  const uint32_t lb = xcd_contiguous(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const uint32_t field = lb / gridDim.x;
+  const uint32_t t = (lb % gridDim.x) * MR_NT + threadIdx.x;
+  if (t >= nc * nc * nrun) return;
+  T* f = u + (int64_t)field * n * n * n;
+  const uint32_t X = t % nc, Y = (t / nc) % nc, R = t / (nc * nc);
+  const uint32_t Z0 = R * lz, Z1 = min(Z0 + lz, nc);
+  const int64_t s2 = 2 * (int64_t)s, pz = s2 * n * n;
+  int64_t xo[4], yo[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     xo[q] = (int64_t)((X + nc - 1 + q) % nc) * s2;
     yo[q] = (int64_t)((Y + nc - 1 + q) % nc) * s2 * n;
-    zo[q] = (int64_t)((Z + nc - 1 + q) % nc) * s2 * n * n;
   }
-  // x: even (the cell's own x) and odd (interpolated) value on each of the
-  // 4 x 4 (y, z) lines
-  T ex[4][4], ox[4][4];
+  T p0[4], p1[4], p2[4], p3[4];  // planes Z-1, Z, Z+1, Z+2
+  mr_plane(f + (int64_t)((Z0 + nc - 1) % nc) * pz, xo, yo, p0);
+  mr_plane(f + (int64_t)Z0 * pz, xo, yo, p1);
+  mr_plane(f + (int64_t)((Z0 + 1) % nc) * pz, xo, yo, p2);
+  const int64_t tofs[4] = {0, s, (int64_t)s * n, (int64_t)s * n + s};
+  for (uint32_t Z = Z0; Z < Z1; ++Z) {
+    mr_plane(f + (int64_t)((Z + 2) % nc) * pz, xo, yo, p3);
+    T* base = f + (int64_t)Z * pz + (int64_t)Y * s2 * n + (int64_t)X * s2;
+    // at stride 1 the even point is stored back unchanged (no thread
+    // changes it in this kernel), so that the rows of even points leave
+    // whole lines written instead of every other value
+    if (s == 1) base[0] = opaque(p1[0]);
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
+    for (int q = 1; q < 4; ++q) base[tofs[q]] = base[tofs[q]] + sign * p1[q];
+    T* odd = base + (int64_t)s * n * n;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const T* row = f + zo[k] + yo[j];
-      const T a0 = row[xo[0]], a1 = row[xo[1]], a2 = row[xo[2]], a3 = row[xo[3]];
-      ex[k][j] = a1;
-      ox[k][j] = T(MR_DD4[0]) * a0 + T(MR_DD4[1]) * a1 + T(MR_DD4[2]) * a2 + T(MR_DD4[3]) * a3;
+    for (int q = 0; q < 4; ++q) {
+      const T pr = T(MR_DD4[0]) * p0[q] + T(MR_DD4[1]) * p1[q] + T(MR_DD4[2]) * p2[q] +
+                   T(MR_DD4[3]) * p3[q];
+      odd[tofs[q]] = odd[tofs[q]] + sign * pr;
     }
-  // y: for x type tx and each z line, even and odd in y
-  T v[2][2][4];  // [tx][ty][k]
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v[0][0][k] = ex[k][1];
-    v[1][0][k] = ox[k][1];
-    v[0][1][k] = T(MR_DD4[0]) * ex[k][0] + T(MR_DD4[1]) * ex[k][1] + T(MR_DD4[2]) * ex[k][2] +
-                 T(MR_DD4[3]) * ex[k][3];
-    v[1][1][k] = T(MR_DD4[0]) * ox[k][0] + T(MR_DD4[1]) * ox[k][1] + T(MR_DD4[2]) * ox[k][2] +
-                 T(MR_DD4[3]) * ox[k][3];
+    for (int q = 0; q < 4; ++q) {
+      p0[q] = p1[q];
+      p1[q] = p2[q];
+      p2[q] = p3[q];
+    }
   }
-  const int64_t bx = (int64_t)X * s2, by = (int64_t)Y * s2 * n, bz = (int64_t)Z * s2 * n * n;
-  const int64_t sy = (int64_t)s * n, sz = (int64_t)s * n * n;
-#pragma unroll
-  for (int c = 0; c < 2; ++c)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        if (a + b + c == 0) continue;
-        const T* w = v[a][b];
-        const T p = c == 0 ? w[1]
-                           : T(MR_DD4[0]) * w[0] + T(MR_DD4[1]) * w[1] + T(MR_DD4[2]) * w[2] +
-                                 T(MR_DD4[3]) * w[3];
-        T* dst = f + bz + c * sz + by + b * sy + bx + a * s;
-        *dst = *dst + sign * p;
-      }
 }
 
 // Low-pass along x with decimation of delta (the stride-s lattice with its
-// even points taken as 0): tx[f][z][y][X] = sum_a h_a delta((2X + a) s, y s,
-// z s), X < nc, y, z < 2 nc.
+// even points taken as 0): tx[f][z][y][X] = sum_a h_a delta((2X + a - 6) s,
+// y s, z s), X < nc, y, z < m = 2 nc.  A workgroup stages k = MR_XROW / m
+// whole rows in LDS, then each output reads its 11 nonzero taps there.
+constexpr uint32_t MR_XROW = 2048;
 template <typename T>
 __global__ __launch_bounds__(MR_NT) void mr_lift_x_kernel(const T* __restrict__ u,
                                                           T* __restrict__ tx, int64_t n, int s,
-                                                          uint32_t nc) {
+                                                          uint32_t nc, uint32_t k) {
+  __shared__ T row[MR_XROW];
   const uint32_t m = 2 * nc;
-  const uint32_t o = blockIdx.x * MR_NT + threadIdx.x;
-  if (o >= nc * m * m) return;
-  const uint32_t X = o % nc, y = (o / nc) % m, z = o / (nc * m);
-  const T* row = u + (int64_t)blockIdx.y * n * n * n + ((int64_t)z * n + y) * n * s;
-  const bool even_line = ((y | z) & 1) == 0;
-  T acc = 0;
-#pragma unroll
-  for (int a = 0; a < 13; ++a) {
-    if (a == 1 || a == 11) continue;  // zero taps
-    if (even_line && (a & 1) == 0) continue;  // even points of delta are 0
-    const uint32_t x = (2 * X + m - 6 + a) % m;
-    acc += T(MR_LIFT[a]) * row[(int64_t)x * s];
+  const uint32_t r0 = blockIdx.x * k;  // first row (y + m z) of this workgroup
+  const uint32_t nr = min(k, m * m - r0);
+  const T* uf = u + (int64_t)blockIdx.y * n * n * n;
+  const uint32_t wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  // one row per wave at a time, the lanes along x
+  for (uint32_t rr = wave; rr < nr; rr += MR_NT / 64) {
+    const uint32_t r = r0 + rr, y = r % m, z = r / m;
+    const bool even_line = ((y | z) & 1) == 0;
+    const T* src = uf + ((int64_t)z * n + y) * n * s;
+    for (uint32_t x = lane; x < m; x += 64)
+      row[rr * m + x] = even_line && (x & 1) == 0 ? T(0) : src[(int64_t)x * s];
   }
-  tx[((int64_t)blockIdx.y * m * m + (int64_t)z * m + y) * nc + X] = acc;
+  __syncthreads();
+  T* out = tx + ((int64_t)blockIdx.y * m * m + r0) * nc;
+  for (uint32_t rr = wave; rr < nr; rr += MR_NT / 64) {
+    const T* lr = row + rr * m;
+    for (uint32_t X = lane; X < nc; X += 64) {
+      T acc = 0;
+#pragma unroll
+      for (int a = 0; a < 13; ++a) {
+        if (a == 1 || a == 11) continue;  // zero taps
+        int x = (int)(2 * X) + a - 6;    // |a - 6| <= 6 < m: one wrap at most
+        x = x < 0 ? x + (int)m : x >= (int)m ? x - (int)m : x;
+        acc += T(MR_LIFT[a]) * lr[x];
+      }
+      out[(int64_t)rr * nc + X] = acc;
+    }
+  }
 }
 
-// Low-pass along y: ty[f][z][Y][X] = sum_b h_b tx[f][z][2Y + b][X].
+// Low-pass with decimation along a column of stride cs (elements) and length
+// m: out[j] = sum_b h_b in[(2 j + b - 6) mod m], for the run of outputs j0 ..
+// j1 - 1, with a 13-value window that moves by 2 points per output.
+template <typename T, typename Store>
+__device__ inline void mr_lift_column(const T* __restrict__ col, int64_t cs, uint32_t m,
+                                      uint32_t j0, uint32_t j1, Store store) {
+  T w[13];
+#pragma unroll
+  for (int b = 0; b < 13; ++b) w[b] = col[(int64_t)((2 * j0 + m - 6 + b) % m) * cs];
+  for (uint32_t j = j0;;) {
+    T acc = 0;
+#pragma unroll
+    for (int b = 0; b < 13; ++b)
+      if (b != 1 && b != 11) acc += T(MR_LIFT[b]) * w[b];
+    store(j, acc);
+    if (++j >= j1) break;
+#pragma unroll
+    for (int b = 0; b < 11; ++b) w[b] = w[b + 2];
+    const uint32_t a = 2 * j + 5, b = a + 1;  // < m + 7: one wrap at most
+    w[11] = col[(int64_t)(a >= m ? a - m : a) * cs];
+    w[12] = col[(int64_t)(b >= m ? b - m : b) * cs];
+  }
+}
+
+// Low-pass along y: ty[f][z][Y][X] = sum_b h_b tx[f][z][2Y + b - 6][X]; one
+// thread per (X, z) and run of ry outputs along Y.
 template <typename T>
 __global__ __launch_bounds__(MR_NT) void mr_lift_y_kernel(const T* __restrict__ tx,
-                                                          T* __restrict__ ty, uint32_t nc) {
-  const uint32_t m = 2 * nc;
-  const uint32_t o = blockIdx.x * MR_NT + threadIdx.x;
-  if (o >= nc * nc * m) return;
-  const uint32_t X = o % nc, Y = (o / nc) % nc, z = o / (nc * nc);
+                                                          T* __restrict__ ty, uint32_t nc,
+                                                          uint32_t ry) {
+  const uint32_t m = 2 * nc, nrun = (nc + ry - 1) / ry;
+  const uint32_t t = blockIdx.x * MR_NT + threadIdx.x;
+  if (t >= nc * m * nrun) return;
+  const uint32_t X = t % nc, z = (t / nc) % m, R = t / (nc * m);
+  const uint32_t Y0 = R * ry, Y1 = min(Y0 + ry, nc);
   const T* col = tx + ((int64_t)blockIdx.y * m + z) * m * nc + X;
-  T acc = 0;
-#pragma unroll
-  for (int b = 0; b < 13; ++b) {
-    if (b == 1 || b == 11) continue;
-    const uint32_t y = (2 * Y + m - 6 + b) % m;
-    acc += T(MR_LIFT[b]) * col[(int64_t)y * nc];
-  }
-  ty[((int64_t)blockIdx.y * m + z) * nc * nc + (int64_t)Y * nc + X] = acc;
+  T* out = ty + ((int64_t)blockIdx.y * m + z) * nc * nc + X;
+  mr_lift_column(col, (int64_t)nc, m, Y0, Y1,
+                 [&](uint32_t Y, T v) { out[(int64_t)Y * nc] = v; });
 }
 
 // Low-pass along z, added to the even points: u((2X, 2Y, 2Z) s) += sign *
-// sum_c h_c ty[f][2Z + c][Y][X].
+// sum_c h_c ty[f][2Z + c - 6][Y][X]; one thread per (X, Y) and run of rz
+// outputs along Z.
 template <typename T>
 __global__ __launch_bounds__(MR_NT) void mr_lift_z_kernel(T* __restrict__ u,
                                                           const T* __restrict__ ty, int64_t n,
-                                                          int s, uint32_t nc, T sign) {
-  const uint32_t m = 2 * nc;
-  const uint32_t o = blockIdx.x * MR_NT + threadIdx.x;
-  if (o >= nc * nc * nc) return;
-  const uint32_t X = o % nc, Y = (o / nc) % nc, Z = o / (nc * nc);
+                                                          int s, uint32_t nc, uint32_t rz,
+                                                          T sign) {
+  const uint32_t m = 2 * nc, nrun = (nc + rz - 1) / rz;
+  const uint32_t t = blockIdx.x * MR_NT + threadIdx.x;
+  if (t >= nc * nc * nrun) return;
+  const uint32_t X = t % nc, Y = (t / nc) % nc, R = t / (nc * nc);
+  const uint32_t Z0 = R * rz, Z1 = min(Z0 + rz, nc);
   const T* col = ty + (int64_t)blockIdx.y * m * nc * nc + (int64_t)Y * nc + X;
-  T acc = 0;
-#pragma unroll
-  for (int c = 0; c < 13; ++c) {
-    if (c == 1 || c == 11) continue;
-    const uint32_t z = (2 * Z + m - 6 + c) % m;
-    acc += T(MR_LIFT[c]) * col[(int64_t)z * nc * nc];
-  }
   const int64_t s2 = 2 * (int64_t)s;
-  T* dst = u + (int64_t)blockIdx.y * n * n * n + (((int64_t)Z * n + Y) * n + X) * s2;
-  *dst = *dst + sign * acc;
+  T* dst = u + (int64_t)blockIdx.y * n * n * n + ((int64_t)Y * n + X) * s2;
+  const int64_t pz = s2 * n * n;
+  mr_lift_column(col, (int64_t)nc * nc, m, Z0, Z1, [&](uint32_t Z, T v) {
+    T* d = dst + (int64_t)Z * pz;
+    // at stride 1 the odd neighbour (not read or changed by this kernel) is
+    // stored back unchanged so that whole lines are written
+    if (s == 1) d[1] = opaque(d[1]);
+    *d = *d + sign * v;
+  });
 }
 
 unsigned blocks_for(uint64_t n) { return (unsigned)((n + MR_NT - 1) / MR_NT); }
@@ -193,11 +268,20 @@ int mr_validate(int64_t n, int32_t nf, int32_t dtype, int32_t wavelet, int32_t n
   return WACM_OK;
 }
 
+// Run length along the marching axis: long runs share the window loads, short
+// ones keep enough threads (about 2^18 per launch) to fill the chip.
+uint32_t run_length(uint64_t outputs, uint32_t len) {
+  uint64_t r = outputs / (1u << 18);
+  r = r < 1 ? 1 : r > 16 ? 16 : r;
+  return (uint32_t)(r > len ? len : r);
+}
+
 template <typename T>
 hipError_t mr_predict(T* u, int64_t n, int32_t nf, int s, T sign, hipStream_t st) {
   const uint32_t nc = (uint32_t)(n / (2 * s));
-  mr_predict_kernel<T><<<dim3(blocks_for((uint64_t)nc * nc * nc), nf), MR_NT, 0, st>>>(u, n, s, nc,
-                                                                                      sign);
+  const uint32_t lz = run_length((uint64_t)nc * nc * nc * nf, nc);
+  const uint64_t threads = (uint64_t)nc * nc * ((nc + lz - 1) / lz);
+  mr_predict_kernel<T><<<dim3(blocks_for(threads), nf), MR_NT, 0, st>>>(u, n, s, nc, lz, sign);
   return hipGetLastError();
 }
 
@@ -206,11 +290,14 @@ hipError_t mr_update(T* u, void* work, int64_t n, int32_t nf, int s, T sign, hip
   const uint32_t nc = (uint32_t)(n / (2 * s)), m = 2 * nc;
   T* tx = (T*)work;
   T* ty = (T*)((char*)work + tx_bytes(n, nf, sizeof(T)));
-  mr_lift_x_kernel<T><<<dim3(blocks_for((uint64_t)nc * m * m), nf), MR_NT, 0, st>>>(u, tx, n, s,
-                                                                                    nc);
-  mr_lift_y_kernel<T><<<dim3(blocks_for((uint64_t)nc * nc * m), nf), MR_NT, 0, st>>>(tx, ty, nc);
-  mr_lift_z_kernel<T><<<dim3(blocks_for((uint64_t)nc * nc * nc), nf), MR_NT, 0, st>>>(u, ty, n, s,
-                                                                                      nc, sign);
+  const uint32_t k = MR_XROW / m;  // rows per workgroup (m <= 1024)
+  mr_lift_x_kernel<T><<<dim3((m * m + k - 1) / k, nf), MR_NT, 0, st>>>(u, tx, n, s, nc, k);
+  const uint32_t ry = run_length((uint64_t)nc * nc * m * nf, nc);
+  mr_lift_y_kernel<T><<<dim3(blocks_for((uint64_t)nc * m * ((nc + ry - 1) / ry)), nf), MR_NT, 0,
+                        st>>>(tx, ty, nc, ry);
+  const uint32_t rz = run_length((uint64_t)nc * nc * nc * nf, nc);
+  mr_lift_z_kernel<T><<<dim3(blocks_for((uint64_t)nc * nc * ((nc + rz - 1) / rz)), nf), MR_NT, 0,
+                        st>>>(u, ty, n, s, nc, rz, sign);
   return hipGetLastError();
 }
 
@@ -245,26 +332,26 @@ int mr_entry(int inverse, int64_t n, int32_t nf, int32_t dtype, int32_t wavelet,
   return WACM_OK;
 }
 
-}  // namespace
+}  // namespace mr
 }  // namespace wacm
 
 extern "C" {
 
 size_t wacm_mr_work_bytes(int64_t n, int32_t nfields, int32_t dtype) {
-  const size_t es = wacm::elem_size(dtype);
+  const size_t es = wacm::mr::elem_size(dtype);
   if (es == 0 || n < 4 || n > 1024 || nfields < 1 || nfields > 65535) return 0;
   const size_t ty = ((size_t)nfields * (size_t)(n / 2) * (n / 2) * n * es + 255) / 256 * 256;
-  return wacm::tx_bytes(n, nfields, es) + ty;
+  return wacm::mr::tx_bytes(n, nfields, es) + ty;
 }
 
 int wacm_mr_forward(int64_t n, int32_t nfields, int32_t dtype, int32_t wavelet, int32_t nlev,
                     void* u, void* work, void* stream) {
-  return wacm::mr_entry(0, n, nfields, dtype, wavelet, nlev, u, work, stream);
+  return wacm::mr::mr_entry(0, n, nfields, dtype, wavelet, nlev, u, work, stream);
 }
 
 int wacm_mr_inverse(int64_t n, int32_t nfields, int32_t dtype, int32_t wavelet, int32_t nlev,
                     void* u, void* work, void* stream) {
-  return wacm::mr_entry(1, n, nfields, dtype, wavelet, nlev, u, work, stream);
+  return wacm::mr::mr_entry(1, n, nfields, dtype, wavelet, nlev, u, work, stream);
 }
 
 }  // extern "C"
