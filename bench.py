@@ -473,6 +473,8 @@ def main():
 
     wacm.lib()
     if args.mr_only:
+        if args.copy_probe > 0:
+            copy_probe(args.copy_probe)
         print(json.dumps({"mr_transform": mr_timings(args.seed)}), flush=True)
         return
     t0 = time.perf_counter()

@@ -38,15 +38,6 @@ __device__ constexpr double MR_LIFT[13] = {-1.0 / 512,  0.0,         18.0 / 512,
                                           -63.0 / 512, -16.0 / 512, 18.0 / 512,  0.0,
                                           -1.0 / 512};
 
-// A value the compiler cannot see through (an empty asm that claims to
-// change its register), so that storing a just-loaded value back to its own
-// address is not removed as a no-op.
-template <typename T>
-__device__ inline T opaque(T x) {
-  asm volatile("" : "+v"(x));
-  return x;
-}
-
 // Workgroups are dispatched to the 8 XCDs round-robin in linear order, each
 // XCD with its own L2.  Renumber them so that every XCD runs one contiguous
 // range of the logical order (neighbouring (X, Y) columns, which share even
@@ -108,10 +99,6 @@ __global__ __launch_bounds__(MR_NT) void mr_predict_kernel(T* __restrict__ u, in
   for (uint32_t Z = Z0; Z < Z1; ++Z) {
     mr_plane(f + (int64_t)((Z + 2) % nc) * pz, xo, yo, p3);
     T* base = f + (int64_t)Z * pz + (int64_t)Y * s2 * n + (int64_t)X * s2;
-    // at stride 1 the even point is stored back unchanged (no thread
-    // changes it in this kernel), so that the rows of even points leave
-    // whole lines written instead of every other value
-    if (s == 1) base[0] = opaque(p1[0]);
 #pragma unroll
     for (int q = 1; q < 4; ++q) base[tofs[q]] = base[tofs[q]] + sign * p1[q];
     T* odd = base + (int64_t)s * n * n;
@@ -231,9 +218,6 @@ __global__ __launch_bounds__(MR_NT) void mr_lift_z_kernel(T* __restrict__ u,
   const int64_t pz = s2 * n * n;
   mr_lift_column(col, (int64_t)nc * nc, m, Z0, Z1, [&](uint32_t Z, T v) {
     T* d = dst + (int64_t)Z * pz;
-    // at stride 1 the odd neighbour (not read or changed by this kernel) is
-    // stored back unchanged so that whole lines are written
-    if (s == 1) d[1] = opaque(d[1]);
     *d = *d + sign * v;
   });
 }
