@@ -315,12 +315,13 @@ int wacm_filter_blocks(wacm_grid* grid, void* U, int32_t level, void* stream);
  * level-m detail.  wacm_mr_inverse reconstructs u up to rounding.
  * Requirements (WACM_E_INVAL otherwise): 4 <= n <= 1024, n a multiple of
  * 2^nlev with n / 2^nlev >= 4, 0 <= nlev <= 9, 1 <= nfields <= 65535, u not
- * NULL; with WACM_CDF44 and nlev > 0, work: a device buffer of
+ * NULL and aligned to two elements (16 bytes FP64, 8 bytes FP32); with
+ * WACM_CDF44 and nlev > 0, work: a device buffer of
  * wacm_mr_work_bytes(n, nfields, dtype) bytes (may be NULL for WACM_CDF40).
  * The caller owns u and work.  No allocation, no host synchronisation:
  * asynchronous on `stream` and graph-capturable.
  */
-size_t wacm_mr_work_bytes(int64_t n, int32_t nfields, int32_t dtype);
+size_t wacm_mr_work_bytes(int64_t n, int32_t nfields, int32_t dtype); /* 0 if invalid */
 int wacm_mr_forward(int64_t n, int32_t nfields, int32_t dtype, int32_t wavelet, int32_t nlev,
                     void* u, void* work, void* stream);
 int wacm_mr_inverse(int64_t n, int32_t nfields, int32_t dtype, int32_t wavelet, int32_t nlev,

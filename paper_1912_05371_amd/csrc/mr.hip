@@ -50,69 +50,123 @@ __device__ inline uint32_t xcd_contiguous(uint32_t l, uint32_t G) {
 // Odd points of the stride-s lattice: u += sign * P(even).  Cell (X, Y, Z)
 // of the stride-2s lattice (nc per axis) owns the odd points (2X + a, 2Y + b,
 // 2Z + c) s, (a, b, c) in {0,1}^3 minus (0,0,0).  One thread per (X, Y) and
-// run of lz cells along Z (field blockIdx.y): per coarse plane it reads the
-// 4 x 4 even points around (X, Y), interpolates them along x then y (the
-// four (a, b) types of that plane), and keeps the last 4 planes in
-// registers; the z interpolation of the odd plane then needs no new loads.
+// run of lz cells along Z (field from the workgroup): per coarse plane the
+// thread loads the even points (X, Y - 1 .. Y + 2) and takes those at X - 1,
+// X + 1 and X + 2 from the lanes that loaded them (consecutive lanes hold
+// consecutive X of one row; a lane whose neighbour is in another wave or row
+// loads it itself), interpolates along x then y (the four (a, b) types of
+// the plane) and keeps the last 4 planes in registers for the z
+// interpolation.  The odd points are updated as (even, odd) pairs along x,
+// 16-byte accesses at stride 1; the even half is stored back unchanged.
 template <typename T>
-__device__ inline void mr_plane(const T* __restrict__ plane, const int64_t (&xo)[4],
-                                const int64_t (&yo)[4], T (&v)[4]) {
-  T ex[4], ox[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const T* row = plane + yo[j];
-    const T a0 = row[xo[0]], a1 = row[xo[1]], a2 = row[xo[2]], a3 = row[xo[3]];
-    ex[j] = a1;
-    ox[j] = T(MR_DD4[0]) * a0 + T(MR_DD4[1]) * a1 + T(MR_DD4[2]) * a2 + T(MR_DD4[3]) * a3;
+struct Pair {
+  T e, o;
+};
+
+template <typename T>
+__device__ inline Pair<T> load_pair(const T* p, int s) {
+  if (s == 1) {
+    using V = HIP_vector_type<T, 2>;
+    const V v = *reinterpret_cast<const V*>(p);
+    return {v.x, v.y};
   }
-  v[0] = ex[1];  // (a, b) = (0, 0)
-  v[1] = ox[1];  // (1, 0)
-  v[2] = T(MR_DD4[0]) * ex[0] + T(MR_DD4[1]) * ex[1] + T(MR_DD4[2]) * ex[2] +
-         T(MR_DD4[3]) * ex[3];  // (0, 1)
-  v[3] = T(MR_DD4[0]) * ox[0] + T(MR_DD4[1]) * ox[1] + T(MR_DD4[2]) * ox[2] +
-         T(MR_DD4[3]) * ox[3];  // (1, 1)
+  return {p[0], p[s]};
+}
+
+template <typename T>
+__device__ inline void store_pair(T* p, int s, Pair<T> v) {
+  if (s == 1) {
+    using V = HIP_vector_type<T, 2>;
+    *reinterpret_cast<V*>(p) = V(v.e, v.o);
+  } else {
+    p[0] = v.e;
+    p[s] = v.o;
+  }
+}
+
+template <typename T>
+__device__ inline T dd4(T a0, T a1, T a2, T a3) {
+  return T(MR_DD4[0]) * a0 + T(MR_DD4[1]) * a1 + T(MR_DD4[2]) * a2 + T(MR_DD4[3]) * a3;
 }
 
 template <typename T>
 __global__ __launch_bounds__(MR_NT) void mr_predict_kernel(T* __restrict__ u, int64_t n, int s,
                                                            uint32_t nc, uint32_t lz, T sign) {
-  const uint32_t nrun = (nc + lz - 1) / lz;
+  const uint32_t nrun = (nc + lz - 1) / lz, total = nc * nc * nrun;
   const uint32_t lb = xcd_contiguous(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const uint32_t field = lb / gridDim.x;
-  const uint32_t t = (lb % gridDim.x) * MR_NT + threadIdx.x;
-  if (t >= nc * nc * nrun) return;
+  const uint32_t t0 = (lb % gridDim.x) * MR_NT + threadIdx.x;
+  // threads past the end repeat the last valid one's loads (they take part
+  // in the shuffles) but store nothing
+  const bool valid = t0 < total;
+  const uint32_t t = valid ? t0 : total - 1;
+  const int lane = (int)(threadIdx.x & 63);
   T* f = u + (int64_t)field * n * n * n;
   const uint32_t X = t % nc, Y = (t / nc) % nc, R = t / (nc * nc);
   const uint32_t Z0 = R * lz, Z1 = min(Z0 + lz, nc);
+  // the lane holding X - 1 / X + 1 / X + 2 of the same row, if any
+  const bool sh0 = lane >= 1 && X >= 1;
+  const bool sh2 = lane + 1 < 64 && X + 1 < nc && t0 + 1 < total;
+  const bool sh3 = lane + 2 < 64 && X + 2 < nc && t0 + 2 < total;
   const int64_t s2 = 2 * (int64_t)s, pz = s2 * n * n;
-  int64_t xo[4], yo[4];
+  const int64_t x0 = (int64_t)((X + nc - 1) % nc) * s2, x1 = (int64_t)X * s2,
+                x2 = (int64_t)((X + 1) % nc) * s2, x3 = (int64_t)((X + 2) % nc) * s2;
+  int64_t yo[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    xo[q] = (int64_t)((X + nc - 1 + q) % nc) * s2;
-    yo[q] = (int64_t)((Y + nc - 1 + q) % nc) * s2 * n;
-  }
+  for (int q = 0; q < 4; ++q) yo[q] = (int64_t)((Y + nc - 1 + q) % nc) * s2 * n;
+  // x then y interpolation of one coarse plane: v[a + 2b], (a, b) = the
+  // parities along x and y
+  auto plane = [&](const T* pl, T(&v)[4]) {
+    T ex[4], ox[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const T* row = pl + yo[j];
+      const T a1 = row[x1];
+      T a0 = __shfl(a1, lane - 1 < 0 ? 0 : lane - 1, 64);
+      T a2 = __shfl(a1, lane + 1 > 63 ? 63 : lane + 1, 64);
+      T a3 = __shfl(a1, lane + 2 > 63 ? 63 : lane + 2, 64);
+      if (!sh0) a0 = row[x0];
+      if (!sh2) a2 = row[x2];
+      if (!sh3) a3 = row[x3];
+      ex[j] = a1;
+      ox[j] = dd4(a0, a1, a2, a3);
+    }
+    v[0] = ex[1];
+    v[1] = ox[1];
+    v[2] = dd4(ex[0], ex[1], ex[2], ex[3]);
+    v[3] = dd4(ox[0], ox[1], ox[2], ox[3]);
+  };
   T p0[4], p1[4], p2[4], p3[4];  // planes Z-1, Z, Z+1, Z+2
-  mr_plane(f + (int64_t)((Z0 + nc - 1) % nc) * pz, xo, yo, p0);
-  mr_plane(f + (int64_t)Z0 * pz, xo, yo, p1);
-  mr_plane(f + (int64_t)((Z0 + 1) % nc) * pz, xo, yo, p2);
-  const int64_t tofs[4] = {0, s, (int64_t)s * n, (int64_t)s * n + s};
+  plane(f + (int64_t)((Z0 + nc - 1) % nc) * pz, p0);
+  plane(f + (int64_t)Z0 * pz, p1);
+  plane(f + (int64_t)((Z0 + 1) % nc) * pz, p2);
+  const int64_t sy = (int64_t)s * n, sz = (int64_t)s * n * n;
   for (uint32_t Z = Z0; Z < Z1; ++Z) {
-    mr_plane(f + (int64_t)((Z + 2) % nc) * pz, xo, yo, p3);
-    T* base = f + (int64_t)Z * pz + (int64_t)Y * s2 * n + (int64_t)X * s2;
+    plane(f + (int64_t)((Z + 2) % nc) * pz, p3);
+    T q[4];
 #pragma unroll
-    for (int q = 1; q < 4; ++q) base[tofs[q]] = base[tofs[q]] + sign * p1[q];
-    T* odd = base + (int64_t)s * n * n;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const T pr = T(MR_DD4[0]) * p0[q] + T(MR_DD4[1]) * p1[q] + T(MR_DD4[2]) * p2[q] +
-                   T(MR_DD4[3]) * p3[q];
-      odd[tofs[q]] = odd[tofs[q]] + sign * pr;
+    for (int k = 0; k < 4; ++k) q[k] = dd4(p0[k], p1[k], p2[k], p3[k]);
+    if (valid) {
+      T* base = f + (int64_t)Z * pz + (int64_t)Y * s2 * n + x1;
+      Pair<T> r0 = load_pair(base, s), r1 = load_pair(base + sy, s);
+      Pair<T> r2 = load_pair(base + sz, s), r3 = load_pair(base + sz + sy, s);
+      r0.o += sign * p1[1];
+      r1.e += sign * p1[2];
+      r1.o += sign * p1[3];
+      r2.e += sign * q[0];
+      r2.o += sign * q[1];
+      r3.e += sign * q[2];
+      r3.o += sign * q[3];
+      store_pair(base, s, r0);
+      store_pair(base + sy, s, r1);
+      store_pair(base + sz, s, r2);
+      store_pair(base + sz + sy, s, r3);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      p0[q] = p1[q];
-      p1[q] = p2[q];
-      p2[q] = p3[q];
+    for (int k = 0; k < 4; ++k) {
+      p0[k] = p1[k];
+      p1[k] = p2[k];
+      p2[k] = p3[k];
     }
   }
 }
@@ -247,6 +301,8 @@ int mr_validate(int64_t n, int32_t nf, int32_t dtype, int32_t wavelet, int32_t n
   if (n % ((int64_t)1 << nlev) != 0 || (n >> nlev) < 4)
     return mr_fail(WACM_E_INVAL, "mr: n must be a multiple of 2^nlev with n / 2^nlev >= 4");
   if (!u) return mr_fail(WACM_E_INVAL, "mr: u is NULL");
+  if ((uintptr_t)u % (2 * elem_size(dtype)) != 0)
+    return mr_fail(WACM_E_INVAL, "mr: u must be aligned to two elements");
   if (wavelet == WACM_CDF44 && nlev > 0 && !work)
     return mr_fail(WACM_E_INVAL, "mr: CDF 4/4 needs the work buffer");
   return WACM_OK;

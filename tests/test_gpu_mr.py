@@ -114,3 +114,8 @@ def test_mr_guards_and_identity():
     with pytest.raises(wacm.WacmError):
         wacm.mr_forward(w, 3, wacm.CDF40)  # 20 is not a multiple of 8
     assert torch.equal(u, v)
+    # a view starting one element in is not aligned to two elements
+    flat = torch.zeros(16 ** 3 + 1, dtype=torch.float64, device="cuda")
+    odd = flat[1:].view(1, 16, 16, 16)
+    with pytest.raises(wacm.WacmError):
+        wacm.mr_forward(odd, 1, wacm.CDF40)
