@@ -11,8 +11,10 @@
 // the stride-s lattice with the details at the odd points and zeros at the
 // even ones (L returns e when applied to e extended by prediction, and it is
 // linear).  The inverse undoes the steps in reverse: e = c - L(delta), then
-// odd = detail + prediction.  A prediction reads only even points and the
-// update only odd ones, so both run in place without hazards.
+// odd = detail + prediction.  A prediction changes only odd points from
+// even ones (the even half of the pairs it stores is the unchanged value),
+// the update only even points from odd ones, so both run in place without
+// hazards.
 //
 // Kernels per step: mr_predict_kernel (the 7 odd points of each coarse cell
 // from its 4^3 even neighbours, interpolated along x, y, then z, marching
