@@ -457,6 +457,9 @@ def main():
     ap.add_argument("--copy-probe", type=float, default=2.0,
                     help="GiB per buffer of a plain device copy timed for the achievable "
                          "bandwidth (0: skip)")
+    ap.add_argument("--aux-only", action="store_true",
+                    help="time only the other calls (the aux block) on the benchmark grid and "
+                         "print them")
     ap.add_argument("--mr-only", action="store_true",
                     help="time only the multiresolution transform (256^3 x 4, 5 levels) and "
                          "print its figures")
@@ -485,6 +488,9 @@ def main():
     log(f"workload: {case.nb} blocks {levels}, {npts} interior points "
         f"(generated in {time.perf_counter() - t0:.1f} s)")
 
+    if args.aux_only:
+        print(json.dumps({"aux": aux_timings(case)}), flush=True)
+        return
     copy = copy_probe(args.copy_probe) if args.copy_probe > 0 else None
     if copy:
         log(f"copy probe: {copy['bytes_moved'] / 1e9:.2f} GB moved at {copy['GBps']:.0f} GB/s")
