@@ -335,8 +335,9 @@ def lifting_timings(seed: int):
 
 def mr_timings(seed: int, n: int = 256, nf: int = 4, nlev: int = 5):
     """Multiresolution transform of the equidistant lattice (n^3 points, nf
-    fields, nlev levels, FP64, periodic): forward and inverse with CDF 4/0
-    and CDF 4/4, each with the compulsory bytes (every lattice value of a
+    fields, nlev levels, periodic; FP64, then FP32 under keys ending in
+    _f32): forward and inverse with CDF 4/0 and CDF 4/4, each with the
+    compulsory bytes (every lattice value of a
     level read once and its changed values written once: 7/8 of them with
     CDF 4/0, all with CDF 4/4) and the fraction of the HBM peak they imply."""
     import torch
@@ -345,29 +346,30 @@ def mr_timings(seed: int, n: int = 256, nf: int = 4, nlev: int = 5):
 
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
-    u = torch.randn((nf, n, n, n), dtype=torch.float64, device="cuda", generator=g)
-    work = wacm.mr_work(u)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     pts = sum((n >> m) ** 3 for m in range(nlev)) * nf
     out = {"n": n, "fields": nf, "levels": nlev, "dtype": "f64"}
-    for wname, wav, wfrac in (("cdf40", wacm.CDF40, 7 / 8), ("cdf44", wacm.CDF44, 1.0)):
-        nbytes = int(pts * (1 + wfrac) * 8)
-        for dname, fn in (("forward", wacm.mr_forward), ("inverse", wacm.mr_inverse)):
-            fn(u, nlev, wav, work)
-            torch.cuda.synchronize()
-            e0.record()
-            reps = 5
-            for _ in range(reps):
+    for tdt, es, suffix in ((torch.float64, 8, ""), (torch.float32, 4, "_f32")):
+        u = torch.randn((nf, n, n, n), dtype=tdt, device="cuda", generator=g)
+        work = wacm.mr_work(u)
+        for wname, wav, wfrac in (("cdf40", wacm.CDF40, 7 / 8), ("cdf44", wacm.CDF44, 1.0)):
+            nbytes = int(pts * (1 + wfrac) * es)
+            for dname, fn in (("forward", wacm.mr_forward), ("inverse", wacm.mr_inverse)):
                 fn(u, nlev, wav, work)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            gbs = nbytes / (ms * 1e-3) / 1e9
-            out[f"{wname}_{dname}"] = {"ms": round(ms, 4), "bytes": nbytes,
-                                       "GBps": round(gbs, 1),
-                                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    del u, work
-    torch.cuda.empty_cache()
+                torch.cuda.synchronize()
+                e0.record()
+                reps = 5
+                for _ in range(reps):
+                    fn(u, nlev, wav, work)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                gbs = nbytes / (ms * 1e-3) / 1e9
+                out[f"{wname}_{dname}{suffix}"] = {"ms": round(ms, 4), "bytes": nbytes,
+                                                   "GBps": round(gbs, 1),
+                                                   "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        del u, work
+        torch.cuda.empty_cache()
     return out
 
 
