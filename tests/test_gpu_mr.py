@@ -122,3 +122,57 @@ def test_mr_guards_and_identity():
     odd = flat[1:].view(1, 16, 16, 16)
     with pytest.raises(wacm.WacmError):
         wacm.mr_forward(odd, 1, wacm.CDF40)
+
+
+def test_mr_maximum_size():
+    """n = 1024 (the largest the entry points accept), 8 levels (coarsest
+    lattice 4^3), one FP32 field: 4096 sampled finest-level details against
+    u - P u written out from the DD4 weights in float64 (the finest level's
+    details do not depend on the coarser steps), and the round trip of both
+    wavelets to the FP32 tolerance."""
+    n, nlev = 1024, 8
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    u0 = torch.randn((1, n, n, n), dtype=torch.float32, device="cuda", generator=g)
+    u = u0.clone()
+    work = wacm.mr_work(u)
+    log("mr maximum size: n 1024, 8 levels, f32")
+    wacm.mr_forward(u, nlev, wacm.CDF40, work)
+    rng = np.random.default_rng(5)
+    pts = rng.integers(0, n, size=(4096, 3))
+    pts = pts[(pts % 2).any(axis=1)]  # odd points of the finest level
+    W = np.array([-1.0, 9.0, 9.0, -1.0]) / 16.0
+    offs, wts = [], []
+    for x, y, z in pts:
+        per = []
+        for c in (x, y, z):
+            per.append([((c + o) % n, w) for o, w in zip((-3, -1, 1, 3), W)] if c % 2 else
+                       [(c, 1.0)])
+        o_, w_ = [], []
+        for zz, wz in per[2]:
+            for yy, wy in per[1]:
+                for xx, wx in per[0]:
+                    o_.append((zz * n + yy) * n + xx)
+                    w_.append(wz * wy * wx)
+        o_ += [o_[0]] * (64 - len(o_))
+        w_ += [0.0] * (64 - len(w_))
+        offs.append(o_)
+        wts.append(w_)
+    flat0 = u0.view(-1)
+    nb = torch.as_tensor(np.array(offs), device="cuda")
+    vals = flat0[nb].double().cpu().numpy()
+    own = np.array([(z * n + y) * n + x for x, y, z in pts])
+    ref = flat0[torch.as_tensor(own, device="cuda")].double().cpu().numpy() - \
+        np.sum(vals * np.array(wts), axis=1)
+    got = u.view(-1)[torch.as_tensor(own, device="cuda")].double().cpu().numpy()
+    scale = float(u0.abs().max())
+    e_det = float(np.max(np.abs(got - ref))) / scale
+    wacm.mr_inverse(u, nlev, wacm.CDF40, work)
+    e40 = float((u - u0).abs().max()) / scale
+    u.copy_(u0)
+    wacm.mr_forward(u, nlev, wacm.CDF44, work)
+    wacm.mr_inverse(u, nlev, wacm.CDF44, work)
+    e44 = float((u - u0).abs().max()) / scale
+    log(f"  {len(pts)} sampled details rel err {e_det:.2e}; round trips {e40:.2e} (CDF 4/0), "
+        f"{e44:.2e} (CDF 4/4)")
+    assert e_det < 1e-5 and e40 < 1e-5 and e44 < 1e-5
