@@ -22,6 +22,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "wacm_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+# a sanitizer build of the same source may be loaded instead (CPU tests only)
+LIB = os.environ.get("WACM_ORACLE_LIB", LIB)
 
 _lib = None
 
