@@ -132,7 +132,7 @@ def run_gpu(case, dtype_code: int, steps: int, warmup: int, use_graph: bool, tun
         ev1.record()
         torch.cuda.synchronize()
         res["graph_ms_per_step"] = ev0.elapsed_time(ev1) / steps
-    out = torch.zeros(9, dtype=torch.float64, device="cuda")
+    out = torch.zeros(10, dtype=torch.float64, device="cuda")
     g.diagnostics(case.params, float(t_dev.item()), pool, out)
     res["t_end"] = float(t_dev.item())
     res["dt_last"] = float(dt_dev.item())
@@ -220,7 +220,7 @@ def aux_timings(case):
     dmax = torch.zeros(nb, dtype=torch.float64, device="cuda")
     mr = torch.zeros(nb, dtype=torch.float64, device="cuda")
     fl = torch.zeros(nb, dtype=torch.int8, device="cuda")
-    diag = torch.zeros(9, dtype=torch.float64, device="cuda")
+    diag = torch.zeros(10, dtype=torch.float64, device="cuda")
     dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
     calls = {
         "sync_ghosts": lambda: g.sync_ghosts(pool),

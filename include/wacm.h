@@ -16,15 +16,20 @@
  * - Return value: WACM_OK (0) or a negative WACM_E_* code.  No exception
  *   crosses the ABI.  Arguments are checked on the host before any launch;
  *   a failed check launches nothing and leaves every buffer untouched.
- *   wacm_last_error() gives a text for the last failure of the calling thread.
+ *   wacm_last_error(grid) gives the text of the last failure of a call on
+ *   that grid, wacm_last_error(NULL) the last failure of the calling thread.
  * - Asynchrony: calls that take a stream only enqueue work on it and return;
  *   errors raised by the device surface at the next synchronising call.
  *   Calls documented as "synchronous" wait for the stream.
  * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
- * - Device memory for the state is owned by the caller.  The library owns the
- *   opaque grid handle, its host metadata and small device tables (neighbour
- *   tables, block lists, reduction partials) allocated in wacm_grid_create /
- *   wacm_adapt and released by wacm_grid_destroy.
+ * - Ownership: the library never allocates device memory.  The caller owns
+ *   every device buffer: the state, the work registers and the workspaces
+ *   whose sizes the library states (wacm_workspace_bytes for the grid's
+ *   tables, wacm_wavelet_workspace_bytes for CDF 4/4, wacm_adj_plan_bytes
+ *   for the adjoint's transpose plans), each 256-byte aligned.  A grid keeps
+ *   pointers into its workspaces until wacm_grid_destroy, so they must stay
+ *   allocated until then.  The library owns only the opaque handle and its
+ *   host metadata.
  *
  * Block pool layout ("pool"): a device array of `capacity` slots; slot s holds
  * 4 fields (u, v, w, p), each a padded cube of P^3 values, P = bs + 2 ng,
@@ -133,25 +138,41 @@ typedef struct {
   double cfl, cfl_eta, cfl_nu; /* time-step constants (Sec. 2.3)                 */
 } wacm_params;
 
-/* Text of the last error on the calling thread ("" if none). */
-const char* wacm_last_error(void);
+/* Text of the last failed call on `grid` ("" if none), or with grid NULL of
+ * the last failure on the calling thread. */
+const char* wacm_last_error(const wacm_grid* grid);
 
 /* Treecode helpers (Sec. 4.1). */
 uint64_t wacm_treecode_encode(int32_t level, int64_t ix, int64_t iy, int64_t iz);
 void wacm_treecode_decode(uint64_t code, int32_t level, int64_t* ix, int64_t* iy, int64_t* iz);
 
 /*
+ * wacm_workspace_bytes -- bytes of the device workspace a grid of this
+ * descriptor needs for its tables (per block: the neighbour table of the
+ * 27 regions around it, the adaptation work lists, the lists of faces and
+ * ghost regions next to other levels, reduction partials; plus the work
+ * counters of the stage kernel), sized for `capacity` blocks so that no
+ * adaptation ever needs more.  0 if the descriptor is invalid.
+ */
+size_t wacm_workspace_bytes(const wacm_grid_desc* desc);
+
+/*
  * wacm_grid_create -- build a grid from `nleaves` leaves (Sec. 4.1).
  * treecodes/levels: host arrays of nleaves entries.  Leaf i is placed in pool
  * slot i (so nleaves <= capacity); the active block list is kept in Morton
- * order.  Validation: sizes (WACM_E_INVAL), exact tiling of the periodic
- * domain (WACM_E_TILING), 2:1 grading over faces, edges and corners
+ * order.  workspace: caller-owned device buffer of ws_bytes >=
+ * wacm_workspace_bytes(desc) bytes, 256-byte aligned, kept by the grid until
+ * wacm_grid_destroy (the tables are built there; the grid never allocates
+ * device memory).  Validation, all before the workspace is touched: sizes
+ * and the workspace (WACM_E_INVAL), exact tiling of the periodic domain
+ * (WACM_E_TILING), 2:1 grading over faces, edges and corners
  * (WACM_E_UNBALANCED).  On success *out receives a new handle.  Synchronous.
  */
 int wacm_grid_create(const wacm_grid_desc* desc, int64_t nleaves, const uint64_t* treecodes,
-                     const int8_t* levels, wacm_grid** out);
+                     const int8_t* levels, void* workspace, size_t ws_bytes, wacm_grid** out);
 
-/* Release the handle and its device tables.  NULL is accepted. */
+/* Release the handle (the caller's workspaces may be freed afterwards).  NULL
+ * is accepted. */
 int wacm_grid_destroy(wacm_grid* grid);
 
 /* Number of active blocks. */
@@ -175,11 +196,16 @@ int wacm_grid_info(const wacm_grid* grid, int64_t* slots, uint64_t* treecodes, i
  * sync, and in wacm_adapt(COARSEN) to the parents (then U must be
  * ghost-synchronised, as it is after thresholding).  Details, prediction and
  * refinement are unchanged.  CDF 4/4 needs ng >= 6 (else WACM_E_INVAL) and
- * device buffers for its ghost phase, which the grid allocates here and on
- * every adaptation (WACM_E_NOMEM if that fails).  Not available with CDF 4/4:
- * wacm_rk4_step(s), wacm_filter_blocks and the adjoint (WACM_E_INVAL).
- * wacm_get_wavelet returns the current choice. */
-int wacm_set_wavelet(wacm_grid* grid, int32_t wavelet);
+ * device buffers for its ghost phase, which the caller provides: ws, ws_bytes >=
+ * wacm_wavelet_workspace_bytes(grid, WACM_CDF44), 256-byte aligned, kept by
+ * the grid until it is destroyed or switched back to CDF 4/0 (ws may be NULL
+ * for WACM_CDF40).  The size covers `capacity` blocks with every ghost point
+ * lifted, so no adaptation needs more.  Not available with CDF 4/4:
+ * wacm_filter_blocks and the adjoint (WACM_E_INVAL); wacm_rk4_step(s) take
+ * the materialised path described at wacm_rk4_step.  wacm_get_wavelet
+ * returns the current choice. */
+size_t wacm_wavelet_workspace_bytes(const wacm_grid* grid, int32_t wavelet); /* 0: none */
+int wacm_set_wavelet(wacm_grid* grid, int32_t wavelet, void* ws, size_t ws_bytes);
 int wacm_get_wavelet(const wacm_grid* grid);
 
 /* Set / read the stage-kernel schedule (values checked: wg_per_cu in [0, 16],
@@ -266,7 +292,10 @@ int wacm_rk4_steps(wacm_grid* grid, const wacm_params* prm, double* t_dev, doubl
  * wacm_diagnostics -- FP64 reductions over interiors at time t:
  * out[0] max Euclidean |u|, out[1..4] max |u|,|v|,|w|,|p|,
  * out[5..7] penalization force C_eta^-1 sum chi (u - u_s) h^3 (Sec. 2.2,
- * midpoint rule), out[8] energy 1/2 sum |u|^2 h^3.  out: 9 device doubles.
+ * midpoint rule), out[8] energy 1/2 sum |u|^2 h^3, out[9] the number of
+ * interior values that are NaN or Inf (the maxima skip them).  out: 10
+ * device doubles.  Synchronous (the stream is waited for): returns
+ * WACM_E_NONFINITE, with out filled, if out[9] > 0.
  */
 int wacm_diagnostics(wacm_grid* grid, const wacm_params* prm, double t, const void* U,
                      const void* dus, double* out, void* stream);
@@ -316,19 +345,22 @@ int wacm_filter_blocks(wacm_grid* grid, void* U, int32_t level, void* stream);
  * Requirements (WACM_E_INVAL otherwise): 4 <= n <= 1024, n a multiple of
  * 2^nlev with n / 2^nlev >= 4, 0 <= nlev <= 9, 1 <= nfields <= 65535, u not
  * NULL and aligned to two elements (16 bytes FP64, 8 bytes FP32); with
- * WACM_CDF44 and nlev > 0, work: a device buffer of
- * wacm_mr_work_bytes(n, nfields, dtype) bytes (may be NULL for WACM_CDF40).
- * The caller owns u and work.  No allocation, no host synchronisation:
- * asynchronous on `stream` and graph-capturable.
+ * WACM_CDF44 and nlev > 0, work: a 256-byte aligned device buffer of
+ * work_size >= wacm_mr_work_bytes(n, nfields, dtype) bytes (work may be NULL
+ * and work_size 0 for WACM_CDF40 or nlev 0).  The caller owns u and work.
+ * No allocation, no host synchronisation: asynchronous on `stream` and
+ * graph-capturable.
  */
 size_t wacm_mr_work_bytes(int64_t n, int32_t nfields, int32_t dtype); /* 0 if invalid */
 int wacm_mr_forward(int64_t n, int32_t nfields, int32_t dtype, int32_t wavelet, int32_t nlev,
-                    void* u, void* work, void* stream);
+                    void* u, void* work, size_t work_size, void* stream);
 int wacm_mr_inverse(int64_t n, int32_t nfields, int32_t dtype, int32_t wavelet, int32_t nlev,
-                    void* u, void* work, void* stream);
+                    void* u, void* work, size_t work_size, void* stream);
 
 /*
- * wacm_adapt -- change the grid (Sec. 3.5).  Synchronous.
+ * wacm_adapt -- change the grid (Sec. 3.5).  Synchronous.  The tables are
+ * rebuilt inside the grid's workspaces; adjoint plans are dropped (set them
+ * again before the next adjoint call).
  * WACM_REFINE_ALL: ghosts of U are synchronised, then every active block below
  *   jmax is replaced by its 8 children (even child points copy the parent,
  *   odd points take the tensor DD4 prediction, Sec. 3.1).  `flags` unused.
@@ -352,14 +384,27 @@ int wacm_adapt(wacm_grid* grid, int32_t op, const int8_t* flags, void* U, int64_
  * use the pool layout and element type; dtheta is a device array of 3
  * doubles and dusbar a device array [capacity][3][bs^3] of doubles (NULL:
  * not wanted); both are accumulated (+=), never cleared.  Reductions run in a
- * fixed order (bitwise reproducible).  The first call of wacm_sync_ghosts_adj
- * / wacm_rk4_step_adj on a grid builds a transpose plan of the ghost fill on
- * the host (synchronous, device memory owned by the grid, dropped by
- * wacm_adapt).
+ * fixed order (bitwise reproducible).  wacm_sync_ghosts_adj needs the
+ * transpose plan of the full ghost fill (face_only 0), wacm_rk4_step_adj the
+ * plan of the depth-3 face star (face_only 1), each set once per grid with
+ * wacm_adj_plan_set (WACM_E_INVAL otherwise).
  */
 
 /* Bytes of the work buffer wacm_rk4_step_adj needs (8 pool-sized registers). */
 size_t wacm_adj_work_bytes(const wacm_grid* grid);
+
+/*
+ * wacm_adj_plan_bytes / wacm_adj_plan_set -- the transpose of the ghost fill
+ * as a gather plan: for every interior point some ghost value is copied or
+ * predicted from (Sec. 3.1 weights), the ghost points that read it, sorted so
+ * the accumulation order is fixed.  wacm_adj_plan_bytes builds the plan on
+ * the host (kept in the handle) and returns its device size (0 on error);
+ * wacm_adj_plan_set copies it into the caller's buffer ws (ws_bytes >= that
+ * size, 256-byte aligned, kept until the grid changes or is destroyed).
+ * Synchronous.  wacm_adapt drops both plans.
+ */
+size_t wacm_adj_plan_bytes(wacm_grid* grid, int32_t face_only);
+int wacm_adj_plan_set(wacm_grid* grid, int32_t face_only, void* ws, size_t ws_bytes);
 
 /*
  * wacm_sync_ghosts_adj -- transpose of wacm_sync_ghosts: the adjoint held at

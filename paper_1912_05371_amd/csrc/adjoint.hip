@@ -16,27 +16,21 @@ namespace wacm {
 // --------------------------------------------------------------------------
 // transpose of the ghost fill: CSR gather plan built on the host
 // --------------------------------------------------------------------------
-static void free_plan(AdjPlan& p) {
-  if (p.d_dst) (void)hipFree(p.d_dst);
-  if (p.d_ptr) (void)hipFree(p.d_ptr);
-  if (p.d_src) (void)hipFree(p.d_src);
-  if (p.d_w) (void)hipFree(p.d_w);
-  if (p.d_ghost) (void)hipFree(p.d_ghost);
-  p = AdjPlan{};
-}
-
 void free_adj_plans(wacm_grid* g) {
-  free_plan(g->plan[0]);
-  free_plan(g->plan[1]);
+  g->plan[0] = AdjPlan{};
+  g->plan[1] = AdjPlan{};
 }
 
 // Every ghost point of the set (0: all ng layers, 1: depth-3 face star) of
 // every active block, with the interior points its value was taken from:
 // rows are the source interior points, entries the ghost points that read
 // them with their prediction weights, sorted so the gather is deterministic.
+// Host part only (kept until the grid changes); upload_adj_plan copies it
+// into the caller's buffer.
 int build_adj_plan(wacm_grid* g, int face_only, std::string& err) {
   AdjPlan& pl = g->plan[face_only ? 1 : 0];
-  if (pl.built) return WACM_OK;
+  if (pl.built || !pl.h_ptr.empty()) return WACM_OK;
+  (void)err;
   const int bs = g->d.bs, ng = g->d.ng, P = g->P;
   Layout L;
   L.P = P;
@@ -61,44 +55,61 @@ int build_adj_plan(wacm_grid* g, int face_only, std::string& err) {
     }
   }
   std::sort(ent.begin(), ent.end());
-  std::vector<int64_t> dst, ptr, src;
-  std::vector<double> w;
-  src.reserve(ent.size());
-  w.reserve(ent.size());
+  AdjPlan np;
+  np.h_src.reserve(ent.size());
+  np.h_w.reserve(ent.size());
   for (size_t e = 0; e < ent.size(); ++e) {
     if (e == 0 || std::get<0>(ent[e]) != std::get<0>(ent[e - 1])) {
-      dst.push_back(std::get<0>(ent[e]));
-      ptr.push_back((int64_t)e);
+      np.h_dst.push_back(std::get<0>(ent[e]));
+      np.h_ptr.push_back((int64_t)e);
     }
-    src.push_back(std::get<1>(ent[e]));
-    w.push_back(std::get<2>(ent[e]));
+    np.h_src.push_back(std::get<1>(ent[e]));
+    np.h_w.push_back(std::get<2>(ent[e]));
   }
-  ptr.push_back((int64_t)ent.size());
-  AdjPlan np;
-  np.nrows = (int64_t)dst.size();
-  np.nnz = (int64_t)src.size();
-  np.nghost = (int64_t)ghosts.size();
+  np.h_ptr.push_back((int64_t)ent.size());
+  np.h_ghost.swap(ghosts);
+  np.nrows = (int64_t)np.h_dst.size();
+  np.nnz = (int64_t)np.h_src.size();
+  np.nghost = (int64_t)np.h_ghost.size();
+  pl = std::move(np);
+  return WACM_OK;
+}
+
+static size_t up256(size_t v) { return (v + 255) / 256 * 256; }
+
+// device bytes of a plan: dst, ptr, src, w, ghost, each 256-byte aligned
+size_t adj_plan_bytes(const AdjPlan& p) {
+  return up256(8 * p.h_dst.size()) + up256(8 * p.h_ptr.size()) + up256(8 * p.h_src.size()) +
+         up256(8 * p.h_w.size()) + up256(8 * p.h_ghost.size());
+}
+
+int upload_adj_plan(wacm_grid* g, int face_only, void* ws, size_t bytes, std::string& err) {
+  AdjPlan& pl = g->plan[face_only ? 1 : 0];
+  if (int rc = build_adj_plan(g, face_only, err)) return rc;
+  if (bytes < adj_plan_bytes(pl)) {
+    err = "adjoint plan buffer smaller than wacm_adj_plan_bytes()";
+    return WACM_E_INVAL;
+  }
+  char* w = (char*)ws;
   hipError_t e = hipSuccess;
-  auto up = [&](auto** d, const auto& v) {
+  auto put = [&](auto** d, const auto& v) {
     using E = typename std::remove_reference<decltype(v)>::type::value_type;
-    if (e != hipSuccess) return;
-    const size_t bytes = sizeof(E) * std::max<size_t>(v.size(), 1);
-    e = hipMalloc((void**)d, bytes);
+    *d = reinterpret_cast<E*>(w);
     if (e == hipSuccess && !v.empty())
-      e = hipMemcpy(*d, v.data(), sizeof(E) * v.size(), hipMemcpyHostToDevice);
+      e = hipMemcpy(w, v.data(), sizeof(E) * v.size(), hipMemcpyHostToDevice);
+    w += up256(sizeof(E) * v.size());
   };
-  up(&np.d_dst, dst);
-  up(&np.d_ptr, ptr);
-  up(&np.d_src, src);
-  up(&np.d_w, w);
-  up(&np.d_ghost, ghosts);
+  put(&pl.d_dst, pl.h_dst);
+  put(&pl.d_ptr, pl.h_ptr);
+  put(&pl.d_src, pl.h_src);
+  put(&pl.d_w, pl.h_w);
+  put(&pl.d_ghost, pl.h_ghost);
   if (e != hipSuccess) {
-    free_plan(np);
+    pl.built = 0;
     err = std::string("adjoint plan upload: ") + hipGetErrorString(e);
     return WACM_E_HIP;
   }
-  np.built = 1;
-  pl = np;
+  pl.built = 1;
   return WACM_OK;
 }
 

@@ -11,14 +11,28 @@ using namespace wacm;
 
 namespace {
 thread_local std::string g_err;
+thread_local const wacm_grid* g_cur = nullptr;  // grid of the current entry point
+
+// Every entry point that takes a grid opens a GridScope: a failure is then
+// recorded for the calling thread and on the grid (wacm_last_error(grid)).
+struct GridScope {
+  const wacm_grid* prev;
+  explicit GridScope(const wacm_grid* g) : prev(g_cur) { g_cur = g; }
+  ~GridScope() { g_cur = prev; }
+};
+
+void record(const std::string& msg) {
+  g_err = msg;
+  if (g_cur) g_cur->last_err = msg;
+}
 
 int fail(int code, const std::string& msg) {
-  g_err = msg;
+  record(msg);
   return code;
 }
 
 int hipfail(hipError_t e, const char* what) {
-  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  record(std::string(what) + ": " + hipGetErrorString(e));
   return WACM_E_HIP;
 }
 
@@ -34,20 +48,15 @@ int check_params(const wacm_params* p) {
   return WACM_OK;
 }
 
+// Drops the references into the caller's buffers (the library never
+// allocates device memory, so there is nothing to free) and the events of
+// the profiler.
 void free_dev(wacm_grid* g) {
   free_adj_plans(g);
   (void)profile_flush(g);
   for (hipEvent_t e : g->prof.spare) (void)hipEventDestroy(e);
   g->prof.spare.clear();
-  if (g->d_tab) (void)hipFree(g->d_tab);
-  if (g->d_part) (void)hipFree(g->d_part);
-  if (g->d_norm) (void)hipFree(g->d_norm);
-  if (g->d_queue) (void)hipFree(g->d_queue);
-  if (g->d_list) (void)hipFree(g->d_list);
-  if (g->d_cface) (void)hipFree(g->d_cface);
-  if (g->d_cregion) (void)hipFree(g->d_cregion);
-  if (g->d_lift) (void)hipFree(g->d_lift);
-  if (g->d_lift_tmp) (void)hipFree(g->d_lift_tmp);
+  g->ws = nullptr;
   g->d_lift = nullptr;
   g->d_lift_tmp = nullptr;
   g->lift_items_cap = g->lift_tmp_cap = 0;
@@ -63,15 +72,38 @@ void free_dev(wacm_grid* g) {
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// descriptor checks shared by wacm_workspace_bytes and wacm_grid_create
+int check_desc(const wacm_grid_desc* d) {
+  if (d->bs % 2 || d->bs < 2 * (d->ng + 3) || d->ng < 3 || d->bs > 64)
+    return fail(WACM_E_INVAL, "bs must be even with 2(ng+3) <= bs <= 64 and ng >= 3");
+  if (d->jmin < 0 || d->jmax > 18 || d->jmin > d->jmax)
+    return fail(WACM_E_INVAL, "need 0 <= jmin <= jmax <= 18");
+  if (d->dtype != WACM_F32 && d->dtype != WACM_F64) return fail(WACM_E_INVAL, "bad dtype");
+  if (d->reserved != 0) return fail(WACM_E_INVAL, "reserved must be 0");
+  if (!(d->L > 0)) return fail(WACM_E_INVAL, "L must be > 0");
+  if (d->capacity <= 0 || d->capacity > (int64_t)1 << 30)
+    return fail(WACM_E_INVAL, "need 0 < capacity <= 2^30");
+  if (d->bs != 16 && d->bs != 24 && d->bs != 32)
+    return fail(WACM_E_INVAL, "kernels are built for bs in {16, 24, 32}");
+  return WACM_OK;
+}
+
 }  // namespace
 
 namespace wacm {
-void set_error(const std::string& s) { g_err = s; }
+void set_error(const std::string& s) { record(s); }
 }  // namespace wacm
 
 extern "C" {
 
-const char* wacm_last_error(void) { return g_err.c_str(); }
+const char* wacm_last_error(const wacm_grid* g) {
+  return g ? g->last_err.c_str() : g_err.c_str();
+}
+
+size_t wacm_workspace_bytes(const wacm_grid_desc* d) {
+  if (!d || check_desc(d) != WACM_OK) return 0;
+  return ws_parts(d->capacity).total;
+}
 
 uint64_t wacm_treecode_encode(int32_t level, int64_t ix, int64_t iy, int64_t iz) {
   uint64_t code = 0;
@@ -98,20 +130,17 @@ void wacm_treecode_decode(uint64_t code, int32_t level, int64_t* ix, int64_t* iy
 }
 
 int wacm_grid_create(const wacm_grid_desc* d, int64_t nleaves, const uint64_t* treecodes,
-                     const int8_t* levels, wacm_grid** out) {
+                     const int8_t* levels, void* workspace, size_t ws_bytes, wacm_grid** out) {
   if (!d || !out || !treecodes || !levels) return fail(WACM_E_INVAL, "NULL argument");
   *out = nullptr;
-  if (d->bs % 2 || d->bs < 2 * (d->ng + 3) || d->ng < 3 || d->bs > 64)
-    return fail(WACM_E_INVAL, "bs must be even with 2(ng+3) <= bs <= 64 and ng >= 3");
-  if (d->jmin < 0 || d->jmax > 18 || d->jmin > d->jmax)
-    return fail(WACM_E_INVAL, "need 0 <= jmin <= jmax <= 18");
-  if (d->dtype != WACM_F32 && d->dtype != WACM_F64) return fail(WACM_E_INVAL, "bad dtype");
-  if (d->reserved != 0) return fail(WACM_E_INVAL, "reserved must be 0");
-  if (!(d->L > 0)) return fail(WACM_E_INVAL, "L must be > 0");
-  if (nleaves <= 0 || nleaves > d->capacity || d->capacity > (int64_t)1 << 30)
-    return fail(WACM_E_INVAL, "need 0 < nleaves <= capacity <= 2^30");
-  if (d->bs != 16 && d->bs != 24 && d->bs != 32)
-    return fail(WACM_E_INVAL, "kernels are built for bs in {16, 24, 32}");
+  if (int rc = check_desc(d)) return rc;
+  if (nleaves <= 0 || nleaves > d->capacity)
+    return fail(WACM_E_INVAL, "need 0 < nleaves <= capacity");
+  const WsParts wp = ws_parts(d->capacity);
+  if (!workspace) return fail(WACM_E_INVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(WACM_E_INVAL, "workspace not 256-byte aligned");
+  if (ws_bytes < wp.total) return fail(WACM_E_INVAL, "workspace smaller than wacm_workspace_bytes()");
 
   wacm_grid* g = new (std::nothrow) wacm_grid();
   if (!g) return fail(WACM_E_NOMEM, "host allocation");
@@ -168,18 +197,16 @@ int wacm_grid_create(const wacm_grid_desc* d, int64_t nleaves, const uint64_t* t
     delete g;
     return fail(rc, err);
   }
-  hipError_t e;
-  if ((e = hipMalloc(&g->d_tab, sizeof(Tab) * d->capacity)) != hipSuccess ||
-      (e = hipMalloc(&g->d_part, sizeof(double) * 16 * (d->capacity + 1024))) != hipSuccess ||
-      (e = hipMalloc(&g->d_norm, sizeof(double) * 16)) != hipSuccess ||
-      (e = hipMalloc(&g->d_queue, sizeof(int32_t) * 512)) != hipSuccess ||
-      (e = hipMalloc(&g->d_list, sizeof(int32_t) * 10 * d->capacity)) != hipSuccess ||
-      (e = hipMalloc(&g->d_cface, sizeof(int32_t) * 12 * d->capacity)) != hipSuccess ||
-      (e = hipMalloc(&g->d_cregion, sizeof(int32_t) * 52 * d->capacity)) != hipSuccess) {
-    free_dev(g);
-    delete g;
-    return hipfail(e, "hipMalloc of grid tables");
-  }
+  // every check passed: the tables go into the caller's workspace
+  char* w = static_cast<char*>(workspace);
+  g->ws = workspace;
+  g->d_tab = reinterpret_cast<Tab*>(w + wp.tab);
+  g->d_part = reinterpret_cast<double*>(w + wp.part);
+  g->d_norm = reinterpret_cast<double*>(w + wp.norm);
+  g->d_queue = reinterpret_cast<int32_t*>(w + wp.queue);
+  g->d_list = reinterpret_cast<int32_t*>(w + wp.list);
+  g->d_cface = reinterpret_cast<int32_t*>(w + wp.cface);
+  g->d_cregion = reinterpret_cast<int32_t*>(w + wp.cregion);
   rc = upload_tables(g, tabs, err);
   if (rc) {
     free_dev(g);
@@ -191,6 +218,7 @@ int wacm_grid_create(const wacm_grid_desc* d, int64_t nleaves, const uint64_t* t
 }
 
 int wacm_grid_destroy(wacm_grid* g) {
+  GridScope gs(g);
   if (!g) return WACM_OK;
   free_dev(g);
   delete g;
@@ -200,6 +228,7 @@ int wacm_grid_destroy(wacm_grid* g) {
 int64_t wacm_grid_nb(const wacm_grid* g) { return g ? g->nb : -1; }
 
 int wacm_grid_info(const wacm_grid* g, int64_t* slots, uint64_t* treecodes, int8_t* levels) {
+  GridScope gs(g);
   if (!g) return fail(WACM_E_INVAL, "NULL grid");
   for (int64_t i = 0; i < g->nb; ++i) {
     const Leaf& l = g->leaves[i];
@@ -211,11 +240,13 @@ int wacm_grid_info(const wacm_grid* g, int64_t* slots, uint64_t* treecodes, int8
 }
 
 size_t wacm_work_bytes(const wacm_grid* g) {
+  GridScope gs(g);
   if (!g) return 0;
   return g->wavelet == WACM_CDF44 ? lift_work_bytes(g) : work_bytes(g);
 }
 
 int wacm_set_schedule(wacm_grid* g, const wacm_schedule* s) {
+  GridScope gs(g);
   if (!g || !s) return fail(WACM_E_INVAL, "NULL argument");
   if (s->wg_per_cu < 0 || s->wg_per_cu > 16 || s->xcd_map < 0 || s->xcd_map > 2 ||
       s->prefetch < -1 || s->prefetch > 1 || (s->nontemporal != 0 && s->nontemporal != 1) ||
@@ -226,6 +257,7 @@ int wacm_set_schedule(wacm_grid* g, const wacm_schedule* s) {
 }
 
 int wacm_get_schedule(const wacm_grid* g, wacm_schedule* s) {
+  GridScope gs(g);
   if (!g || !s) return fail(WACM_E_INVAL, "NULL argument");
   *s = g->sched;
   return WACM_OK;
@@ -240,21 +272,52 @@ static hipError_t full_sync(const wacm_grid* g, void* U, hipStream_t st) {
 }
 
 int wacm_sync_ghosts(wacm_grid* g, void* U, void* stream) {
+  GridScope gs(g);
   if (!elem_ok(g) || !U) return fail(WACM_E_INVAL, "NULL argument");
   hipError_t e = full_sync(g, U, S(stream));
   return e == hipSuccess ? WACM_OK : hipfail(e, "sync_ghosts launch");
 }
 
-int wacm_set_wavelet(wacm_grid* g, int32_t wavelet) {
+size_t wacm_wavelet_workspace_bytes(const wacm_grid* g, int32_t wavelet) {
+  GridScope gs(g);
+  if (!elem_ok(g) || wavelet != WACM_CDF44) return 0;
+  return lift_ws_bytes(g->d.capacity, g->d.bs, g->d.ng, g->d.dtype == WACM_F64 ? 8 : 4);
+}
+
+int wacm_set_wavelet(wacm_grid* g, int32_t wavelet, void* ws, size_t ws_bytes) {
+  GridScope gs(g);
   if (!elem_ok(g)) return fail(WACM_E_INVAL, "NULL argument");
   if (wavelet != WACM_CDF40 && wavelet != WACM_CDF44) return fail(WACM_E_INVAL, "wavelet");
-  if (wavelet == WACM_CDF44 && g->d.ng < 6)
-    return fail(WACM_E_INVAL, "CDF 4/4 needs ng >= 6 (the lifted stencil reaches 6 fine points)");
+  if (wavelet == WACM_CDF44) {
+    if (g->d.ng < 6)
+      return fail(WACM_E_INVAL, "CDF 4/4 needs ng >= 6 (the lifted stencil reaches 6 fine points)");
+    if (!ws || reinterpret_cast<uintptr_t>(ws) % 256)
+      return fail(WACM_E_INVAL, "CDF 4/4 needs a 256-byte aligned wavelet workspace");
+    if (ws_bytes < wacm_wavelet_workspace_bytes(g, WACM_CDF44))
+      return fail(WACM_E_INVAL, "wavelet workspace smaller than wacm_wavelet_workspace_bytes()");
+  }
   const int old = g->wavelet;
+  int32_t* old_items = g->d_lift;
+  void* old_tmp = g->d_lift_tmp;
+  const size_t old_icap = g->lift_items_cap, old_tcap = g->lift_tmp_cap;
   g->wavelet = wavelet;
+  if (wavelet == WACM_CDF44) {
+    g->d_lift = static_cast<int32_t*>(ws);
+    g->lift_items_cap = lift_items_bytes(g->d.capacity);
+    g->d_lift_tmp = static_cast<char*>(ws) + g->lift_items_cap;
+    g->lift_tmp_cap = ws_bytes - g->lift_items_cap;
+  } else {
+    g->d_lift = nullptr;
+    g->d_lift_tmp = nullptr;
+    g->lift_items_cap = g->lift_tmp_cap = 0;
+  }
   std::string err;
   if (int rc = build_lift(g, g->h_tab, err)) {
     g->wavelet = old;
+    g->d_lift = old_items;
+    g->d_lift_tmp = old_tmp;
+    g->lift_items_cap = old_icap;
+    g->lift_tmp_cap = old_tcap;
     build_lift(g, g->h_tab, err);
     return fail(rc, err);
   }
@@ -265,6 +328,7 @@ int wacm_get_wavelet(const wacm_grid* g) { return g ? g->wavelet : WACM_E_INVAL;
 
 int wacm_rhs_acm(wacm_grid* g, const wacm_params* p, double t, const void* U, void* dU,
                  const void* dus, void* stream) {
+  GridScope gs(g);
   if (!elem_ok(g) || !U || !dU) return fail(WACM_E_INVAL, "NULL argument");
   if (int rc = check_params(p)) return rc;
   hipError_t e = launch_rhs(g, p, t, U, dU, dus, S(stream));
@@ -273,6 +337,7 @@ int wacm_rhs_acm(wacm_grid* g, const wacm_params* p, double t, const void* U, vo
 
 int wacm_compute_dt(wacm_grid* g, const wacm_params* p, const void* U, double* dt_dev,
                     void* stream) {
+  GridScope gs(g);
   if (!elem_ok(g) || !U || !dt_dev) return fail(WACM_E_INVAL, "NULL argument");
   if (int rc = check_params(p)) return rc;
   hipError_t e = launch_dt(g, p, U, dt_dev, S(stream));
@@ -297,26 +362,38 @@ static int rk4_common(wacm_grid* g, const wacm_params* p, double* t_dev, double*
 
 int wacm_rk4_step(wacm_grid* g, const wacm_params* p, double* t_dev, double* dt_dev, void* U,
                   void* work, const void* dus, int32_t dt_mode, void* stream) {
+  GridScope gs(g);
   return rk4_common(g, p, t_dev, dt_dev, U, work, dus, dt_mode, 1, stream, "rk4_step launch");
 }
 
 int wacm_rk4_steps(wacm_grid* g, const wacm_params* p, double* t_dev, double* dt_dev, void* U,
                    void* work, const void* dus, int32_t dt_mode, int64_t nsteps, void* stream) {
+  GridScope gs(g);
   return rk4_common(g, p, t_dev, dt_dev, U, work, dus, dt_mode, nsteps, stream,
                     "rk4_steps launch");
 }
 
 int wacm_diagnostics(wacm_grid* g, const wacm_params* p, double t, const void* U,
                      const void* dus, double* out, void* stream) {
+  GridScope gs(g);
   if (!elem_ok(g) || !U || !out) return fail(WACM_E_INVAL, "NULL argument");
   if (int rc = check_params(p)) return rc;
   hipError_t e = launch_diag(g, p, t, U, dus, out, S(stream));
-  return e == hipSuccess ? WACM_OK : hipfail(e, "diagnostics launch");
+  if (e != hipSuccess) return hipfail(e, "diagnostics launch");
+  double h[10];
+  e = hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, S(stream));
+  if (e == hipSuccess) e = hipStreamSynchronize(S(stream));
+  if (e != hipSuccess) return hipfail(e, "diagnostics read-back");
+  if (h[9] > 0)
+    return fail(WACM_E_NONFINITE, std::to_string((int64_t)h[9]) +
+                                      " interior values of the state are NaN or Inf");
+  return WACM_OK;
 }
 
 int wacm_threshold_blocks(wacm_grid* g, const wacm_params* p, double t, const void* U,
                           double eps, int32_t dealias, double* dmax, double* mrange,
                           int8_t* flags, void* stream) {
+  GridScope gs(g);
   if (!elem_ok(g) || !U || !dmax || !mrange || !flags) return fail(WACM_E_INVAL, "NULL argument");
   if (int rc = check_params(p)) return rc;
   if (!(eps >= 0)) return fail(WACM_E_INVAL, "eps must be >= 0");
@@ -325,6 +402,7 @@ int wacm_threshold_blocks(wacm_grid* g, const wacm_params* p, double t, const vo
 }
 
 int wacm_filter_blocks(wacm_grid* g, void* U, int32_t level, void* stream) {
+  GridScope gs(g);
   if (!elem_ok(g) || !U) return fail(WACM_E_INVAL, "NULL argument");
   if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "filtering is CDF 4/0 only");
   hipError_t e = launch_filter(g, U, level, S(stream));
@@ -333,6 +411,7 @@ int wacm_filter_blocks(wacm_grid* g, void* U, int32_t level, void* stream) {
 
 int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* nb_out,
                void* stream) {
+  GridScope gs(g);
   if (!elem_ok(g) || !U) return fail(WACM_E_INVAL, "NULL argument");
   hipStream_t st = S(stream);
   const int bs = g->d.bs;
@@ -484,17 +563,39 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
 
 size_t wacm_adj_work_bytes(const wacm_grid* g) { return g ? adj_work_bytes(g) : 0; }
 
+size_t wacm_adj_plan_bytes(wacm_grid* g, int32_t face_only) {
+  GridScope gs(g);
+  if (!elem_ok(g) || (face_only != 0 && face_only != 1)) return 0;
+  std::string err;
+  if (build_adj_plan(g, face_only, err)) return 0;
+  return adj_plan_bytes(g->plan[face_only]);
+}
+
+int wacm_adj_plan_set(wacm_grid* g, int32_t face_only, void* ws, size_t ws_bytes) {
+  GridScope gs(g);
+  if (!elem_ok(g) || !ws) return fail(WACM_E_INVAL, "NULL argument");
+  if (face_only != 0 && face_only != 1) return fail(WACM_E_INVAL, "face_only must be 0 or 1");
+  if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "the adjoint is CDF 4/0 only");
+  if (reinterpret_cast<uintptr_t>(ws) % 256)
+    return fail(WACM_E_INVAL, "plan buffer not 256-byte aligned");
+  std::string err;
+  if (int rc = upload_adj_plan(g, face_only, ws, ws_bytes, err)) return fail(rc, err);
+  return WACM_OK;
+}
+
 int wacm_sync_ghosts_adj(wacm_grid* g, void* Ub, void* stream) {
+  GridScope gs(g);
   if (!elem_ok(g) || !Ub) return fail(WACM_E_INVAL, "NULL argument");
   if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "the adjoint is CDF 4/0 only");
-  std::string err;
-  if (int rc = build_adj_plan(g, 0, err)) return fail(rc, err);
+  if (!g->plan[0].built)
+    return fail(WACM_E_INVAL, "no plan of the ghost-fill transpose: wacm_adj_plan_set(grid, 0, ...)");
   hipError_t e = launch_sync_adj(g, Ub, 0, S(stream));
   return e == hipSuccess ? WACM_OK : hipfail(e, "sync_ghosts_adj launch");
 }
 
 int wacm_rhs_acm_adj(wacm_grid* g, const wacm_params* p, double t, const void* U, const void* V,
                      void* Ub, double* dtheta, double* dusbar, const void* dus, void* stream) {
+  GridScope gs(g);
   if (!elem_ok(g) || !U || !V || !Ub || !dtheta) return fail(WACM_E_INVAL, "NULL argument");
   if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "the adjoint is CDF 4/0 only");
   if (int rc = check_params(p)) return rc;
@@ -504,6 +605,7 @@ int wacm_rhs_acm_adj(wacm_grid* g, const wacm_params* p, double t, const void* U
 
 int wacm_force_adj(wacm_grid* g, const wacm_params* p, double t, double weight, const void* U,
                    void* Ub, double* dtheta, double* dusbar, const void* dus, void* stream) {
+  GridScope gs(g);
   if (!elem_ok(g) || !U || !Ub || !dtheta) return fail(WACM_E_INVAL, "NULL argument");
   if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "the adjoint is CDF 4/0 only");
   if (int rc = check_params(p)) return rc;
@@ -514,23 +616,26 @@ int wacm_force_adj(wacm_grid* g, const wacm_params* p, double t, double weight, 
 int wacm_rk4_step_adj(wacm_grid* g, const wacm_params* p, double t, double dt, const void* Un,
                       void* lam, double* dtheta, double* dusbar, const void* dus, void* work,
                       void* stream) {
+  GridScope gs(g);
   if (!elem_ok(g) || !Un || !lam || !dtheta || !work) return fail(WACM_E_INVAL, "NULL argument");
   if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "the adjoint is CDF 4/0 only");
   if (reinterpret_cast<uintptr_t>(work) % 256) return fail(WACM_E_INVAL, "work not 256-aligned");
   if (int rc = check_params(p)) return rc;
-  std::string err;
-  if (int rc = build_adj_plan(g, 1, err)) return fail(rc, err);
+  if (!g->plan[1].built)
+    return fail(WACM_E_INVAL, "no plan of the face-star transpose: wacm_adj_plan_set(grid, 1, ...)");
   hipError_t e = launch_rk4_adj(g, p, t, dt, Un, lam, dtheta, dusbar, dus, work, S(stream));
   return e == hipSuccess ? WACM_OK : hipfail(e, "rk4_step_adj launch");
 }
 
 int wacm_profile_enable(wacm_grid* g, int32_t on) {
+  GridScope gs(g);
   if (!g) return fail(WACM_E_INVAL, "NULL grid");
   g->prof.on = on != 0;
   return WACM_OK;
 }
 
 int wacm_profile_read(wacm_grid* g, double* ms, int64_t* launches) {
+  GridScope gs(g);
   if (!g || !ms || !launches) return fail(WACM_E_INVAL, "NULL argument");
   hipError_t e = profile_flush(g);
   for (int c = 0; c < 4; ++c) {

@@ -195,6 +195,38 @@ int lift_items(const wacm_grid* g, const std::vector<Tab>& tabs, std::vector<int
   return WACM_OK;
 }
 
+static size_t up256(size_t v) { return (v + 255) / 256 * 256; }
+
+WsParts ws_parts(int64_t cap) {
+  const size_t c = (size_t)cap;
+  WsParts w;
+  size_t o = 0;
+  w.tab = o, o += up256(sizeof(Tab) * c);
+  // reduction partials: 10 per block (diagnostics) or one per stage work item
+  // (at most 4 per block), 16 reserved per block plus a margin
+  w.part = o, o += up256(sizeof(double) * 16 * (c + 1024));
+  w.norm = o, o += up256(sizeof(double) * 16);
+  w.queue = o, o += up256(sizeof(int32_t) * 512);
+  w.list = o, o += up256(sizeof(int32_t) * 10 * c);
+  w.cface = o, o += up256(sizeof(int32_t) * 12 * c);
+  w.cregion = o, o += up256(sizeof(int32_t) * 52 * c);
+  w.total = o;
+  return w;
+}
+
+size_t lift_items_bytes(int64_t cap) {
+  return up256(sizeof(int32_t) * 12 * LIFT_ITEMS_PER_BLOCK * (size_t)cap);
+}
+
+size_t lift_ws_bytes(int64_t cap, int bs, int ng, size_t es) {
+  const size_t P = (size_t)bs + 2 * ng;
+  const size_t shell = P * P * P - (size_t)bs * bs * bs;
+  return lift_items_bytes(cap) + up256((size_t)cap * shell * 4 * es);
+}
+
+// Lifted ghost items of the tables into the caller's wavelet workspace
+// (d_lift, d_lift_tmp, set by wacm_set_wavelet).  Never allocates: the
+// workspace is sized for `capacity` blocks with every ghost point lifted.
 int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
   g->n_lift = 0;
   if (g->wavelet != 1 || tabs.empty()) return WACM_OK;
@@ -204,35 +236,25 @@ int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
     g->n_lift = -1;
     return rc;
   }
-  if (pts > (int64_t(1) << 30)) {
+  if (pts > (int64_t(1) << 30)) {  // staging offsets are int32
     g->n_lift = -1;
     err = "too many lifted ghost points";
     return WACM_E_CAPACITY;
   }
   const size_t es = g->d.dtype == WACM_F64 ? 8 : 4;
   const size_t ibytes = it.size() * sizeof(int32_t), tbytes = (size_t)pts * 4 * es;
+  if (!g->d_lift || !g->d_lift_tmp || ibytes > g->lift_items_cap || tbytes > g->lift_tmp_cap) {
+    g->n_lift = -1;
+    err = "lifted ghost items exceed the wavelet workspace";
+    return WACM_E_CAPACITY;
+  }
   hipError_t e = hipSuccess;
-  if (ibytes > g->lift_items_cap) {
-    if (g->d_lift) (void)hipFree(g->d_lift);
-    g->d_lift = nullptr;
-    g->lift_items_cap = 0;
-    e = hipMalloc(&g->d_lift, ibytes);
-    if (e == hipSuccess) g->lift_items_cap = ibytes;
-  }
-  if (e == hipSuccess && tbytes > g->lift_tmp_cap) {
-    if (g->d_lift_tmp) (void)hipFree(g->d_lift_tmp);
-    g->d_lift_tmp = nullptr;
-    g->lift_tmp_cap = 0;
-    e = hipMalloc(&g->d_lift_tmp, tbytes);
-    if (e == hipSuccess) g->lift_tmp_cap = tbytes;
-  }
-  if (e == hipSuccess && ibytes > 0)
-    e = hipMemcpy(g->d_lift, it.data(), ibytes, hipMemcpyHostToDevice);
+  if (ibytes > 0) e = hipMemcpy(g->d_lift, it.data(), ibytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     // no usable items: the lifted phase refuses to run until a rebuild works
     g->n_lift = -1;
     err = std::string("lifted ghost items: ") + hipGetErrorString(e);
-    return e == hipErrorOutOfMemory ? WACM_E_NOMEM : WACM_E_HIP;
+    return WACM_E_HIP;
   }
   g->n_lift = (int64_t)it.size() / 12;
   return WACM_OK;

@@ -922,26 +922,29 @@ __global__ void advance_time(double* t, const double* dt) {
 }
 
 // diagnostics partials per block: [max|u|^2, max|u|, max|v|, max|w|, max|p|,
-// sum chi(u-us) x3 (times h^3/C_eta), sum |u|^2 (times h^3/2)]
+// sum chi(u-us) x3 (times h^3/C_eta), sum |u|^2 (times h^3/2), number of
+// NaN or Inf values]; the maxima ignore NaN, the count sees it
+constexpr int NDIAG = 10;
 template <typename T>
 __global__ __launch_bounds__(NT_GEN) void diag_kernel(const Tab* __restrict__ tab, int64_t nb,
                                                       const T* __restrict__ U, Layout L, int bs,
                                                       const T* __restrict__ dus, double Ldom,
                                                       wacm_params p, double t,
                                                       double* __restrict__ part) {
-  __shared__ double red[9][NT_GEN];
+  __shared__ double red[NDIAG][NT_GEN];
   const int n3 = bs * bs * bs;
   for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
     const int32_t* m = tab[ib].meta;
     const int slot = m[0], J = m[1];
     const double h = Ldom / (double(int64_t(1) << J) * bs);
     const T* b = U + (int64_t)slot * L.bstride;
-    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[NDIAG] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int q = threadIdx.x; q < n3; q += blockDim.x) {
       const int i = q % bs, j = (q / bs) % bs, k = q / (bs * bs);
       const int64_t o = ((int64_t)(k + L.ng) * L.P + (j + L.ng)) * L.P + (i + L.ng);
       double u[4];
       for (int c = 0; c < 4; ++c) u[c] = b[o + c * L.fstride];
+      for (int c = 0; c < 4; ++c) acc[9] += isfinite(u[c]) ? 0.0 : 1.0;
       const double m2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
       acc[0] = fmax(acc[0], m2);
       for (int c = 0; c < 4; ++c) acc[1 + c] = fmax(acc[1 + c], fabs(u[c]));
@@ -956,46 +959,48 @@ __global__ __launch_bounds__(NT_GEN) void diag_kernel(const Tab* __restrict__ ta
       acc[8] += m2;
     }
     __syncthreads();
-    for (int c = 0; c < 9; ++c) red[c][threadIdx.x] = acc[c];
+    for (int c = 0; c < NDIAG; ++c) red[c][threadIdx.x] = acc[c];
     __syncthreads();
     for (int s = NT_GEN / 2; s > 0; s >>= 1) {
       if ((int)threadIdx.x < s) {
         for (int c = 0; c < 5; ++c)
           red[c][threadIdx.x] = fmax(red[c][threadIdx.x], red[c][threadIdx.x + s]);
-        for (int c = 5; c < 9; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+        for (int c = 5; c < NDIAG; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
       }
       __syncthreads();
     }
     if (threadIdx.x == 0) {
       const double vol = h * h * h;
-      for (int c = 0; c < 5; ++c) part[ib * 9 + c] = red[c][0];
-      for (int c = 5; c < 8; ++c) part[ib * 9 + c] = p.mask ? red[c][0] * vol / p.c_eta : 0.0;
-      part[ib * 9 + 8] = 0.5 * red[8][0] * vol;
+      for (int c = 0; c < 5; ++c) part[ib * NDIAG + c] = red[c][0];
+      for (int c = 5; c < 8; ++c)
+        part[ib * NDIAG + c] = p.mask ? red[c][0] * vol / p.c_eta : 0.0;
+      part[ib * NDIAG + 8] = 0.5 * red[8][0] * vol;
+      part[ib * NDIAG + 9] = red[9][0];
     }
   }
 }
 
 __global__ __launch_bounds__(NT_GEN) void diag_finalize(const double* __restrict__ part,
                                                         int64_t nb, double* __restrict__ out) {
-  __shared__ double red[9][NT_GEN];
-  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  __shared__ double red[NDIAG][NT_GEN];
+  double acc[NDIAG] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) {
-    for (int c = 0; c < 5; ++c) acc[c] = fmax(acc[c], part[q * 9 + c]);
-    for (int c = 5; c < 9; ++c) acc[c] += part[q * 9 + c];
+    for (int c = 0; c < 5; ++c) acc[c] = fmax(acc[c], part[q * NDIAG + c]);
+    for (int c = 5; c < NDIAG; ++c) acc[c] += part[q * NDIAG + c];
   }
-  for (int c = 0; c < 9; ++c) red[c][threadIdx.x] = acc[c];
+  for (int c = 0; c < NDIAG; ++c) red[c][threadIdx.x] = acc[c];
   __syncthreads();
   for (int s = NT_GEN / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
       for (int c = 0; c < 5; ++c)
         red[c][threadIdx.x] = fmax(red[c][threadIdx.x], red[c][threadIdx.x + s]);
-      for (int c = 5; c < 9; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+      for (int c = 5; c < NDIAG; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     out[0] = sqrt(red[0][0]);
-    for (int c = 1; c < 9; ++c) out[c] = red[c][0];
+    for (int c = 1; c < NDIAG; ++c) out[c] = red[c][0];
   }
 }
 

@@ -292,8 +292,13 @@ size_t tx_bytes(int64_t n, int32_t nf, size_t es) {
   return ((size_t)nf * (size_t)(n / 2) * n * n * es + 255) / 256 * 256;
 }
 
+size_t work_bytes_of(int64_t n, int32_t nf, size_t es) {
+  const size_t ty = ((size_t)nf * (size_t)(n / 2) * (n / 2) * n * es + 255) / 256 * 256;
+  return tx_bytes(n, nf, es) + ty;
+}
+
 int mr_validate(int64_t n, int32_t nf, int32_t dtype, int32_t wavelet, int32_t nlev,
-                const void* u, const void* work) {
+                const void* u, const void* work, size_t work_size) {
   if (elem_size(dtype) == 0) return mr_fail(WACM_E_INVAL, "mr: dtype must be WACM_F32 or WACM_F64");
   if (wavelet != WACM_CDF40 && wavelet != WACM_CDF44)
     return mr_fail(WACM_E_INVAL, "mr: unknown wavelet");
@@ -305,8 +310,13 @@ int mr_validate(int64_t n, int32_t nf, int32_t dtype, int32_t wavelet, int32_t n
   if (!u) return mr_fail(WACM_E_INVAL, "mr: u is NULL");
   if ((uintptr_t)u % (2 * elem_size(dtype)) != 0)
     return mr_fail(WACM_E_INVAL, "mr: u must be aligned to two elements");
-  if (wavelet == WACM_CDF44 && nlev > 0 && !work)
-    return mr_fail(WACM_E_INVAL, "mr: CDF 4/4 needs the work buffer");
+  if (wavelet == WACM_CDF44 && nlev > 0) {
+    if (!work) return mr_fail(WACM_E_INVAL, "mr: CDF 4/4 needs the work buffer");
+    if ((uintptr_t)work % 256 != 0)
+      return mr_fail(WACM_E_INVAL, "mr: the work buffer must be 256-byte aligned");
+    if (work_size < work_bytes_of(n, nf, elem_size(dtype)))
+      return mr_fail(WACM_E_INVAL, "mr: the work buffer is smaller than wacm_mr_work_bytes()");
+  }
   return WACM_OK;
 }
 
@@ -362,8 +372,8 @@ hipError_t mr_run(int inverse, int64_t n, int32_t nf, int32_t wavelet, int32_t n
 }
 
 int mr_entry(int inverse, int64_t n, int32_t nf, int32_t dtype, int32_t wavelet, int32_t nlev,
-             void* u, void* work, void* stream) {
-  int rc = mr_validate(n, nf, dtype, wavelet, nlev, u, work);
+             void* u, void* work, size_t work_size, void* stream) {
+  int rc = mr_validate(n, nf, dtype, wavelet, nlev, u, work, work_size);
   if (rc != WACM_OK) return rc;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = dtype == WACM_F64
@@ -382,18 +392,17 @@ extern "C" {
 size_t wacm_mr_work_bytes(int64_t n, int32_t nfields, int32_t dtype) {
   const size_t es = wacm::mr::elem_size(dtype);
   if (es == 0 || n < 4 || n > 1024 || nfields < 1 || nfields > 65535) return 0;
-  const size_t ty = ((size_t)nfields * (size_t)(n / 2) * (n / 2) * n * es + 255) / 256 * 256;
-  return wacm::mr::tx_bytes(n, nfields, es) + ty;
+  return wacm::mr::work_bytes_of(n, nfields, es);
 }
 
 int wacm_mr_forward(int64_t n, int32_t nfields, int32_t dtype, int32_t wavelet, int32_t nlev,
-                    void* u, void* work, void* stream) {
-  return wacm::mr::mr_entry(0, n, nfields, dtype, wavelet, nlev, u, work, stream);
+                    void* u, void* work, size_t work_size, void* stream) {
+  return wacm::mr::mr_entry(0, n, nfields, dtype, wavelet, nlev, u, work, work_size, stream);
 }
 
 int wacm_mr_inverse(int64_t n, int32_t nfields, int32_t dtype, int32_t wavelet, int32_t nlev,
-                    void* u, void* work, void* stream) {
-  return wacm::mr::mr_entry(1, n, nfields, dtype, wavelet, nlev, u, work, stream);
+                    void* u, void* work, size_t work_size, void* stream) {
+  return wacm::mr::mr_entry(1, n, nfields, dtype, wavelet, nlev, u, work, work_size, stream);
 }
 
 }  // extern "C"

@@ -127,16 +127,33 @@ struct Profiler {
 
 // Transpose of the ghost fill as a gather: for each interior point that some
 // ghost value was read from (rows, element offset of field 0), the ghosts that
-// read it with their weights; plus the list of ghost points to clear.
+// read it with their weights; plus the list of ghost points to clear.  Built
+// on the host (h_*), then copied into a device buffer the caller owns (d_*
+// point into it; `built` once uploaded).
 struct AdjPlan {
   int built = 0;
   int64_t nrows = 0, nnz = 0, nghost = 0;
+  std::vector<int64_t> h_dst, h_ptr, h_src, h_ghost;
+  std::vector<double> h_w;
   int64_t* d_dst = nullptr;
   int64_t* d_ptr = nullptr;
   int64_t* d_src = nullptr;
   double* d_w = nullptr;
   int64_t* d_ghost = nullptr;
 };
+
+// Device tables of a grid inside the caller's workspace (wacm_workspace_bytes),
+// byte offsets of 256-byte aligned parts sized for `capacity` blocks.
+struct WsParts {
+  size_t tab, part, norm, queue, list, cface, cregion, total;
+};
+WsParts ws_parts(int64_t capacity);
+// CDF 4/4 buffers (wacm_wavelet_workspace_bytes): the lifted ghost items
+// (at most 56 of 12 int32 per block) and their staging values (at most the
+// whole ghost shell, 4 fields per point)
+constexpr int LIFT_ITEMS_PER_BLOCK = 56;
+size_t lift_items_bytes(int64_t capacity);
+size_t lift_ws_bytes(int64_t capacity, int bs, int ng, size_t es);
 
 }  // namespace wacm
 
@@ -148,7 +165,9 @@ struct wacm_grid {
   std::vector<int32_t> slots;          // pool slot of each active block
   wacm::LeafIndex index;               // leaf key -> active index
   std::vector<int32_t> free_slots;     // unused pool slots (stack)
-  // device tables, sized for `capacity` blocks
+  mutable std::string last_err;  // text of the last failed call on this grid
+  // device tables, sized for `capacity` blocks, inside the caller's workspace
+  void* ws = nullptr;
   wacm::Tab* d_tab = nullptr;
   double* d_part = nullptr;      // reduction partials: capacity * 16 doubles
   int32_t* d_queue = nullptr;    // work counters (schedule xcd_map 2): stage kernel, face halo
@@ -165,7 +184,8 @@ struct wacm_grid {
   wacm::AdjPlan plan[2];         // ghost-fill transposes: all layers / face star
   // restriction wavelet: 0 CDF 4/0 (decimation), 1 CDF 4/4 (lifted); with
   // CDF 4/4, the work items of the lifted ghost phase (12 int32 each) and
-  // their staging buffer (4 fields per output point)
+  // their staging buffer (4 fields per output point), both in the caller's
+  // wavelet workspace
   int wavelet = 0;
   int32_t* d_lift = nullptr;
   int64_t n_lift = 0;
@@ -231,7 +251,9 @@ hipError_t launch_decimate(const wacm_grid* g, void* U, int64_t n, hipStream_t s
 size_t work_bytes(const wacm_grid* g);
 // adjoint (adjoint.hip)
 size_t adj_work_bytes(const wacm_grid* g);
-int build_adj_plan(wacm_grid* g, int face_only, std::string& err);
+int build_adj_plan(wacm_grid* g, int face_only, std::string& err);  // host part
+size_t adj_plan_bytes(const AdjPlan& p);
+int upload_adj_plan(wacm_grid* g, int face_only, void* ws, size_t bytes, std::string& err);
 void free_adj_plans(wacm_grid* g);
 hipError_t launch_sync_adj(const wacm_grid* g, void* Ub, int face_only, hipStream_t st);
 hipError_t launch_rhs_adj(const wacm_grid* g, const wacm_params* p, double t, const void* U,

@@ -31,7 +31,8 @@ EXPORTS = ["wacm_last_error", "wacm_treecode_encode", "wacm_treecode_decode", "w
            "wacm_profile_enable", "wacm_profile_read", "wacm_adj_work_bytes", "wacm_sync_ghosts_adj",
            "wacm_rhs_acm_adj", "wacm_force_adj", "wacm_rk4_step_adj", "wacm_set_schedule",
            "wacm_get_schedule", "wacm_set_wavelet", "wacm_get_wavelet", "wacm_mr_work_bytes",
-           "wacm_mr_forward", "wacm_mr_inverse"]
+           "wacm_mr_forward", "wacm_mr_inverse", "wacm_workspace_bytes",
+           "wacm_wavelet_workspace_bytes", "wacm_adj_plan_bytes", "wacm_adj_plan_set"]
 
 
 class GridDesc(C.Structure):
@@ -96,12 +97,15 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
         L.wacm_last_error.restype = C.c_char_p
-        L.wacm_last_error.argtypes = []
+        L.wacm_last_error.argtypes = [vp]
         L.wacm_treecode_encode.restype = C.c_uint64
         L.wacm_treecode_encode.argtypes = [i32, i64, i64, i64]
         L.wacm_treecode_decode.restype = None
         L.wacm_treecode_decode.argtypes = [C.c_uint64, i32, vp, vp, vp]
-        L.wacm_grid_create.argtypes = [C.POINTER(GridDesc), i64, vp, vp, C.POINTER(vp)]
+        L.wacm_workspace_bytes.restype = C.c_size_t
+        L.wacm_workspace_bytes.argtypes = [C.POINTER(GridDesc)]
+        L.wacm_grid_create.argtypes = [C.POINTER(GridDesc), i64, vp, vp, vp, C.c_size_t,
+                                       C.POINTER(vp)]
         L.wacm_grid_destroy.argtypes = [vp]
         L.wacm_grid_nb.restype = i64
         L.wacm_grid_nb.argtypes = [vp]
@@ -117,15 +121,20 @@ def lib():
         L.wacm_threshold_blocks.argtypes = [vp, C.POINTER(Params), dbl, vp, dbl, i32, vp, vp, vp,
                                             vp]
         L.wacm_filter_blocks.argtypes = [vp, vp, i32, vp]
-        L.wacm_set_wavelet.argtypes = [vp, i32]
+        L.wacm_wavelet_workspace_bytes.restype = C.c_size_t
+        L.wacm_wavelet_workspace_bytes.argtypes = [vp, i32]
+        L.wacm_set_wavelet.argtypes = [vp, i32, vp, C.c_size_t]
         L.wacm_mr_work_bytes.restype = C.c_size_t
         L.wacm_mr_work_bytes.argtypes = [i64, i32, i32]
-        L.wacm_mr_forward.argtypes = [i64, i32, i32, i32, i32, vp, vp, vp]
-        L.wacm_mr_inverse.argtypes = [i64, i32, i32, i32, i32, vp, vp, vp]
+        L.wacm_mr_forward.argtypes = [i64, i32, i32, i32, i32, vp, vp, C.c_size_t, vp]
+        L.wacm_mr_inverse.argtypes = [i64, i32, i32, i32, i32, vp, vp, C.c_size_t, vp]
         L.wacm_get_wavelet.argtypes = [vp]
         L.wacm_adapt.argtypes = [vp, i32, vp, vp, vp, vp]
         L.wacm_adj_work_bytes.restype = C.c_size_t
         L.wacm_adj_work_bytes.argtypes = [vp]
+        L.wacm_adj_plan_bytes.restype = C.c_size_t
+        L.wacm_adj_plan_bytes.argtypes = [vp, i32]
+        L.wacm_adj_plan_set.argtypes = [vp, i32, vp, C.c_size_t]
         L.wacm_sync_ghosts_adj.argtypes = [vp, vp, vp]
         L.wacm_rhs_acm_adj.argtypes = [vp, C.POINTER(Params), dbl, vp, vp, vp, vp, vp, vp, vp]
         L.wacm_force_adj.argtypes = [vp, C.POINTER(Params), dbl, dbl, vp, vp, vp, vp, vp, vp]
@@ -139,9 +148,21 @@ def lib():
     return _lib
 
 
-def _check(rc: int):
+def _check(rc: int, handle=None):
+    """Raise WacmError for a failed call; the text is the grid's last error
+    (handle given) or the calling thread's."""
     if rc != OK:
-        raise WacmError(rc, lib().wacm_last_error().decode())
+        raise WacmError(rc, lib().wacm_last_error(handle).decode())
+
+
+def _device_buffer(nbytes: int, device="cuda"):
+    """A caller-owned device buffer (uint8 torch tensor, 256-byte aligned by
+    torch's allocator) for one of the library's workspaces."""
+    import torch
+    t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    if t.data_ptr() % 256:
+        raise RuntimeError("device buffer is not 256-byte aligned")
+    return t
 
 
 def treecode_encode(level, ix, iy, iz) -> int:
@@ -188,18 +209,39 @@ def mr_work(u):
     return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=u.device)
 
 
+def _mr_work_arg(u, work):
+    """(pointer, size) of the work buffer; a buffer that is given must be a
+    contiguous CUDA tensor on u's device, 256-byte aligned, with at least
+    wacm_mr_work_bytes() bytes (the C call checks the size and alignment
+    again)."""
+    if work is None:
+        return None, 0
+    n, nf, dt = _mr_args(u)
+    need = int(lib().wacm_mr_work_bytes(n, nf, dt))
+    size = work.numel() * work.element_size()
+    if not work.is_cuda or work.device != u.device or not work.is_contiguous():
+        raise ValueError("mr transform: work must be a contiguous CUDA tensor on u's device")
+    if work.data_ptr() % 256 != 0:
+        raise ValueError("mr transform: work must be 256-byte aligned")
+    if size < need:
+        raise ValueError(f"mr transform: work has {size} bytes, {need} needed")
+    return _ptr(work), size
+
+
 def mr_forward(u, nlev: int, wavelet: int = CDF40, work=None, stream=None):
     """Multiresolution transform of the periodic fields u ([nf, n, n, n] or
     [n, n, n], contiguous, cuda), in place."""
     n, nf, dt = _mr_args(u)
-    _check(lib().wacm_mr_forward(n, nf, dt, int(wavelet), int(nlev), _ptr(u), _ptr(work),
+    wp, ws = _mr_work_arg(u, work)
+    _check(lib().wacm_mr_forward(n, nf, dt, int(wavelet), int(nlev), _ptr(u), wp, ws,
                                  _stream(stream)))
 
 
 def mr_inverse(u, nlev: int, wavelet: int = CDF40, work=None, stream=None):
     """Inverse of :func:`mr_forward`, in place."""
     n, nf, dt = _mr_args(u)
-    _check(lib().wacm_mr_inverse(n, nf, dt, int(wavelet), int(nlev), _ptr(u), _ptr(work),
+    wp, ws = _mr_work_arg(u, work)
+    _check(lib().wacm_mr_inverse(n, nf, dt, int(wavelet), int(nlev), _ptr(u), wp, ws,
                                  _stream(stream)))
 
 
@@ -212,10 +254,19 @@ class Grid:
         n = len(treecodes)
         self.desc = GridDesc(int(bs), int(ng), int(jmin), int(jmax), int(dtype), 0,
                              int(capacity if capacity is not None else n), float(L))
+        self._h = None
+        nbytes = int(lib().wacm_workspace_bytes(C.byref(self.desc)))
+        if nbytes == 0:
+            _check(E_INVAL)
+        # the grid's tables live in this caller-owned buffer until close()
+        self._ws = _device_buffer(nbytes)
+        self._wav_ws = None
+        self._plan_ws = {0: None, 1: None}
         h = C.c_void_p()
-        _check(lib().wacm_grid_create(C.byref(self.desc), n,
+        self._call(lib().wacm_grid_create(C.byref(self.desc), n,
                                       treecodes.ctypes.data_as(C.c_void_p),
-                                      levels.ctypes.data_as(C.c_void_p), C.byref(h)))
+                                      levels.ctypes.data_as(C.c_void_p), _ptr(self._ws), nbytes,
+                                      C.byref(h)))
         self._h = h
         self.bs, self.ng, self.L, self.jmin, self.jmax = int(bs), int(ng), float(L), jmin, jmax
         self.P = self.bs + 2 * self.ng
@@ -233,6 +284,15 @@ class Grid:
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().wacm_grid_destroy(self._h)
             self._h = None
+        # the workspaces may go only after the handle that points into them
+        self._ws = self._wav_ws = None
+        self._plan_ws = {0: None, 1: None}
+
+    def last_error(self) -> str:
+        return lib().wacm_last_error(self._h).decode()
+
+    def _call(self, rc: int):
+        _check(rc, self._h)
 
     def __del__(self):
         try:
@@ -249,7 +309,7 @@ class Grid:
         slots = np.zeros(nb, np.int64)
         codes = np.zeros(nb, np.uint64)
         levels = np.zeros(nb, np.int8)
-        _check(lib().wacm_grid_info(self._h, slots.ctypes.data_as(C.c_void_p),
+        self._call(lib().wacm_grid_info(self._h, slots.ctypes.data_as(C.c_void_p),
                                     codes.ctypes.data_as(C.c_void_p),
                                     levels.ctypes.data_as(C.c_void_p)))
         return slots, codes, levels
@@ -294,21 +354,21 @@ class Grid:
     # ---- entry points (same names as the C ABI) ----------------------------------
     def sync_ghosts(self, U, stream=None):
         self._chk_pool(U)
-        _check(lib().wacm_sync_ghosts(self._h, _ptr(U), _stream(stream)))
+        self._call(lib().wacm_sync_ghosts(self._h, _ptr(U), _stream(stream)))
 
     def rhs_acm(self, params: dict, t: float, U, dU, dus=None, stream=None):
         self._chk_pool(U)
         self._chk_pool(dU)
         self._chk_dus(dus)
         p = make_params(params)
-        _check(lib().wacm_rhs_acm(self._h, C.byref(p), float(t), _ptr(U), _ptr(dU), _ptr(dus),
+        self._call(lib().wacm_rhs_acm(self._h, C.byref(p), float(t), _ptr(U), _ptr(dU), _ptr(dus),
                                   _stream(stream)))
 
     def compute_dt(self, params: dict, U, dt_dev, stream=None):
         self._chk_pool(U)
         self._chk_vec(dt_dev, 1, "f64", "dt_dev")
         p = make_params(params)
-        _check(lib().wacm_compute_dt(self._h, C.byref(p), _ptr(U), _ptr(dt_dev), _stream(stream)))
+        self._call(lib().wacm_compute_dt(self._h, C.byref(p), _ptr(U), _ptr(dt_dev), _stream(stream)))
 
     def rk4_step(self, params: dict, t_dev, dt_dev, U, work, dus=None, dt_mode=DT_CFL,
                  stream=None, _p=None):
@@ -319,7 +379,7 @@ class Grid:
         if not work.is_cuda or work.numel() * work.element_size() < self.work_bytes():
             raise ValueError("work buffer too small")
         p = _p if _p is not None else make_params(params)
-        _check(lib().wacm_rk4_step(self._h, C.byref(p), _ptr(t_dev), _ptr(dt_dev), _ptr(U),
+        self._call(lib().wacm_rk4_step(self._h, C.byref(p), _ptr(t_dev), _ptr(dt_dev), _ptr(U),
                                    _ptr(work), _ptr(dus), int(dt_mode), _stream(stream)))
 
     def rk4_steps(self, params: dict, t_dev, dt_dev, U, work, nsteps: int, dus=None,
@@ -331,17 +391,17 @@ class Grid:
         if not work.is_cuda or work.numel() * work.element_size() < self.work_bytes():
             raise ValueError("work buffer too small")
         p = _p if _p is not None else make_params(params)
-        _check(lib().wacm_rk4_steps(self._h, C.byref(p), _ptr(t_dev), _ptr(dt_dev), _ptr(U),
+        self._call(lib().wacm_rk4_steps(self._h, C.byref(p), _ptr(t_dev), _ptr(dt_dev), _ptr(U),
                                     _ptr(work), _ptr(dus), int(dt_mode), int(nsteps),
                                     _stream(stream)))
 
     def diagnostics(self, params: dict, t: float, U, out, dus=None, stream=None):
         self._chk_pool(U)
         self._chk_dus(dus)
-        self._chk_vec(out, 9, "f64", "out")
+        self._chk_vec(out, 10, "f64", "out")
         p = make_params(params)
-        _check(lib().wacm_diagnostics(self._h, C.byref(p), float(t), _ptr(U), _ptr(dus), _ptr(out),
-                                      _stream(stream)))
+        self._call(lib().wacm_diagnostics(self._h, C.byref(p), float(t), _ptr(U), _ptr(dus),
+                                          _ptr(out), _stream(stream)))
 
     def threshold_blocks(self, params: dict, t: float, U, eps: float, dealias: bool, dmax,
                          mrange, flags, stream=None):
@@ -351,13 +411,17 @@ class Grid:
         self._chk_vec(mrange, nb, "f64", "mrange")
         self._chk_vec(flags, nb, "i8", "flags")
         p = make_params(params)
-        _check(lib().wacm_threshold_blocks(self._h, C.byref(p), float(t), _ptr(U), float(eps),
+        self._call(lib().wacm_threshold_blocks(self._h, C.byref(p), float(t), _ptr(U), float(eps),
                                            int(bool(dealias)), _ptr(dmax), _ptr(mrange),
                                            _ptr(flags), _stream(stream)))
 
     def set_wavelet(self, wavelet: int):
-        """CDF40 (restriction = decimation) or CDF44 (lifted, needs ng >= 6)."""
-        _check(lib().wacm_set_wavelet(self._h, int(wavelet)))
+        """CDF40 (restriction = decimation) or CDF44 (lifted, needs ng >= 6;
+        its ghost-phase buffers are allocated here, sized for the capacity)."""
+        nbytes = int(lib().wacm_wavelet_workspace_bytes(self._h, int(wavelet)))
+        ws = _device_buffer(nbytes) if nbytes else None
+        self._call(lib().wacm_set_wavelet(self._h, int(wavelet), _ptr(ws), nbytes))
+        self._wav_ws = ws
 
     def get_wavelet(self) -> int:
         return int(lib().wacm_get_wavelet(self._h))
@@ -366,7 +430,7 @@ class Grid:
         """Remove the details of the blocks of `level` (all if < 0) in place;
         U ghost-synced."""
         self._chk_pool(U)
-        _check(lib().wacm_filter_blocks(self._h, _ptr(U), int(level), _stream(stream)))
+        self._call(lib().wacm_filter_blocks(self._h, _ptr(U), int(level), _stream(stream)))
 
     def adapt(self, op: int, U, flags=None, stream=None) -> int:
         self._chk_pool(U)
@@ -377,29 +441,31 @@ class Grid:
             if len(flags) != self.nb:
                 raise ValueError("flags must have nb entries")
             fptr = flags.ctypes.data_as(C.c_void_p)
-        _check(lib().wacm_adapt(self._h, int(op), fptr, _ptr(U), C.byref(nb), _stream(stream)))
+        self._call(lib().wacm_adapt(self._h, int(op), fptr, _ptr(U), C.byref(nb),
+                                    _stream(stream)))
+        self._plan_ws = {0: None, 1: None}  # the library dropped its plans
         return nb.value
 
     def set_schedule(self, **kw):
         s = Schedule()
-        _check(lib().wacm_get_schedule(self._h, C.byref(s)))
+        self._call(lib().wacm_get_schedule(self._h, C.byref(s)))
         for k, v in kw.items():
             setattr(s, k, int(v))
-        _check(lib().wacm_set_schedule(self._h, C.byref(s)))
+        self._call(lib().wacm_set_schedule(self._h, C.byref(s)))
 
     def get_schedule(self) -> dict:
         s = Schedule()
-        _check(lib().wacm_get_schedule(self._h, C.byref(s)))
+        self._call(lib().wacm_get_schedule(self._h, C.byref(s)))
         return s.as_dict()
 
     def profile_enable(self, on: bool = True):
-        _check(lib().wacm_profile_enable(self._h, int(bool(on))))
+        self._call(lib().wacm_profile_enable(self._h, int(bool(on))))
 
     def profile_read(self):
         """(ms[4], launches[4]) per kernel class: dt, sync, stage, time update."""
         ms = np.zeros(4)
         n = np.zeros(4, np.int64)
-        _check(lib().wacm_profile_read(self._h, ms.ctypes.data_as(C.c_void_p),
+        self._call(lib().wacm_profile_read(self._h, ms.ctypes.data_as(C.c_void_p),
                                        n.ctypes.data_as(C.c_void_p)))
         return ms, n
 
@@ -419,9 +485,24 @@ class Grid:
                 dusbar.dtype != torch.float64 or not dusbar.is_contiguous() or not dusbar.is_cuda:
             raise ValueError("dusbar must be (capacity, 3, bs^3) float64 contiguous on the GPU")
 
+    def adj_plan(self, face_only: int):
+        """Build the transpose plan of the ghost fill (0: all layers, for
+        sync_ghosts_adj; 1: the depth-3 face star, for rk4_step_adj) and copy
+        it into a buffer owned here; a no-op if it is already set."""
+        f = int(face_only)
+        if self._plan_ws[f] is not None:
+            return
+        nbytes = int(lib().wacm_adj_plan_bytes(self._h, f))
+        if nbytes == 0:
+            self._call(E_INVAL)
+        ws = _device_buffer(nbytes)
+        self._call(lib().wacm_adj_plan_set(self._h, f, _ptr(ws), nbytes))
+        self._plan_ws[f] = ws
+
     def sync_ghosts_adj(self, Ub, stream=None):
         self._chk_pool(Ub)
-        _check(lib().wacm_sync_ghosts_adj(self._h, _ptr(Ub), _stream(stream)))
+        self.adj_plan(0)
+        self._call(lib().wacm_sync_ghosts_adj(self._h, _ptr(Ub), _stream(stream)))
 
     def rhs_acm_adj(self, params: dict, t: float, U, V, Ub, dtheta, dusbar=None, dus=None,
                     stream=None):
@@ -431,7 +512,7 @@ class Grid:
         self._chk_dusbar(dusbar)
         self._chk_dus(dus)
         p = make_params(params)
-        _check(lib().wacm_rhs_acm_adj(self._h, C.byref(p), float(t), _ptr(U), _ptr(V), _ptr(Ub),
+        self._call(lib().wacm_rhs_acm_adj(self._h, C.byref(p), float(t), _ptr(U), _ptr(V), _ptr(Ub),
                                       _ptr(dtheta), _ptr(dusbar), _ptr(dus), _stream(stream)))
 
     def force_adj(self, params: dict, t: float, weight: float, U, Ub, dtheta, dusbar=None,
@@ -442,7 +523,7 @@ class Grid:
         self._chk_dusbar(dusbar)
         self._chk_dus(dus)
         p = make_params(params)
-        _check(lib().wacm_force_adj(self._h, C.byref(p), float(t), float(weight), _ptr(U),
+        self._call(lib().wacm_force_adj(self._h, C.byref(p), float(t), float(weight), _ptr(U),
                                     _ptr(Ub), _ptr(dtheta), _ptr(dusbar), _ptr(dus),
                                     _stream(stream)))
 
@@ -456,7 +537,8 @@ class Grid:
         if work is None or not work.is_cuda or \
                 work.numel() * work.element_size() < self.adj_work_bytes():
             raise ValueError("adjoint work buffer too small")
+        self.adj_plan(1)
         p = make_params(params)
-        _check(lib().wacm_rk4_step_adj(self._h, C.byref(p), float(t), float(dt), _ptr(Un),
+        self._call(lib().wacm_rk4_step_adj(self._h, C.byref(p), float(t), float(dt), _ptr(Un),
                                        _ptr(lam), _ptr(dtheta), _ptr(dusbar), _ptr(dus),
                                        _ptr(work), _stream(stream)))

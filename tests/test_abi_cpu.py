@@ -49,3 +49,107 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(wacm, "_lib", None)
     with pytest.raises(RuntimeError):
         wacm.lib()
+
+
+# ---------------------------------------------------------------- error codes
+# Every failure below is detected by the host-side validation that runs
+# before the library touches any device buffer, so the fake (aligned, never
+# dereferenced) device addresses are safe without a GPU.  None of these
+# calls has a valid full argument set.
+FAKE_DEV = 1 << 40  # 256-byte aligned, never dereferenced
+
+
+def _desc(bs=16, ng=4, jmin=1, jmax=3, dtype=wacm.F64, cap=64, L=1.0, reserved=0):
+    return wacm.GridDesc(bs, ng, jmin, jmax, dtype, reserved, cap, L)
+
+
+def _create(desc, leaves, ws=FAKE_DEV, ws_bytes=None):
+    L = wacm.lib()
+    lev = np.array([l[0] for l in leaves], np.int8)
+    codes = np.array([wacm.treecode_encode(*l) for l in leaves], np.uint64)
+    if ws_bytes is None:
+        ws_bytes = int(L.wacm_workspace_bytes(ctypes.byref(desc)))
+    h = ctypes.c_void_p()
+    rc = L.wacm_grid_create(ctypes.byref(desc), len(leaves), codes.ctypes.data_as(ctypes.c_void_p),
+                            lev.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(ws), ws_bytes,
+                            ctypes.byref(h))
+    assert not h.value  # no handle on failure
+    return rc, L.wacm_last_error(None).decode()
+
+
+def _uniform(J):
+    n = 1 << J
+    return [(J, x, y, z) for z in range(n) for y in range(n) for x in range(n)]
+
+
+def test_workspace_bytes():
+    L = wacm.lib()
+    a = int(L.wacm_workspace_bytes(ctypes.byref(_desc(cap=64))))
+    b = int(L.wacm_workspace_bytes(ctypes.byref(_desc(cap=128))))
+    assert a > 64 * 928 and b > a and a % 256 == 0 and b % 256 == 0
+    for bad in (_desc(bs=18), _desc(ng=2), _desc(dtype=3), _desc(cap=0), _desc(reserved=1),
+                _desc(jmin=4, jmax=3), _desc(L=0.0)):
+        assert L.wacm_workspace_bytes(ctypes.byref(bad)) == 0
+
+
+def test_grid_create_inval():
+    leaves = _uniform(1)
+    for desc, what in ((_desc(bs=20), "bs"), (_desc(ng=2), "ng"), (_desc(dtype=0), "dtype"),
+                       (_desc(cap=4), "capacity"), (_desc(reserved=7), "reserved")):
+        rc, msg = _create(desc, leaves)
+        assert rc == wacm.E_INVAL, (what, rc)
+        assert msg
+    d = _desc()
+    need = int(wacm.lib().wacm_workspace_bytes(ctypes.byref(d)))
+    assert _create(d, leaves, ws=0)[0] == wacm.E_INVAL                    # NULL workspace
+    assert _create(d, leaves, ws=FAKE_DEV + 64)[0] == wacm.E_INVAL        # misaligned
+    rc, msg = _create(d, leaves, ws_bytes=need - 256)                     # too small
+    assert rc == wacm.E_INVAL and "workspace" in msg
+    rc, msg = _create(d, [(4, 0, 0, 0)] + leaves[1:])                      # level above jmax
+    assert rc == wacm.E_INVAL
+
+
+def test_grid_create_tiling():
+    leaves = _uniform(1)
+    rc, msg = _create(_desc(), leaves + [leaves[3]])                       # repeated leaf
+    assert rc == wacm.E_TILING and "repeated" in msg
+    rc, msg = _create(_desc(), leaves[:-1])                                # a gap
+    assert rc == wacm.E_TILING and "cover" in msg
+    kids = [(2, 2 * 1 + (c & 1), (c >> 1) & 1, (c >> 2) & 1) for c in range(8)]
+    rc, msg = _create(_desc(), leaves + kids)                              # overlap
+    assert rc == wacm.E_TILING and "inside" in msg
+
+
+def test_grid_create_unbalanced():
+    # block (0,0,0) of level 1 split to level 2, one of those to level 3: the
+    # level-3 leaves touch level-1 leaves (a 2-level jump)
+    leaves = [l for l in _uniform(1) if l != (1, 0, 0, 0)]
+    l2 = [(2, c & 1, (c >> 1) & 1, (c >> 2) & 1) for c in range(8)]
+    l2.remove((2, 1, 1, 1))
+    l3 = [(3, 2 + (c & 1), 2 + ((c >> 1) & 1), 2 + ((c >> 2) & 1)) for c in range(8)]
+    rc, msg = _create(_desc(jmax=3, cap=64), leaves + l2 + l3)
+    assert rc == wacm.E_UNBALANCED and "balanced" in msg
+
+
+def test_mr_work_buffer_checked_before_launch():
+    L = wacm.lib()
+    n, nf = 16, 2
+    need = int(L.wacm_mr_work_bytes(n, nf, wacm.F64))
+    assert need > 0
+    u = ctypes.c_void_p(FAKE_DEV)
+    for work, size, text in ((FAKE_DEV, need - 8, "smaller"), (FAKE_DEV + 8, need, "aligned"),
+                             (0, need, "needs the work")):
+        rc = L.wacm_mr_forward(n, nf, wacm.F64, wacm.CDF44, 1, u, ctypes.c_void_p(work), size,
+                               None)
+        assert rc == wacm.E_INVAL
+        assert text in L.wacm_last_error(None).decode()
+        rc = L.wacm_mr_inverse(n, nf, wacm.F64, wacm.CDF44, 2, u, ctypes.c_void_p(work), size,
+                               None)
+        assert rc == wacm.E_INVAL
+
+
+def test_last_error_of_null_grid_is_thread_text():
+    L = wacm.lib()
+    assert L.wacm_grid_nb(None) == -1
+    assert L.wacm_sync_ghosts(None, ctypes.c_void_p(FAKE_DEV), None) == wacm.E_INVAL
+    assert "NULL" in L.wacm_last_error(None).decode()

@@ -124,6 +124,32 @@ def test_mr_guards_and_identity():
         wacm.mr_forward(odd, 1, wacm.CDF40)
 
 
+def test_mr_work_buffer_guards():
+    """The binding refuses a CDF 4/4 work buffer that is too small, on another
+    device type, or misaligned, before any launch; the field is unchanged."""
+    u = torch.from_numpy(field(32, 2, 5)).cuda()
+    v = u.clone()
+    need = int(wacm.lib().wacm_mr_work_bytes(32, 2, wacm.F64))
+    small = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        wacm.mr_forward(v, 2, wacm.CDF44, small)
+    with pytest.raises(ValueError):
+        wacm.mr_inverse(v, 2, wacm.CDF44, small)
+    with pytest.raises(ValueError):
+        wacm.mr_forward(v, 2, wacm.CDF44, torch.empty(need, dtype=torch.uint8))  # host memory
+    big = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        wacm.mr_forward(v, 2, wacm.CDF44, big[8:])  # not 256-byte aligned
+    torch.cuda.synchronize()
+    assert torch.equal(u, v)
+    # the C entry point checks the size itself too
+    rc = wacm.lib().wacm_mr_forward(32, 2, wacm.F64, wacm.CDF44, 2, wacm._ptr(v),
+                                    wacm._ptr(big), need - 1, None)
+    assert rc == wacm.E_INVAL
+    torch.cuda.synchronize()
+    assert torch.equal(u, v)
+
+
 def test_mr_maximum_size():
     """n = 1024 (the largest the entry points accept), 8 levels (coarsest
     lattice 4^3), one FP32 field: 4096 sampled finest-level details against

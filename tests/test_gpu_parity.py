@@ -223,7 +223,7 @@ def test_diagnostics_match_oracle(orc, name):
     t = 0.05
     d_o = og.diagnostics(c.params, t, U)
     pool = to_pool(gg, U)
-    out = torch.zeros(9, dtype=torch.float64, device="cuda")
+    out = torch.zeros(10, dtype=torch.float64, device="cuda")
     gg.diagnostics(c.params, t, pool, out)
     d_g = out.cpu().numpy()
     log(f"  oracle {d_o}\n  gpu    {d_g}")
@@ -231,6 +231,54 @@ def test_diagnostics_match_oracle(orc, name):
     scale = max(np.max(np.abs(d_o[5:8])), 1e-300)
     assert np.max(np.abs(d_g[5:8] - d_o[5:8])) <= 1e-12 * scale
     assert abs(d_g[8] - d_o[8]) <= 1e-12 * d_o[8]
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf"), -float("inf")])
+def test_diagnostics_report_nonfinite(bad):
+    """A NaN or Inf interior value makes wacm_diagnostics return
+    WACM_E_NONFINITE, with out[9] the number of such values; ghost values
+    are not counted."""
+    log(f"diagnostics nonfinite {bad}")
+    c = get_case("octree_bs24")
+    gg = wacm.Grid.from_case(c, dtype=wacm.F64)
+    U = c.padded()
+    pool = to_pool(gg, U)
+    out = torch.zeros(10, dtype=torch.float64, device="cuda")
+    gg.diagnostics(c.params, 0.0, pool, out)
+    assert out[9].item() == 0.0
+    ok = out.clone()
+    pool[0, 0, 0, 0, 0] = bad  # a ghost corner: not counted
+    gg.diagnostics(c.params, 0.0, pool, out)
+    assert torch.equal(out, ok)
+    ng, bs = c.ng, c.bs
+    pool[3, 2, ng + 5, ng + 1, ng + bs - 1] = bad
+    pool[7, 3, ng, ng, ng] = bad
+    with pytest.raises(wacm.WacmError) as ei:
+        gg.diagnostics(c.params, 0.0, pool, out)
+    assert ei.value.code == wacm.E_NONFINITE
+    assert "NaN or Inf" in gg.last_error()
+    assert out[9].item() == 2.0
+    # the maxima skip the non-finite values
+    assert torch.equal(out[1:3], ok[1:3])
+
+
+def test_last_error_is_per_grid():
+    log("last error per grid")
+    c = get_case("taylor_green")
+    g1 = wacm.Grid.from_case(c, dtype=wacm.F64)
+    g2 = wacm.Grid.from_case(c, dtype=wacm.F64)
+    pool = g1.pool()
+    d = torch.zeros(g1.nb, dtype=torch.float64, device="cuda")
+    f = torch.zeros(g1.nb, dtype=torch.int8, device="cuda")
+    with pytest.raises(wacm.WacmError) as ei:
+        g1.threshold_blocks(c.params, 0.0, pool, -1.0, False, d, d.clone(), f)
+    assert ei.value.code == wacm.E_INVAL
+    assert "eps" in g1.last_error()
+    assert g2.last_error() == ""
+    bad = dict(c.params, mask=1, c_eta=0.0)
+    with pytest.raises(wacm.WacmError):
+        g2.rhs_acm(bad, 0.0, pool, pool.clone())
+    assert "c_eta" in g2.last_error() and "eps" in g1.last_error()
 
 
 def test_rk4_is_deterministic():
