@@ -84,7 +84,9 @@ def run_gpu(case, dtype_code: int, steps: int, warmup: int, use_graph: bool, tun
         if os.path.exists(write_tuned):
             with open(write_tuned) as f:
                 data = json.load(f)
-        data[autotune.workload_key(g)] = {"schedule": schedule, "trials": trials}
+        best_ms = min(ms for ms, _ in trials)
+        data[autotune.workload_key(g)] = {"schedule": schedule, "ms_per_step": best_ms,
+                                          "candidates": len(trials)}
         with open(write_tuned, "w") as f:
             json.dump(data, f, indent=1, sort_keys=True)
         log(f"  tuned schedule {schedule} written to {write_tuned}")
@@ -92,7 +94,8 @@ def run_gpu(case, dtype_code: int, steps: int, warmup: int, use_graph: bool, tun
         from paper_1912_05371_amd import autotune
         schedule, trials = autotune.tune(g, case.params, pool, steps=2, use_cache=False,
                                          shipped=shipped)
-        log(f"  autotuned schedule {schedule} (best of {len(trials)})")
+        log(f"  schedule {schedule} " + (f"(best of {len(trials)} timed)" if trials else
+                                          "(the tuner's stored choice for this workload)"))
     schedule = g.get_schedule()
     g.rk4_steps(None, t_dev, dt_dev, pool, work, warmup, dt_mode=wacm.DT_CFL, _p=p)
     torch.cuda.synchronize()
@@ -291,6 +294,106 @@ def aux_timings(case):
     return out
 
 
+def c3_run(nsteps: int = 200, every: int = 10):
+    """The rotating-plate adaptive case as configured (levels 2..6, bs 16, 4
+    ghost layers, eps 1e-3 on the max-norm details, dealiasing, adapt every
+    step): FP64 runs free (its own coarsening flags, CFL time step), FP32
+    follows it in lockstep -- the same time steps and FP64's flags in every
+    merge pass (replay), its own flags computed and counted where they
+    differ.  Per step: block counts, FP32-vs-FP64 relative interior
+    difference (drift, not gated), own-flag disagreements.  Host wall time
+    per phase of the FP64 run."""
+    import torch
+
+    from paper_1912_05371_amd import cases, wacm
+
+    c = cases.plate_adaptive()
+    eps, dealias = c.extra["eps"], c.extra["dealias"]
+    cap = 40000  # refine-all of the largest grid of the run must fit
+    grids = {k: wacm.Grid.from_case(c, dtype=d, capacity=cap)
+             for k, d in (("f64", wacm.F64), ("f32", wacm.F32))}
+    pools, works = {}, {}
+    for k, g in grids.items():
+        pools[k] = g.pool()
+        pools[k][:c.nb] = torch.from_numpy(c.padded()).to("cuda", g.torch_dtype())
+        works[k] = None
+    t64 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt64 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t32 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt32 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    I = slice(c.ng, c.ng + c.bs)
+    recs, phases = [], {}
+
+    def timed(name, fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        phases[name] = phases.get(name, 0.0) + (time.perf_counter() - t0) * 1e3
+        return r
+
+    def flags_of(k, t):
+        g, U = grids[k], pools[k]
+        n = g.nb
+        dm = torch.empty(n, dtype=torch.float64, device="cuda")
+        mr = torch.empty(n, dtype=torch.float64, device="cuda")
+        fl = torch.empty(n, dtype=torch.int8, device="cuda")
+        g.sync_ghosts(U)
+        g.threshold_blocks(c.params, t, U, eps, dealias, dm, mr, fl)
+        return fl.cpu().numpy()
+
+    wall0 = time.perf_counter()
+    for step in range(nsteps):
+        nb0 = grids["f64"].nb
+        for k in grids:
+            n = (timed if k == "f64" else (lambda _n, f: f()))(
+                "refine_all", lambda: grids[k].adapt(wacm.REFINE_ALL, pools[k]))
+            if works[k] is None or works[k].numel() < grids[k].work_bytes():
+                works[k] = grids[k].work()
+        nref = grids["f64"].nb
+        timed("rk4_step", lambda: grids["f64"].rk4_step(c.params, t64, dt64, pools["f64"],
+                                                        works["f64"], dt_mode=wacm.DT_CFL))
+        dt32.copy_(dt64)
+        grids["f32"].rk4_step(c.params, t32, dt32, pools["f32"], works["f32"],
+                              dt_mode=wacm.DT_FIXED)
+        t = float(t64.item())
+        disagree, passes = 0, 0
+        while True:
+            a, b = grids["f64"].info(), grids["f32"].info()
+            assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+            f64 = timed("sync_threshold", lambda: flags_of("f64", t))
+            f32 = flags_of("f32", t)
+            disagree += int(np.sum(f64 != f32))
+            n = grids["f64"].nb
+            if timed("coarsen", lambda: grids["f64"].adapt(wacm.COARSEN, pools["f64"], f64)) == n:
+                grids["f32"].adapt(wacm.COARSEN, pools["f32"], f64)
+                break
+            grids["f32"].adapt(wacm.COARSEN, pools["f32"], f64)
+            passes += 1
+        s64 = torch.as_tensor(grids["f64"].info()[0], device="cuda")
+        s32 = torch.as_tensor(grids["f32"].info()[0], device="cuda")
+        A = pools["f64"][:, :, I, I, I].index_select(0, s64)
+        B = pools["f32"][:, :, I, I, I].index_select(0, s32).double()
+        drift = float((A - B).abs().max() / A.abs().max())
+        recs.append({"step": step, "t": t, "dt": float(dt64.item()), "blocks": [nb0, nref,
+                     grids["f64"].nb], "merge_passes": passes, "drift": drift,
+                     "flag_disagreements": disagree})
+        if step % every == 0 or step == nsteps - 1:
+            log(f"  C3 step {step}: t {t:.5f} blocks {nb0}->{nref}->{grids['f64'].nb} "
+                f"passes {passes} drift {drift:.2e} flag disagreements {disagree}")
+    wall = time.perf_counter() - wall0
+    nbs = [r["blocks"][2] for r in recs]
+    return {"case": "rotating plate, levels 2-6, bs 16, ng 4, eps 1e-3, dealiasing",
+            "steps": nsteps, "t_end": float(t64.item()), "wall_s": round(wall, 2),
+            "blocks_min_max": [min(nbs), max(nbs)],
+            "refined_max": max(r["blocks"][1] for r in recs),
+            "drift_max": max(r["drift"] for r in recs), "drift_end": recs[-1]["drift"],
+            "flag_disagreements_total": sum(r["flag_disagreements"] for r in recs),
+            "steps_with_disagreements": sum(1 for r in recs if r["flag_disagreements"]),
+            "f64_ms_per_step_by_phase": {k: round(v / nsteps, 3) for k, v in phases.items()},
+            "records": recs}
+
+
 def lifting_timings(seed: int):
     """CDF 4/4 (lifted restriction) on a random octree with 6 ghost layers
     (bs 24, levels 3-6, ~4000 blocks, FP64): the full ghost sync with CDF 4/0
@@ -462,6 +565,9 @@ def main():
     ap.add_argument("--aux-only", action="store_true",
                     help="time only the other calls (the aux block) on the benchmark grid and "
                          "print them")
+    ap.add_argument("--c3-run", type=int, default=0, metavar="STEPS",
+                    help="run the adaptive rotating-plate case for STEPS steps (FP64 free, "
+                         "FP32 replaying its flags) and print drift and flag disagreements")
     ap.add_argument("--mr-only", action="store_true",
                     help="time only the multiresolution transform (256^3 x 4, 5 levels) and "
                          "print its figures")
@@ -477,6 +583,9 @@ def main():
     from paper_1912_05371_amd import wacm
 
     wacm.lib()
+    if args.c3_run:
+        print(json.dumps({"c3_run": c3_run(args.c3_run)}), flush=True)
+        return
     if args.mr_only:
         if args.copy_probe > 0:
             copy_probe(args.copy_probe)

@@ -275,3 +275,84 @@ def test_adaptive_driver_matches_oracle(orc):
         assert merged == len(passes)
         assert e < 1e-12
         assert abs(float(t_dev.item()) - t) <= 1e-12 * t
+
+
+@pytest.fixture(scope="module")
+def c3_oracle_steps(orc):
+    """The rotating plate as configured (levels 2..6, bs 16, eps 1e-3,
+    dealiasing; start grid refined to level 5 around the plate): two adaptive
+    steps of the oracle, with their coarsening passes."""
+    c = cases.plate_adaptive()
+    assert (c.jmin, c.jmax) == (2, 6)
+    eps, dealias = c.extra["eps"], c.extra["dealias"]
+    og = orc.Grid(c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix, c.iy, c.iz)
+    U = c.padded()
+    steps, t = [], 0.0
+    for _ in range(2):
+        og_n, U_n, dt, passes = adaptive_step_oracle(og, U.copy(), c.params, t, eps, dealias)
+        steps.append((og, U, t, og_n, U_n, dt, passes))
+        og, U, t = og_n, U_n, t + dt
+    return c, steps
+
+
+def test_plate_c3_driver_matches_oracle(c3_oracle_steps):
+    """adaptive.adaptive_step on the configured rotating-plate case (its own
+    FP64 flags) against the oracle's first two adaptive steps: the same leaves
+    after every step, the state to 1e-12 and the same time."""
+    from paper_1912_05371_amd.adaptive import adaptive_step
+    c, steps = c3_oracle_steps
+    eps, dealias = c.extra["eps"], c.extra["dealias"]
+    og0 = steps[0][0]
+    gg = wacm.Grid.from_case(c, dtype=wacm.F64, capacity=10 * c.nb + 64)
+    pool = put(gg, og0, steps[0][1])
+    work = gg.work()
+    t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for k, (og, U, t, og_n, U_n, dt, passes) in enumerate(steps):
+        r = adaptive_step(gg, c.params, pool, work, t_dev, dt_dev, eps, dealias)
+        assert same_leaves(gg, og_n)
+        e = rel_err(from_pool(pool, slot_map(gg, og_n)), U_n, c.bs, c.ng)
+        log(f"  C3 step {k}: {og.nb} -> {r['refined']} -> {og_n.nb} blocks, "
+            f"{r['merged_passes']} merging passes (oracle {len(passes)}), rel err {e:.2e}, "
+            f"dt {float(dt_dev.item()):.6e} vs {dt:.6e}")
+        assert r["merged_passes"] == len(passes)
+        assert e < 1e-12
+        assert abs(float(t_dev.item()) - (t + dt)) <= 1e-12 * (t + dt)
+
+
+def test_plate_c3_fp32_replay_matches_oracle(c3_oracle_steps):
+    """FP32 on the configured rotating-plate case, each step from the oracle's
+    state rounded to FP32 and following the oracle's flags: 1e-5 relative."""
+    c, steps = c3_oracle_steps
+    eps, dealias = c.extra["eps"], c.extra["dealias"]
+    for k, (og, U, t, og_n, U_n, dt, passes) in enumerate(steps):
+        codes = [wacm.treecode_encode(l, x, y, z) for l, x, y, z in
+                 zip(og.lev, og.ix, og.iy, og.iz)]
+        gg = wacm.Grid(c.bs, c.ng, c.L, c.jmin, c.jmax, codes, og.lev, wacm.F32,
+                       capacity=10 * og.nb + 64)
+        pool = put(gg, og, U.astype(np.float32).astype(np.float64))
+        gg.adapt(wacm.REFINE_ALL, pool)
+        work = gg.work()
+        t_dev = torch.tensor([t], dtype=torch.float64, device="cuda")
+        dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
+        gg.rk4_step(c.params, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_FIXED)
+        disagree = 0
+        for g_o, fl_o in passes:
+            assert same_leaves(gg, g_o)
+            gg.sync_ghosts(pool)
+            nb = gg.nb
+            dmax = torch.zeros(nb, dtype=torch.float64, device="cuda")
+            mr = torch.zeros(nb, dtype=torch.float64, device="cuda")
+            fl = torch.zeros(nb, dtype=torch.int8, device="cuda")
+            gg.threshold_blocks(c.params, t + dt, pool, eps, dealias, dmax, mr, fl)
+            ai = active_index(gg, g_o)
+            disagree += int(np.sum(fl.cpu().numpy()[ai] != fl_o))
+            flags_g = np.zeros(nb, np.int8)
+            flags_g[ai] = fl_o
+            gg.adapt(wacm.COARSEN, pool, flags_g)
+        assert same_leaves(gg, og_n)
+        e = rel_err(from_pool(pool, slot_map(gg, og_n)), U_n, c.bs, c.ng)
+        log(f"  C3 FP32 step {k}: rel err {e:.2e}, own-flag disagreements {disagree}")
+        assert e < 1e-5
+        del gg, pool, work
+        torch.cuda.empty_cache()

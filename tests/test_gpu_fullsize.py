@@ -13,20 +13,39 @@ at this size, so these checks use properties that hold at any size:
 - n steps in one call = n single-step calls, bitwise;
 - every stage-kernel schedule gives the same state, bitwise;
 - the FP32 path against the FP64 one after one step: 1e-5 relative.
+
+Each runs the schedules bench.py times: the ones shipped for this workload
+in tuned_schedules.json (FP64 and FP32).  A C4-shaped octree small enough
+for the oracle (3011 blocks of 24^3, levels 3-7 with uneven counts) is
+compared with the oracle directly under those schedules.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
-from paper_1912_05371_amd import cases, inputs, wacm
+from paper_1912_05371_amd import autotune, cases, inputs, wacm
 
-from gpu_util import log
+from gpu_util import log, rel_err, to_pool
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
 SEED = 12345
-BENCH_SCHEDULE = dict(tile_rows=8, wg_per_cu=2, xcd_map=0, prefetch=1, nontemporal=1)
+OTHER_SCHEDULE = dict(tile_rows=8, wg_per_cu=2, xcd_map=0, prefetch=1, nontemporal=1)
+
+
+def shipped(dtype_name):
+    """The schedule shipped for the benchmark workload (the one bench.py's
+    tuner loads), matched on everything but the device name."""
+    with open(autotune.SHIPPED) as f:
+        data = json.load(f)
+    tail = f"|{dtype_name}|bs24|ng4|nb20028|"
+    hits = [v["schedule"] for k, v in data.items() if tail in k]
+    assert len(hits) == 1, f"no shipped {dtype_name} schedule for the benchmark workload"
+    return dict(hits[0])
 
 
 @pytest.fixture(scope="module")
@@ -63,7 +82,9 @@ def scalars():
 def test_fullsize_fast_path_matches_assembled_rk4(full):
     c = full
     g = wacm.Grid.from_case(c, dtype=wacm.F64)
-    g.set_schedule(**BENCH_SCHEDULE)
+    sched = shipped("f64")
+    g.set_schedule(**sched)
+    assert g.get_schedule() == sched
     U0 = filled(g, c)
     A = U0.clone()
     work = g.work()
@@ -112,12 +133,12 @@ def test_fullsize_multi_step_call_and_schedules_bitwise(full):
     g = wacm.Grid.from_case(c, dtype=wacm.F64)
     U0 = filled(g, c)
     work = g.work()
-    g.set_schedule(**BENCH_SCHEDULE)
+    g.set_schedule(**shipped("f64"))
     A = U0.clone()
     t, dt = scalars()
     g.rk4_steps(c.params, t, dt, A, work, 2, dt_mode=wacm.DT_CFL)
-    for sched in (dict(BENCH_SCHEDULE), dict(tile_rows=0, wg_per_cu=0, xcd_map=1, prefetch=0,
-                                              nontemporal=0),
+    for sched in (shipped("f64"), shipped("f32"), dict(OTHER_SCHEDULE),
+                  dict(tile_rows=0, wg_per_cu=0, xcd_map=1, prefetch=0, nontemporal=0),
                   dict(tile_rows=8, wg_per_cu=0, xcd_map=2, prefetch=0, nontemporal=1)):
         g.set_schedule(**sched)
         B = U0.clone()
@@ -135,6 +156,8 @@ def test_fullsize_fp32_against_fp64(full):
     c = full
     g64 = wacm.Grid.from_case(c, dtype=wacm.F64)
     g32 = wacm.Grid.from_case(c, dtype=wacm.F32)
+    g64.set_schedule(**shipped("f64"))
+    g32.set_schedule(**shipped("f32"))
     U64 = filled(g64, c)
     U32 = U64.float()
     w64 = g64.work()
@@ -151,3 +174,36 @@ def test_fullsize_fp32_against_fp64(full):
     log(f"  one step FP32 vs FP64: rel err {e:.2e}; dt {dt3.item():.9e} vs {dt.item():.9e}")
     assert e < 1e-5
     assert abs(dt3.item() - dt.item()) <= 1e-6 * dt.item()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_c4_shaped_octree_matches_oracle(orc, prec):
+    """3011 blocks of 24^3 (levels 3..7: 295, 1631, 809, 244, 32), the
+    benchmark's field recipe, one CFL step with the shipped schedule of the
+    precision, against the oracle's step from the same input: 1e-12 (FP64)
+    or 1e-5 (FP32, input rounded to FP32) relative over interiors, and the
+    same time step."""
+    c = cases.random_octree(bs=24, ng=4, target=3000, j0=3, jmax=7, seed=7)
+    levels = np.bincount(c.lev, minlength=8)[3:8].tolist()
+    log(f"c4-shaped octree {prec}: {c.nb} blocks, levels 3..7 {levels}")
+    assert c.nb == 3011 and min(levels) > 0
+    og = orc.Grid(c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix, c.iy, c.iz)
+    U = c.padded()
+    if prec == "f32":
+        U = U.astype(np.float32).astype(np.float64)
+    dto = og.dt(c.params, U)
+    Uo = U.copy()
+    og.rk4_step(c.params, 0.0, dto, Uo)
+    g = wacm.Grid.from_case(c, dtype=wacm.F64 if prec == "f64" else wacm.F32)
+    g.set_schedule(**shipped(prec))
+    pool = to_pool(g, U)
+    work = g.work()
+    t, dt = scalars()
+    g.rk4_steps(c.params, t, dt, pool, work, 1, dt_mode=wacm.DT_CFL)
+    torch.cuda.synchronize()
+    Ug = pool[:c.nb].double().cpu().numpy()
+    e = rel_err(Ug, Uo, c.bs, c.ng)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    log(f"  one step vs oracle: rel err {e:.2e} (tol {tol:g}); dt {dt.item():.9e} vs {dto:.9e}")
+    assert e < tol
+    assert abs(dt.item() - dto) <= (1e-14 if prec == "f64" else 1e-6) * dto
