@@ -358,6 +358,28 @@ int wacm_mr_inverse(int64_t n, int32_t nfields, int32_t dtype, int32_t wavelet, 
                     void* u, void* work, size_t work_size, void* stream);
 
 /*
+ * wacm_mr_forward_noalloc -- wacm_mr_forward for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and results, with the
+ * CDF 4/4 work buffer taken from a static device array of
+ * WACM_MR_SCRATCH_BYTES bytes that the library holds on each GPU it runs on
+ * until the process ends, instead of a `work` argument.  The caller still
+ * passes u (on the current device).  No allocation of any kind.  Sizes whose
+ * wacm_mr_work_bytes() exceeds WACM_MR_SCRATCH_BYTES are rejected with
+ * WACM_E_INVAL when the wavelet is CDF 4/4 and nlev > 0 (e.g. FP64 allows
+ * n = 128 with 4 fields; FP32 n = 256 with 1 field); other arguments as for
+ * wacm_mr_forward.  Every call on one GPU shares that GPU's array: calls
+ * that overlap in time on one GPU (different streams, or other threads)
+ * race on it and must be ordered by the caller.  Each call writes every work
+ * value it reads, so nothing carried over from an earlier call is used.
+ * The first call on a device looks up the array's address there
+ * (hipGetSymbolAddress), synchronously.
+ */
+#define WACM_MR_SCRATCH_BYTES (64 << 20)
+int wacm_mr_forward_noalloc(int64_t n, int32_t nfields, int32_t dtype, int32_t wavelet,
+                            int32_t nlev, void* u, void* stream);
+
+/*
  * wacm_adapt -- change the grid (Sec. 3.5).  Synchronous.  The tables are
  * rebuilt inside the grid's workspaces; adjoint plans are dropped (set them
  * again before the next adjoint call).

@@ -22,6 +22,7 @@
 // buffer (x into tx, y into ty, z added into the even points).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 
 #include "wacm_internal.h"
@@ -297,8 +298,9 @@ size_t work_bytes_of(int64_t n, int32_t nf, size_t es) {
   return tx_bytes(n, nf, es) + ty;
 }
 
-int mr_validate(int64_t n, int32_t nf, int32_t dtype, int32_t wavelet, int32_t nlev,
-                const void* u, const void* work, size_t work_size) {
+// every argument except the work buffer
+int mr_validate_sizes(int64_t n, int32_t nf, int32_t dtype, int32_t wavelet, int32_t nlev,
+                      const void* u) {
   if (elem_size(dtype) == 0) return mr_fail(WACM_E_INVAL, "mr: dtype must be WACM_F32 or WACM_F64");
   if (wavelet != WACM_CDF40 && wavelet != WACM_CDF44)
     return mr_fail(WACM_E_INVAL, "mr: unknown wavelet");
@@ -310,6 +312,12 @@ int mr_validate(int64_t n, int32_t nf, int32_t dtype, int32_t wavelet, int32_t n
   if (!u) return mr_fail(WACM_E_INVAL, "mr: u is NULL");
   if ((uintptr_t)u % (2 * elem_size(dtype)) != 0)
     return mr_fail(WACM_E_INVAL, "mr: u must be aligned to two elements");
+  return WACM_OK;
+}
+
+int mr_validate(int64_t n, int32_t nf, int32_t dtype, int32_t wavelet, int32_t nlev,
+                const void* u, const void* work, size_t work_size) {
+  if (int rc = mr_validate_sizes(n, nf, dtype, wavelet, nlev, u)) return rc;
   if (wavelet == WACM_CDF44 && nlev > 0) {
     if (!work) return mr_fail(WACM_E_INVAL, "mr: CDF 4/4 needs the work buffer");
     if ((uintptr_t)work % 256 != 0)
@@ -384,10 +392,60 @@ int mr_entry(int inverse, int64_t n, int32_t nf, int32_t dtype, int32_t wavelet,
   return WACM_OK;
 }
 
+// Work buffer of wacm_mr_forward_noalloc: a file-scope device array, one
+// copy per GPU, alive until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol): the device address comes from hipGetSymbolAddress, fetched once
+// per device with that device current and kept here.
+static __device__ __align__(256) unsigned char scratch[WACM_MR_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch`.
+int scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return mr_fail(WACM_E_HIP, std::string("mr: hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= MAX_DEVICES) return mr_fail(WACM_E_INVAL, "mr: device index out of range");
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return mr_fail(WACM_E_HIP, std::string("mr: hipGetSymbolAddress(scratch): ") +
+                                     hipGetErrorString(e));
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return WACM_OK;
+}
+
 }  // namespace mr
 }  // namespace wacm
 
 extern "C" {
+
+int wacm_mr_forward_noalloc(int64_t n, int32_t nfields, int32_t dtype, int32_t wavelet,
+                            int32_t nlev, void* u, void* stream) {
+  using namespace wacm::mr;
+  // the checks of wacm_mr_forward, then the scratch limit
+  int rc = mr_validate_sizes(n, nfields, dtype, wavelet, nlev, u);
+  if (rc != WACM_OK) return rc;
+  void* work = nullptr;
+  size_t wbytes = 0;
+  if (wavelet == WACM_CDF44 && nlev > 0) {
+    wbytes = work_bytes_of(n, nfields, elem_size(dtype));
+    if (wbytes > (size_t)WACM_MR_SCRATCH_BYTES)
+      return mr_fail(WACM_E_INVAL, "mr noalloc: the work of this size (" +
+                                       std::to_string(wbytes) + " bytes) exceeds the " +
+                                       std::to_string((size_t)WACM_MR_SCRATCH_BYTES) +
+                                       "-byte scratch array");
+    if ((rc = scratch_address(&work)) != WACM_OK) return rc;
+  }
+  return mr_entry(0, n, nfields, dtype, wavelet, nlev, u, work, wbytes, stream);
+}
 
 size_t wacm_mr_work_bytes(int64_t n, int32_t nfields, int32_t dtype) {
   const size_t es = wacm::mr::elem_size(dtype);

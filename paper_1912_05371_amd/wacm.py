@@ -32,7 +32,9 @@ EXPORTS = ["wacm_last_error", "wacm_treecode_encode", "wacm_treecode_decode", "w
            "wacm_rhs_acm_adj", "wacm_force_adj", "wacm_rk4_step_adj", "wacm_set_schedule",
            "wacm_get_schedule", "wacm_set_wavelet", "wacm_get_wavelet", "wacm_mr_work_bytes",
            "wacm_mr_forward", "wacm_mr_inverse", "wacm_workspace_bytes",
-           "wacm_wavelet_workspace_bytes", "wacm_adj_plan_bytes", "wacm_adj_plan_set"]
+           "wacm_wavelet_workspace_bytes", "wacm_adj_plan_bytes", "wacm_adj_plan_set",
+           "wacm_mr_forward_noalloc"]
+MR_SCRATCH_BYTES = 64 << 20  # WACM_MR_SCRATCH_BYTES
 
 
 class GridDesc(C.Structure):
@@ -128,6 +130,7 @@ def lib():
         L.wacm_mr_work_bytes.argtypes = [i64, i32, i32]
         L.wacm_mr_forward.argtypes = [i64, i32, i32, i32, i32, vp, vp, C.c_size_t, vp]
         L.wacm_mr_inverse.argtypes = [i64, i32, i32, i32, i32, vp, vp, C.c_size_t, vp]
+        L.wacm_mr_forward_noalloc.argtypes = [i64, i32, i32, i32, i32, vp, vp]
         L.wacm_get_wavelet.argtypes = [vp]
         L.wacm_adapt.argtypes = [vp, i32, vp, vp, vp, vp]
         L.wacm_adj_work_bytes.restype = C.c_size_t
@@ -235,6 +238,15 @@ def mr_forward(u, nlev: int, wavelet: int = CDF40, work=None, stream=None):
     wp, ws = _mr_work_arg(u, work)
     _check(lib().wacm_mr_forward(n, nf, dt, int(wavelet), int(nlev), _ptr(u), wp, ws,
                                  _stream(stream)))
+
+
+def mr_forward_noalloc(u, nlev: int, wavelet: int = CDF40, stream=None):
+    """:func:`mr_forward` without a work buffer: the library's static device
+    scratch array (MR_SCRATCH_BYTES per GPU) serves as the CDF 4/4 work; no
+    allocation.  u must be on the current device."""
+    n, nf, dt = _mr_args(u)
+    _check(lib().wacm_mr_forward_noalloc(n, nf, dt, int(wavelet), int(nlev), _ptr(u),
+                                         _stream(stream)))
 
 
 def mr_inverse(u, nlev: int, wavelet: int = CDF40, work=None, stream=None):
