@@ -147,6 +147,44 @@ def run_gpu(case, dtype_code: int, steps: int, warmup: int, use_graph: bool, tun
     return res
 
 
+def fp32_error(case):
+    """R23 on the benchmark workload: one CFL step in FP64 and one in FP32
+    from the same state (the FP64 state rounded to FP32), max |U32 - U64| /
+    max |U64| over the interiors of the 4-component state; outside the timed
+    region, each precision with its shipped schedule."""
+    import torch
+
+    from paper_1912_05371_amd import autotune, inputs, wacm
+
+    res = {}
+    for name, code in (("f64", wacm.F64), ("f32", wacm.F32)):
+        g = wacm.Grid.from_case(case, dtype=code)
+        pool = g.pool() if name == "f64" else None
+        if name == "f64":
+            modes = inputs.fourier_modes(case_seed(case), 4, 16, 8, 1.0 / 16.0)
+            inputs.fourier_fill_device(pool, modes, case.bs, case.ng, case.L, case.lev, case.ix,
+                                       case.iy, case.iz, np.arange(case.nb))
+            start = pool.float()  # the FP32 input: the FP64 state rounded
+        else:
+            pool = start
+        autotune.tune(g, case.params, pool, steps=1, use_cache=False)
+        work = g.work()
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        g.rk4_steps(case.params, t, dt, pool, work, 1, dt_mode=wacm.DT_CFL)
+        torch.cuda.synchronize()
+        I = slice(case.ng, case.ng + case.bs)
+        res[name] = (pool[:case.nb, :, I, I, I].double() if name == "f32"
+                     else pool[:case.nb, :, I, I, I].clone(), float(dt.item()))
+        del work, pool, g
+        torch.cuda.empty_cache()
+    a, b = res["f64"][0], res["f32"][0]
+    err = float((b - a).abs().max() / a.abs().max())
+    return {"rel_err_one_step": err, "tolerance": 1e-5, "metric": "max|U32-U64|/max|U64| over "
+            "interiors of (u,v,w,p) after one CFL step from the same state",
+            "dt_f64": res["f64"][1], "dt_f32": res["f32"][1]}
+
+
 def case_seed(case):
     return case.extra.get("seed", 12345)
 
@@ -194,7 +232,7 @@ def roofline(res, npts: int, es: int):
         "kernel": "stage_kernel (fused rhs + RK4 stage)",
         "kernel_avg_ms": round(stage_ms, 4),
         "bytes_per_launch": bytes_per_launch,
-        # interior bytes the implementation itself moves per launch (8, 16, 20, 12 values)
+        # interior bytes the implementation itself moves per launch (8, 16, 12, 12 values)
         "moved_min_bytes_per_launch": 12 * es * npts,
         "whole_step_frac": round(step_bytes / (res["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                  4),
@@ -394,6 +432,50 @@ def c3_run(nsteps: int = 200, every: int = 10):
             "records": recs}
 
 
+def small_configs_gpu():
+    """The Taylor-Green (64 blocks, 10 steps) and two-level sphere (736 blocks,
+    20 steps) configurations in full on the GPU, FP64 and FP32: one
+    wacm_rk4_steps call of the configuration's step count, HIP events on the
+    launch stream, median of 5 repetitions from the same initial state."""
+    import torch
+
+    from paper_1912_05371_amd import cases, wacm
+
+    out = {}
+    for name, mk in (("taylor_green_64blocks_10steps", cases.taylor_green),
+                     ("sphere_two_level_736blocks_20steps", cases.sphere_two_level)):
+        c = mk()
+        npts = c.nb * c.bs ** 3
+        rec = {"blocks": c.nb, "steps": c.steps, "interior_points": npts}
+        for dname, code in (("f64", wacm.F64), ("f32", wacm.F32)):
+            g = wacm.Grid.from_case(c, dtype=code)
+            U0 = g.pool()
+            U0[:c.nb] = torch.from_numpy(c.padded()).to("cuda", g.torch_dtype())
+            U = U0.clone()
+            work = g.work()
+            t = torch.zeros(1, dtype=torch.float64, device="cuda")
+            dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            times = []
+            for rep in range(6):
+                U.copy_(U0)
+                t.zero_()
+                torch.cuda.synchronize()
+                e0.record()
+                g.rk4_steps(c.params, t, dt, U, work, c.steps, dt_mode=wacm.DT_CFL)
+                e1.record()
+                torch.cuda.synchronize()
+                if rep:
+                    times.append(e0.elapsed_time(e1) / c.steps)
+            ms = float(np.median(times))
+            rec[dname] = {"ms_per_step": round(ms, 4),
+                          "updates_per_s": round(npts * 4 / (ms * 1e-3), 1)}
+            del U, U0, work, g
+        out[name] = rec
+    torch.cuda.empty_cache()
+    return out
+
+
 def lifting_timings(seed: int):
     """CDF 4/4 (lifted restriction) on a random octree with 6 ghost layers
     (bs 24, levels 3-6, ~4000 blocks, FP64): the full ghost sync with CDF 4/0
@@ -503,15 +585,25 @@ def copy_probe(gib: float):
             "GBps": round(moved / (ms * 1e-3) / 1e9, 1)}
 
 
-def cpu_baseline(seed: int, min_seconds: float = 10.0):
-    """The FP64 oracle on a bounded sample of the same workload: RK4 steps
-    (each with its CFL time step) on a smaller random octree built by the
-    same generator (bs 24, 4 ghost layers, levels 2..4), repeated until
-    `min_seconds` of wall time have passed."""
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_sample(seed: int, min_seconds: float, target: int, j0: int, jmax: int):
+    """RK4 steps (each with its CFL time step) of the FP64 oracle on a random
+    octree of the benchmark's generator (bs 24, ng 4), repeated until
+    `min_seconds` of wall time have passed: (updates/s, steps, seconds,
+    blocks, interior points)."""
     from oracle import oracle
     from paper_1912_05371_amd import cases
     oracle.build(force=False)
-    c = cases.random_octree(bs=24, ng=4, target=600, j0=2, jmax=4, seed=seed)
+    c = cases.random_octree(bs=24, ng=4, target=target, j0=j0, jmax=jmax, seed=seed)
     og = oracle.Grid(c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix, c.iy, c.iz)
     U = c.padded()
     t, n = 0.0, 0
@@ -525,17 +617,73 @@ def cpu_baseline(seed: int, min_seconds: float = 10.0):
         if el >= min_seconds:
             break
     npts = c.nb * c.bs ** 3
+    return npts * 4 * n / el, n, el, c.nb, npts
+
+
+def oracle_configs():
+    """The Taylor-Green (10 steps) and two-level sphere (20 steps)
+    configurations in full with the FP64 oracle: updates/s and seconds."""
+    from oracle import oracle
+    from paper_1912_05371_amd import cases
+    oracle.build(force=False)
+    out = {}
+    for name, mk in (("taylor_green_64blocks_10steps", cases.taylor_green),
+                     ("sphere_two_level_736blocks_20steps", cases.sphere_two_level)):
+        c = mk()
+        og = oracle.Grid(c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix, c.iy, c.iz)
+        U = c.padded()
+        t = 0.0
+        t0 = time.perf_counter()
+        for _ in range(c.steps):
+            dt = og.dt(c.params, U)
+            og.rk4_step(c.params, t, dt, U)
+            t += dt
+        el = time.perf_counter() - t0
+        npts = c.nb * c.bs ** 3
+        out[name] = {"seconds": round(el, 3), "updates_per_s": round(npts * 4 * c.steps / el, 1)}
+    return out
+
+
+def _child_json(expr: str, threads: int) -> dict:
+    """Evaluate `expr` (a call into this module) in a child Python process
+    with OMP_NUM_THREADS=threads (the oracle's OpenMP team is fixed when it
+    loads, so other thread counts need their own process)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    code = f"import json, bench; print(json.dumps({expr}))"
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(r.stderr[-2000:])
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(seed: int, min_seconds: float = 10.0):
+    """The FP64 oracle on the host cores: a bounded sample of the benchmark
+    workload (a 603-block octree of the same generator, levels 2..4, RK4
+    steps repeated for >= min_seconds) with every host core, the same sample
+    on one core, and the Taylor-Green and sphere configurations in full (all
+    cores; Taylor-Green also on one core)."""
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    rate, n, el, nb, npts = oracle_sample(seed, min_seconds, 600, 2, 4)
+    one = _child_json(f"bench.oracle_sample({seed}, {min_seconds}, 600, 2, 4)", 1)
+    cfg = _child_json("bench.oracle_configs()", threads)
+    cfg1 = _child_json("bench.oracle_configs()['taylor_green_64blocks_10steps']", 1)
+    cfg["taylor_green_64blocks_10steps"]["one_thread"] = cfg1
     return {
-        "value": round(npts * 4 * n / el, 1),
+        "value": round(rate, 1),
         "unit": "block-point updates/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"{n} RK4 steps (+CFL dt each) of the FP64 oracle on a {c.nb}-block random "
+        "sample": f"{n} RK4 steps (+CFL dt each) of the FP64 oracle on a {nb}-block random "
                   f"octree (bs 24, ng 4, levels 2-4, {npts} interior points), same generator; "
                   f"{el:.2f} s wall with OpenMP over blocks",
         "seconds": round(el, 3),
         "core_seconds_per_point_rhs": el * threads / (npts * 4 * n),
+        "cpu_model": cpu_model(),
+        "one_thread": {"value": round(one[0], 1), "steps": one[1], "seconds": round(one[2], 3),
+                       "core_seconds_per_point_rhs": one[2] / (one[4] * 4 * one[1])},
+        "configs": cfg,
     }
 
 
@@ -674,6 +822,13 @@ def main():
     if copy:
         line["copy_probe"] = copy
         line["roofline"]["frac_of_copy"] = round(R["roofline"]["achieved"] / copy["GBps"], 4)
+    if "f64" in results and "f32" in results:
+        log("FP32 against FP64 after one step")
+        line["f32"]["error_vs_f64"] = fp32_error(case)
+        log(f"  rel err {line['f32']['error_vs_f64']['rel_err_one_step']:.3e}")
+    if not args.no_aux:
+        log("timing the Taylor-Green and sphere configurations")
+        line["configs_gpu"] = small_configs_gpu()
     if not args.no_aux and "f64" in results:
         log("timing the other calls")
         line["aux"] = aux_timings(case)
