@@ -21,6 +21,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "wacm_oracle.c")
+SRC2D = os.path.join(HERE, "wacm_oracle2d.c")
 LIB = os.path.join(HERE, "liboracle.so")
 # a sanitizer build of the same source may be loaded instead (CPU tests only)
 LIB = os.environ.get("WACM_ORACLE_LIB", LIB)
@@ -32,7 +33,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
     if force or not os.path.exists(LIB):
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
-               "-shared", "-std=c11", "-o", LIB + ".tmp", SRC, "-lm"]
+               "-shared", "-std=c11", "-o", LIB + ".tmp", SRC, SRC2D, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(LIB + ".tmp", LIB)
     return LIB
@@ -122,6 +123,30 @@ def lib():
                                       dp, vp, vp]
         L.orc_rk4_step_adj.argtypes = [vp, C.POINTER(OrcParams), C.c_double, C.c_double, vp,
                                        vp, dp, vp, vp]
+        # two-dimensional form
+        L.orc2_grid_create.restype = vp
+        L.orc2_grid_create.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
+                                       C.c_int64, vp, vp, vp, C.POINTER(C.c_int)]
+        L.orc2_grid_free.argtypes = [vp]
+        L.orc2_grid_nb.restype = C.c_int64
+        L.orc2_grid_nb.argtypes = [vp]
+        L.orc2_grid_leaves.argtypes = [vp, vp, vp, vp]
+        L.orc2_sync.argtypes = [vp, vp]
+        L.orc2_rhs.argtypes = [vp, C.POINTER(OrcParams), vp, vp]
+        L.orc2_dt.restype = C.c_double
+        L.orc2_dt.argtypes = [vp, C.POINTER(OrcParams), vp]
+        L.orc2_rk4_step.argtypes = [vp, C.POINTER(OrcParams), C.c_double, vp]
+        L.orc2_diagnostics.argtypes = [vp, vp, vp]
+        L.orc2_details.argtypes = [vp, vp, vp]
+        L.orc2_flags.argtypes = [vp, vp, C.c_double, C.c_int, vp]
+        L.orc2_refine_count.restype = C.c_int64
+        L.orc2_refine_count.argtypes = [vp]
+        L.orc2_refine_all.restype = vp
+        L.orc2_refine_all.argtypes = [vp, vp, vp]
+        L.orc2_coarsen_count.restype = C.c_int64
+        L.orc2_coarsen_count.argtypes = [vp, vp]
+        L.orc2_coarsen.restype = vp
+        L.orc2_coarsen.argtypes = [vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -364,3 +389,88 @@ class Grid:
     def treecodes(self) -> np.ndarray:
         return np.array([treecode_encode(int(l), int(x), int(y), int(z))
                          for l, x, y, z in zip(self.lev, self.ix, self.iy, self.iz)], np.uint64)
+
+
+class Grid2D:
+    """A quadtree leaf set (levels and block indices (ix, iy)) with the 2D
+    oracle's operations.  A state U is a float64 array (nb, 3, P, P), fields
+    (u, v, p), x fastest."""
+
+    def __init__(self, bs, ng, L, jmin, jmax, lev, ix, iy, _handle=None):
+        self.bs, self.ng, self.L, self.jmin, self.jmax = int(bs), int(ng), float(L), jmin, jmax
+        self.P = self.bs + 2 * self.ng
+        if _handle is None:
+            lev = np.ascontiguousarray(lev, dtype=np.int32)
+            ix = np.ascontiguousarray(ix, dtype=np.int64)
+            iy = np.ascontiguousarray(iy, dtype=np.int64)
+            err = C.c_int(0)
+            h = lib().orc2_grid_create(self.bs, self.ng, self.L, jmin, jmax, len(lev), _ptr(lev),
+                                       _ptr(ix), _ptr(iy), C.byref(err))
+            if not h:
+                raise OracleError(err.value)
+            _handle = h
+        self._h = C.c_void_p(_handle)
+        self.nb = int(lib().orc2_grid_nb(self._h))
+        self.lev = np.zeros(self.nb, np.int32)
+        self.ix = np.zeros(self.nb, np.int64)
+        self.iy = np.zeros(self.nb, np.int64)
+        lib().orc2_grid_leaves(self._h, _ptr(self.lev), _ptr(self.ix), _ptr(self.iy))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.orc2_grid_free(h)
+            self._h = None
+
+    def _child(self, handle) -> "Grid2D":
+        return Grid2D(self.bs, self.ng, self.L, self.jmin, self.jmax, None, None, None,
+                      _handle=handle)
+
+    def zeros(self) -> np.ndarray:
+        return np.zeros((self.nb, 3, self.P, self.P), np.float64)
+
+    def sync(self, U: np.ndarray) -> None:
+        lib().orc2_sync(self._h, _ptr(U))
+
+    def rhs(self, params: dict, U: np.ndarray) -> np.ndarray:
+        dU = self.zeros()
+        p = make_params(params)
+        lib().orc2_rhs(self._h, C.byref(p), _ptr(U), _ptr(dU))
+        return dU
+
+    def dt(self, params: dict, U: np.ndarray) -> float:
+        p = make_params(params)
+        return float(lib().orc2_dt(self._h, C.byref(p), _ptr(U)))
+
+    def rk4_step(self, params: dict, dt: float, U: np.ndarray) -> None:
+        p = make_params(params)
+        lib().orc2_rk4_step(self._h, C.byref(p), dt, _ptr(U))
+
+    def diagnostics(self, U: np.ndarray) -> np.ndarray:
+        out = np.zeros(9)
+        lib().orc2_diagnostics(self._h, _ptr(U), _ptr(out))
+        return out
+
+    def details(self, U: np.ndarray) -> np.ndarray:
+        d = np.zeros(self.nb)
+        lib().orc2_details(self._h, _ptr(U), _ptr(d))
+        return d
+
+    def flags(self, dmax, eps: float, dealias: bool) -> np.ndarray:
+        f = np.zeros(self.nb, np.int8)
+        lib().orc2_flags(self._h, _ptr(np.ascontiguousarray(dmax, np.float64)), eps,
+                         int(dealias), _ptr(f))
+        return f
+
+    def refine_all(self, U: np.ndarray):
+        n = int(lib().orc2_refine_count(self._h))
+        Un = np.zeros((n, 3, self.P, self.P))
+        h = lib().orc2_refine_all(self._h, _ptr(U), _ptr(Un))
+        return self._child(h), Un
+
+    def coarsen(self, flags: np.ndarray, U: np.ndarray):
+        flags = np.ascontiguousarray(flags, np.int8)
+        n = int(lib().orc2_coarsen_count(self._h, _ptr(flags)))
+        Un = np.zeros((n, 3, self.P, self.P))
+        h = lib().orc2_coarsen(self._h, _ptr(flags), _ptr(U), _ptr(Un))
+        return self._child(h), Un

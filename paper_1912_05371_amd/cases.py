@@ -21,6 +21,11 @@ Cases (all synthetic, seed 12345):
   levels 3..7, >= 20000 blocks; 16 random Fourier modes per field (k <= 8);
   nu 1e-2, C0 20, C_gamma 1, no mask, CFL 0.5.  Throughput workload.
 * ``plate_adjoint`` -- the plate on a frozen grid, levels 2..5, bs 16.
+* ``three_vortices`` (two dimensions) -- [0, 2pi)^2 periodic, three Gaussian
+  vortices (circulations 1, 1, -1/2, core 1/pi, centres (0.75, 1) pi,
+  (1.25, 1) pi, (1.25, 1.25) pi), nu 5e-5, C0 10, C_gamma 1, p = 0; on a
+  uniform level (equidistant runs) or on a quadtree refined around the
+  vortex cores (adaptive runs).
 """
 from __future__ import annotations
 
@@ -161,3 +166,63 @@ def plate_adjoint(bs: int = 16, ng: int = 4) -> Case:
     noise = smooth_noise(SEED, bs, L, lev, ix, iy, iz)
     noise[3] = np.zeros_like(noise[3])
     return Case("plate_adjoint", bs, ng, L, 2, 5, lev, ix, iy, iz, prm, noise, steps=100)
+
+
+@dataclass
+class Case2:
+    """A two-dimensional case: quadtree leaves and 3 interior fields (u, v, p)
+    of shape (nb, bs, bs)."""
+    name: str
+    bs: int
+    ng: int
+    L: float
+    jmin: int
+    jmax: int
+    lev: np.ndarray
+    ix: np.ndarray
+    iy: np.ndarray
+    params: dict
+    fields: list = field(default_factory=list)
+    steps: int = 1
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def nb(self) -> int:
+        return len(self.lev)
+
+    @property
+    def P(self) -> int:
+        return self.bs + 2 * self.ng
+
+    def padded(self, fill: float = 0.0) -> np.ndarray:
+        return inputs.pack2(self.fields, self.bs, self.ng, fill)
+
+
+def three_vortex_params() -> dict:
+    return params(nu=5e-5, c0=10.0, c_gamma=1.0, cfl=0.5)
+
+
+def _three_vortex_fields(bs, lev, ix, iy, jtop):
+    N = (1 << jtop) * bs
+    u, v = inputs.three_vortex_velocity(N)
+    return [inputs.sample2(u, bs, lev, ix, iy), inputs.sample2(v, bs, lev, ix, iy),
+            np.zeros((len(lev), bs, bs))]
+
+
+def three_vortices(bs: int = 16, ng: int = 4, J: int = 4) -> Case2:
+    """Equidistant: uniform level J ((2^J bs)^2 points)."""
+    lev, ix, iy = inputs.uniform_leaves2(J)
+    return Case2("three_vortices", bs, ng, 2.0 * math.pi, J, J, lev, ix, iy,
+                 three_vortex_params(), _three_vortex_fields(bs, lev, ix, iy, J), steps=10)
+
+
+def three_vortices_adaptive(bs: int = 16, ng: int = 4, jmin: int = 2, jmax: int = 6,
+                            jstart: int | None = None, radius: float = 1.0) -> Case2:
+    """Adaptive: every block within `radius` of a vortex centre refined to
+    jstart (default jmax - 1), 2:1 balanced; eps 1e-3, dealiasing."""
+    jtop = jmax - 1 if jstart is None else jstart
+    lev, ix, iy = inputs.disc_refined_leaves2(2.0 * math.pi, jmin, jtop,
+                                              inputs.THREE_VORTICES["centres"], radius)
+    return Case2("three_vortices_adaptive", bs, ng, 2.0 * math.pi, jmin, jmax, lev, ix, iy,
+                 three_vortex_params(), _three_vortex_fields(bs, lev, ix, iy, jmax), steps=20,
+                 extra=dict(eps=1e-3, dealias=True))

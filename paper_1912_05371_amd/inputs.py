@@ -273,3 +273,188 @@ def fourier_fill_device(pool, modes: np.ndarray, bs: int, ng: int, L: float, lev
                 acc += a * torch.cos(s * (kx * X[:, None, None, :] + ky * Y[:, None, :, None]
                                           + kz * Z[:, :, None, None]) + ph)
             pool[slots_t[b0:b1], c, ng:ng + bs, ng:ng + bs, ng:ng + bs] = acc.to(pool.dtype)
+
+
+# --------------------------------------------------------------------------
+# Two dimensions: quadtree leaves (level, ix, iy) of the periodic square
+# [0, L)^2, square blocks, the same non-redundant positions.  Leaves are
+# ordered like the octree's with iz = 0 (x bit below y bit per level); the
+# library takes the treecode of (ix, iy, 0).
+# --------------------------------------------------------------------------
+def _sorted2(leaves):
+    lev = np.array([l[0] for l in leaves], np.int32)
+    ix = np.array([l[1] for l in leaves], np.int64)
+    iy = np.array([l[2] for l in leaves], np.int64)
+    order = np.argsort(morton_key(lev, ix, iy, np.zeros_like(ix)), kind="stable")
+    return lev[order], ix[order], iy[order]
+
+
+def uniform_leaves2(J: int):
+    n = 1 << J
+    return _sorted2([(J, x, y) for y in range(n) for x in range(n)])
+
+
+class LeafSet2:
+    """Mutable set of quadtree leaves {(lev, x, y)} with 8-neighbour 2:1
+    balancing on refinement (grid generation only)."""
+
+    def __init__(self, leaves, jmin: int):
+        self.s = set((int(a), int(b), int(c)) for a, b, c in leaves)
+        self.jmin = jmin
+
+    def leaf_covering(self, J, x, y):
+        n = 1 << J
+        x, y = x % n, y % n
+        for K in range(J, self.jmin - 1, -1):
+            key = (K, x >> (J - K), y >> (J - K))
+            if key in self.s:
+                return key
+        return None
+
+    def refine(self, leaf, created=None):
+        J, x, y = leaf
+        if leaf not in self.s:
+            return
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dx == dy == 0:
+                    continue
+                nb = self.leaf_covering(J, x + dx, y + dy)
+                if nb is not None and nb[0] < J:
+                    self.refine(nb, created)
+        self.s.discard(leaf)
+        for c in range(4):
+            ch = (J + 1, 2 * x + (c & 1), 2 * y + (c >> 1))
+            self.s.add(ch)
+            if created is not None:
+                created.add(ch)
+
+    def arrays(self):
+        return _sorted2(sorted(self.s))
+
+
+def random_balanced_leaves2(seed: int, j0: int, jmax: int, target: int):
+    """Random 2:1-balanced quadtree: refine uniformly drawn leaves below jmax
+    of a uniform level-j0 grid until at least `target` leaves."""
+    rng = np.random.default_rng(seed)
+    n0 = 1 << j0
+    ls = LeafSet2([(j0, x, y) for y in range(n0) for x in range(n0)], j0)
+    cand = sorted(ls.s) if j0 < jmax else []
+    while len(ls.s) < target and cand:
+        k = int(rng.integers(len(cand)))
+        pick = cand[k]
+        cand[k] = cand[-1]
+        cand.pop()
+        if pick not in ls.s:
+            continue
+        created = set()
+        ls.refine(pick, created=created)
+        cand.extend(sorted(l for l in created if l[0] < jmax))
+    return ls.arrays()
+
+
+def disc_refined_leaves2(L: float, jmin: int, jtop: int, centres, radius: float):
+    """Every block meeting one of the discs |x - c| < radius (periodic) is
+    refined up to level jtop, with 2:1 balancing, from a uniform level-jmin
+    grid (geometry only)."""
+    n0 = 1 << jmin
+    ls = LeafSet2([(jmin, x, y) for y in range(n0) for x in range(n0)], jmin)
+    cs = np.asarray(centres, float)
+
+    def meets(leaf):
+        J, x, y = leaf
+        w = L / (1 << J)
+        lo = np.array([x, y]) * w
+        for c in cs:
+            for sx in (-L, 0.0, L):
+                for sy in (-L, 0.0, L):
+                    cc = c + np.array([sx, sy])
+                    d = np.sqrt(np.sum(np.maximum(0.0, np.maximum(lo - cc, cc - lo - w)) ** 2))
+                    if d < radius:
+                        return True
+        return False
+
+    todo = sorted(l for l in ls.s if l[0] < jtop and meets(l))
+    while todo:
+        nxt = []
+        for leaf in todo:
+            if leaf in ls.s:
+                created = set()
+                ls.refine(leaf, created=created)
+                nxt.extend(l for l in created if l[0] < jtop and meets(l))
+        todo = sorted(set(nxt))
+    return ls.arrays()
+
+
+# the three Gaussian vortices of the results section (periodic [0, 2 pi)^2):
+# circulations, centres, core size a = 1/pi
+THREE_VORTICES = dict(gamma=(1.0, 1.0, -0.5),
+                      centres=((0.75 * math.pi, math.pi), (1.25 * math.pi, math.pi),
+                               (1.25 * math.pi, 1.25 * math.pi)),
+                      a=1.0 / math.pi)
+
+
+def three_vortex_vorticity(N: int, L: float = 2.0 * math.pi, images: int = 2):
+    """omega = sum_i Gamma_i / (pi a^2) exp(-|x - x_i|^2 / a^2) on the N x N
+    lattice (array [y, x]), with periodic images of each Gaussian."""
+    tv = THREE_VORTICES
+    a = tv["a"]
+    x = np.arange(N) * (L / N)
+    X, Y = x[None, :], x[:, None]
+    w = np.zeros((N, N))
+    for g, (cx, cy) in zip(tv["gamma"], tv["centres"]):
+        for sx in range(-images, images + 1):
+            for sy in range(-images, images + 1):
+                r2 = (X - cx - sx * L) ** 2 + (Y - cy - sy * L) ** 2
+                w += g / (math.pi * a * a) * np.exp(-r2 / (a * a))
+    return w
+
+
+def three_vortex_velocity(N: int, L: float = 2.0 * math.pi):
+    """Initial velocity of the three vortices on the N x N lattice (arrays
+    [y, x]): the periodic field whose vorticity dv/dx - du/dy is omega minus
+    its mean (a periodic velocity carries no net circulation), built from the
+    streamfunction psi with -lap psi = omega - mean, u = dpsi/dy, v = -dpsi/dx,
+    evaluated by FFT.  This only constructs the initial condition; the method
+    itself differentiates with finite differences."""
+    w = three_vortex_vorticity(N, L)
+    k = np.fft.fftfreq(N, d=L / N) * 2.0 * math.pi
+    KX, KY = k[None, :], k[:, None]
+    k2 = KX ** 2 + KY ** 2
+    wh = np.fft.fft2(w)
+    k2[0, 0] = 1.0
+    ph = wh / k2
+    ph[0, 0] = 0.0
+    u = np.real(np.fft.ifft2(1j * KY * ph))
+    v = np.real(np.fft.ifft2(-1j * KX * ph))
+    return u, v
+
+
+def sample2(field: np.ndarray, bs: int, lev, ix, iy) -> np.ndarray:
+    """Values of a lattice field (N x N, array [y, x], N = 2^J bs for some J
+    at least every level) at the interior points of each block: (nb, bs, bs)
+    in (y, x) order."""
+    N = field.shape[0]
+    out = np.zeros((len(lev), bs, bs))
+    i = np.arange(bs)
+    for b, (J, x, y) in enumerate(zip(lev, ix, iy)):
+        st = N // ((1 << int(J)) * bs)
+        assert st * (1 << int(J)) * bs == N
+        gx = (int(x) * bs + i) * st
+        gy = (int(y) * bs + i) * st
+        out[b] = field[np.ix_(gy, gx)]
+    return out
+
+
+def pack2(fields, bs: int, ng: int, fill: float = 0.0) -> np.ndarray:
+    """3 interior fields (nb, bs, bs) into a padded 2D pool (nb, 3, P, P)."""
+    nb = fields[0].shape[0]
+    P = bs + 2 * ng
+    U = np.full((nb, 3, P, P), fill, np.float64)
+    for c in range(3):
+        U[:, c, ng:ng + bs, ng:ng + bs] = fields[c]
+    return U
+
+
+def interior2(U: np.ndarray, bs: int, ng: int) -> np.ndarray:
+    return U[..., ng:ng + bs, ng:ng + bs]

@@ -43,7 +43,7 @@ def san_env():
     lib = os.path.join(BUILD, "liboracle_san.so")
     subprocess.run(["gcc", *SAN, "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
                     "-shared", "-std=c11", "-o", lib, os.path.join(ROOT, "oracle", "wacm_oracle.c"),
-                    "-lm"], check=True)
+                    os.path.join(ROOT, "oracle", "wacm_oracle2d.c"), "-lm"], check=True)
     env = dict(os.environ)
     env["LD_PRELOAD"] = _runtime("libasan.so") + ":" + _runtime("libubsan.so")
     env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=0:exitcode=86"
@@ -62,7 +62,7 @@ def test_oracle_pins_under_sanitizers(san_env):
             "and not test_objective_gradient_dus_and_state_match_fd")
     files = [os.path.join(ROOT, "tests", f) for f in
              ("test_oracle_pins.py", "test_oracle_pins_model.py", "test_oracle_mr.py",
-              "test_oracle_adjoint.py")]
+              "test_oracle_adjoint.py", "test_oracle2d_pins.py")]
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         "-k", skip, *files], env=san_env, capture_output=True, text=True,
                        cwd=ROOT, timeout=900)
