@@ -43,6 +43,19 @@
  * interior point i at x = (bx bs + i) h_J (non-redundant blocks; bs even).
  * Treecode: one octal digit per level, level-1 digit most significant,
  * digit = xbit + 2 ybit + 4 zbit (Sec. 4.1).
+ *
+ * Two dimensions (wacm_grid_desc.dim = 2; the model of Sec. 2.1 with D = 2):
+ * a periodic quadtree of square blocks on [0,L]^2 with the same spacing and
+ * positions in x and y.  Leaves are given by the octal treecode of (bx, by, 0)
+ * (digits 0..3).  The pool holds 3 fields (u, v, p) per slot, each a padded
+ * square of P^2 values, x fastest:
+ *   pool[((s*3 + c)*P + (j+ng))*P + (i+ng)].
+ * Available in 2D: grid creation and queries, wacm_sync_ghosts, wacm_rhs_acm,
+ * wacm_compute_dt, wacm_rk4_step(s), wacm_diagnostics (w and the force read
+ * 0), wacm_threshold_blocks and wacm_adapt, all with the CDF 4/0 wavelet,
+ * without mask, sponge or extra solid velocity (params.mask and
+ * params.sponge 0, dus NULL; WACM_E_INVAL otherwise).  The other calls return
+ * WACM_E_INVAL for a 2D grid.
  */
 #ifndef WACM_H
 #define WACM_H
@@ -89,7 +102,7 @@ typedef struct {
   int32_t jmin;     /* coarsest level allowed                                    */
   int32_t jmax;     /* finest level allowed, <= 18 (Sec. 3.5)                    */
   int32_t dtype;    /* WACM_F32 or WACM_F64                                      */
-  int32_t reserved; /* must be 0                                                 */
+  int32_t dim;      /* 3 (octree; 0 is read as 3) or 2 (quadtree, see below)      */
   int64_t capacity; /* number of pool slots                                      */
   double L;         /* domain edge length                                        */
 } wacm_grid_desc;

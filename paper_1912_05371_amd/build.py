@@ -22,7 +22,8 @@ BUILD = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["kernels.hip", "adjoint.hip", "lifting.hip", "mr.hip", "api.cpp", "grid.cpp"]
+SOURCES = ["kernels.hip", "kernels2d.hip", "adjoint.hip", "lifting.hip", "mr.hip", "api.cpp",
+           "grid.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", f"-I{INC}", f"-I{CSRC}", "-Wall"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-ffp-contract=fast", "-munsafe-fp-atomics"]

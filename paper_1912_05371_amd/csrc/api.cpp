@@ -38,6 +38,20 @@ int hipfail(hipError_t e, const char* what) {
 
 bool elem_ok(const wacm_grid* g) { return g && (g->d.dtype == WACM_F32 || g->d.dtype == WACM_F64); }
 
+// the two-dimensional path has no mask, sponge or extra solid velocity
+int check_2d(const wacm_grid* g, const wacm_params* p, const void* dus) {
+  if (g->dim != 2) return WACM_OK;
+  if (p && (p->mask || p->sponge))
+    return fail(WACM_E_INVAL, "two dimensions: no mask or sponge (params.mask, params.sponge 0)");
+  if (dus) return fail(WACM_E_INVAL, "two dimensions: no extra solid velocity (dus NULL)");
+  return WACM_OK;
+}
+
+int not_2d(const wacm_grid* g, const char* what) {
+  return g->dim == 2 ? fail(WACM_E_INVAL, std::string(what) + " is not available in two dimensions")
+                     : WACM_OK;
+}
+
 int check_params(const wacm_params* p) {
   if (!p) return fail(WACM_E_INVAL, "params is NULL");
   if (p->mask < 0 || p->mask > 2) return fail(WACM_E_INVAL, "unknown mask kind");
@@ -79,7 +93,7 @@ int check_desc(const wacm_grid_desc* d) {
   if (d->jmin < 0 || d->jmax > 18 || d->jmin > d->jmax)
     return fail(WACM_E_INVAL, "need 0 <= jmin <= jmax <= 18");
   if (d->dtype != WACM_F32 && d->dtype != WACM_F64) return fail(WACM_E_INVAL, "bad dtype");
-  if (d->reserved != 0) return fail(WACM_E_INVAL, "reserved must be 0");
+  if (d->dim != 0 && d->dim != 2 && d->dim != 3) return fail(WACM_E_INVAL, "dim must be 2 or 3");
   if (!(d->L > 0)) return fail(WACM_E_INVAL, "L must be > 0");
   if (d->capacity <= 0 || d->capacity > (int64_t)1 << 30)
     return fail(WACM_E_INVAL, "need 0 < capacity <= 2^30");
@@ -145,7 +159,9 @@ int wacm_grid_create(const wacm_grid_desc* d, int64_t nleaves, const uint64_t* t
   wacm_grid* g = new (std::nothrow) wacm_grid();
   if (!g) return fail(WACM_E_NOMEM, "host allocation");
   g->d = *d;
+  g->dim = d->dim == 2 ? 2 : 3;
   g->P = d->bs + 2 * d->ng;
+  const int vsh = g->dim;  // a level-J leaf covers 2^(dim (jmax - J)) finest boxes
   g->leaves.resize(nleaves);
   g->slots.resize(nleaves);
   // tiling: unique, in range, no leaf inside another, volumes add up
@@ -165,13 +181,17 @@ int wacm_grid_create(const wacm_grid_desc* d, int64_t nleaves, const uint64_t* t
     Leaf l;
     l.J = J;
     wacm_treecode_decode(treecodes[i], J, &l.x, &l.y, &l.z);
+    if (g->dim == 2 && l.z != 0) {
+      delete g;
+      return fail(WACM_E_INVAL, "two dimensions: treecodes of (bx, by, 0) only");
+    }
     if (!seen.emplace(leaf_key(J, l.x, l.y, l.z), (int32_t)i).second) {
       delete g;
       return fail(WACM_E_TILING, "repeated leaf");
     }
     g->leaves[i] = l;
     g->slots[i] = (int32_t)i;
-    vol += (unsigned __int128)1 << (3 * (d->jmax - J));
+    vol += (unsigned __int128)1 << (vsh * (d->jmax - J));
   }
   for (int64_t i = 0; i < nleaves; ++i) {
     const Leaf& l = g->leaves[i];
@@ -183,7 +203,7 @@ int wacm_grid_create(const wacm_grid_desc* d, int64_t nleaves, const uint64_t* t
       }
     }
   }
-  if (vol != ((unsigned __int128)1 << (3 * d->jmax))) {
+  if (vol != ((unsigned __int128)1 << (vsh * d->jmax))) {
     delete g;
     return fail(WACM_E_TILING, "leaves do not cover the domain");
   }
@@ -242,6 +262,7 @@ int wacm_grid_info(const wacm_grid* g, int64_t* slots, uint64_t* treecodes, int8
 size_t wacm_work_bytes(const wacm_grid* g) {
   GridScope gs(g);
   if (!g) return 0;
+  if (g->dim == 2) return work_bytes_2d(g);
   return g->wavelet == WACM_CDF44 ? lift_work_bytes(g) : work_bytes(g);
 }
 
@@ -266,6 +287,7 @@ int wacm_get_schedule(const wacm_grid* g, wacm_schedule* s) {
 // Full ghost fill with the grid's wavelet: the CDF 4/0 fill, then with CDF
 // 4/4 the lifted values of ghost points whose owner is finer.
 static hipError_t full_sync(const wacm_grid* g, void* U, hipStream_t st) {
+  if (g->dim == 2) return launch_sync_2d(g, U, st);
   hipError_t e = launch_sync(g, U, 0, st);
   if (e == hipSuccess && g->wavelet == WACM_CDF44) e = launch_lift_sync(g, U, st);
   return e;
@@ -289,6 +311,7 @@ int wacm_set_wavelet(wacm_grid* g, int32_t wavelet, void* ws, size_t ws_bytes) {
   if (!elem_ok(g)) return fail(WACM_E_INVAL, "NULL argument");
   if (wavelet != WACM_CDF40 && wavelet != WACM_CDF44) return fail(WACM_E_INVAL, "wavelet");
   if (wavelet == WACM_CDF44) {
+    if (int rc = not_2d(g, "CDF 4/4")) return rc;
     if (g->d.ng < 6)
       return fail(WACM_E_INVAL, "CDF 4/4 needs ng >= 6 (the lifted stencil reaches 6 fine points)");
     if (!ws || reinterpret_cast<uintptr_t>(ws) % 256)
@@ -331,7 +354,9 @@ int wacm_rhs_acm(wacm_grid* g, const wacm_params* p, double t, const void* U, vo
   GridScope gs(g);
   if (!elem_ok(g) || !U || !dU) return fail(WACM_E_INVAL, "NULL argument");
   if (int rc = check_params(p)) return rc;
-  hipError_t e = launch_rhs(g, p, t, U, dU, dus, S(stream));
+  if (int rc = check_2d(g, p, dus)) return rc;
+  hipError_t e = g->dim == 2 ? launch_rhs_2d(g, p, U, dU, S(stream))
+                             : launch_rhs(g, p, t, U, dU, dus, S(stream));
   return e == hipSuccess ? WACM_OK : hipfail(e, "rhs_acm launch");
 }
 
@@ -340,7 +365,9 @@ int wacm_compute_dt(wacm_grid* g, const wacm_params* p, const void* U, double* d
   GridScope gs(g);
   if (!elem_ok(g) || !U || !dt_dev) return fail(WACM_E_INVAL, "NULL argument");
   if (int rc = check_params(p)) return rc;
-  hipError_t e = launch_dt(g, p, U, dt_dev, S(stream));
+  if (int rc = check_2d(g, p, nullptr)) return rc;
+  hipError_t e = g->dim == 2 ? launch_dt_2d(g, p, U, dt_dev, S(stream))
+                             : launch_dt(g, p, U, dt_dev, S(stream));
   return e == hipSuccess ? WACM_OK : hipfail(e, "compute_dt launch");
 }
 
@@ -353,6 +380,11 @@ static int rk4_common(wacm_grid* g, const wacm_params* p, double* t_dev, double*
   if (nsteps < 0) return fail(WACM_E_INVAL, "nsteps must be >= 0");
   if (reinterpret_cast<uintptr_t>(work) % 256) return fail(WACM_E_INVAL, "work not 256-aligned");
   if (int rc = check_params(p)) return rc;
+  if (int rc = check_2d(g, p, dus)) return rc;
+  if (g->dim == 2) {
+    hipError_t e = launch_rk4_2d(g, p, t_dev, dt_dev, U, work, dt_mode, nsteps, S(stream));
+    return e == hipSuccess ? WACM_OK : hipfail(e, what);
+  }
   hipError_t e = g->wavelet == WACM_CDF44
                      ? launch_rk4_lifted(g, p, t_dev, dt_dev, U, work, dus, dt_mode, nsteps,
                                          S(stream))
@@ -378,7 +410,9 @@ int wacm_diagnostics(wacm_grid* g, const wacm_params* p, double t, const void* U
   GridScope gs(g);
   if (!elem_ok(g) || !U || !out) return fail(WACM_E_INVAL, "NULL argument");
   if (int rc = check_params(p)) return rc;
-  hipError_t e = launch_diag(g, p, t, U, dus, out, S(stream));
+  if (int rc = check_2d(g, p, dus)) return rc;
+  hipError_t e = g->dim == 2 ? launch_diag_2d(g, U, out, S(stream))
+                             : launch_diag(g, p, t, U, dus, out, S(stream));
   if (e != hipSuccess) return hipfail(e, "diagnostics launch");
   double h[10];
   e = hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, S(stream));
@@ -397,13 +431,17 @@ int wacm_threshold_blocks(wacm_grid* g, const wacm_params* p, double t, const vo
   if (!elem_ok(g) || !U || !dmax || !mrange || !flags) return fail(WACM_E_INVAL, "NULL argument");
   if (int rc = check_params(p)) return rc;
   if (!(eps >= 0)) return fail(WACM_E_INVAL, "eps must be >= 0");
-  hipError_t e = launch_threshold(g, p, t, U, eps, dealias, dmax, mrange, flags, S(stream));
+  if (int rc = check_2d(g, p, nullptr)) return rc;
+  hipError_t e = g->dim == 2
+                     ? launch_threshold_2d(g, U, eps, dealias, dmax, mrange, flags, S(stream))
+                     : launch_threshold(g, p, t, U, eps, dealias, dmax, mrange, flags, S(stream));
   return e == hipSuccess ? WACM_OK : hipfail(e, "threshold_blocks launch");
 }
 
 int wacm_filter_blocks(wacm_grid* g, void* U, int32_t level, void* stream) {
   GridScope gs(g);
   if (!elem_ok(g) || !U) return fail(WACM_E_INVAL, "NULL argument");
+  if (int rc = not_2d(g, "wavelet filtering")) return rc;
   if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "filtering is CDF 4/0 only");
   hipError_t e = launch_filter(g, U, level, S(stream));
   return e == hipSuccess ? WACM_OK : hipfail(e, "filter_blocks launch");
@@ -428,6 +466,7 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
     return true;
   };
   int64_t nwork = 0;
+  const int nchild = g->dim == 2 ? 4 : 8;  // children of a block
   if (op == WACM_REFINE_ALL) {
     for (int64_t i = 0; i < g->nb; ++i) {
       const Leaf& l = g->leaves[i];
@@ -436,7 +475,7 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
         newslots.push_back(g->slots[i]);
         continue;
       }
-      for (int c = 0; c < 8; ++c) {
+      for (int c = 0; c < nchild; ++c) {
         Leaf ch{l.J + 1, 2 * l.x + (c & 1), 2 * l.y + ((c >> 1) & 1), 2 * l.z + ((c >> 2) & 1)};
         int32_t s;
         if (!take(s)) return fail(WACM_E_CAPACITY, "refinement needs more pool slots");
@@ -462,7 +501,7 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
       int64_t sidx[8];
       int64_t px = l.x >> 1, py = l.y >> 1, pz = l.z >> 1;
       if (merge) {
-        for (int c = 0; c < 8 && merge; ++c) {
+        for (int c = 0; c < nchild && merge; ++c) {
           const int32_t si = g->index.find(
               leaf_key(l.J, 2 * px + (c & 1), 2 * py + ((c >> 1) & 1), 2 * pz + ((c >> 2) & 1)));
           if (si < 0 || !flags[si]) {
@@ -478,14 +517,17 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
         // check the level-(J+1) boxes around the parent box
         const int64_t n1 = int64_t(1) << (l.J + 1);
         int64_t base[3] = {4 * px, 4 * py, 4 * pz};  // parent origin in level-(J+1) boxes
-        for (int dz = -1; dz <= 4 && merge; ++dz)
+        // in two dimensions only the plane z = 0: the z offset is 0 and the
+        // z range counts as inside
+        const int dz0 = g->dim == 2 ? 0 : -1, dz1 = g->dim == 2 ? 0 : 4;
+        for (int dz = dz0; dz <= dz1 && merge; ++dz)
           for (int dy = -1; dy <= 4 && merge; ++dy)
             for (int dx = -1; dx <= 4 && merge; ++dx) {
               bool inside = dx >= 0 && dx < 4 && dy >= 0 && dy < 4 && dz >= 0 && dz < 4;
               if (inside) continue;
               int64_t bx = ((base[0] + dx) % n1 + n1) % n1;
               int64_t by = ((base[1] + dy) % n1 + n1) % n1;
-              int64_t bz = ((base[2] + dz) % n1 + n1) % n1;
+              int64_t bz = g->dim == 2 ? 0 : ((base[2] + dz) % n1 + n1) % n1;
               // is this level-(J+1) box covered by a leaf of level <= J ?
               bool covered = false;
               for (int K = l.J; K >= g->d.jmin && !covered; --K) {
@@ -508,6 +550,10 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
       newslots.push_back(s);
       list.push_back(s);
       for (int c = 0; c < 8; ++c) {
+        if (c >= nchild) {
+          list.push_back(-1);
+          continue;
+        }
         list.push_back(sis[c]);
         done[sidx[c]] = 1;
         freed.push_back(sis[c]);
@@ -521,6 +567,7 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
   // commit: new leaf set and its tables (validated before anything on the device changes)
   wacm_grid tmp;
   tmp.d = g->d;
+  tmp.dim = g->dim;
   tmp.P = g->P;
   tmp.leaves = newleaves;
   tmp.slots = newslots;
@@ -538,7 +585,10 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
     e = hipMemcpyAsync(g->d_list, list.data(), sizeof(int32_t) * list.size(),
                        hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hipfail(e, "adapt list upload");
-    if (op == WACM_REFINE_ALL)
+    if (g->dim == 2)
+      e = op == WACM_REFINE_ALL ? launch_prolong_2d(g, U, nwork, st)
+                                : launch_decimate_2d(g, U, nwork, st);
+    else if (op == WACM_REFINE_ALL)
       e = launch_prolong(g, U, nwork, st);
     else
       e = g->wavelet == WACM_CDF44 ? launch_lift_coarsen(g, U, nwork, st)
@@ -574,6 +624,7 @@ size_t wacm_adj_plan_bytes(wacm_grid* g, int32_t face_only) {
 int wacm_adj_plan_set(wacm_grid* g, int32_t face_only, void* ws, size_t ws_bytes) {
   GridScope gs(g);
   if (!elem_ok(g) || !ws) return fail(WACM_E_INVAL, "NULL argument");
+  if (int rc = not_2d(g, "the adjoint")) return rc;
   if (face_only != 0 && face_only != 1) return fail(WACM_E_INVAL, "face_only must be 0 or 1");
   if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "the adjoint is CDF 4/0 only");
   if (reinterpret_cast<uintptr_t>(ws) % 256)
@@ -586,6 +637,7 @@ int wacm_adj_plan_set(wacm_grid* g, int32_t face_only, void* ws, size_t ws_bytes
 int wacm_sync_ghosts_adj(wacm_grid* g, void* Ub, void* stream) {
   GridScope gs(g);
   if (!elem_ok(g) || !Ub) return fail(WACM_E_INVAL, "NULL argument");
+  if (int rc = not_2d(g, "the adjoint")) return rc;
   if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "the adjoint is CDF 4/0 only");
   if (!g->plan[0].built)
     return fail(WACM_E_INVAL, "no plan of the ghost-fill transpose: wacm_adj_plan_set(grid, 0, ...)");
@@ -597,6 +649,7 @@ int wacm_rhs_acm_adj(wacm_grid* g, const wacm_params* p, double t, const void* U
                      void* Ub, double* dtheta, double* dusbar, const void* dus, void* stream) {
   GridScope gs(g);
   if (!elem_ok(g) || !U || !V || !Ub || !dtheta) return fail(WACM_E_INVAL, "NULL argument");
+  if (int rc = not_2d(g, "the adjoint")) return rc;
   if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "the adjoint is CDF 4/0 only");
   if (int rc = check_params(p)) return rc;
   hipError_t e = launch_rhs_adj(g, p, t, U, V, Ub, dtheta, dusbar, dus, S(stream));
@@ -607,6 +660,7 @@ int wacm_force_adj(wacm_grid* g, const wacm_params* p, double t, double weight, 
                    void* Ub, double* dtheta, double* dusbar, const void* dus, void* stream) {
   GridScope gs(g);
   if (!elem_ok(g) || !U || !Ub || !dtheta) return fail(WACM_E_INVAL, "NULL argument");
+  if (int rc = not_2d(g, "the adjoint")) return rc;
   if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "the adjoint is CDF 4/0 only");
   if (int rc = check_params(p)) return rc;
   hipError_t e = launch_force_adj(g, p, t, weight, U, Ub, dtheta, dusbar, dus, S(stream));
@@ -618,6 +672,7 @@ int wacm_rk4_step_adj(wacm_grid* g, const wacm_params* p, double t, double dt, c
                       void* stream) {
   GridScope gs(g);
   if (!elem_ok(g) || !Un || !lam || !dtheta || !work) return fail(WACM_E_INVAL, "NULL argument");
+  if (int rc = not_2d(g, "the adjoint")) return rc;
   if (g->wavelet != WACM_CDF40) return fail(WACM_E_INVAL, "the adjoint is CDF 4/0 only");
   if (reinterpret_cast<uintptr_t>(work) % 256) return fail(WACM_E_INVAL, "work not 256-aligned");
   if (int rc = check_params(p)) return rc;

@@ -59,8 +59,11 @@ void reorder_leaves(wacm_grid* g) {
 }
 
 
+// In two dimensions only the 9 regions of the plane (rz = 1) and the 4
+// sub-boxes with sz = 0 are filled; the others stay unused.
 int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err) {
   const int64_t nb = g->nb;
+  const int rz0 = g->dim == 2 ? 1 : 0, rz1 = g->dim == 2 ? 1 : 2, nsub = g->dim == 2 ? 4 : 8;
   tabs.assign(nb, Tab{});
   for (int64_t i = 0; i < nb; ++i) {
     const Leaf& b = g->leaves[i];
@@ -71,7 +74,7 @@ int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err) {
     t.meta[3] = (int32_t)b.y;
     t.meta[4] = (int32_t)b.z;
     const int64_t n = int64_t(1) << b.J;
-    for (int rz = 0; rz < 3; ++rz)
+    for (int rz = rz0; rz <= rz1; ++rz)
       for (int ry = 0; ry < 3; ++ry)
         for (int rx = 0; rx < 3; ++rx) {
           int r = rx + 3 * ry + 9 * rz;
@@ -93,7 +96,7 @@ int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err) {
           // the neighbour box must be split into level-(J+1) leaves; every
           // sub-box touching this block has to be a leaf (2:1 grading)
           bool anyfine = false;
-          for (int s = 0; s < 8; ++s) {
+          for (int s = 0; s < nsub; ++s) {
             int sx = s & 1, sy = (s >> 1) & 1, sz = (s >> 2) & 1;
             bool touch = (rx == 1 || sx == (rx == 0 ? 1 : 0)) &&
                          (ry == 1 || sy == (ry == 0 ? 1 : 0)) &&

@@ -1872,6 +1872,25 @@ hipError_t launch_prolong(const wacm_grid* g, void* U, int64_t n, hipStream_t st
                                 : prolong_t(g, (float*)U, n, st);
 }
 
+// reductions shared with the two-dimensional path (kernels2d.hip)
+hipError_t finalize_dt(const double* part, int64_t n, const wacm_params& p, double hmin,
+                       double* dt_dev, hipStream_t st) {
+  dt_finalize<<<1, NT_GEN, 0, st>>>(part, n, p, hmin, dt_dev);
+  return hipGetLastError();
+}
+hipError_t finalize_diag(const double* part, int64_t n, double* out, hipStream_t st) {
+  diag_finalize<<<1, NT_GEN, 0, st>>>(part, n, out);
+  return hipGetLastError();
+}
+hipError_t finalize_norm(const double* part, int64_t n, double* norm, hipStream_t st) {
+  norm_finalize<<<1, NT_GEN, 0, st>>>(part, n, norm);
+  return hipGetLastError();
+}
+hipError_t add_dt_to_time(double* t_dev, const double* dt_dev, hipStream_t st) {
+  advance_time<<<1, 64, 0, st>>>(t_dev, dt_dev);
+  return hipGetLastError();
+}
+
 hipError_t launch_decimate(const wacm_grid* g, void* U, int64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (g->d.dtype == WACM_F64)

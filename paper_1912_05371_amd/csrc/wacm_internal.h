@@ -159,6 +159,7 @@ size_t lift_ws_bytes(int64_t capacity, int bs, int ng, size_t es);
 
 struct wacm_grid {
   wacm_grid_desc d{};
+  int dim = 3;  // 3: octree, 2: quadtree (leaves with z index 0)
   int P = 0;
   int64_t nb = 0;
   std::vector<wacm::Leaf> leaves;      // active, Morton order
@@ -266,5 +267,21 @@ hipError_t launch_rk4_adj(const wacm_grid* g, const wacm_params* p, double t, do
                           const void* Un, void* lam, double* dtheta, double* dusbar,
                           const void* dus, void* work, hipStream_t st);
 hipError_t profile_flush(const wacm_grid* g);  // accumulate recorded events
+
+// two dimensions (kernels2d.hip): pool [slot][3][P][P]; the RK4 work buffer
+// holds 3 pool-shaped registers
+size_t work_bytes_2d(const wacm_grid* g);
+hipError_t launch_sync_2d(const wacm_grid* g, void* U, hipStream_t st);
+hipError_t launch_rhs_2d(const wacm_grid* g, const wacm_params* p, const void* U, void* dU,
+                         hipStream_t st);
+hipError_t launch_dt_2d(const wacm_grid* g, const wacm_params* p, const void* U, double* dt_dev,
+                        hipStream_t st);
+hipError_t launch_rk4_2d(const wacm_grid* g, const wacm_params* p, double* t_dev, double* dt_dev,
+                         void* U, void* work, int dt_mode, int64_t nsteps, hipStream_t st);
+hipError_t launch_diag_2d(const wacm_grid* g, const void* U, double* out, hipStream_t st);
+hipError_t launch_threshold_2d(const wacm_grid* g, const void* U, double eps, int dealias,
+                               double* dmax, double* mrange, int8_t* flags, hipStream_t st);
+hipError_t launch_prolong_2d(const wacm_grid* g, void* U, int64_t n, hipStream_t st);
+hipError_t launch_decimate_2d(const wacm_grid* g, void* U, int64_t n, hipStream_t st);
 
 }  // namespace wacm

@@ -39,7 +39,7 @@ MR_SCRATCH_BYTES = 64 << 20  # WACM_MR_SCRATCH_BYTES
 
 class GridDesc(C.Structure):
     _fields_ = [("bs", C.c_int32), ("ng", C.c_int32), ("jmin", C.c_int32), ("jmax", C.c_int32),
-                ("dtype", C.c_int32), ("reserved", C.c_int32), ("capacity", C.c_int64),
+                ("dtype", C.c_int32), ("dim", C.c_int32), ("capacity", C.c_int64),
                 ("L", C.c_double)]
 
 
@@ -260,11 +260,15 @@ def mr_inverse(u, nlev: int, wavelet: int = CDF40, work=None, stream=None):
 class Grid:
     """Opaque grid handle plus the geometry needed to shape tensors."""
 
-    def __init__(self, bs, ng, L, jmin, jmax, treecodes, levels, dtype=F64, capacity=None):
+    def __init__(self, bs, ng, L, jmin, jmax, treecodes, levels, dtype=F64, capacity=None,
+                 dim=3):
+        """dim 3: octree; dim 2: quadtree (treecodes of (bx, by, 0), pool of 3
+        fields (u, v, p) per slot, P^2 values each)."""
         treecodes = np.ascontiguousarray(treecodes, np.uint64)
         levels = np.ascontiguousarray(levels, np.int8)
         n = len(treecodes)
-        self.desc = GridDesc(int(bs), int(ng), int(jmin), int(jmax), int(dtype), 0,
+        self.dim = int(dim)
+        self.desc = GridDesc(int(bs), int(ng), int(jmin), int(jmax), int(dtype), self.dim,
                              int(capacity if capacity is not None else n), float(L))
         self._h = None
         nbytes = int(lib().wacm_workspace_bytes(C.byref(self.desc)))
@@ -287,6 +291,10 @@ class Grid:
 
     @classmethod
     def from_case(cls, case, dtype=F64, capacity=None):
+        if not hasattr(case, "iz"):  # a two-dimensional case
+            codes = [treecode_encode(l, x, y, 0) for l, x, y in zip(case.lev, case.ix, case.iy)]
+            return cls(case.bs, case.ng, case.L, case.jmin, case.jmax, codes, case.lev, dtype,
+                       capacity, dim=2)
         codes = [treecode_encode(l, x, y, z) for l, x, y, z in
                  zip(case.lev, case.ix, case.iy, case.iz)]
         return cls(case.bs, case.ng, case.L, case.jmin, case.jmax, codes, case.lev, dtype,
@@ -334,20 +342,24 @@ class Grid:
         import torch
         return torch.float64 if self.dtype == F64 else torch.float32
 
+    def pool_shape(self):
+        if self.dim == 2:
+            return (self.capacity, 3, self.P, self.P)
+        return (self.capacity, 4, self.P, self.P, self.P)
+
     def pool(self, device="cuda"):
         import torch
-        return torch.zeros((self.capacity, 4, self.P, self.P, self.P), dtype=self.torch_dtype(),
-                           device=device)
+        return torch.zeros(self.pool_shape(), dtype=self.torch_dtype(), device=device)
 
     def work(self, device="cuda"):
         import torch
         return torch.empty(self.work_bytes(), dtype=torch.uint8, device=device)
 
     def _chk_pool(self, U):
-        if tuple(U.shape) != (self.capacity, 4, self.P, self.P, self.P) or \
+        if tuple(U.shape) != self.pool_shape() or \
                 U.dtype != self.torch_dtype() or not U.is_contiguous() or not U.is_cuda:
             raise ValueError("pool tensor must be a contiguous CUDA tensor of shape "
-                             f"{(self.capacity, 4, self.P, self.P, self.P)} / {self.torch_dtype()}")
+                             f"{self.pool_shape()} / {self.torch_dtype()}")
 
     @staticmethod
     def _chk_vec(t, n, dtype_name, what):

@@ -59,8 +59,8 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
 FAKE_DEV = 1 << 40  # 256-byte aligned, never dereferenced
 
 
-def _desc(bs=16, ng=4, jmin=1, jmax=3, dtype=wacm.F64, cap=64, L=1.0, reserved=0):
-    return wacm.GridDesc(bs, ng, jmin, jmax, dtype, reserved, cap, L)
+def _desc(bs=16, ng=4, jmin=1, jmax=3, dtype=wacm.F64, cap=64, L=1.0, dim=3):
+    return wacm.GridDesc(bs, ng, jmin, jmax, dtype, dim, cap, L)
 
 
 def _create(desc, leaves, ws=FAKE_DEV, ws_bytes=None):
@@ -87,7 +87,7 @@ def test_workspace_bytes():
     a = int(L.wacm_workspace_bytes(ctypes.byref(_desc(cap=64))))
     b = int(L.wacm_workspace_bytes(ctypes.byref(_desc(cap=128))))
     assert a > 64 * 928 and b > a and a % 256 == 0 and b % 256 == 0
-    for bad in (_desc(bs=18), _desc(ng=2), _desc(dtype=3), _desc(cap=0), _desc(reserved=1),
+    for bad in (_desc(bs=18), _desc(ng=2), _desc(dtype=3), _desc(cap=0), _desc(dim=1),
                 _desc(jmin=4, jmax=3), _desc(L=0.0)):
         assert L.wacm_workspace_bytes(ctypes.byref(bad)) == 0
 
@@ -95,7 +95,7 @@ def test_workspace_bytes():
 def test_grid_create_inval():
     leaves = _uniform(1)
     for desc, what in ((_desc(bs=20), "bs"), (_desc(ng=2), "ng"), (_desc(dtype=0), "dtype"),
-                       (_desc(cap=4), "capacity"), (_desc(reserved=7), "reserved")):
+                       (_desc(cap=4), "capacity"), (_desc(dim=7), "dim")):
         rc, msg = _create(desc, leaves)
         assert rc == wacm.E_INVAL, (what, rc)
         assert msg
@@ -129,6 +129,32 @@ def test_grid_create_unbalanced():
     l3 = [(3, 2 + (c & 1), 2 + ((c >> 1) & 1), 2 + ((c >> 2) & 1)) for c in range(8)]
     rc, msg = _create(_desc(jmax=3, cap=64), leaves + l2 + l3)
     assert rc == wacm.E_UNBALANCED and "balanced" in msg
+
+
+def _uniform2(J):
+    n = 1 << J
+    return [(J, x, y, 0) for y in range(n) for x in range(n)]
+
+
+def test_grid_create_2d_errors():
+    # quadtrees: treecodes of (bx, by, 0), areas add up in 2D, 2:1 in the plane
+    leaves = _uniform2(2)
+    d2 = _desc(jmin=1, jmax=3, dim=2)
+    rc, msg = _create(d2, leaves[:-1])
+    assert rc == wacm.E_TILING and "cover" in msg
+    rc, msg = _create(d2, leaves[:-1] + [(2, 3, 3, 1)])  # a z index in 2D
+    assert rc == wacm.E_INVAL and "two dimensions" in msg
+    rc, msg = _create(d2, leaves + [leaves[0]])
+    assert rc == wacm.E_TILING
+    # level 1 next to level 3: (1, 1, 1, 0) replaced by level-2 children,
+    # one of which is split to level 3 at the corner touching level 1
+    base = [(1, x, y, 0) for y in range(2) for x in range(2) if (x, y) != (0, 0)]
+    l2 = [(2, x, y, 0) for y in range(2) for x in range(2) if (x, y) != (0, 0)]
+    l3 = [(3, x, y, 0) for y in range(2) for x in range(2)]
+    rc, msg = _create(d2, base + l2 + l3)
+    assert rc == wacm.E_UNBALANCED
+    # the octree reading of the same codes is not a tiling of the cube
+    assert _create(_desc(jmin=2, jmax=2), leaves)[0] == wacm.E_TILING
 
 
 def test_mr_work_buffer_checked_before_launch():

@@ -110,3 +110,54 @@ def test_lift_items_match_resolver(harness, tmp_path, bs):
         assert r.returncode == 0, (r.returncode, r.stderr)
         n = int(r.stdout.split()[2].rstrip(","))
         assert n > 0
+
+
+# ---------------------------------------------------------------- two dimensions
+BIN2 = os.path.join(ROOT, "_build", "resolver2d_harness")
+
+
+@pytest.fixture(scope="module")
+def harness2d():
+    os.makedirs(os.path.dirname(BIN2), exist_ok=True)
+    cmd = ["/opt/rocm/bin/hipcc", "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-DWACM_HOST_CHECK",
+           "-O1", "-std=c++17", "-I/opt/rocm/include", f"-I{os.path.join(ROOT, 'include')}",
+           f"-I{CSRC}", "-o", BIN2, os.path.join(ROOT, "tests", "resolver2d_harness.cpp"),
+           os.path.join(CSRC, "grid.cpp")]
+    subprocess.run(cmd, check=True)
+    return BIN2
+
+
+def run_case2d(orc, harness, tmp_path, bs, ng, L, jmin, jmax, lev, ix, iy, seed=0):
+    og = orc.Grid2D(bs, ng, L, jmin, jmax, lev, ix, iy)
+    P = bs + 2 * ng
+    U = np.random.default_rng(seed).standard_normal((og.nb, 3, P, P))
+    lf = tmp_path / "leaves2.txt"
+    with open(lf, "w") as f:
+        f.write(f"{bs} {ng} {L!r} {jmin} {jmax} {og.nb} {og.nb}\n")
+        for l, x, y in zip(lev, ix, iy):
+            f.write(f"{l} {x} {y}\n")
+    U.tofile(tmp_path / "in2.bin")
+    r = subprocess.run([harness, str(lf), str(tmp_path / "in2.bin"), str(tmp_path / "out2.bin")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    Ug = np.fromfile(tmp_path / "out2.bin").reshape(U.shape)
+    Uo = U.copy()
+    og.sync(Uo)
+    assert np.max(np.abs(Ug - Uo)) <= 8 * np.finfo(float).eps * np.max(np.abs(Uo))
+    return og.nb
+
+
+@pytest.mark.parametrize("bs,ng", [(16, 4), (24, 4), (16, 5), (32, 4), (32, 6)])
+def test_2d_random_quadtrees(orc, harness2d, tmp_path, bs, ng):
+    for seed in range(3):
+        lev, ix, iy = inputs.random_balanced_leaves2(60 + seed, 1, 5, 120)
+        run_case2d(orc, harness2d, tmp_path, bs, ng, 1.0, 1, 5, lev, ix, iy, seed)
+
+
+def test_2d_small_and_refined(orc, harness2d, tmp_path):
+    for J in (0, 1):  # a block that is its own neighbour; 2 x 2 blocks
+        lev, ix, iy = inputs.uniform_leaves2(J)
+        run_case2d(orc, harness2d, tmp_path, 16, 4, 1.0, 0, 2, lev, ix, iy)
+    c = cases.three_vortices_adaptive(bs=16, ng=4, jmin=2, jmax=5, jstart=5, radius=0.6)
+    assert run_case2d(orc, harness2d, tmp_path, c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix,
+                      c.iy) == c.nb
