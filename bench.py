@@ -476,6 +476,147 @@ def small_configs_gpu():
     return out
 
 
+def _lattice_of(g, pool, N):
+    """Interior values of a 2D pool assembled into N x N lattice arrays
+    ([c][y, x]) at the points the grid holds (NaN elsewhere)."""
+    slots, codes, levels = g.info()
+    out = np.full((3, N, N), np.nan)
+    bs = g.bs
+    P = pool[:, :, g.ng:g.ng + bs, g.ng:g.ng + bs].double().cpu().numpy()
+    from paper_1912_05371_amd import wacm
+    for s, code, J in zip(slots, codes, levels):
+        bx, by, _ = wacm.treecode_decode(int(code), int(J))
+        st = N // ((1 << int(J)) * bs)
+        gx = (bx * bs + np.arange(bs)) * st
+        gy = (by * bs + np.arange(bs)) * st
+        out[:, gy[:, None], gx[None, :]] = P[s]
+    return out
+
+
+def vortex_study(T_eq: float = 1.0, T_ad: float = 0.5):
+    """The three vortices in two dimensions on the GPU.
+
+    Self-convergence of the equidistant runs: levels J = 3..6 (N = 128..1024
+    points per axis, blocks of 16^2), all with the time step of the finest
+    (CFL 0.5 at N = 1024), to t = T_eq; the error of each run is the max-norm
+    difference of (u, v) from the finest run at its own points, relative to
+    the finest field's max norm, and the observed order log2(e_N / e_2N).
+
+    Thresholding error of adaptive runs (refine, step, coarsen every step,
+    CDF 4/0): Jmax = 4 (N = 256), eps = 1e-2 .. 1e-6, the start grid obtained
+    by coarsening the uniform level-4 initial field until no family merges;
+    error against the equidistant level-4 run with the same time step, at the
+    adaptive grid's points, to t = T_ad.  Without dealiasing the error is the
+    thresholding error alone and vanishes with eps; with dealiasing every
+    level-4 block is coarsened after each step, so the runs approach the
+    level-4 evolution of level-3 data instead."""
+    import torch
+
+    from paper_1912_05371_amd import cases, wacm
+    from paper_1912_05371_amd.adaptive import adaptive_step
+
+    prm = cases.three_vortex_params()
+    p = wacm.make_params(prm)
+
+    def uniform_run(J, dt, T):
+        c = cases.three_vortices(bs=16, ng=4, J=J)
+        g = wacm.Grid.from_case(c, dtype=wacm.F64)
+        U = g.pool()
+        U[:c.nb] = torch.from_numpy(c.padded()).cuda()
+        work = g.work()
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dtd = torch.tensor([dt], dtype=torch.float64, device="cuda")
+        n = int(math.ceil(T / dt - 1e-9))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.rk4_steps(None, t, dtd, U, work, n, dt_mode=wacm.DT_FIXED, _p=p)
+        e1.record()
+        torch.cuda.synchronize()
+        lat = _lattice_of(g, U, (1 << J) * 16)
+        return lat, n, e0.elapsed_time(e1) / n, c.nb
+
+    # the finest run's CFL time step
+    cf = cases.three_vortices(bs=16, ng=4, J=6)
+    gf = wacm.Grid.from_case(cf, dtype=wacm.F64)
+    Uf = gf.pool()
+    Uf[:cf.nb] = torch.from_numpy(cf.padded()).cuda()
+    dtt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gf.compute_dt(prm, Uf, dtt)
+    dt_f = float(dtt.item())
+    del Uf, gf
+    runs = {}
+    for J in (6, 5, 4, 3):
+        lat, n, ms, nb = uniform_run(J, dt_f, T_eq)
+        runs[J] = lat
+        log(f"  vortices level {J} ({nb} blocks): {n} steps, {ms:.3f} ms/step")
+    ref = runs[6]
+    scale = np.max(np.abs(ref[:2]))
+    eq = []
+    for J in (3, 4, 5):
+        st = 1 << (6 - J)
+        e = float(np.max(np.abs(runs[J][:2] - ref[:2, ::st, ::st])) / scale)
+        eq.append({"level": J, "N": (1 << J) * 16, "rel_err_vs_N1024": e})
+    for a, b in zip(eq, eq[1:]):
+        a["order_to_next"] = round(math.log2(a["rel_err_vs_N1024"] / b["rel_err_vs_N1024"]), 3)
+
+    # thresholding error
+    jmax = 4
+    c4 = cases.three_vortices(bs=16, ng=4, J=jmax)
+    g4 = wacm.Grid.from_case(c4, dtype=wacm.F64)
+    U4 = g4.pool()
+    U4[:c4.nb] = torch.from_numpy(c4.padded()).cuda()
+    g4.compute_dt(prm, U4, dtt)
+    dt4 = float(dtt.item())
+    del U4, g4
+    ref4, n4, _, _ = uniform_run(jmax, dt4, T_ad)
+    scale4 = np.max(np.abs(ref4[:2]))
+    ad = {False: [], True: []}
+    for dealias, eps in [(d, e) for d in (False, True) for e in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6)]:
+        c = cases.three_vortices(bs=16, ng=4, J=jmax)
+        c.jmin = 1
+        # refine-all holds a grid's blocks and their children at once
+        g = wacm.Grid.from_case(c, dtype=wacm.F64, capacity=2 * c.nb)
+        U = g.pool()
+        U[:c.nb] = torch.from_numpy(c.padded()).cuda()
+        # start grid: coarsen the fully resolved initial field
+        for _ in range(8):
+            n0 = g.nb
+            dm = torch.empty(n0, dtype=torch.float64, device="cuda")
+            mr = torch.empty(n0, dtype=torch.float64, device="cuda")
+            fl = torch.empty(n0, dtype=torch.int8, device="cuda")
+            g.sync_ghosts(U)
+            g.threshold_blocks(prm, 0.0, U, eps, False, dm, mr, fl)
+            if g.adapt(wacm.COARSEN, U, fl.cpu().numpy()) == n0:
+                break
+        nb_start = g.nb
+        work = g.work()
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dtd = torch.tensor([dt4], dtype=torch.float64, device="cuda")
+        nbs = []
+        wall0 = time.perf_counter()
+        for _ in range(n4):
+            adaptive_step(g, prm, U, work, t, dtd, eps, dealias, dt_mode=wacm.DT_FIXED)
+            nbs.append(g.nb)
+        wall = time.perf_counter() - wall0
+        lat = _lattice_of(g, U, (1 << jmax) * 16)
+        m = ~np.isnan(lat[0])
+        e = float(np.max(np.abs(lat[:2][:, m] - ref4[:2][:, m])) / scale4)
+        ad[dealias].append({"eps": eps, "rel_err_vs_equidistant": e, "blocks_start": nb_start,
+                   "blocks_mean": round(float(np.mean(nbs)), 1), "blocks_end": nbs[-1],
+                   "grid_fraction_end": round(nbs[-1] * 16 * 16 / float((1 << jmax) * 16) ** 2,
+                                              4),
+                   "steps": n4, "ms_per_adaptive_step": round(wall / n4 * 1e3, 3)})
+        log(f"  adaptive eps {eps:g} dealias {dealias}: {nb_start} -> {nbs[-1]} blocks, "
+            f"rel err {e:.3e}")
+        del U, work, g
+    torch.cuda.empty_cache()
+    return {"case": "three Gaussian vortices, [0,2pi)^2, nu 5e-5, C0 10, C_gamma 1, FP64, "
+                    "blocks of 16^2, CDF 4/0",
+            "equidistant": {"t_end": T_eq, "dt": dt_f, "runs": eq},
+            "adaptive": {"t_end": T_ad, "dt": dt4, "jmax": jmax, "runs": ad[False],
+                         "runs_dealias": ad[True]}}
+
+
 def lifting_timings(seed: int):
     """CDF 4/4 (lifted restriction) on a random octree with 6 ghost layers
     (bs 24, levels 3-6, ~4000 blocks, FP64): the full ghost sync with CDF 4/0
@@ -716,6 +857,9 @@ def main():
     ap.add_argument("--c3-run", type=int, default=0, metavar="STEPS",
                     help="run the adaptive rotating-plate case for STEPS steps (FP64 free, "
                          "FP32 replaying its flags) and print drift and flag disagreements")
+    ap.add_argument("--vortex-study", action="store_true",
+                    help="two-dimensional three-vortex runs: self-convergence of equidistant "
+                         "runs and the thresholding error of adaptive runs")
     ap.add_argument("--mr-only", action="store_true",
                     help="time only the multiresolution transform (256^3 x 4, 5 levels) and "
                          "print its figures")
@@ -733,6 +877,9 @@ def main():
     wacm.lib()
     if args.c3_run:
         print(json.dumps({"c3_run": c3_run(args.c3_run)}), flush=True)
+        return
+    if args.vortex_study:
+        print(json.dumps({"vortex_study": vortex_study()}), flush=True)
         return
     if args.mr_only:
         if args.copy_probe > 0:
