@@ -218,6 +218,12 @@ struct StageArgs {
   const double* t_dev;
   const double* dt_dev;
   double* umax_part;  // stage 4: per work item max |u|^2 of the new U^n, or null
+  // optional block list: the blocks of this launch are blist[off + i],
+  // i < bcnt[bsel], off = bsel ? bcnt[0] : 0 (the list holds the blocks
+  // without penalization first, then the others; null: every block)
+  const int32_t* blist;
+  const int32_t* bcnt;
+  int bsel;
   double t_host;
   double L;
   int xcd_map;  // 1: give each XCD a contiguous run of work items
@@ -443,7 +449,12 @@ void stage_kernel(StageArgs<T> a) {
   // work items: static (round-robin or contiguous per XCD) or from the
   // per-XCD queues, whose next item thread 0 requests while the current one
   // is processed and publishes in qitem before the loop's first barrier
-  const int64_t nitems = a.nb * NTY;
+  int64_t nblk = a.nb, boff = 0;
+  if (a.blist) {
+    boff = a.bsel ? a.bcnt[0] : 0;
+    nblk = a.bcnt[a.bsel];
+  }
+  const int64_t nitems = nblk * NTY;
   const bool dyn = a.queue != nullptr;
   BlockIter it(nitems, a.xcd_map);
   int qh = blockIdx.x & 7, qpend = 0;
@@ -455,8 +466,9 @@ void stage_kernel(StageArgs<T> a) {
     const int64_t item = dyn ? (int64_t)__builtin_amdgcn_readfirstlane(qitem) : it.ib;
     if (item >= (dyn ? nitems : it.end)) break;
     if (!dyn) it.ib += it.step;
-    const int64_t ibk = item / NTY;
-    const int y0 = (int)(item - ibk * NTY) * TY;
+    const int64_t il = item / NTY;
+    const int64_t ibk = a.blist ? a.blist[boff + il] : il;
+    const int y0 = (int)(item - il * NTY) * TY;
     const int y = y0 + yl;
     if (tid < 6) fds[tid] = face_desc<T, BS, GH>(a.tab[ibk], a, tid, xin);
     if (tid < 5) meta[tid] = a.tab[ibk].meta[tid];
@@ -699,7 +711,7 @@ void stage_kernel(StageArgs<T> a) {
         double mx = red[0];
 #pragma unroll
         for (int w = 1; w < NT / 64; ++w) mx = fmax(mx, red[w]);
-        a.umax_part[item] = mx;
+        a.umax_part[boff * NTY + item] = mx;
       }
     }
     if (dyn && tid == 0) qitem = queue_take(a.queue, qh, qchunk, (int)nitems, qpend);
@@ -1362,6 +1374,66 @@ __global__ __launch_bounds__(NT_GEN) void decimate_kernel(const int32_t* __restr
 }
 
 // --------------------------------------------------------------------------
+// blocks without penalization
+// --------------------------------------------------------------------------
+// One workgroup of 1024 threads: list = the far blocks (active order), then
+// the others; cnt = {far count, other count}.  Each thread classifies a
+// contiguous run of blocks twice (count, then place), with a workgroup
+// prefix sum of the counts between, so that each part keeps the active
+// (Morton) order.  With t_dev given, the plate is classified for the pitch
+// angles of the window [t, t + dt] of one step; else for every angle.
+__global__ __launch_bounds__(1024) void pen_classify(const Tab* __restrict__ tab, int64_t nb,
+                                                     wacm_params p, double L, int bs,
+                                                     const double* __restrict__ t_dev,
+                                                     const double* __restrict__ dt_dev,
+                                                     int32_t* __restrict__ list,
+                                                     int32_t* __restrict__ cnt) {
+  __shared__ int32_t wsum[2][16], woff[2][16], tot[2];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  PitchWindow win{0.0, 0.0, false};
+  if (t_dev) win = pitch_window(p, *t_dev, *t_dev + *dt_dev);
+  const int64_t per = (nb + 1023) / 1024;
+  const int64_t b0 = t * per < nb ? t * per : nb, b1 = b0 + per < nb ? b0 + per : nb;
+  int32_t nf = 0, nn = 0;
+  for (int64_t b = b0; b < b1; ++b) (pen_far(p, L, bs, tab[b].meta, win) ? nf : nn) += 1;
+  // inclusive scans within the wave, then over the 16 waves' totals
+  int32_t sf = nf, sn = nn;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t xf = __shfl_up(sf, o), xn = __shfl_up(sn, o);
+    if (lane >= o) {
+      sf += xf;
+      sn += xn;
+    }
+  }
+  if (lane == 63) {
+    wsum[0][wv] = sf;
+    wsum[1][wv] = sn;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int32_t af = 0, an = 0;
+    for (int w = 0; w < 16; ++w) {
+      woff[0][w] = af;
+      woff[1][w] = an;
+      af += wsum[0][w];
+      an += wsum[1][w];
+    }
+    tot[0] = af;
+    tot[1] = an;
+    cnt[0] = af;
+    cnt[1] = an;
+  }
+  __syncthreads();
+  int32_t of = woff[0][wv] + sf - nf, on = tot[0] + woff[1][wv] + sn - nn;
+  for (int64_t b = b0; b < b1; ++b) {
+    if (pen_far(p, L, bs, tab[b].meta, win))
+      list[of++] = (int32_t)b;
+    else
+      list[on++] = (int32_t)b;
+  }
+}
+
+// --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
 static int num_cus() {
@@ -1593,6 +1665,18 @@ template <typename T, int BS, int MODE>
 static hipError_t stage_launch(const StageArgs<T>& a, const wacm_schedule& s, hipStream_t st) {
   const bool pen = a.p.mask || a.p.sponge || a.dus;
   const bool pref = s.prefetch < 0 ? sizeof(T) == 4 : s.prefetch != 0;
+  if (pen && a.blist) {
+    // the blocks where the penalization vanishes take the unpenalized
+    // variant, the others the penalized one
+    StageArgs<T> f = a, n = a;
+    f.bsel = 0;
+    n.bsel = 1;
+    hipError_t e = pref ? stage_launch_pp<T, BS, MODE, false, true>(f, s, st)
+                        : stage_launch_pp<T, BS, MODE, false, false>(f, s, st);
+    if (e != hipSuccess) return e;
+    return pref ? stage_launch_pp<T, BS, MODE, true, true>(n, s, st)
+                : stage_launch_pp<T, BS, MODE, true, false>(n, s, st);
+  }
   if (pen)
     return pref ? stage_launch_pp<T, BS, MODE, true, true>(a, s, st)
                 : stage_launch_pp<T, BS, MODE, true, false>(a, s, st);
@@ -1707,6 +1791,22 @@ static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
   Layout lins[4] = {Lp, Ls, Ls, Ls};
   const double hmin = g->d.L / (double(int64_t(1) << g->jfine) * g->d.bs);
   const int64_t items = stage_items(g);
+  // blocks without penalization first (the adaptation lists are free
+  // during a step: capacity entries of the list, then the 2 counts); a
+  // pitching plate is classified per step, for the angles of that step
+  const bool split = g->sched.pen_split && (p->mask || p->sponge || dus);
+  const bool split_step = split && p->mask == WACM_MASK_PLATE;
+  int32_t* const plist = g->d_list;
+  int32_t* const pcnt = g->d_list + g->d.capacity;
+  if (split) {
+    a.blist = plist;
+    a.bcnt = pcnt;
+  }
+  if (split && !split_step) {
+    pen_classify<<<1, 1024, 0, st>>>(g->d_tab, g->nb, *p, g->d.L, g->d.bs, nullptr, nullptr,
+                                     plist, pcnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   for (int64_t k = 0; k < nsteps; ++k) {
     if (dt_mode == WACM_DT_CFL) {
       ProfScope ps(g, 0, st);
@@ -1737,6 +1837,11 @@ static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
         if ((e = nlface_launch<T>(g, a.in, a.Lin, hb, st)) != hipSuccess) return e;
       }
       ProfScope ps(g, 2, st);
+      if (s == 0 && split_step) {
+        pen_classify<<<1, 1024, 0, st>>>(g->d_tab, g->nb, *p, g->d.L, g->d.bs, t_dev, dt_dev,
+                                         plist, pcnt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
       switch (s) {
         case 0:
           e = stage_dispatch<T, 1>(g->d.bs, a, g->sched, st);

@@ -298,4 +298,94 @@ WACM_HD inline void shell_point(int idx, int bs, int ng, int P, int mode, int& i
   }
 }
 
+// The pitch angles the plate takes over a time window [t0, t1]: alpha lies in
+// [am - da, am + da], am the angle at the window's midpoint, da from the
+// bound |d alpha / dt| <= |amp| 2 pi |freq| plus 1e-9 for the rounding of the
+// angle here and in the stage kernel.  on = false: no window (any angle).
+struct PitchWindow {
+  double am, da;
+  bool on;
+};
+
+WACM_HD inline PitchWindow pitch_window(const wacm_params& p, double t0, double t1) {
+  PitchWindow w{0.0, 0.0, false};
+  if (p.mask != WACM_MASK_PLATE) return w;
+  const double twopi = 6.283185307179586476925286766559;
+  w.am = p.amp * sin(twopi * p.freq * (0.5 * (t0 + t1)) + p.phase);
+  w.da = fabs(p.amp) * twopi * fabs(p.freq) * 0.5 * fabs(t1 - t0) + 1e-9;
+  w.on = true;
+  return w;
+}
+
+// A block "far" from the mask and the sponge gets chi = 0 and sponge 0 at
+// every interior point (at every time, or at every time of the window), so
+// the penalization terms of the rhs vanish exactly there and the
+// unpenalized stage kernel gives the same values.  Conservative tests, with
+// a margin of 40 w beyond the body where every tanh of the smoothed mask
+// (Sec. 2.2) is exactly +-1 in FP64; with clipping (chi < 1e-8 set to 0)
+// 12 w suffice: beyond it one tanh factor of the mask stays below 4e-11.
+//  - sphere: the distance from the centre to the block's point box exceeds
+//    R + 40 w;
+//  - plate, any angle: either the block's y points miss the span widened by
+//    40 w, or their distance from the pitch axis (x and z relative to x_le; a
+//    rotation about the axis keeps it) exceeds the farthest corner of the
+//    chord x thickness rectangle widened by 40 w;
+//  - plate, angles of a window: or the body-frame chord or thickness
+//    coordinate of every point of the box, at every angle of the window,
+//    misses the widened rectangle's range: bounded by its value at the box
+//    centre and the window's mid angle, plus the box's half-widths projected,
+//    plus da times the box's largest distance from the axis;
+//  - sponge: the block's extreme points lie inside [l_sp, L - l_sp] on every
+//    axis, evaluated with the same expressions as the stage kernel.
+WACM_HD inline bool pen_far(const wacm_params& p, double L, int bs, const int32_t* m,
+                            const PitchWindow& win) {
+  const double h = L / (double(int64_t(1) << m[1]) * bs);
+  double lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = (double)(m[2 + d] * bs) * h;
+    hi[d] = (double)(m[2 + d] * bs + bs - 1) * h;
+  }
+  if (p.sponge)
+    for (int d = 0; d < 3; ++d)
+      if (!(lo[d] >= p.l_sp && hi[d] <= L - p.l_sp)) return false;
+  const double mg = (p.clip ? 12.0 : 40.0) * p.w;
+  if (p.mask == WACM_MASK_SPHERE) {
+    double s = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double q = fmax(0.0, fmax(lo[d] - p.sph_c[d], p.sph_c[d] - hi[d]));
+      s += q * q;
+    }
+    return sqrt(s) > p.sph_r + mg;
+  }
+  if (p.mask == WACM_MASK_PLATE) {
+    const double ylo = lo[1] - p.x_le[1], yhi = hi[1] - p.x_le[1];
+    if (yhi < p.lo[1] - mg || ylo > p.hi[1] + mg) return true;
+    double rmax = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        const double cx = a ? p.hi[0] + mg : p.lo[0] - mg;
+        const double cz = b ? p.hi[2] + mg : p.lo[2] - mg;
+        rmax = fmax(rmax, sqrt(cx * cx + cz * cz));
+      }
+    double s = 0.0;
+    for (int d = 0; d < 3; d += 2) {
+      const double q = fmax(0.0, fmax(lo[d] - p.x_le[d], p.x_le[d] - hi[d]));
+      s += q * q;
+    }
+    if (sqrt(s) > rmax) return true;
+    if (!win.on) return false;
+    const double ca = cos(win.am), sa = sin(win.am);
+    const double cx = 0.5 * (lo[0] + hi[0]) - p.x_le[0], cz = 0.5 * (lo[2] + hi[2]) - p.x_le[2];
+    const double hx = 0.5 * (hi[0] - lo[0]), hz = 0.5 * (hi[2] - lo[2]);
+    const double fx = fmax(fabs(lo[0] - p.x_le[0]), fabs(hi[0] - p.x_le[0]));
+    const double fz = fmax(fabs(lo[2] - p.x_le[2]), fabs(hi[2] - p.x_le[2]));
+    const double sw = win.da * sqrt(fx * fx + fz * fz);
+    const double b0 = ca * cx - sa * cz, e0 = fabs(ca) * hx + fabs(sa) * hz + sw;
+    const double b2 = sa * cx + ca * cz, e2 = fabs(sa) * hx + fabs(ca) * hz + sw;
+    if (b0 + e0 < p.lo[0] - mg || b0 - e0 > p.hi[0] + mg) return true;
+    return b2 + e2 < p.lo[2] - mg || b2 - e2 > p.hi[2] + mg;
+  }
+  return true;
+}
+
 }  // namespace wacm

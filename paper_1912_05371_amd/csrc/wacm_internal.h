@@ -181,7 +181,7 @@ struct wacm_grid {
   int jfine = 0;                 // finest active level
   mutable wacm::Profiler prof;   // kernel timing, off by default
   std::vector<wacm::Tab> h_tab;  // host copy of the tables
-  wacm_schedule sched{0, 1, -1, 1, 0};  // launch schedule of the stage kernel
+  wacm_schedule sched{0, 1, -1, 1, 0, 1};  // launch schedule of the stage kernel
   wacm::AdjPlan plan[2];         // ghost-fill transposes: all layers / face star
   // restriction wavelet: 0 CDF 4/0 (decimation), 1 CDF 4/4 (lifted); with
   // CDF 4/4, the work items of the lifted ghost phase (12 int32 each) and

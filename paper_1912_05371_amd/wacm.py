@@ -45,7 +45,7 @@ class GridDesc(C.Structure):
 
 class Schedule(C.Structure):
     _fields_ = [("wg_per_cu", C.c_int32), ("xcd_map", C.c_int32), ("prefetch", C.c_int32),
-                ("nontemporal", C.c_int32), ("tile_rows", C.c_int32)]
+                ("nontemporal", C.c_int32), ("tile_rows", C.c_int32), ("pen_split", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

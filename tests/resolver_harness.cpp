@@ -5,6 +5,10 @@
 // every source access checked to be an interior point of a valid slot.
 //
 //   resolver_harness leaves.txt state_in.bin state_out.bin
+//   resolver_harness leaves.txt lift
+//   resolver_harness leaves.txt penfar params.bin [t0 t1]
+//     (prints pen_far per leaf, input order; with t0 t1, for the plate's
+//     pitch angles over that window, else for every angle)
 // leaves.txt: "bs ng L jmin jmax capacity n" then n lines "J x y z" (slot i = line i)
 // state: n * 4 * P^3 doubles (pool layout).  Exit 0 on success.
 #include <cmath>
@@ -124,7 +128,8 @@ int main(int argc, char** argv) {
       std::fprintf(stderr, "x-split order of bs %d is not a bijection\n", bs);
       return 7;
     }
-  if (argc != 4 && !(argc == 3 && std::string(argv[2]) == "lift")) return 2;
+  const bool penfar = (argc == 4 || argc == 6) && std::string(argv[2]) == "penfar";
+  if (argc != 4 && !penfar && !(argc == 3 && std::string(argv[2]) == "lift")) return 2;
   FILE* f = std::fopen(argv[1], "r");
   if (!f) return 2;
   wacm_grid g;
@@ -156,6 +161,20 @@ int main(int argc, char** argv) {
     return 3;
   }
   if (argc == 3) return check_lift(g, tabs);
+  if (penfar) {
+    // the stage kernel's classification of blocks without penalization, per
+    // leaf in input order (slot i = leaf i)
+    wacm_params prm;
+    FILE* fp = std::fopen(argv[3], "rb");
+    if (!fp || std::fread(&prm, sizeof(prm), 1, fp) != 1) return 2;
+    std::fclose(fp);
+    PitchWindow win{0.0, 0.0, false};
+    if (argc == 6) win = pitch_window(prm, std::atof(argv[4]), std::atof(argv[5]));
+    std::vector<int> far(g.nb, -1);
+    for (const Tab& t : tabs) far[t.meta[0]] = pen_far(prm, g.d.L, g.d.bs, t.meta, win) ? 1 : 0;
+    for (int64_t i = 0; i < g.nb; ++i) std::printf("%d\n", far[i]);
+    return 0;
+  }
   const int bs = g.d.bs, ng = g.d.ng, P = g.P;
   Layout L;
   L.P = P;

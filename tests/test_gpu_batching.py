@@ -101,7 +101,9 @@ def test_autotuner_picks_a_candidate(octree, tmp_path, monkeypatch):
     U0 = to_pool(g, c.padded())
     before = U0.clone()
     best, trials = autotune.tune(g, c.params, U0, steps=1, log=log, shipped=False)
-    assert best in autotune.CANDIDATES and g.get_schedule() == best
+    got = g.get_schedule()
+    assert best in autotune.CANDIDATES and {k: got[k] for k in best} == best
+    assert got["pen_split"] == 1  # not a tuning knob: left at its default
     assert len(trials) == len(autotune.CANDIDATES)
     assert torch.equal(U0, before)  # the caller's state is untouched
     best2, _ = autotune.tune(g, c.params, U0, shipped=False)  # cache hit
@@ -158,3 +160,40 @@ def test_multi_step_call_penalized_and_fixed_dt(orc):
     assert torch.equal(U, U0) and t.item() == 0.0 and d.item() == 7.0
     with pytest.raises(wacm.WacmError):
         g.rk4_steps(c.params, t, d, U, work, -1)
+
+
+
+@pytest.mark.parametrize("which", ["sphere_sponge", "plate_clip", "plate_noclip"])
+@pytest.mark.parametrize("prec", [wacm.F64, wacm.F32])
+def test_pen_split_is_bitwise(which, prec):
+    """Blocks without penalization through the unpenalized stage kernel
+    (schedule pen_split 1) give bit for bit the state of every block through
+    the penalized one (pen_split 0): 3 CFL steps; the unclipped plate also
+    carries a solid velocity field."""
+    if which.startswith("plate"):
+        c = cases.plate_adaptive(jmin=2, jmax=5, jstart=4)
+        c.params = cases.plate_params(5, c.bs, c.L, clip=1 if which == "plate_clip" else 0)
+    else:
+        c = cases.sphere_two_level()
+    log(f"pen_split {which}, {c.nb} blocks, dtype {prec}")
+    g = wacm.Grid.from_case(c, dtype=prec)
+    U0 = to_pool(g, c.padded())
+    dus = None
+    if which == "plate_noclip":
+        gen = torch.Generator(device="cuda").manual_seed(3)
+        dus = (0.01 * torch.randn((g.capacity, 3, c.bs ** 3), generator=gen, device="cuda",
+                                  dtype=torch.float64)).to(g.torch_dtype()).contiguous()
+    work = g.work()
+    out = []
+    for split in (0, 1):
+        g.set_schedule(pen_split=split)
+        U = U0.clone()
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        g.rk4_steps(c.params, t, dt, U, work, 3, dus=dus, dt_mode=wacm.DT_CFL)
+        torch.cuda.synchronize()
+        I = slice(c.ng, c.ng + c.bs)
+        out.append((U[:c.nb, :, I, I, I].clone(), t.item()))
+    eq = torch.equal(out[0][0], out[1][0])
+    log(f"  equal {eq}, t {out[0][1]!r} {out[1][1]!r}")
+    assert eq and out[0][1] == out[1][1]

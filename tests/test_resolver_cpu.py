@@ -161,3 +161,76 @@ def test_2d_small_and_refined(orc, harness2d, tmp_path):
     c = cases.three_vortices_adaptive(bs=16, ng=4, jmin=2, jmax=5, jstart=5, radius=0.6)
     assert run_case2d(orc, harness2d, tmp_path, c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix,
                       c.iy) == c.nb
+
+
+# ---------------------------------------------------------------- penalization split
+def _penfar(harness, tmp_path, c, prm, window=None):
+    from paper_1912_05371_amd import wacm
+    lf = tmp_path / "leaves_pf.txt"
+    with open(lf, "w") as f:
+        f.write(f"{c.bs} {c.ng} {c.L!r} {c.jmin} {c.jmax} {c.nb} {c.nb}\n")
+        for l, x, y, z in zip(c.lev, c.ix, c.iy, c.iz):
+            f.write(f"{l} {x} {y} {z}\n")
+    pb = tmp_path / "params.bin"
+    pb.write_bytes(bytes(wacm.make_params(prm)))
+    extra = [repr(float(window[0])), repr(float(window[1]))] if window is not None else []
+    r = subprocess.run([harness, str(lf), "penfar", str(pb), *extra], capture_output=True,
+                       text=True)
+    assert r.returncode == 0, r.stderr
+    return np.array([int(v) for v in r.stdout.split()], bool)
+
+
+@pytest.mark.parametrize("which", ["plate_clip", "plate_noclip", "sphere_sponge"])
+def test_pen_far_blocks_have_no_penalization(orc, harness, tmp_path, which):
+    """The blocks the stage kernel runs without penalization: at every
+    interior point, at every sampled time of the plate's pitch cycle, the
+    oracle's mask is exactly 0 and the sponge term vanishes."""
+    if which.startswith("plate"):
+        c = cases.plate_adaptive(jmin=2, jmax=5, jstart=4)
+        c.params = cases.plate_params(5, c.bs, c.L, clip=1 if which == "plate_clip" else 0)
+        prm = c.params
+    else:
+        c = cases.sphere_two_level()
+        prm = c.params
+    far = _penfar(harness, tmp_path, c, prm)
+    assert far.sum() > 0.1 * c.nb and (~far).sum() > 0
+    og = orc.Grid(c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix, c.iy, c.iz)
+    for t in np.linspace(0.0, 1.0, 9) + 0.013:
+        chi, _ = og.mask(prm, float(t))
+        assert np.all(chi[far] == 0.0), t
+    if prm["sponge"]:
+        # rhs of a constant state away from the sponge target: the sponge
+        # term is the only nonzero one
+        U = og.zeros()
+        U[:, 0] = 3.0
+        U[:, 3] = -2.0
+        og.sync(U)
+        base = dict(prm, mask=0)
+        R = inputs.interior(og.rhs(base, 0.0, U), c.bs, c.ng)
+        assert np.all(R[far] == 0.0)
+        assert np.any(R[~far] != 0.0)
+    log_far = f"{which}: {int(far.sum())} of {c.nb} blocks without penalization"
+    print(log_far)
+
+
+@pytest.mark.parametrize("clip", [1, 0])
+def test_pen_far_pitch_window(orc, harness, tmp_path, clip):
+    """Per-step classification of the pitching plate: a block called far for
+    the window [t, t + dt] has the oracle's mask exactly 0 at every interior
+    point at the step's stage times and at times between; every block far
+    for any angle stays far, and the window leaves fewer blocks near."""
+    c = cases.plate_adaptive(jmin=2, jmax=5, jstart=5)
+    prm = cases.plate_params(5, c.bs, c.L, clip=clip)
+    og = orc.Grid(c.bs, c.ng, c.L, c.jmin, c.jmax, c.lev, c.ix, c.iy, c.iz)
+    static = _penfar(harness, tmp_path, c, prm)
+    for t0, dt in ((0.0, 0.02), (0.21, 0.005), (0.37, 0.1), (0.8, 1e-4)):
+        far = _penfar(harness, tmp_path, c, prm, (t0, t0 + dt))
+        assert np.all(far[static]), (t0, dt)
+        if clip:  # unclipped, the 40 w margin exceeds the chord: little to gain
+            assert (~far).sum() < 0.75 * (~static).sum(), (t0, dt, (~far).sum(),
+                                                             (~static).sum())
+        for t in t0 + dt * np.array([0.0, 0.3, 0.5, 1.0]):
+            chi, _ = og.mask(prm, float(t))
+            assert np.all(chi[far] == 0.0), (t0, dt, t)
+        print(f"clip {clip} window ({t0}, {t0 + dt}): {int((~far).sum())} blocks near, "
+              f"{int((~static).sum())} for any angle, of {c.nb}")
