@@ -1376,26 +1376,36 @@ __global__ __launch_bounds__(NT_GEN) void decimate_kernel(const int32_t* __restr
 // --------------------------------------------------------------------------
 // blocks without penalization
 // --------------------------------------------------------------------------
-// One workgroup of 1024 threads: list = the far blocks (active order), then
-// the others; cnt = {far count, other count}.  Each thread classifies a
-// contiguous run of blocks twice (count, then place), with a workgroup
-// prefix sum of the counts between, so that each part keeps the active
-// (Morton) order.  With t_dev given, the plate is classified for the pitch
-// angles of the window [t, t + dt] of one step; else for every angle.
-__global__ __launch_bounds__(1024) void pen_classify(const Tab* __restrict__ tab, int64_t nb,
-                                                     wacm_params p, double L, int bs,
-                                                     const double* __restrict__ t_dev,
-                                                     const double* __restrict__ dt_dev,
-                                                     int32_t* __restrict__ list,
-                                                     int32_t* __restrict__ cnt) {
-  __shared__ int32_t wsum[2][16], woff[2][16], tot[2];
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  PitchWindow win{0.0, 0.0, false};
+// Two kernels: pen_flags marks each active block (1: far, 0: not), one
+// thread per block; pen_compact, one workgroup of 1024 threads, writes
+// list = the far blocks (active order), then the others, and cnt = {far
+// count, other count}: each thread takes a contiguous run of flags, counts,
+// and places its blocks after a workgroup prefix sum of the counts, so that
+// each part keeps the active (Morton) order.  With t_dev given, the plate is
+// classified for the pitch angles of the window [t, t + dt] of one step;
+// else for every angle.
+__global__ __launch_bounds__(NT_GEN) void pen_flags(const Tab* __restrict__ tab, int64_t nb,
+                                                    wacm_params p, double L, int bs,
+                                                    const double* __restrict__ t_dev,
+                                                    const double* __restrict__ dt_dev,
+                                                    int8_t* __restrict__ flag) {
+  const int64_t b = (int64_t)blockIdx.x * NT_GEN + threadIdx.x;
+  if (b >= nb) return;
+  PitchWindow win{1.0, 0.0, 0.0, false};
   if (t_dev) win = pitch_window(p, *t_dev, *t_dev + *dt_dev);
+  flag[b] = pen_far(p, L, bs, tab[b].meta, win) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(1024) void pen_compact(const int8_t* __restrict__ flag, int64_t nb,
+                                                    int32_t* __restrict__ list,
+                                                    int32_t* __restrict__ cnt) {
+  __shared__ int32_t wsum[2][16], woff[2][16], tot;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t per = (nb + 1023) / 1024;
   const int64_t b0 = t * per < nb ? t * per : nb, b1 = b0 + per < nb ? b0 + per : nb;
-  int32_t nf = 0, nn = 0;
-  for (int64_t b = b0; b < b1; ++b) (pen_far(p, L, bs, tab[b].meta, win) ? nf : nn) += 1;
+  int32_t nf = 0;
+  for (int64_t b = b0; b < b1; ++b) nf += flag[b];
+  const int32_t nn = (int32_t)(b1 - b0) - nf;
   // inclusive scans within the wave, then over the 16 waves' totals
   int32_t sf = nf, sn = nn;
   for (int o = 1; o < 64; o <<= 1) {
@@ -1418,19 +1428,32 @@ __global__ __launch_bounds__(1024) void pen_classify(const Tab* __restrict__ tab
       af += wsum[0][w];
       an += wsum[1][w];
     }
-    tot[0] = af;
-    tot[1] = an;
+    tot = af;
     cnt[0] = af;
     cnt[1] = an;
   }
   __syncthreads();
-  int32_t of = woff[0][wv] + sf - nf, on = tot[0] + woff[1][wv] + sn - nn;
+  int32_t of = woff[0][wv] + sf - nf, on = tot + woff[1][wv] + sn - nn;
   for (int64_t b = b0; b < b1; ++b) {
-    if (pen_far(p, L, bs, tab[b].meta, win))
+    if (flag[b])
       list[of++] = (int32_t)b;
     else
       list[on++] = (int32_t)b;
   }
+}
+
+// the two lists of blocks with and without penalization, in list/cnt
+static hipError_t pen_classify(const wacm_grid* g, const wacm_params* p, const double* t_dev,
+                               const double* dt_dev, int32_t* list, int32_t* cnt,
+                               int8_t* flag, hipStream_t st) {
+  const unsigned nwg = (unsigned)((g->nb + NT_GEN - 1) / NT_GEN);
+  if (nwg > 0) {
+    pen_flags<<<nwg, NT_GEN, 0, st>>>(g->d_tab, g->nb, *p, g->d.L, g->d.bs, t_dev, dt_dev, flag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  pen_compact<<<1, 1024, 0, st>>>(flag, g->nb, list, cnt);
+  return hipGetLastError();
 }
 
 // --------------------------------------------------------------------------
@@ -1798,15 +1821,14 @@ static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
   const bool split_step = split && p->mask == WACM_MASK_PLATE;
   int32_t* const plist = g->d_list;
   int32_t* const pcnt = g->d_list + g->d.capacity;
+  int8_t* const pflag = reinterpret_cast<int8_t*>(g->d_list + g->d.capacity + 2);
   if (split) {
     a.blist = plist;
     a.bcnt = pcnt;
   }
-  if (split && !split_step) {
-    pen_classify<<<1, 1024, 0, st>>>(g->d_tab, g->nb, *p, g->d.L, g->d.bs, nullptr, nullptr,
-                                     plist, pcnt);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
+  if (split && !split_step &&
+      (e = pen_classify(g, p, nullptr, nullptr, plist, pcnt, pflag, st)) != hipSuccess)
+    return e;
   for (int64_t k = 0; k < nsteps; ++k) {
     if (dt_mode == WACM_DT_CFL) {
       ProfScope ps(g, 0, st);
@@ -1837,11 +1859,9 @@ static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
         if ((e = nlface_launch<T>(g, a.in, a.Lin, hb, st)) != hipSuccess) return e;
       }
       ProfScope ps(g, 2, st);
-      if (s == 0 && split_step) {
-        pen_classify<<<1, 1024, 0, st>>>(g->d_tab, g->nb, *p, g->d.L, g->d.bs, t_dev, dt_dev,
-                                         plist, pcnt);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-      }
+      if (s == 0 && split_step &&
+          (e = pen_classify(g, p, t_dev, dt_dev, plist, pcnt, pflag, st)) != hipSuccess)
+        return e;
       switch (s) {
         case 0:
           e = stage_dispatch<T, 1>(g->d.bs, a, g->sched, st);

@@ -303,15 +303,17 @@ WACM_HD inline void shell_point(int idx, int bs, int ng, int P, int mode, int& i
 // bound |d alpha / dt| <= |amp| 2 pi |freq| plus 1e-9 for the rounding of the
 // angle here and in the stage kernel.  on = false: no window (any angle).
 struct PitchWindow {
-  double am, da;
+  double ca, sa, da;  // cos and sin of am
   bool on;
 };
 
 WACM_HD inline PitchWindow pitch_window(const wacm_params& p, double t0, double t1) {
-  PitchWindow w{0.0, 0.0, false};
+  PitchWindow w{1.0, 0.0, 0.0, false};
   if (p.mask != WACM_MASK_PLATE) return w;
   const double twopi = 6.283185307179586476925286766559;
-  w.am = p.amp * sin(twopi * p.freq * (0.5 * (t0 + t1)) + p.phase);
+  const double am = p.amp * sin(twopi * p.freq * (0.5 * (t0 + t1)) + p.phase);
+  w.ca = cos(am);
+  w.sa = sin(am);
   w.da = fabs(p.amp) * twopi * fabs(p.freq) * 0.5 * fabs(t1 - t0) + 1e-9;
   w.on = true;
   return w;
@@ -374,7 +376,7 @@ WACM_HD inline bool pen_far(const wacm_params& p, double L, int bs, const int32_
     }
     if (sqrt(s) > rmax) return true;
     if (!win.on) return false;
-    const double ca = cos(win.am), sa = sin(win.am);
+    const double ca = win.ca, sa = win.sa;
     const double cx = 0.5 * (lo[0] + hi[0]) - p.x_le[0], cz = 0.5 * (lo[2] + hi[2]) - p.x_le[2];
     const double hx = 0.5 * (hi[0] - lo[0]), hz = 0.5 * (hi[2] - lo[2]);
     const double fx = fmax(fabs(lo[0] - p.x_le[0]), fabs(hi[0] - p.x_le[0]));

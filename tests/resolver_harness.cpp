@@ -168,7 +168,7 @@ int main(int argc, char** argv) {
     FILE* fp = std::fopen(argv[3], "rb");
     if (!fp || std::fread(&prm, sizeof(prm), 1, fp) != 1) return 2;
     std::fclose(fp);
-    PitchWindow win{0.0, 0.0, false};
+    PitchWindow win{1.0, 0.0, 0.0, false};
     if (argc == 6) win = pitch_window(prm, std::atof(argv[4]), std::atof(argv[5]));
     std::vector<int> far(g.nb, -1);
     for (const Tab& t : tabs) far[t.meta[0]] = pen_far(prm, g.d.L, g.d.bs, t.meta, win) ? 1 : 0;

@@ -54,12 +54,15 @@ def san_env():
 
 
 def test_oracle_pins_under_sanitizers(san_env):
-    # the pins minus the four longest runs (two finite-difference gradients,
-    # the RK4 time-order study and the CDF 4/4 refine/coarsen round trip);
-    # the routines those exercise are also run by the other pins
+    # the pins minus the six longest runs (two finite-difference gradients,
+    # the RK4 time-order study, the CDF 4/4 refine/coarsen round trip, the
+    # two-dimensional spectral convergence study and the extrusion
+    # comparison); the routines those exercise are also run by the other pins
     skip = ("not test_rk4_time_order and not test_cdf44_refine_then_coarsen_is_identity "
             "and not test_objective_gradient_theta_matches_fd "
-            "and not test_objective_gradient_dus_and_state_match_fd")
+            "and not test_objective_gradient_dus_and_state_match_fd "
+            "and not test_rhs_fourth_order_against_spectral "
+            "and not test_2d_details_and_adaptation_equal_3d_extruded")
     files = [os.path.join(ROOT, "tests", f) for f in
              ("test_oracle_pins.py", "test_oracle_pins_model.py", "test_oracle_mr.py",
               "test_oracle_adjoint.py", "test_oracle2d_pins.py")]
