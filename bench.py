@@ -319,17 +319,44 @@ def aux_timings(case):
     work = ga.work()
     t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
     dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
-    ph = {}
-    nb0 = ga.nb
-    r = adaptive_step(ga, c.params, U, work, t_dev, dt_dev, eps, dealias, timings=ph)
+    # the first step from the start grid, then 3 steps from the adapted grid,
+    # each phase synchronised and split into host and device time
+    steps = []
+    for i in range(4):
+        ph = {}
+        nb0 = ga.nb
+        r = adaptive_step(ga, c.params, U, work, t_dev, dt_dev, eps, dealias, timings=ph)
+        steps.append((nb0, r, ph))
     out["adaptive_plate_step"] = {
-        "blocks": [nb0, r["refined"], r["blocks"]], "merging_passes": r["merged_passes"],
-        "ms": {k: round(v, 3) for k, v in ph.items()},
-        "total_ms": round(sum(ph.values()), 3)}
+        "first": _adaptive_record(*steps[0], 1),
+        "steady_mean_of_3": _adaptive_record(steps[1][0], steps[3][1],
+                                             _sum_phases([s[2] for s in steps[1:]]), 3)}
     del U, work
     ga.close()
     torch.cuda.empty_cache()
     return out
+
+
+def _sum_phases(phs):
+    tot = {}
+    for ph in phs:
+        for k, v in ph.items():
+            rec = tot.setdefault(k, {"wall": 0.0, "host": 0.0, "device": 0.0})
+            for q in rec:
+                rec[q] += v[q]
+    return tot
+
+
+def _adaptive_record(nb0, r, ph, nsteps):
+    """Per-phase wall / host / device ms (mean over nsteps adaptive steps) and
+    the host share of the step's wall time."""
+    wall = sum(v["wall"] for v in ph.values())
+    host = sum(v["host"] for v in ph.values())
+    return {"blocks": [nb0, r["refined"], r["blocks"]], "merging_passes": r["merged_passes"],
+            "ms_by_phase": {k: {q: round(x / nsteps, 3) for q, x in v.items()}
+                            for k, v in ph.items()},
+            "wall_ms": round(wall / nsteps, 3), "host_ms": round(host / nsteps, 3),
+            "host_share": round(host / wall, 3) if wall > 0 else None}
 
 
 def c3_run(nsteps: int = 200, every: int = 10):
@@ -363,11 +390,23 @@ def c3_run(nsteps: int = 200, every: int = 10):
     recs, phases = [], {}
 
     def timed(name, fn):
+        # wall ms of the phase; host ms: for the adaptation calls the
+        # library's host share, else the wall time outside the stream events
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        e0.record()
         r = fn()
+        e1.record()
         torch.cuda.synchronize()
-        phases[name] = phases.get(name, 0.0) + (time.perf_counter() - t0) * 1e3
+        w = (time.perf_counter() - t0) * 1e3
+        dev = grids["f64"].adapt_timing()[1] if name in ("refine_all", "coarsen") else \
+            min(e0.elapsed_time(e1), w)
+        rec = phases.setdefault(name, {"wall": 0.0, "host": 0.0, "device": 0.0})
+        rec["wall"] += w
+        rec["device"] += dev
+        rec["host"] += w - dev
         return r
 
     def flags_of(k, t):
@@ -428,7 +467,10 @@ def c3_run(nsteps: int = 200, every: int = 10):
             "drift_max": max(r["drift"] for r in recs), "drift_end": recs[-1]["drift"],
             "flag_disagreements_total": sum(r["flag_disagreements"] for r in recs),
             "steps_with_disagreements": sum(1 for r in recs if r["flag_disagreements"]),
-            "f64_ms_per_step_by_phase": {k: round(v / nsteps, 3) for k, v in phases.items()},
+            "f64_ms_per_step_by_phase": {k: {q: round(x / nsteps, 3) for q, x in v.items()}
+                                         for k, v in phases.items()},
+            "f64_host_share": round(sum(v["host"] for v in phases.values()) /
+                                    sum(v["wall"] for v in phases.values()), 3),
             "records": recs}
 
 

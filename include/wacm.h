@@ -498,6 +498,13 @@ int wacm_rk4_step_adj(wacm_grid* grid, const wacm_params* prm, double t, double 
 int wacm_profile_enable(wacm_grid* grid, int32_t on);
 int wacm_profile_read(wacm_grid* grid, double* ms, int64_t* launches);
 
+/* Wall milliseconds of the last successful wacm_adapt on this grid, split
+ * into ms[0] host work (leaf lists, merge decisions, table building and
+ * uploads) and ms[1] device work (its ghost sync and refinement or
+ * coarsening kernels, launch to completion); host array of 2.  Zero before
+ * the first adaptation. */
+int wacm_adapt_timing(const wacm_grid* grid, double* ms);
+
 #pragma GCC visibility pop
 #ifdef __cplusplus
 }

@@ -22,22 +22,37 @@ def adaptive_step(grid: wacm.Grid, params: dict, U, work, t_dev, dt_dev, eps: fl
     "blocks": blocks at the end}.  U and work are the grid's pool and
     work buffer (capacity must hold the refined grid: wacm_adapt raises
     WACM_E_CAPACITY and leaves the grid unchanged otherwise).  With `timings`
-    (a dict), host wall milliseconds per phase are accumulated into it, each
-    phase synchronised."""
+    (a dict), each phase is synchronised and its milliseconds accumulated into
+    timings[phase] = {"wall", "host", "device"}: for the adaptation calls the
+    library's own split (host: leaf lists, merge decisions, tables and their
+    upload; device: its kernels), for the others the device time between two
+    stream events around the call and the rest of the wall time as host."""
     import torch
 
-    def phase(name, fn):
+    def phase(name, fn, adapt=False):
         if timings is None:
             return fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        e0.record()
         r = fn()
+        e1.record()
         torch.cuda.synchronize()
-        timings[name] = timings.get(name, 0.0) + (time.perf_counter() - t0) * 1e3
+        wall = (time.perf_counter() - t0) * 1e3
+        if adapt:
+            dev = grid.adapt_timing()[1]
+        else:
+            dev = min(e0.elapsed_time(e1), wall)
+        rec = timings.setdefault(name, {"wall": 0.0, "host": 0.0, "device": 0.0})
+        rec["wall"] += wall
+        rec["device"] += dev
+        rec["host"] += wall - dev
         return r
 
     p = wacm.make_params(params)
-    refined = phase("refine_all", lambda: grid.adapt(wacm.REFINE_ALL, U))
+    refined = phase("refine_all", lambda: grid.adapt(wacm.REFINE_ALL, U), adapt=True)
     phase("rk4_step", lambda: grid.rk4_step(None, t_dev, dt_dev, U, work, dt_mode=dt_mode, _p=p))
     t = float(t_dev.item())
     merged = 0
@@ -49,8 +64,8 @@ def adaptive_step(grid: wacm.Grid, params: dict, U, work, t_dev, dt_dev, eps: fl
         phase("sync_ghosts", lambda: grid.sync_ghosts(U))
         phase("threshold_blocks",
               lambda: grid.threshold_blocks(params, t, U, eps, dealias, dmax, mrange, flags))
-        host_flags = flags.cpu().numpy()
-        n_new = phase("coarsen", lambda: grid.adapt(wacm.COARSEN, U, host_flags))
+        host_flags = phase("flags_to_host", lambda: flags.cpu().numpy())
+        n_new = phase("coarsen", lambda: grid.adapt(wacm.COARSEN, U, host_flags), adapt=True)
         if n_new == n:
             break
         merged += 1

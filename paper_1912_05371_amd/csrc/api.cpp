@@ -1,5 +1,6 @@
 // extern "C" entry points of libwacm (declared in include/wacm.h).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -449,6 +450,7 @@ int wacm_filter_blocks(wacm_grid* g, void* U, int32_t level, void* stream) {
 
 int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* nb_out,
                void* stream) {
+  const auto t_call = std::chrono::steady_clock::now();
   GridScope gs(g);
   if (!elem_ok(g) || !U) return fail(WACM_E_INVAL, "NULL argument");
   hipStream_t st = S(stream);
@@ -513,29 +515,19 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
         }
       }
       if (merge) {
-        // grading: the parent (level J-1) must not touch leaves of level J+1;
-        // check the level-(J+1) boxes around the parent box
-        const int64_t n1 = int64_t(1) << (l.J + 1);
-        int64_t base[3] = {4 * px, 4 * py, 4 * pz};  // parent origin in level-(J+1) boxes
-        // in two dimensions only the plane z = 0: the z offset is 0 and the
-        // z range counts as inside
-        const int dz0 = g->dim == 2 ? 0 : -1, dz1 = g->dim == 2 ? 0 : 4;
-        for (int dz = dz0; dz <= dz1 && merge; ++dz)
-          for (int dy = -1; dy <= 4 && merge; ++dy)
-            for (int dx = -1; dx <= 4 && merge; ++dx) {
-              bool inside = dx >= 0 && dx < 4 && dy >= 0 && dy < 4 && dz >= 0 && dz < 4;
-              if (inside) continue;
-              int64_t bx = ((base[0] + dx) % n1 + n1) % n1;
-              int64_t by = ((base[1] + dy) % n1 + n1) % n1;
-              int64_t bz = g->dim == 2 ? 0 : ((base[2] + dz) % n1 + n1) % n1;
-              // is this level-(J+1) box covered by a leaf of level <= J ?
-              bool covered = false;
-              for (int K = l.J; K >= g->d.jmin && !covered; --K) {
-                int s = l.J + 1 - K;
-                covered = g->index.find(leaf_key(K, bx >> s, by >> s, bz >> s)) >= 0;
-              }
-              if (!covered) merge = false;
+        // grading: the parent (level J-1) must not touch a leaf of level
+        // J+1.  Such a leaf lies in a neighbour region of some sister outside
+        // the family, which the sister's table then marks finer; conversely
+        // every finer region of a sister holds leaves of level J+1 touching
+        // the sister, hence the parent box.
+        for (int c = 0; c < nchild && merge; ++c) {
+          const int8_t* kd = g->h_tab[sidx[c]].kind;
+          for (int r = 0; r < 27; ++r)
+            if (kd[r] > 0) {
+              merge = false;
+              break;
             }
+        }
       }
       if (!merge) {
         done[i] = 1;
@@ -564,20 +556,32 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
   } else {
     return fail(WACM_E_INVAL, "unknown adapt op");
   }
+  if (nwork == 0) {
+    // nothing to refine or merge: the leaves, slots and tables stay; the
+    // adjoint plans are dropped all the same, as after any adaptation
+    free_adj_plans(g);
+    if (nb_out) *nb_out = g->nb;
+    g->adapt_ms[0] =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_call).count();
+    g->adapt_ms[1] = 0.0;
+    return WACM_OK;
+  }
   // commit: new leaf set and its tables (validated before anything on the device changes)
   wacm_grid tmp;
   tmp.d = g->d;
   tmp.dim = g->dim;
   tmp.P = g->P;
-  tmp.leaves = newleaves;
-  tmp.slots = newslots;
+  tmp.leaves.swap(newleaves);
+  tmp.slots.swap(newslots);
   reorder_leaves(&tmp);
-  std::vector<Tab> tabs;
+  std::vector<Tab>& tabs = g->h_tab_next;
   std::string err;
   int rc = build_tables(&tmp, tabs, err);
   if (rc) return fail(rc, err);
   hipError_t e;
+  double dev_ms = 0.0;
   if (nwork > 0) {
+    const auto d0 = std::chrono::steady_clock::now();
     if (op == WACM_REFINE_ALL) {
       e = full_sync(g, U, st);
       if (e != hipSuccess) return hipfail(e, "adapt sync");
@@ -596,6 +600,7 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
     if (e != hipSuccess) return hipfail(e, "adapt kernel");
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hipfail(e, "adapt synchronize");
+    dev_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - d0).count();
   }
   for (int32_t s : freed) freelist.push_back(s);
   g->leaves.swap(tmp.leaves);
@@ -608,6 +613,18 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
   rc = upload_tables(g, tabs, err);
   if (rc) return fail(rc, err);
   if (nb_out) *nb_out = g->nb;
+  const double all_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_call).count();
+  g->adapt_ms[0] = all_ms - dev_ms;
+  g->adapt_ms[1] = dev_ms;
+  return WACM_OK;
+}
+
+int wacm_adapt_timing(const wacm_grid* g, double* ms) {
+  GridScope gs(g);
+  if (!g || !ms) return fail(WACM_E_INVAL, "NULL argument");
+  ms[0] = g->adapt_ms[0];
+  ms[1] = g->adapt_ms[1];
   return WACM_OK;
 }
 

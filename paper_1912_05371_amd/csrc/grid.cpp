@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "wacm_internal.h"
 
@@ -61,13 +62,13 @@ void reorder_leaves(wacm_grid* g) {
 
 // In two dimensions only the 9 regions of the plane (rz = 1) and the 4
 // sub-boxes with sz = 0 are filled; the others stay unused.
-int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err) {
-  const int64_t nb = g->nb;
+static int build_range(const wacm_grid* g, Tab* tabs, int64_t i0, int64_t i1, int64_t& bad,
+                       std::string& err) {
   const int rz0 = g->dim == 2 ? 1 : 0, rz1 = g->dim == 2 ? 1 : 2, nsub = g->dim == 2 ? 4 : 8;
-  tabs.assign(nb, Tab{});
-  for (int64_t i = 0; i < nb; ++i) {
+  for (int64_t i = i0; i < i1; ++i) {
     const Leaf& b = g->leaves[i];
     Tab& t = tabs[i];
+    t = Tab{};
     t.meta[0] = g->slots[i];
     t.meta[1] = b.J;
     t.meta[2] = (int32_t)b.x;
@@ -103,6 +104,7 @@ int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err) {
                          (rz == 1 || sz == (rz == 0 ? 1 : 0));
             int32_t sf = find_slot(g, b.J + 1, 2 * nx + sx, 2 * ny + sy, 2 * nz + sz);
             if (touch && sf < 0) {
+              bad = i;
               err = "grid is not 2:1 balanced around block (level " + std::to_string(b.J) +
                     ", " + std::to_string(b.x) + "," + std::to_string(b.y) + "," +
                     std::to_string(b.z) + ")";
@@ -112,6 +114,7 @@ int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err) {
             anyfine = anyfine || sf >= 0;
           }
           if (!anyfine) {
+            bad = i;
             err = "no neighbour found";
             return WACM_E_UNBALANCED;
           }
@@ -121,24 +124,64 @@ int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err) {
   return WACM_OK;
 }
 
+// The blocks are split into contiguous runs built by up to 8 threads (each
+// block's table depends only on the read-only leaf index); the error
+// reported is that of the first failing block in active order, whatever the
+// thread count.  `tabs` keeps its allocation from call to call.
+int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err) {
+  const int64_t nb = g->nb;
+  tabs.resize(nb);
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int64_t nt = std::max<int64_t>(1, std::min<int64_t>({8, hw, nb / 1024}));
+  std::vector<int> rc(nt, WACM_OK);
+  std::vector<int64_t> bad(nt, -1);
+  std::vector<std::string> msg(nt);
+  auto run = [&](int64_t k) {
+    const int64_t i0 = nb * k / nt, i1 = nb * (k + 1) / nt;
+    rc[k] = build_range(g, tabs.data(), i0, i1, bad[k], msg[k]);
+  };
+  if (nt == 1) {
+    run(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int64_t k = 1; k < nt; ++k) th.emplace_back(run, k);
+    run(0);
+    for (auto& x : th) x.join();
+  }
+  for (int64_t k = 0; k < nt; ++k)  // runs are in active order
+    if (rc[k] != WACM_OK) {
+      err = msg[k];
+      return rc[k];
+    }
+  return WACM_OK;
+}
+
 std::vector<int32_t> coarse_faces(const std::vector<Tab>& tabs) {
-  std::vector<int32_t> cf;
+  size_t n = 0;
+  for (const Tab& t : tabs)
+    for (int f = 0; f < 6; ++f) n += t.kind[FACE_REGION[f]] != 0;
+  std::vector<int32_t> cf(2 * n);
+  size_t k = 0;
   for (size_t i = 0; i < tabs.size(); ++i)
     for (int f = 0; f < 6; ++f)
       if (tabs[i].kind[FACE_REGION[f]] != 0) {
-        cf.push_back((int32_t)i);
-        cf.push_back(f);
+        cf[k++] = (int32_t)i;
+        cf[k++] = f;
       }
   return cf;
 }
 
 std::vector<int32_t> coarser_regions(const std::vector<Tab>& tabs) {
-  std::vector<int32_t> cr;
+  size_t n = 0;
+  for (const Tab& t : tabs)
+    for (int r = 0; r < 27; ++r) n += r != 13 && t.kind[r] < 0;
+  std::vector<int32_t> cr(2 * n);
+  size_t k = 0;
   for (size_t i = 0; i < tabs.size(); ++i)
     for (int r = 0; r < 27; ++r)
       if (r != 13 && tabs[i].kind[r] < 0) {
-        cr.push_back((int32_t)i);
-        cr.push_back(r);
+        cr[k++] = (int32_t)i;
+        cr[k++] = r;
       }
   return cr;
 }
@@ -263,7 +306,9 @@ int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
   return WACM_OK;
 }
 
-int upload_tables(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
+// The tables become the grid's host copy by exchange: `tabs` receives the
+// previous host copy, whose allocation the next build reuses.
+int upload_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err) {
   if (tabs.empty()) return WACM_OK;
   hipError_t e = hipMemcpy(g->d_tab, tabs.data(), sizeof(Tab) * tabs.size(),
                            hipMemcpyHostToDevice);
@@ -279,8 +324,8 @@ int upload_tables(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) 
   }
   g->n_cface = (int64_t)cf.size() / 2;
   g->n_cregion = (int64_t)cr.size() / 2;
-  g->h_tab = tabs;
-  return build_lift(g, tabs, err);
+  g->h_tab.swap(tabs);
+  return build_lift(g, g->h_tab, err);
 }
 
 }  // namespace wacm

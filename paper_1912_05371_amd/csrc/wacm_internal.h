@@ -181,6 +181,8 @@ struct wacm_grid {
   int jfine = 0;                 // finest active level
   mutable wacm::Profiler prof;   // kernel timing, off by default
   std::vector<wacm::Tab> h_tab;  // host copy of the tables
+  std::vector<wacm::Tab> h_tab_next;  // the next tables' buffer (allocation reused)
+  double adapt_ms[2] = {0, 0};   // last wacm_adapt: host work, device work (ms)
   wacm_schedule sched{0, 1, -1, 1, 0, 1};  // launch schedule of the stage kernel
   wacm::AdjPlan plan[2];         // ghost-fill transposes: all layers / face star
   // restriction wavelet: 0 CDF 4/0 (decimation), 1 CDF 4/4 (lifted); with
@@ -200,7 +202,7 @@ namespace wacm {
 // host-side helpers (grid.cpp)
 void reorder_leaves(wacm_grid* g);  // Morton order, key index, finest level
 int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err);
-int upload_tables(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err);
+int upload_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err);
 std::vector<int32_t> coarse_faces(const std::vector<Tab>& tabs);  // non-same-level faces
 std::vector<int32_t> coarser_regions(const std::vector<Tab>& tabs);  // regions in coarser leaves
 // CDF 4/4: builds the lifted ghost-phase items of the current tables and

@@ -33,7 +33,7 @@ EXPORTS = ["wacm_last_error", "wacm_treecode_encode", "wacm_treecode_decode", "w
            "wacm_get_schedule", "wacm_set_wavelet", "wacm_get_wavelet", "wacm_mr_work_bytes",
            "wacm_mr_forward", "wacm_mr_inverse", "wacm_workspace_bytes",
            "wacm_wavelet_workspace_bytes", "wacm_adj_plan_bytes", "wacm_adj_plan_set",
-           "wacm_mr_forward_noalloc"]
+           "wacm_mr_forward_noalloc", "wacm_adapt_timing"]
 MR_SCRATCH_BYTES = 64 << 20  # WACM_MR_SCRATCH_BYTES
 
 
@@ -147,6 +147,7 @@ def lib():
         L.wacm_get_schedule.argtypes = [vp, C.POINTER(Schedule)]
         L.wacm_profile_enable.argtypes = [vp, i32]
         L.wacm_profile_read.argtypes = [vp, vp, vp]
+        L.wacm_adapt_timing.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -484,6 +485,12 @@ class Grid:
 
     def profile_enable(self, on: bool = True):
         self._call(lib().wacm_profile_enable(self._h, int(bool(on))))
+
+    def adapt_timing(self):
+        """(host ms, device ms) of the last adapt call."""
+        ms = np.zeros(2)
+        self._call(lib().wacm_adapt_timing(self._h, ms.ctypes.data_as(C.c_void_p)))
+        return float(ms[0]), float(ms[1])
 
     def profile_read(self):
         """(ms[4], launches[4]) per kernel class: dt, sync, stage, time update."""
