@@ -1019,34 +1019,8 @@ __global__ __launch_bounds__(NT_GEN) void diag_finalize(const double* __restrict
 // --------------------------------------------------------------------------
 // wavelet details and coarsening flags (Sec. 3.1, 3.3-3.5)
 // --------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(NT_GEN) void norm_kernel(const Tab* __restrict__ tab, int64_t nb,
-                                                      const T* __restrict__ U, Layout L, int bs,
-                                                      double* __restrict__ part) {
-  __shared__ double red[4][NT_GEN / 64];
-  const int n3 = bs * bs * bs;
-  for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
-    const T* b = U + (int64_t)tab[ib].meta[0] * L.bstride;
-    double m[4] = {0, 0, 0, 0};
-    for (int q = threadIdx.x; q < n3; q += blockDim.x) {
-      const int i = q % bs, j = (q / bs) % bs, k = q / (bs * bs);
-      const int64_t o = ((int64_t)(k + L.ng) * L.P + (j + L.ng)) * L.P + (i + L.ng);
-      for (int c = 0; c < 4; ++c) m[c] = fmax(m[c], fabs((double)b[o + c * L.fstride]));
-    }
-    __syncthreads();
-    for (int c = 0; c < 4; ++c) {
-      const double v = wave_max(m[c]);
-      if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-      double r = red[threadIdx.x][0];
-      for (int w = 1; w < NT_GEN / 64; ++w) r = fmax(r, red[threadIdx.x][w]);
-      part[ib * 4 + threadIdx.x] = r;
-    }
-  }
-}
-
+// max over blocks of the per-block field maxima part[4 ib + c] -> norm[c]
+// (1 where the field vanishes); used by the two-dimensional thresholding
 __global__ __launch_bounds__(NT_GEN) void norm_finalize(const double* __restrict__ part,
                                                         int64_t nb, double* __restrict__ norm) {
   __shared__ double red[4][NT_GEN / 64];
@@ -1066,41 +1040,49 @@ __global__ __launch_bounds__(NT_GEN) void norm_finalize(const double* __restrict
 }
 
 // Wavelet details (Sec. 3.1) of one block: d = u - P R u at every interior
-// point, P R u the tensor-product DD4 prediction from the block's even
-// lattice (ghost-synchronised pool), evaluated separably and z-marching: for
-// each coarse plane k' the x pass gives X(i, j', k') on the coarse rows j',
-// the y pass Y(i, j, k') on the whole plane (a ring of the last 4 coarse
-// planes in LDS), and the z pass the prediction of the fine plane k' (even)
-// and k' - 3 (odd).  Per block: max over fields of max |d| / ||u_c||,
-// the mask range and the coarsening flag (Sec. 3.3-3.5).
+// point with an odd index, P R u the tensor-product DD4 prediction from the
+// block's even lattice (ghost-synchronised pool), evaluated separably while
+// marching in z over the coarse planes k' = -2, 0, ..., bs + 2: the x pass
+// gives X(i, j', k') on the coarse rows (LDS, two buffers), the y pass
+// Y(i, j, k') of the thread's own column (one thread per column, the last 4
+// coarse planes in registers), the z pass the prediction of the fine plane k'
+// (even) and k' - 3 (odd).  All 4 fields at once: one barrier per coarse
+// plane.  One workgroup per block; per block and field the maxima of |u_c|
+// and |d_c| over the interior (part[8 ib + c], part[8 ib + 4 + c]), and the
+// mask range (0 without a mask, and for a block where the mask vanishes at
+// time t); thr_finalize turns them into the normalised detail maximum and the
+// coarsening flag (Sec. 3.3-3.5).
 template <typename T, int BS>
-__global__ __launch_bounds__(NT_GEN) void detail_kernel(
-    const Tab* __restrict__ tab, int64_t nb, const T* __restrict__ U, Layout L,
-    const double* __restrict__ norm, double Ldom, wacm_params p, double t, double eps,
-    int dealias, int jmin, int jmax, double* __restrict__ dmax, double* __restrict__ mrange,
-    int8_t* __restrict__ flags) {
+__global__ __launch_bounds__(BS* BS) void detail_kernel(const Tab* __restrict__ tab, int64_t nb,
+                                                        const T* __restrict__ U, Layout L,
+                                                        double Ldom, wacm_params p, double t,
+                                                        double* __restrict__ part,
+                                                        double* __restrict__ mrange) {
   constexpr int S = BS / 2 + 3;  // even positions -2, 0, ..., bs+2
-  constexpr int B2 = BS * BS;
-  __shared__ T xp[S * BS];       // X(i, j') of the current coarse plane
-  __shared__ T yr[4][B2];        // Y(i, j) of the last 4 coarse planes
-  __shared__ double red[3][NT_GEN / 64];
+  constexpr int NT = BS * BS;
+  __shared__ T xp[2][4][S * BS];
+  __shared__ double red[10][NT / 64];
   const T w0 = T(DDW0), w1 = T(DDW1);
   const int tid = threadIdx.x;
+  const int i = tid % BS, j = tid / BS;
   const int P = L.P, ng = L.ng;
-  const MaskTime mt = p.mask ? mask_time(p, t) : MaskTime{1.0, 0.0, 0.0};
-  for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
-    const int32_t* m = tab[ib].meta;
-    const int slot = m[0], J = m[1];
-    const double h = Ldom / (double(int64_t(1) << J) * BS);
-    const T* b = U + (int64_t)slot * L.bstride;
-    // element of local point (i, j, k)
-    auto at = [&](int c, int i, int j, int k) -> T {
-      return b[c * L.fstride + ((int64_t)(k + ng) * P + (j + ng)) * P + (i + ng)];
-    };
-    double dm = 0.0, cmin = 1e300, cmax = -1e300;
-    if (p.mask) {
-      for (int q = tid; q < B2 * BS; q += NT_GEN) {
-        const int i = q % BS, j = (q / BS) % BS, k = q / B2;
+  const int64_t ib = blockIdx.x;
+  if (ib >= nb) return;  // whole workgroup
+  const int32_t* m = tab[ib].meta;
+  const T* b = U + (int64_t)m[0] * L.bstride;
+  auto at = [&](int c, int ii, int jj, int kk) -> T {
+    return b[c * L.fstride + ((int64_t)(kk + ng) * P + (jj + ng)) * P + (ii + ng)];
+  };
+  double cmin = 1e300, cmax = -1e300;
+  if (p.mask) {
+    wacm_params pm = p;
+    pm.sponge = 0;
+    if (pen_far(pm, Ldom, BS, m, pitch_window(p, t, t))) {
+      cmin = cmax = 0.0;  // the mask is exactly 0 on the whole block
+    } else {
+      const MaskTime mt = mask_time(p, t);
+      const double h = Ldom / (double(int64_t(1) << m[1]) * BS);
+      for (int k = 0; k < BS; ++k) {
         double chi, us[3];
         mask_point(p, mt, (double)(m[2] * BS + i) * h, (double)(m[3] * BS + j) * h,
                    (double)(m[4] * BS + k) * h, chi, us);
@@ -1108,82 +1090,136 @@ __global__ __launch_bounds__(NT_GEN) void detail_kernel(
         cmax = fmax(cmax, chi);
       }
     }
+  }
+  double dmc[4] = {0, 0, 0, 0}, umc[4] = {0, 0, 0, 0};
+  T y0[4], y1[4], y2[4], y3[4];  // Y of the coarse planes mm, mm-1, mm-2, mm-3
+#pragma unroll
+  for (int c = 0; c < 4; ++c) y0[c] = y1[c] = y2[c] = y3[c] = T(0);
+  const bool oddij = ((i | j) & 1) != 0;
+  for (int mm = 0; mm < S; ++mm) {
+    const int kc = 2 * mm - 2;  // coarse plane
+    // x pass on the coarse rows j' = 2 jj - 2 of plane kc; the buffer of
+    // plane mm - 2 is free: every thread has passed plane mm - 1's barrier
+    T(*xb)[S * BS] = xp[mm & 1];
+    for (int q = tid; q < S * BS; q += NT) {
+      const int jj = q / BS, ii = q - jj * BS, jc = 2 * jj - 2;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        T v;
+        if ((ii & 1) == 0)
+          v = at(c, ii, jc, kc);
+        else
+          v = w0 * at(c, ii - 3, jc, kc) + w1 * at(c, ii - 1, jc, kc) +
+              w1 * at(c, ii + 1, jc, kc) + w0 * at(c, ii + 3, jc, kc);
+        xb[c][q] = v;
+      }
+    }
+    __syncthreads();
+    // y pass: Y(i, j) of plane kc for the thread's column
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const double inv = 1.0 / norm[c];
-      for (int mm = 0; mm < S; ++mm) {
-        const int kc = 2 * mm - 2;  // coarse plane
-        __syncthreads();            // xp and the ring slot are free again
-        // x pass on the coarse rows j' = 2 jj - 2 of plane kc
-        for (int q = tid; q < S * BS; q += NT_GEN) {
-          const int jj = q / BS, i = q - jj * BS, jc = 2 * jj - 2;
-          T v;
-          if ((i & 1) == 0)
-            v = at(c, i, jc, kc);
-          else
-            v = w0 * at(c, i - 3, jc, kc) + w1 * at(c, i - 1, jc, kc) +
-                w1 * at(c, i + 1, jc, kc) + w0 * at(c, i + 3, jc, kc);
-          xp[q] = v;
-        }
-        __syncthreads();
-        // y pass: Y(i, j) of plane kc into ring slot mm % 4
-        T* yo = yr[mm & 3];
-        for (int q = tid; q < B2; q += NT_GEN) {
-          const int j = q / BS, i = q - j * BS;
-          T v;
-          if ((j & 1) == 0) {
-            v = xp[(j / 2 + 1) * BS + i];
-          } else {
-            const int jj = (j - 3) / 2 + 1;  // coarse row of j - 3
-            v = w0 * xp[jj * BS + i] + w1 * xp[(jj + 1) * BS + i] + w1 * xp[(jj + 2) * BS + i] +
-                w0 * xp[(jj + 3) * BS + i];
-          }
-          yo[q] = v;
-        }
-        __syncthreads();
-        // z pass: the even fine plane kc and the odd fine plane kc - 3
-        for (int q = tid; q < B2; q += NT_GEN) {
-          const int j = q / BS, i = q - j * BS;
-          if (kc >= 0 && kc < BS && ((i | j) & 1))
-            dm = fmax(dm, fabs((double)(at(c, i, j, kc) - yo[q])) * inv);
-          const int ko = kc - 3;
-          if (ko >= 0 && ko < BS) {
-            // taps ko-3, ko-1, ko+1, ko+3 = coarse planes mm-3 .. mm
-            const T pr = w0 * yr[(mm + 1) & 3][q] + w1 * yr[(mm + 2) & 3][q] +
-                         w1 * yr[(mm + 3) & 3][q] + w0 * yo[q];
-            dm = fmax(dm, fabs((double)(at(c, i, j, ko) - pr)) * inv);
-          }
-        }
+      y3[c] = y2[c];
+      y2[c] = y1[c];
+      y1[c] = y0[c];
+      if ((j & 1) == 0) {
+        y0[c] = xb[c][(j / 2 + 1) * BS + i];
+      } else {
+        const int jj = (j - 3) / 2 + 1;  // coarse row of j - 3
+        y0[c] = w0 * xb[c][jj * BS + i] + w1 * xb[c][(jj + 1) * BS + i] +
+                w1 * xb[c][(jj + 2) * BS + i] + w0 * xb[c][(jj + 3) * BS + i];
       }
     }
-    dm = wave_max(dm);
-    cmin = wave_min(cmin);
-    cmax = wave_max(cmax);
-    __syncthreads();
-    if ((tid & 63) == 0) {
-      red[0][tid >> 6] = dm;
-      red[1][tid >> 6] = cmin;
-      red[2][tid >> 6] = cmax;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double r0 = red[0][0], r1 = red[1][0], r2 = red[2][0];
-      for (int w = 1; w < NT_GEN / 64; ++w) {
-        r0 = fmax(r0, red[0][w]);
-        r1 = fmin(r1, red[1][w]);
-        r2 = fmax(r2, red[2][w]);
+    // z pass: the even fine plane kc and the odd fine plane kc - 3 (taps
+    // kc-6, kc-4, kc-2, kc = coarse planes mm-3 .. mm)
+    if (kc >= 0 && kc < BS) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const T u = at(c, i, j, kc);
+        umc[c] = fmax(umc[c], fabs((double)u));
+        if (oddij) dmc[c] = fmax(dmc[c], fabs((double)(u - y0[c])));
       }
-      const double mr = p.mask ? r2 - r1 : 0.0;
-      dmax[ib] = r0;
-      mrange[ib] = mr;
-      int f = 0;
-      if (J > jmin) {
-        if (dealias && J == jmax)
-          f = 1;
-        else if (r0 < eps && mr == 0.0)
-          f = 1;
-      }
-      flags[ib] = (int8_t)f;
     }
+    const int ko = kc - 3;
+    if (ko >= 0 && ko < BS) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const T u = at(c, i, j, ko);
+        const T pr = w0 * y3[c] + w1 * y2[c] + w1 * y1[c] + w0 * y0[c];
+        umc[c] = fmax(umc[c], fabs((double)u));
+        dmc[c] = fmax(dmc[c], fabs((double)(u - pr)));
+      }
+    }
+  }
+  double v[10];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    v[c] = wave_max(umc[c]);
+    v[4 + c] = wave_max(dmc[c]);
+  }
+  v[8] = wave_min(cmin);
+  v[9] = wave_max(cmax);
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 10; ++q) red[q][tid >> 6] = v[q];
+  __syncthreads();
+  if (tid < 10) {
+    double r = red[tid][0];
+    for (int w = 1; w < NT / 64; ++w) r = tid == 8 ? fmin(r, red[tid][w]) : fmax(r, red[tid][w]);
+    red[tid][0] = r;
+  }
+  __syncthreads();
+  if (tid < 8) part[ib * 8 + tid] = red[tid][0];
+  if (tid == 0) mrange[ib] = p.mask ? red[9][0] - red[8][0] : 0.0;
+}
+
+// One workgroup: the field norms (max |u_c| over all blocks, 1 where a field
+// vanishes) into norm, then per block the normalised detail maximum
+// max_c max|d_c| / norm_c (equal to the maximum of the normalised details:
+// scaling by a positive factor keeps the order) and the coarsening flag:
+// 1 iff J > jmin and either dealiasing at J = jmax or the maximum is below
+// eps with a constant mask.
+__global__ __launch_bounds__(1024) void thr_finalize(const Tab* __restrict__ tab, int64_t nb,
+                                                     const double* __restrict__ part,
+                                                     const double* __restrict__ mrange,
+                                                     double eps, int dealias, int jmin, int jmax,
+                                                     double* __restrict__ norm,
+                                                     double* __restrict__ dmax,
+                                                     int8_t* __restrict__ flags) {
+  __shared__ double red[4][1024 / 64];
+  __shared__ double inv[4];
+  const int tid = threadIdx.x;
+  double mx[4] = {0, 0, 0, 0};
+  for (int64_t q = tid; q < nb; q += blockDim.x)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) mx[c] = fmax(mx[c], part[q * 8 + c]);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double v = wave_max(mx[c]);
+    if ((tid & 63) == 0) red[c][tid >> 6] = v;
+  }
+  __syncthreads();
+  if (tid < 4) {
+    double r = red[tid][0];
+    for (int w = 1; w < (int)blockDim.x / 64; ++w) r = fmax(r, red[tid][w]);
+    const double nrm = r > 0.0 ? r : 1.0;
+    norm[tid] = nrm;
+    inv[tid] = 1.0 / nrm;
+  }
+  __syncthreads();
+  for (int64_t q = tid; q < nb; q += blockDim.x) {
+    double dm = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dm = fmax(dm, part[q * 8 + 4 + c] * inv[c]);
+    dmax[q] = dm;
+    const int J = tab[q].meta[1];
+    int f = 0;
+    if (J > jmin) {
+      if (dealias && J == jmax)
+        f = 1;
+      else if (dm < eps && mrange[q] == 0.0)
+        f = 1;
+    }
+    flags[q] = (int8_t)f;
   }
 }
 
@@ -1916,17 +1952,13 @@ static hipError_t thr_t(const wacm_grid* g, const wacm_params* p, double t, cons
                         double eps, int dealias, double* dmax, double* mrange, int8_t* flags,
                         hipStream_t st) {
   if (g->nb == 0) return hipSuccess;
-  norm_kernel<T><<<grid_for(g->nb, 8), NT_GEN, 0, st>>>(g->d_tab, g->nb, U, pool_layout(g),
-                                                        g->d.bs, g->d_part);
-  norm_finalize<<<1, NT_GEN, 0, st>>>(g->d_part, g->nb, g->d_norm);
-  const unsigned grid = grid_for(g->nb, 8);
   const Layout L = pool_layout(g);
   switch (g->d.bs) {
 #define WACM_DETAIL(BSV)                                                                    \
   case BSV:                                                                                 \
-    detail_kernel<T, BSV><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, L, g->d_norm, g->d.L, \
-                                                   *p, t, eps, dealias, g->d.jmin, g->d.jmax, \
-                                                   dmax, mrange, flags);                    \
+    detail_kernel<T, BSV><<<(unsigned)g->nb, BSV * BSV, 0, st>>>(g->d_tab, g->nb, U, L,    \
+                                                                  g->d.L, *p, t, g->d_part, \
+                                                                  mrange);                  \
     break;
     WACM_DETAIL(16)
     WACM_DETAIL(24)
@@ -1935,6 +1967,9 @@ static hipError_t thr_t(const wacm_grid* g, const wacm_params* p, double t, cons
     default:
       return hipErrorInvalidValue;
   }
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+  thr_finalize<<<1, 1024, 0, st>>>(g->d_tab, g->nb, g->d_part, mrange, eps, dealias, g->d.jmin,
+                                   g->d.jmax, g->d_norm, dmax, flags);
   return hipGetLastError();
 }
 
