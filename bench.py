@@ -415,7 +415,7 @@ def c3_run(nsteps: int = 200, every: int = 10):
         dm = torch.empty(n, dtype=torch.float64, device="cuda")
         mr = torch.empty(n, dtype=torch.float64, device="cuda")
         fl = torch.empty(n, dtype=torch.int8, device="cuda")
-        g.sync_ghosts(U)
+        g.sync_ghosts_lattice(U)
         g.threshold_blocks(c.params, t, U, eps, dealias, dm, mr, fl)
         return fl.cpu().numpy()
 

@@ -1,10 +1,10 @@
 """One adaptive time step of the wavelet-adaptive method (Sec. 3.5) over the
 C ABI: refine every block below Jmax, advance one RK4 step on the refined
 grid, then coarsen until no family merges -- each pass synchronises the ghost
-nodes, thresholds the wavelet details of every block (Sec. 3.1, 3.3-3.4) and
-merges the flagged sister groups (Sec. 3.5).  All arithmetic runs in libwacm;
-this module only sequences the calls and carries the per-pass flags from the
-device to the host call of wacm_adapt.
+nodes the details read, thresholds the wavelet details of every block (Sec.
+3.1, 3.3-3.4) and merges the flagged sister groups (Sec. 3.5).  All
+arithmetic runs in libwacm; this module only sequences the calls and carries
+the per-pass flags from the device to the host call of wacm_adapt.
 """
 from __future__ import annotations
 
@@ -61,7 +61,8 @@ def adaptive_step(grid: wacm.Grid, params: dict, U, work, t_dev, dt_dev, eps: fl
         dmax = torch.empty(n, dtype=torch.float64, device=U.device)
         mrange = torch.empty(n, dtype=torch.float64, device=U.device)
         flags = torch.empty(n, dtype=torch.int8, device=U.device)
-        phase("sync_ghosts", lambda: grid.sync_ghosts(U))
+        # the thresholding reads only the even lattice's ghosts
+        phase("sync_ghosts", lambda: grid.sync_ghosts_lattice(U))
         phase("threshold_blocks",
               lambda: grid.threshold_blocks(params, t, U, eps, dealias, dmax, mrange, flags))
         host_flags = phase("flags_to_host", lambda: flags.cpu().numpy())

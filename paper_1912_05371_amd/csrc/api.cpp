@@ -71,6 +71,10 @@ void free_dev(wacm_grid* g) {
   (void)profile_flush(g);
   for (hipEvent_t e : g->prof.spare) (void)hipEventDestroy(e);
   g->prof.spare.clear();
+  for (hipEvent_t& e : g->adapt_ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   g->ws = nullptr;
   g->d_lift = nullptr;
   g->d_lift_tmp = nullptr;
@@ -299,6 +303,14 @@ int wacm_sync_ghosts(wacm_grid* g, void* U, void* stream) {
   if (!elem_ok(g) || !U) return fail(WACM_E_INVAL, "NULL argument");
   hipError_t e = full_sync(g, U, S(stream));
   return e == hipSuccess ? WACM_OK : hipfail(e, "sync_ghosts launch");
+}
+
+int wacm_sync_ghosts_lattice(wacm_grid* g, void* U, void* stream) {
+  GridScope gs(g);
+  if (!elem_ok(g) || !U) return fail(WACM_E_INVAL, "NULL argument");
+  hipError_t e = g->dim == 3 && g->wavelet == WACM_CDF40 ? launch_sync_lattice(g, U, S(stream))
+                                                         : full_sync(g, U, S(stream));
+  return e == hipSuccess ? WACM_OK : hipfail(e, "sync_ghosts_lattice launch");
 }
 
 size_t wacm_wavelet_workspace_bytes(const wacm_grid* g, int32_t wavelet) {
@@ -566,7 +578,11 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
     g->adapt_ms[1] = 0.0;
     return WACM_OK;
   }
-  // commit: new leaf set and its tables (validated before anything on the device changes)
+  // the new leaf set in Morton order; the kernels below need only the work
+  // list, so they are launched first and the new tables are built on the host
+  // while they run.  Before the tables are known to be valid only free pool
+  // slots and ghost layers are written: on error the grid and the active
+  // blocks' interiors are unchanged.
   wacm_grid tmp;
   tmp.d = g->d;
   tmp.dim = g->dim;
@@ -574,34 +590,36 @@ int wacm_adapt(wacm_grid* g, int32_t op, const int8_t* flags, void* U, int64_t* 
   tmp.leaves.swap(newleaves);
   tmp.slots.swap(newslots);
   reorder_leaves(&tmp);
+  hipError_t e;
+  for (hipEvent_t& ev : g->adapt_ev)
+    if (!ev && (e = hipEventCreate(&ev)) != hipSuccess) return hipfail(e, "adapt event");
+  if ((e = hipEventRecord(g->adapt_ev[0], st)) != hipSuccess) return hipfail(e, "adapt event");
+  if (op == WACM_REFINE_ALL) {
+    e = full_sync(g, U, st);
+    if (e != hipSuccess) return hipfail(e, "adapt sync");
+  }
+  e = hipMemcpyAsync(g->d_list, list.data(), sizeof(int32_t) * list.size(),
+                     hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hipfail(e, "adapt list upload");
+  if (g->dim == 2)
+    e = op == WACM_REFINE_ALL ? launch_prolong_2d(g, U, nwork, st)
+                              : launch_decimate_2d(g, U, nwork, st);
+  else if (op == WACM_REFINE_ALL)
+    e = launch_prolong(g, U, nwork, st);
+  else
+    e = g->wavelet == WACM_CDF44 ? launch_lift_coarsen(g, U, nwork, st)
+                                 : launch_decimate(g, U, nwork, st);
+  if (e != hipSuccess) return hipfail(e, "adapt kernel");
+  if ((e = hipEventRecord(g->adapt_ev[1], st)) != hipSuccess) return hipfail(e, "adapt event");
   std::vector<Tab>& tabs = g->h_tab_next;
   std::string err;
   int rc = build_tables(&tmp, tabs, err);
+  e = hipStreamSynchronize(st);
   if (rc) return fail(rc, err);
-  hipError_t e;
-  double dev_ms = 0.0;
-  if (nwork > 0) {
-    const auto d0 = std::chrono::steady_clock::now();
-    if (op == WACM_REFINE_ALL) {
-      e = full_sync(g, U, st);
-      if (e != hipSuccess) return hipfail(e, "adapt sync");
-    }
-    e = hipMemcpyAsync(g->d_list, list.data(), sizeof(int32_t) * list.size(),
-                       hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hipfail(e, "adapt list upload");
-    if (g->dim == 2)
-      e = op == WACM_REFINE_ALL ? launch_prolong_2d(g, U, nwork, st)
-                                : launch_decimate_2d(g, U, nwork, st);
-    else if (op == WACM_REFINE_ALL)
-      e = launch_prolong(g, U, nwork, st);
-    else
-      e = g->wavelet == WACM_CDF44 ? launch_lift_coarsen(g, U, nwork, st)
-                                   : launch_decimate(g, U, nwork, st);
-    if (e != hipSuccess) return hipfail(e, "adapt kernel");
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hipfail(e, "adapt synchronize");
-    dev_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - d0).count();
-  }
+  if (e != hipSuccess) return hipfail(e, "adapt synchronize");
+  float dev_ms = 0.0f;
+  if ((e = hipEventElapsedTime(&dev_ms, g->adapt_ev[0], g->adapt_ev[1])) != hipSuccess)
+    return hipfail(e, "adapt event");
   for (int32_t s : freed) freelist.push_back(s);
   g->leaves.swap(tmp.leaves);
   g->slots.swap(tmp.slots);

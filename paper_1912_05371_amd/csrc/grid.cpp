@@ -132,7 +132,7 @@ int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err) {
   const int64_t nb = g->nb;
   tabs.resize(nb);
   const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-  const int64_t nt = std::max<int64_t>(1, std::min<int64_t>({8, hw, nb / 1024}));
+  const int64_t nt = std::max<int64_t>(1, std::min<int64_t>({8, hw, (nb + 255) / 256}));
   std::vector<int> rc(nt, WACM_OK);
   std::vector<int64_t> bad(nt, -1);
   std::vector<std::string> msg(nt);

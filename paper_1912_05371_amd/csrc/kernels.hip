@@ -67,6 +67,37 @@ __global__ __launch_bounds__(NT_GEN) void sync_kernel(const Tab* __restrict__ ta
   }
 }
 
+// Ghost points of the even lattice within 3 of the block: (i, j, k) all even
+// in [-2, bs+2]^3 outside the interior, the points the wavelet details read
+// (detail_kernel).  Each is a copy: an even point is a lattice point of a
+// coarser leaf and coincides with a point of a finer one (Sec. 3.1), and
+// every source is an interior point of its leaf, so no write is read.
+template <typename T, int BS>
+__global__ __launch_bounds__(NT_GEN) void sync_lattice_kernel(const Tab* __restrict__ tab,
+                                                              int64_t nb, T* __restrict__ U,
+                                                              Layout L) {
+  constexpr int S = BS / 2 + 3, S3 = S * S * S;  // even positions -2, 0, ..., bs+2
+  __shared__ Tab st;
+  for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
+    __syncthreads();
+    load_tab(tab + ib, st);
+    __syncthreads();
+    T* dst = U + (int64_t)st.meta[0] * L.bstride;
+    for (int q = threadIdx.x; q < S3; q += NT_GEN) {
+      const int a = q % S, b = (q / S) % S, c = q / (S * S);
+      const int i = 2 * a - 2, j = 2 * b - 2, k = 2 * c - 2;
+      if (i >= 0 && i < BS && j >= 0 && j < BS && k >= 0 && k < BS) continue;
+      const int64_t so = point_offset(st, BS, L, i, j, k);
+      const int64_t o = ((int64_t)(k + L.ng) * L.P + (j + L.ng)) * L.P + (i + L.ng);
+      T v[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) v[f] = U[so + f * L.fstride];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) dst[o + f * L.fstride] = v[f];
+    }
+  }
+}
+
 // Ghost regions that lie in a coarser leaf (Sec. 3.1 prediction, Sec. 4.2):
 // one work item per (block, region).  The region's box of ghost points is
 // predicted separably: the even lattice box around it (read from whichever
@@ -1670,6 +1701,32 @@ static hipError_t sync_t(const wacm_grid* g, T* U, int mode, hipStream_t st) {
     }
   }
   return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t sync_lattice_t(const wacm_grid* g, T* U, hipStream_t st) {
+  if (g->nb == 0) return hipSuccess;
+  const unsigned grid = grid_for(g->nb, 8);
+  const Layout L = pool_layout(g);
+  switch (g->d.bs) {
+    case 16:
+      sync_lattice_kernel<T, 16><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, L);
+      break;
+    case 24:
+      sync_lattice_kernel<T, 24><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, L);
+      break;
+    case 32:
+      sync_lattice_kernel<T, 32><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, L);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sync_lattice(const wacm_grid* g, void* U, hipStream_t st) {
+  return g->d.dtype == WACM_F64 ? sync_lattice_t(g, (double*)U, st)
+                                : sync_lattice_t(g, (float*)U, st);
 }
 
 hipError_t launch_sync(const wacm_grid* g, void* U, int face_only, hipStream_t st) {

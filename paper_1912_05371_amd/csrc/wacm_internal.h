@@ -183,6 +183,7 @@ struct wacm_grid {
   std::vector<wacm::Tab> h_tab;  // host copy of the tables
   std::vector<wacm::Tab> h_tab_next;  // the next tables' buffer (allocation reused)
   double adapt_ms[2] = {0, 0};   // last wacm_adapt: host work, device work (ms)
+  hipEvent_t adapt_ev[2] = {nullptr, nullptr};  // around wacm_adapt's kernels
   wacm_schedule sched{0, 1, -1, 1, 0, 1};  // launch schedule of the stage kernel
   wacm::AdjPlan plan[2];         // ghost-fill transposes: all layers / face star
   // restriction wavelet: 0 CDF 4/0 (decimation), 1 CDF 4/4 (lifted); with
@@ -222,6 +223,8 @@ struct Regs {  // pointers and layouts of the RK registers
   Layout Ls;
 };
 
+// ghost points of the even lattice within 3 of each block (CDF 4/0, 3D)
+hipError_t launch_sync_lattice(const wacm_grid* g, void* U, hipStream_t st);
 hipError_t launch_sync(const wacm_grid* g, void* U, int face_only, hipStream_t st);
 hipError_t launch_rhs(const wacm_grid* g, const wacm_params* p, double t, const void* U,
                       void* dU, const void* dus, hipStream_t st);

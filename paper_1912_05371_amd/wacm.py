@@ -33,7 +33,7 @@ EXPORTS = ["wacm_last_error", "wacm_treecode_encode", "wacm_treecode_decode", "w
            "wacm_get_schedule", "wacm_set_wavelet", "wacm_get_wavelet", "wacm_mr_work_bytes",
            "wacm_mr_forward", "wacm_mr_inverse", "wacm_workspace_bytes",
            "wacm_wavelet_workspace_bytes", "wacm_adj_plan_bytes", "wacm_adj_plan_set",
-           "wacm_mr_forward_noalloc", "wacm_adapt_timing"]
+           "wacm_mr_forward_noalloc", "wacm_adapt_timing", "wacm_sync_ghosts_lattice"]
 MR_SCRATCH_BYTES = 64 << 20  # WACM_MR_SCRATCH_BYTES
 
 
@@ -115,6 +115,7 @@ def lib():
         L.wacm_work_bytes.restype = C.c_size_t
         L.wacm_work_bytes.argtypes = [vp]
         L.wacm_sync_ghosts.argtypes = [vp, vp, vp]
+        L.wacm_sync_ghosts_lattice.argtypes = [vp, vp, vp]
         L.wacm_rhs_acm.argtypes = [vp, C.POINTER(Params), dbl, vp, vp, vp, vp]
         L.wacm_compute_dt.argtypes = [vp, C.POINTER(Params), vp, vp, vp]
         L.wacm_rk4_step.argtypes = [vp, C.POINTER(Params), vp, vp, vp, vp, vp, i32, vp]
@@ -380,6 +381,12 @@ class Grid:
     def sync_ghosts(self, U, stream=None):
         self._chk_pool(U)
         self._call(lib().wacm_sync_ghosts(self._h, _ptr(U), _stream(stream)))
+
+    def sync_ghosts_lattice(self, U, stream=None):
+        """The ghost points the thresholding reads (the even lattice within 3
+        of each block), as sync_ghosts fills them."""
+        self._chk_pool(U)
+        self._call(lib().wacm_sync_ghosts_lattice(self._h, _ptr(U), _stream(stream)))
 
     def rhs_acm(self, params: dict, t: float, U, dU, dus=None, stream=None):
         self._chk_pool(U)

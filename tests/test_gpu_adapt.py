@@ -13,7 +13,7 @@ import pytest
 
 from paper_1912_05371_amd import cases, inputs, wacm
 
-from gpu_util import from_pool, log, rel_err, slot_map
+from gpu_util import from_pool, log, rel_err, slot_map, to_pool
 
 pytestmark = pytest.mark.gpu
 
@@ -356,3 +356,50 @@ def test_plate_c3_fp32_replay_matches_oracle(c3_oracle_steps):
         assert e < 1e-5
         del gg, pool, work
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("which", ["plate", "oct24", "oct32"])
+@pytest.mark.parametrize("prec", [wacm.F64, wacm.F32])
+def test_lattice_sync_matches_full_sync(which, prec):
+    """wacm_sync_ghosts_lattice writes exactly the ghost points of the even
+    lattice within 3 of each block, with the values wacm_sync_ghosts gives
+    them, and leaves every other point alone; thresholding after it gives
+    bitwise the results it gives after the full sync."""
+    if which == "plate":
+        c = cases.plate_adaptive()
+        eps, dealias = 1e-3, True
+    else:
+        bs, ng, target, seed = (24, 4, 1500, 8) if which == "oct24" else (32, 5, 300, 9)
+        c = cases.random_octree(bs=bs, ng=ng, target=target, j0=2, jmax=5, seed=seed,
+                                with_fields=False)
+        rng = np.random.default_rng(seed)
+        c.fields = [rng.standard_normal((c.nb, bs, bs, bs)) for _ in range(4)]
+        eps, dealias = 1.0, which == "oct32"
+    log(f"lattice sync, {which} {c.nb} blocks, dtype {prec}")
+    g = wacm.Grid.from_case(c, dtype=prec)
+    U0 = to_pool(g, c.padded(fill=7.0), fill=7.0)
+    A, B = U0.clone(), U0.clone()
+    g.sync_ghosts(A)
+    g.sync_ghosts_lattice(B)
+    torch.cuda.synchronize()
+    bs, ng, P = c.bs, c.ng, c.bs + 2 * c.ng
+    q = np.arange(P) - ng
+    lat = (q % 2 == 0) & (q >= -2) & (q <= bs + 2)
+    inner = (q >= 0) & (q < bs)
+    L3 = lat[:, None, None] & lat[None, :, None] & lat[None, None, :]
+    I3 = inner[:, None, None] & inner[None, :, None] & inner[None, None, :]
+    sel = torch.as_tensor(L3 & ~I3, device="cuda")
+    a, b, u0 = A[:c.nb], B[:c.nb], U0[:c.nb]
+    assert torch.equal(b[:, :, sel], a[:, :, sel])
+    assert torch.equal(b[:, :, ~sel], u0[:, :, ~sel])
+    n = g.nb
+    out = []
+    for V in (A, B):
+        dm = torch.empty(n, dtype=torch.float64, device="cuda")
+        mr = torch.empty_like(dm)
+        fl = torch.empty(n, dtype=torch.int8, device="cuda")
+        g.threshold_blocks(c.params, 0.05, V, eps, dealias, dm, mr, fl)
+        out.append((dm, mr, fl))
+    torch.cuda.synchronize()
+    for x, y in zip(*out):
+        assert torch.equal(x, y)
