@@ -414,18 +414,23 @@ __device__ __forceinline__ void ntstore(T v, T* p, int nt) {
 // whole bs-16 block (4 waves) to 2 per SIMD, which keeps two workgroups per
 // CU for the penalized FP64 variant at the cost of a few spills (measured
 // faster than one workgroup per CU without spills).
-template <typename T, int BS, int TY, int MODE, bool PEN, bool PREF>
+// MODEX = MODE (0 rhs only, 1..4 RK stage) or 10 + MODE: the RK stage with
+// every register in the padded pool layout and the input's halos read from
+// its own synchronised ghost layers (the lifted-wavelet step).
+template <typename T, int BS, int TY, int MODEX, bool PEN, bool PREF>
 __global__ __launch_bounds__(BS* TY) __attribute__((amdgpu_waves_per_eu(TY == BS ? (BS == 16 ? 2 : 1) : (sizeof(T) == 8 ? 2 : 3))))
 void stage_kernel(StageArgs<T> a) {
   constexpr int H = 3, W = BS + 2 * H, WY = TY + 2 * H, NT = BS * TY;
   constexpr int NTY = BS / TY, NH = 6 * TY + 6 * BS;
   static_assert(NH <= NT || TY == BS, "halo points per plane exceed the threads");
-  constexpr bool GH = (MODE == 0);
+  constexpr int MODE = MODEX % 10;
+  constexpr bool OWNG = MODEX >= 10;
+  constexpr bool GH = MODE == 0 || OWNG;
   // the stage registers between stages are x-split; U^n is the pool or, from
   // the second step of a multi-step call on, an x-split register too
-  const bool xin = MODE >= 2 || (MODE == 1 && a.Lin.xs != 0);
+  const bool xin = !OWNG && (MODE >= 2 || (MODE == 1 && a.Lin.xs != 0));
   const bool xun = MODE >= 2 && a.Lun.xs != 0;
-  constexpr bool XOUT = MODE >= 1 && MODE <= 3;
+  constexpr bool XOUT = !OWNG && MODE >= 1 && MODE <= 3;
   __shared__ T slab[2][4][W * WY];
   __shared__ FaceDesc<T> fds[6];
   __shared__ int32_t meta[5];
@@ -761,8 +766,12 @@ void stage_kernel(StageArgs<T> a) {
 // `queue` (schedule xcd_map 2) the faces, listed in the blocks' Morton order,
 // are taken from per-XCD work counters like the stage kernel's items, so the
 // faces of sister blocks, which read the same coarse data, meet in one L2.
+// FP32: held to 4 waves per SIMD (a few spilled registers; 0.64 -> 0.60 ms
+// per launch on the 20k-block octree); FP64 keeps its registers (2 waves:
+// held to 4 it spills ~70 and slows down).
 template <typename T, int BS>
-__global__ __launch_bounds__(NT_GEN) void nlface_kernel(const Tab* __restrict__ tab,
+__global__ __launch_bounds__(NT_GEN) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+void nlface_kernel(const Tab* __restrict__ tab,
                                                         const int32_t* __restrict__ cf, int64_t n,
                                                         const T* __restrict__ in, Layout Lin,
                                                         T* __restrict__ hb, int* queue) {
@@ -1826,6 +1835,61 @@ static StageArgs<T> base_args(const wacm_grid* g, const wacm_params* p) {
   a.nt = g->sched.nontemporal;
   a.p = *p;
   return a;
+}
+
+// One RK stage s (1..4) of the fused kernel whose input carries its own
+// synchronised ghost layers: input, U^n, output and accumulator in the
+// padded pool layout, no face-halo buffer (the lifted-wavelet step, whose
+// stage inputs are synchronised in full before each stage).  Tiles of 8
+// rows; early epilogue loads for FP32.
+template <typename T, int BS, int S>
+static hipError_t stage_owng_bs(const StageArgs<T>& a, int wg_per_cu, hipStream_t st) {
+  constexpr bool PREF = sizeof(T) == 4;
+  return a.p.mask || a.p.sponge || a.dus
+             ? stage_launch_t<T, BS, 8, 10 + S, true, PREF>(a, wg_per_cu, st)
+             : stage_launch_t<T, BS, 8, 10 + S, false, PREF>(a, wg_per_cu, st);
+}
+
+template <typename T>
+static hipError_t stage_owng_t(const wacm_grid* g, const wacm_params* p, int s,
+                               const double* t_dev, const double* dt_dev, const T* in, T* un,
+                               T* out, T* acc, const T* dus, hipStream_t st) {
+  if (g->nb == 0) return hipSuccess;
+  StageArgs<T> a = base_args<T>(g, p);
+  const Layout L = pool_layout(g);
+  a.in = in;
+  a.Lin = L;
+  a.un = un;
+  a.Lun = L;
+  a.out = out;
+  a.Lout = L;
+  a.acc = acc;
+  a.Lacc = L;
+  a.dus = dus;
+  a.t_dev = t_dev;
+  a.dt_dev = dt_dev;
+  const int w = g->sched.wg_per_cu;
+  switch (g->d.bs * 10 + s) {
+    case 241: return stage_owng_bs<T, 24, 1>(a, w, st);
+    case 242: return stage_owng_bs<T, 24, 2>(a, w, st);
+    case 243: return stage_owng_bs<T, 24, 3>(a, w, st);
+    case 244: return stage_owng_bs<T, 24, 4>(a, w, st);
+    case 321: return stage_owng_bs<T, 32, 1>(a, w, st);
+    case 322: return stage_owng_bs<T, 32, 2>(a, w, st);
+    case 323: return stage_owng_bs<T, 32, 3>(a, w, st);
+    case 324: return stage_owng_bs<T, 32, 4>(a, w, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_stage_owng(const wacm_grid* g, const wacm_params* p, int s,
+                             const double* t_dev, const double* dt_dev, const void* in, void* un,
+                             void* out, void* acc, const void* dus, hipStream_t st) {
+  return g->d.dtype == WACM_F64
+             ? stage_owng_t(g, p, s, t_dev, dt_dev, (const double*)in, (double*)un,
+                            (double*)out, (double*)acc, (const double*)dus, st)
+             : stage_owng_t(g, p, s, t_dev, dt_dev, (const float*)in, (float*)un, (float*)out,
+                            (float*)acc, (const float*)dus, st);
 }
 
 template <typename T>

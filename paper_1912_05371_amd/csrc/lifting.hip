@@ -201,12 +201,13 @@ hipError_t launch_lift_coarsen(const wacm_grid* g, void* U, int64_t nparents, hi
 }
 
 // --------------------------------------------------------------------------
-// Classical RK4 with CDF 4/4 ghosts.  The fused stage path reads same-level
+// Classical RK4 with CDF 4/4 ghosts.  The CDF 4/0 step reads same-level
 // halos in place and fills face halos next to other levels itself; with the
 // lifted restriction every stage input is instead synchronised in full (CDF
-// 4/0 fill, then the lifted phase) and the rhs read from its own ghost
-// layers: per stage a sync, the rhs and one combination kernel, registers Y,
-// K and the accumulator A in the padded pool layout in `work`.
+// 4/0 fill, then the lifted phase) and the fused stage kernel reads its
+// halos from those ghost layers: per stage a sync and one stage kernel, with
+// the CDF 4/0 step's register arrangement (Y2/Y4, Y3 and W) in the padded
+// pool layout in `work`.
 // --------------------------------------------------------------------------
 struct LiftWork {
   size_t y, k, a, total;
@@ -220,33 +221,6 @@ static LiftWork lift_work(const wacm_grid* g) {
 
 size_t lift_work_bytes(const wacm_grid* g) { return lift_work(g).total; }
 
-// RK4 combinations on the interiors of the active blocks, after the rhs K of
-// a stage: mode 0 (stage 1) A = U + sa K, Y = U + sy K; mode 1 (stages 2, 3)
-// A += sa K, Y = U + sy K; mode 2 (stage 4) U = A + sa K.
-template <typename T, int BS>
-__global__ __launch_bounds__(NT_GEN) void rk_combine_kernel(const Tab* __restrict__ tab,
-                                                            int64_t nb, T* U, const T* K, T* A,
-                                                            T* Y, T sa, T sy, int mode, Layout L) {
-  constexpr int N3 = BS * BS * BS;
-  for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
-    const int64_t so = (int64_t)tab[ib].meta[0] * L.bstride;
-    for (int q = threadIdx.x; q < 4 * N3; q += blockDim.x) {
-      const int c = q / N3, r = q - c * N3;
-      const int i = r % BS, j = (r / BS) % BS, k = r / (BS * BS);
-      const int64_t o =
-          so + c * L.fstride + ((int64_t)(k + L.ng) * L.P + (j + L.ng)) * L.P + (i + L.ng);
-      const T kv = K[o];
-      if (mode == 2) {
-        U[o] = A[o] + sa * kv;
-      } else {
-        const T u = U[o];
-        A[o] = (mode == 0 ? u : A[o]) + sa * kv;
-        Y[o] = u + sy * kv;
-      }
-    }
-  }
-}
-
 __global__ void lift_advance_time(double* t_dev, const double* dt_dev) {
   if (threadIdx.x == 0) t_dev[0] += dt_dev[0];
 }
@@ -257,52 +231,23 @@ static hipError_t rk4_lifted_t(const wacm_grid* g, const wacm_params* p, double*
                                int64_t nsteps, hipStream_t st) {
   if (g->nb == 0) return hipSuccess;
   const LiftWork wp = lift_work(g);
-  T* Y = (T*)((char*)work + wp.y);
-  T* K = (T*)((char*)work + wp.k);
-  T* A = (T*)((char*)work + wp.a);
-  const Layout L = lift_layout(g);
-  const unsigned grid = lift_grid(g->nb);
+  T* Ya = (T*)((char*)work + wp.y);  // Y2, then Y4
+  T* Yb = (T*)((char*)work + wp.k);  // Y3
+  T* Wr = (T*)((char*)work + wp.a);  // W = (U^n + Y2)/3 + dt/3 k2
   hipError_t e;
-  auto comb = [&](double sa, double sy, int mode) {
-    switch (g->d.bs) {
-      case 24:
-        rk_combine_kernel<T, 24><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, K, A, Y, T(sa),
-                                                          T(sy), mode, L);
-        break;
-      case 32:
-        rk_combine_kernel<T, 32><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, K, A, Y, T(sa),
-                                                          T(sy), mode, L);
-        break;
-      default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-  };
-  auto sync = [&](T* X) {
-    hipError_t r = launch_sync(g, X, 0, st);
-    return r == hipSuccess ? launch_lift_sync(g, X, st) : r;
+  // each stage input synchronised in full (CDF 4/0 fill, then the lifted
+  // phase), then the fused stage reading its ghost layers; t and dt stay on
+  // the device
+  auto stage = [&](int s, T* in, T* out) {
+    hipError_t r = launch_sync(g, in, 0, st);
+    if (r == hipSuccess) r = launch_lift_sync(g, in, st);
+    if (r == hipSuccess) r = launch_stage_owng(g, p, s, t_dev, dt_dev, in, U, out, Wr, dus, st);
+    return r;
   };
   for (int64_t n = 0; n < nsteps; ++n) {
     if (dt_mode == WACM_DT_CFL && (e = launch_dt(g, p, U, dt_dev, st)) != hipSuccess) return e;
-    // the stage times enter the rhs as host values: read t and dt back once
-    // per step
-    double h[2];
-    if ((e = hipMemcpyAsync(&h[0], t_dev, sizeof(double), hipMemcpyDeviceToHost, st)) !=
-            hipSuccess ||
-        (e = hipMemcpyAsync(&h[1], dt_dev, sizeof(double), hipMemcpyDeviceToHost, st)) !=
-            hipSuccess ||
-        (e = hipStreamSynchronize(st)) != hipSuccess)
-      return e;
-    const double t = h[0], dt = h[1];
-    // stage 1 reads U^n with its own ghost layers, synchronised in place
-    if ((e = sync(U)) != hipSuccess || (e = launch_rhs(g, p, t, U, K, dus, st)) != hipSuccess ||
-        (e = comb(dt / 6.0, 0.5 * dt, 0)) != hipSuccess || (e = sync(Y)) != hipSuccess ||
-        (e = launch_rhs(g, p, t + 0.5 * dt, Y, K, dus, st)) != hipSuccess ||
-        (e = comb(dt / 3.0, 0.5 * dt, 1)) != hipSuccess || (e = sync(Y)) != hipSuccess ||
-        (e = launch_rhs(g, p, t + 0.5 * dt, Y, K, dus, st)) != hipSuccess ||
-        (e = comb(dt / 3.0, dt, 1)) != hipSuccess || (e = sync(Y)) != hipSuccess ||
-        (e = launch_rhs(g, p, t + dt, Y, K, dus, st)) != hipSuccess ||
-        (e = comb(dt / 6.0, 0.0, 2)) != hipSuccess)
+    if ((e = stage(1, U, Ya)) != hipSuccess || (e = stage(2, Ya, Yb)) != hipSuccess ||
+        (e = stage(3, Yb, Ya)) != hipSuccess || (e = stage(4, Ya, U)) != hipSuccess)
       return e;
     lift_advance_time<<<1, 64, 0, st>>>(t_dev, dt_dev);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -226,6 +226,11 @@ struct Regs {  // pointers and layouts of the RK registers
 // ghost points of the even lattice within 3 of each block (CDF 4/0, 3D)
 hipError_t launch_sync_lattice(const wacm_grid* g, void* U, hipStream_t st);
 hipError_t launch_sync(const wacm_grid* g, void* U, int face_only, hipStream_t st);
+// one RK stage (1..4) of the fused kernel reading the input's own ghost
+// layers; every register in the padded pool layout
+hipError_t launch_stage_owng(const wacm_grid* g, const wacm_params* p, int s,
+                             const double* t_dev, const double* dt_dev, const void* in, void* un,
+                             void* out, void* acc, const void* dus, hipStream_t st);
 hipError_t launch_rhs(const wacm_grid* g, const wacm_params* p, double t, const void* U,
                       void* dU, const void* dus, hipStream_t st);
 hipError_t launch_dt(const wacm_grid* g, const wacm_params* p, const void* U, double* dt_dev,

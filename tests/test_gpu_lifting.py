@@ -228,3 +228,47 @@ def test_cdf44_uniform_grid_is_cdf40(orc):
     g.sync_ghosts(B)
     torch.cuda.synchronize()
     assert torch.equal(A, B)
+
+
+@pytest.mark.parametrize("prec", [wacm.F64, wacm.F32])
+def test_cdf44_rk4_graph_replay_matches_eager(prec):
+    """The lifted step keeps t and dt on the device and launches no copy,
+    memset or synchronisation: a captured wacm_rk4_step (CFL time step)
+    replayed three times, with eager work and synchronisation between the
+    replays, equals eager steps from the same states bitwise."""
+    c = cases.random_octree(bs=24, ng=6, target=300, j0=2, jmax=4, seed=23)
+    g = wacm.Grid.from_case(c, dtype=prec, capacity=c.nb + 8)
+    g.set_wavelet(wacm.CDF44)
+    log(f"CDF 4/4 graph replay, {c.nb} blocks, dtype {prec}")
+    U0 = g.pool()
+    U0[:c.nb] = torch.from_numpy(c.padded()).to("cuda", g.torch_dtype())
+    pool = U0.clone()
+    work = g.work()
+    t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    p = wacm.make_params(c.params)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        g.rk4_step(None, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_CFL, _p=p)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g.rk4_step(None, t_dev, dt_dev, pool, work, dt_mode=wacm.DT_CFL, _p=p)
+    torch.cuda.synchronize()
+    state = U0.clone()
+    for rep in range(3):
+        ref = state.clone()
+        te = torch.zeros(1, dtype=torch.float64, device="cuda")
+        de = torch.zeros(1, dtype=torch.float64, device="cuda")
+        g.rk4_step(None, te, de, ref, work, dt_mode=wacm.DT_CFL, _p=p)
+        torch.cuda.synchronize()
+        pool.copy_(state)
+        t_dev.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(pool, ref), f"replay {rep} differs from eager"
+        assert float(t_dev.item()) == float(te.item()) == float(de.item())
+        state = ref
+        _ = (state * 2.0).sum().item()
