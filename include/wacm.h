@@ -118,12 +118,14 @@ typedef struct {
  * after the rhs, -1 default; nontemporal: 1 streams U^n and the accumulator
  * with non-temporal loads/stores; tile_rows: 0 gives each workgroup a whole
  * block (bs^2 threads), 8 a tile of 8 rows of the block's columns (8 bs
- * threads, smaller workgroups, more of them per CU); pen_split: 1 runs the
+ * threads, smaller workgroups, more of them per CU); pen_split: 2 runs the
  * blocks where the penalization and sponge terms vanish at every point (far
- * from the mask by 40 smoothing widths, outside the sponge) through the
- * unpenalized variant and the others through the penalized one, 0 runs every
- * block through the penalized one when a mask, sponge or dus is present.
- * Default {0, 1, -1, 1, 0, 1}. */
+ * from the mask by 40 smoothing widths, 12 with clipping, and outside the
+ * sponge) through the unpenalized variant and the others through the
+ * penalized one, 1 does so when it pays (at least 2048 active blocks and,
+ * for a static mask or sponge, at least 512 without penalization), 0 runs
+ * every block through the penalized one when a mask, sponge or dus is
+ * present.  Results are the same bit for bit.  Default {0, 1, -1, 1, 0, 1}. */
 typedef struct {
   int32_t wg_per_cu;
   int32_t xcd_map;
@@ -229,7 +231,7 @@ int wacm_get_wavelet(const wacm_grid* grid);
 
 /* Set / read the stage-kernel schedule (values checked: wg_per_cu in [0, 16],
  * xcd_map in {0, 1, 2}, nontemporal in {0, 1}, prefetch in {-1, 0, 1}, tile_rows in
- * {0, 8}, pen_split in {0, 1}). */
+ * {0, 8}, pen_split in {0, 1, 2}). */
 int wacm_set_schedule(wacm_grid* grid, const wacm_schedule* s);
 int wacm_get_schedule(const wacm_grid* grid, wacm_schedule* s);
 

@@ -276,7 +276,7 @@ int wacm_set_schedule(wacm_grid* g, const wacm_schedule* s) {
   if (!g || !s) return fail(WACM_E_INVAL, "NULL argument");
   if (s->wg_per_cu < 0 || s->wg_per_cu > 16 || s->xcd_map < 0 || s->xcd_map > 2 ||
       s->prefetch < -1 || s->prefetch > 1 || (s->nontemporal != 0 && s->nontemporal != 1) ||
-      (s->tile_rows != 0 && s->tile_rows != 8) || (s->pen_split != 0 && s->pen_split != 1))
+      (s->tile_rows != 0 && s->tile_rows != 8) || (s->pen_split < 0 || s->pen_split > 2))
     return fail(WACM_E_INVAL, "schedule value out of range");
   g->sched = *s;
   return WACM_OK;

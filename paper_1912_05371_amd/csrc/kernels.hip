@@ -1945,6 +1945,24 @@ static int64_t stage_items(const wacm_grid* g) {
 // step's last stage formed while writing U (the same value, bit for bit).
 // Between the steps of one call the state stays in the x-split register uc:
 // only the first step reads the pool and only the last one writes it.
+// Whether to split the blocks of a penalized stage (schedule pen_split: 0
+// never, 2 always, 1 when it pays).  Two launches per stage and their tails
+// cost more than the unpenalized kernel saves on small grids: the split
+// needs at least 2048 active blocks, and, for a static mask or sponge, at
+// least 512 blocks without penalization (counted here from the host copy of
+// the tables).  A pitching plate's per-step lists leave only the blocks near
+// the plate penalized, so its grids need only the size.
+static bool pen_split_pays(const wacm_grid* g, const wacm_params* p) {
+  if (g->sched.pen_split != 1) return g->sched.pen_split == 2;
+  if (g->nb < 2048) return false;
+  if (p->mask == WACM_MASK_PLATE) return true;
+  const PitchWindow any{1.0, 0.0, 0.0, false};
+  int64_t nfar = 0;
+  for (int64_t b = 0; b < g->nb && nfar < 512; ++b)
+    nfar += pen_far(*p, g->d.L, g->d.bs, g->h_tab[b].meta, any) ? 1 : 0;
+  return nfar >= 512;
+}
+
 template <typename T>
 static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev, double* dt_dev,
                         T* U, void* work, const T* dus, int dt_mode, int64_t nsteps,
@@ -1974,7 +1992,7 @@ static hipError_t rk4_t(const wacm_grid* g, const wacm_params* p, double* t_dev,
   // blocks without penalization first (the adaptation lists are free
   // during a step: capacity entries of the list, then the 2 counts); a
   // pitching plate is classified per step, for the angles of that step
-  const bool split = g->sched.pen_split && (p->mask || p->sponge || dus);
+  const bool split = (p->mask || p->sponge || dus) && pen_split_pays(g, p);
   const bool split_step = split && p->mask == WACM_MASK_PLATE;
   int32_t* const plist = g->d_list;
   int32_t* const pcnt = g->d_list + g->d.capacity;

@@ -167,9 +167,9 @@ def test_multi_step_call_penalized_and_fixed_dt(orc):
 @pytest.mark.parametrize("prec", [wacm.F64, wacm.F32])
 def test_pen_split_is_bitwise(which, prec):
     """Blocks without penalization through the unpenalized stage kernel
-    (schedule pen_split 1) give bit for bit the state of every block through
-    the penalized one (pen_split 0): 3 CFL steps; the unclipped plate also
-    carries a solid velocity field."""
+    (schedule pen_split 2, always split) give bit for bit the state of every
+    block through the penalized one (pen_split 0): 3 CFL steps; the
+    unclipped plate also carries a solid velocity field."""
     if which.startswith("plate"):
         c = cases.plate_adaptive(jmin=2, jmax=5, jstart=4)
         c.params = cases.plate_params(5, c.bs, c.L, clip=1 if which == "plate_clip" else 0)
@@ -185,7 +185,7 @@ def test_pen_split_is_bitwise(which, prec):
                                   dtype=torch.float64)).to(g.torch_dtype()).contiguous()
     work = g.work()
     out = []
-    for split in (0, 1):
+    for split in (0, 2):
         g.set_schedule(pen_split=split)
         U = U0.clone()
         t = torch.zeros(1, dtype=torch.float64, device="cuda")
