@@ -297,11 +297,11 @@ int wacm_compute_dt(wacm_grid* grid, const wacm_params* prm, const void* U, doub
  * unspecified values (call wacm_sync_ghosts before a call that reads them).
  * With the CDF 4/0 wavelet: no host synchronisation and no allocation, so the
  * call may be captured in a HIP graph as long as the grid is not changed.
- * With CDF 4/4 (wacm_set_wavelet): every stage input is synchronised in
- * full first (U's ghost layers in place: on return they hold the ghosts of
- * the state the last step started from, not of the result), and the work
- * buffer is 3 padded registers (wacm_work_bytes); no host synchronisation or
- * allocation either, so this call may be captured in a HIP graph too.
+ * With CDF 4/4 (wacm_set_wavelet): every stage input is synchronised first,
+ * as far as the stage and the lifted values read (U's ghost layers in place;
+ * on return they are unspecified too), and the work buffer is 3 padded
+ * registers (wacm_work_bytes); no host synchronisation or allocation either,
+ * so this call may be captured in a HIP graph too.
  */
 int wacm_rk4_step(wacm_grid* grid, const wacm_params* prm, double* t_dev, double* dt_dev,
                   void* U, void* work, const void* dus, int32_t dt_mode, void* stream);

@@ -191,52 +191,67 @@ std::vector<int32_t> coarser_regions(const std::vector<Tab>& tabs) {
 // is [-ng, 0) (children of the upper half), [bs, bs+ng) (lower half) or the
 // block's own range split into its two halves; an output at block-local
 // coarse index i is centred on the child's fine point 2 (i - (r-1) bs) - h bs,
-// whose 13-point stencil must lie in the child's padded array.
+// whose 13-point stencil must lie in the child's padded array.  Face regions
+// are cut along their normal into the 3 layers next to the block and the
+// rest: the items of the first n_face of the list are exactly the lifted
+// points of the depth-3 face star (what a stage reads), the others the
+// remaining lifted ghost points.
 // The items of the tables (12 int32 each, pts = output points); also used
 // by the host harness that checks them against the point resolver.
 int lift_items(const wacm_grid* g, const std::vector<Tab>& tabs, std::vector<int32_t>& it,
-               int64_t& pts, std::string& err) {
+               int64_t& pts, int64_t& n_face, std::string& err) {
   const int bs = g->d.bs, ng = g->d.ng, hb = bs / 2;
   it.clear();
   pts = 0;
-  for (size_t ib = 0; ib < tabs.size(); ++ib) {
-    const Tab& t = tabs[ib];
-    for (int r = 0; r < 27; ++r) {
-      if (r == 13 || t.kind[r] <= 0) continue;
-      const int rr[3] = {r % 3, (r / 3) % 3, r / 9};
-      int st[3][2], cnt[3][2], half[3][2], nseg[3];
-      for (int d = 0; d < 3; ++d) {
-        if (rr[d] == 0) {
-          nseg[d] = 1, st[d][0] = -ng, cnt[d][0] = ng, half[d][0] = 1;
-        } else if (rr[d] == 2) {
-          nseg[d] = 1, st[d][0] = bs, cnt[d][0] = ng, half[d][0] = 0;
-        } else {
-          nseg[d] = 2;
-          st[d][0] = 0, cnt[d][0] = hb, half[d][0] = 0;
-          st[d][1] = hb, cnt[d][1] = hb, half[d][1] = 1;
-        }
-      }
-      for (int c = 0; c < nseg[2]; ++c)
-        for (int b = 0; b < nseg[1]; ++b)
-          for (int a = 0; a < nseg[0]; ++a) {
-            const int sg[3] = {a, b, c};
-            int f0[3], n3[3], o0[3], oct = 0;
-            for (int d = 0; d < 3; ++d) {
-              o0[d] = st[d][sg[d]];
-              n3[d] = cnt[d][sg[d]];
-              f0[d] = 2 * (o0[d] - (rr[d] - 1) * bs) - half[d][sg[d]] * bs;
-              oct += half[d][sg[d]] << d;
-              if (f0[d] - 6 < -ng || f0[d] + 2 * (n3[d] - 1) + 6 > bs + ng - 1) {
-                err = "lifted restriction stencil leaves the child's ghost layers";
-                return WACM_E_INVAL;
-              }
-            }
-            const int32_t item[12] = {t.meta[0], o0[0], o0[1], o0[2], n3[0], n3[1], n3[2],
-                                      t.slot[r][oct], f0[0], f0[1], f0[2], (int32_t)pts};
-            it.insert(it.end(), item, item + 12);
-            pts += (int64_t)n3[0] * n3[1] * n3[2];
+  n_face = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (size_t ib = 0; ib < tabs.size(); ++ib) {
+      const Tab& t = tabs[ib];
+      for (int r = 0; r < 27; ++r) {
+        if (r == 13 || t.kind[r] <= 0) continue;
+        const int rr[3] = {r % 3, (r / 3) % 3, r / 9};
+        const bool face = (rr[0] == 1) + (rr[1] == 1) + (rr[2] == 1) == 2;
+        if (pass == 0 && !face) continue;
+        int st[3][2], cnt[3][2], half[3][2], nseg[3];
+        for (int d = 0; d < 3; ++d) {
+          if (rr[d] == 1) {
+            nseg[d] = 2;
+            st[d][0] = 0, cnt[d][0] = hb, half[d][0] = 0;
+            st[d][1] = hb, cnt[d][1] = hb, half[d][1] = 1;
+            continue;
           }
+          nseg[d] = 1;
+          half[d][0] = rr[d] == 0 ? 1 : 0;
+          // a face region's normal range: the 3 layers next to the block
+          // (pass 0) or the others (pass 1); otherwise all ng layers
+          const int lo = face && pass == 1 ? 3 : 0, hi = face && pass == 0 ? 3 : ng;
+          cnt[d][0] = hi - lo;
+          st[d][0] = rr[d] == 0 ? -hi : bs + lo;
+        }
+        if (cnt[0][0] <= 0 || cnt[1][0] <= 0 || cnt[2][0] <= 0) continue;
+        for (int c = 0; c < nseg[2]; ++c)
+          for (int b = 0; b < nseg[1]; ++b)
+            for (int a = 0; a < nseg[0]; ++a) {
+              const int sg[3] = {a, b, c};
+              int f0[3], n3[3], o0[3], oct = 0;
+              for (int d = 0; d < 3; ++d) {
+                o0[d] = st[d][sg[d]];
+                n3[d] = cnt[d][sg[d]];
+                f0[d] = 2 * (o0[d] - (rr[d] - 1) * bs) - half[d][sg[d]] * bs;
+                oct += half[d][sg[d]] << d;
+                if (f0[d] - 6 < -ng || f0[d] + 2 * (n3[d] - 1) + 6 > bs + ng - 1) {
+                  err = "lifted restriction stencil leaves the child's ghost layers";
+                  return WACM_E_INVAL;
+                }
+              }
+              const int32_t item[12] = {t.meta[0], o0[0], o0[1], o0[2], n3[0], n3[1], n3[2],
+                                        t.slot[r][oct], f0[0], f0[1], f0[2], (int32_t)pts};
+              it.insert(it.end(), item, item + 12);
+              pts += (int64_t)n3[0] * n3[1] * n3[2];
+            }
+      }
     }
+    if (pass == 0) n_face = (int64_t)it.size() / 12;
   }
   return WACM_OK;
 }
@@ -260,8 +275,13 @@ WsParts ws_parts(int64_t cap) {
   return w;
 }
 
-size_t lift_items_bytes(int64_t cap) {
+size_t lift_list_bytes(int64_t cap) {
   return up256(sizeof(int32_t) * 12 * LIFT_ITEMS_PER_BLOCK * (size_t)cap);
+}
+
+// the items, then the active blocks in the order the lifted step syncs them
+size_t lift_items_bytes(int64_t cap) {
+  return lift_list_bytes(cap) + up256(sizeof(int32_t) * (size_t)cap);
 }
 
 size_t lift_ws_bytes(int64_t cap, int bs, int ng, size_t es) {
@@ -277,8 +297,8 @@ int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
   g->n_lift = 0;
   if (g->wavelet != 1 || tabs.empty()) return WACM_OK;
   std::vector<int32_t> it;
-  int64_t pts = 0;
-  if (int rc = lift_items(g, tabs, it, pts, err)) {
+  int64_t pts = 0, n_face = 0;
+  if (int rc = lift_items(g, tabs, it, pts, n_face, err)) {
     g->n_lift = -1;
     return rc;
   }
@@ -294,8 +314,25 @@ int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
     err = "lifted ghost items exceed the wavelet workspace";
     return WACM_E_CAPACITY;
   }
+  // the active blocks next to a coarser leaf (a lifted value reads their
+  // padded arrays), then the others
+  std::vector<int32_t> order;
+  order.reserve(tabs.size());
+  int64_t nfine = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (size_t ib = 0; ib < tabs.size(); ++ib) {
+      bool next_to_coarser = false;
+      for (int r = 0; r < 27; ++r)
+        next_to_coarser = next_to_coarser || (r != 13 && tabs[ib].kind[r] < 0);
+      if (next_to_coarser == (pass == 0)) order.push_back((int32_t)ib);
+    }
+    if (pass == 0) nfine = (int64_t)order.size();
+  }
   hipError_t e = hipSuccess;
   if (ibytes > 0) e = hipMemcpy(g->d_lift, it.data(), ibytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess && g->d_lift_blocks)
+    e = hipMemcpy(g->d_lift_blocks, order.data(), sizeof(int32_t) * order.size(),
+                  hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     // no usable items: the lifted phase refuses to run until a rebuild works
     g->n_lift = -1;
@@ -303,6 +340,8 @@ int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
     return WACM_E_HIP;
   }
   g->n_lift = (int64_t)it.size() / 12;
+  g->n_lift_face = n_face;
+  g->n_lift_fine = nfine;
   return WACM_OK;
 }
 

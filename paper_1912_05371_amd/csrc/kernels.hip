@@ -40,16 +40,17 @@ __device__ __forceinline__ T wave_min(T v) {
 // Point-wise ghost fill: mode 0 every ghost point of all ng layers, mode 1 the
 // depth-3 face star (the points the rhs stencils read).  With skip_coarser,
 // points of regions that lie in a coarser leaf are left to
-// sync_coarser_kernel.
+// sync_coarser_kernel.  With `list`, the blocks list[0..nb) only.
 template <typename T>
 __global__ __launch_bounds__(NT_GEN) void sync_kernel(const Tab* __restrict__ tab, int64_t nb,
                                                       T* __restrict__ U, Layout L, int bs,
-                                                      int mode, int skip_coarser) {
+                                                      int mode, int skip_coarser,
+                                                      const int32_t* __restrict__ list) {
   __shared__ Tab st;
   const int npts = mode == 1 ? 18 * bs * bs : L.P * L.P * L.P - bs * bs * bs;
   for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
     __syncthreads();
-    load_tab(tab + ib, st);
+    load_tab(tab + (list ? list[ib] : ib), st);
     __syncthreads();
     T* dst = U + (int64_t)st.meta[0] * L.bstride;
     for (int p = threadIdx.x; p < npts; p += blockDim.x) {
@@ -1693,7 +1694,7 @@ static hipError_t sync_t(const wacm_grid* g, T* U, int mode, hipStream_t st) {
   if (g->nb == 0) return hipSuccess;
   const bool split = mode == 0 && g->d.ng <= SC_MAXG && g->n_cregion > 0;
   sync_kernel<T><<<grid_for(g->nb, 8), NT_GEN, 0, st>>>(g->d_tab, g->nb, U, pool_layout(g),
-                                                        g->d.bs, mode, split ? 1 : 0);
+                                                        g->d.bs, mode, split ? 1 : 0, nullptr);
   if (split) {
     switch (g->d.bs) {
       case 16:
@@ -1736,6 +1737,45 @@ static hipError_t sync_lattice_t(const wacm_grid* g, T* U, hipStream_t st) {
 hipError_t launch_sync_lattice(const wacm_grid* g, void* U, hipStream_t st) {
   return g->d.dtype == WACM_F64 ? sync_lattice_t(g, (double*)U, st)
                                 : sync_lattice_t(g, (float*)U, st);
+}
+
+// The CDF 4/0 phase of a lifted stage's sync: the blocks a lifted value
+// reads from (those next to a coarser leaf, list[0..nf)) get every ghost
+// point, the others only the face star a stage reads; regions in a coarser
+// leaf (all in the first group) by the region kernel.
+template <typename T>
+static hipError_t sync_lifted_stage_t(const wacm_grid* g, T* U, const int32_t* list, int64_t nf,
+                                      hipStream_t st) {
+  if (g->nb == 0) return hipSuccess;
+  if (g->d.ng > SC_MAXG || !list) return sync_t(g, U, 0, st);
+  const Layout L = pool_layout(g);
+  if (nf > 0)
+    sync_kernel<T><<<grid_for(nf, 8), NT_GEN, 0, st>>>(g->d_tab, nf, U, L, g->d.bs, 0, 1, list);
+  if (g->nb > nf)
+    sync_kernel<T><<<grid_for(g->nb - nf, 8), NT_GEN, 0, st>>>(g->d_tab, g->nb - nf, U, L,
+                                                                g->d.bs, 1, 0, list + nf);
+  if (g->n_cregion > 0) {
+    switch (g->d.bs) {
+      case 16:
+        sync_coarser_launch<T, 16>(g, U, st);
+        break;
+      case 24:
+        sync_coarser_launch<T, 24>(g, U, st);
+        break;
+      case 32:
+        sync_coarser_launch<T, 32>(g, U, st);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sync_lifted_stage(const wacm_grid* g, void* U, const int32_t* list, int64_t nf,
+                                    hipStream_t st) {
+  return g->d.dtype == WACM_F64 ? sync_lifted_stage_t(g, (double*)U, list, nf, st)
+                                : sync_lifted_stage_t(g, (float*)U, list, nf, st);
 }
 
 hipError_t launch_sync(const wacm_grid* g, void* U, int face_only, hipStream_t st) {

@@ -177,20 +177,26 @@ static hipError_t lift_box(const wacm_grid* g, const int32_t* items, int64_t n, 
   }
 }
 
+// the first n items of the list (all of them, or the face star's)
 template <typename T>
-static hipError_t lift_sync_t(const wacm_grid* g, T* U, hipStream_t st) {
+static hipError_t lift_sync_t(const wacm_grid* g, T* U, int64_t n, hipStream_t st) {
   if (g->n_lift < 0) return hipErrorOutOfMemory;  // the last item build failed
-  if (g->n_lift == 0) return hipSuccess;
+  if (n == 0) return hipSuccess;
   T* tmp = (T*)g->d_lift_tmp;
-  hipError_t e = lift_box<T>(g, g->d_lift, g->n_lift, U, tmp, 0, st);
+  hipError_t e = lift_box<T>(g, g->d_lift, n, U, tmp, 0, st);
   if (e != hipSuccess) return e;
-  lift_scatter_kernel<T><<<lift_grid(g->n_lift), NT_GEN, 0, st>>>(g->d_lift, g->n_lift, tmp, U,
-                                                                  lift_layout(g));
+  lift_scatter_kernel<T><<<lift_grid(n), NT_GEN, 0, st>>>(g->d_lift, n, tmp, U, lift_layout(g));
   return hipGetLastError();
 }
 
 hipError_t launch_lift_sync(const wacm_grid* g, void* U, hipStream_t st) {
-  return g->d.dtype == WACM_F64 ? lift_sync_t(g, (double*)U, st) : lift_sync_t(g, (float*)U, st);
+  return g->d.dtype == WACM_F64 ? lift_sync_t(g, (double*)U, g->n_lift, st)
+                                : lift_sync_t(g, (float*)U, g->n_lift, st);
+}
+
+hipError_t launch_lift_sync_face(const wacm_grid* g, void* U, hipStream_t st) {
+  return g->d.dtype == WACM_F64 ? lift_sync_t(g, (double*)U, g->n_lift_face, st)
+                                : lift_sync_t(g, (float*)U, g->n_lift_face, st);
 }
 
 hipError_t launch_lift_coarsen(const wacm_grid* g, void* U, int64_t nparents, hipStream_t st) {
@@ -203,9 +209,11 @@ hipError_t launch_lift_coarsen(const wacm_grid* g, void* U, int64_t nparents, hi
 // --------------------------------------------------------------------------
 // Classical RK4 with CDF 4/4 ghosts.  The CDF 4/0 step reads same-level
 // halos in place and fills face halos next to other levels itself; with the
-// lifted restriction every stage input is instead synchronised in full (CDF
-// 4/0 fill, then the lifted phase) and the fused stage kernel reads its
-// halos from those ghost layers: per stage a sync and one stage kernel, with
+// lifted restriction every stage input is instead synchronised (the CDF 4/0
+// fill: every ghost of the blocks next to a coarser leaf, whose padded
+// arrays the lifted values read, the face star of the others; then the
+// lifted phase of the face star) and the fused stage kernel reads its halos
+// from those ghost layers: per stage a sync and one stage kernel, with
 // the CDF 4/0 step's register arrangement (Y2/Y4, Y3 and W) in the padded
 // pool layout in `work`.
 // --------------------------------------------------------------------------
@@ -239,8 +247,8 @@ static hipError_t rk4_lifted_t(const wacm_grid* g, const wacm_params* p, double*
   // phase), then the fused stage reading its ghost layers; t and dt stay on
   // the device
   auto stage = [&](int s, T* in, T* out) {
-    hipError_t r = launch_sync(g, in, 0, st);
-    if (r == hipSuccess) r = launch_lift_sync(g, in, st);
+    hipError_t r = launch_sync_lifted_stage(g, in, g->d_lift_blocks, g->n_lift_fine, st);
+    if (r == hipSuccess) r = launch_lift_sync_face(g, in, st);
     if (r == hipSuccess) r = launch_stage_owng(g, p, s, t_dev, dt_dev, in, U, out, Wr, dus, st);
     return r;
   };

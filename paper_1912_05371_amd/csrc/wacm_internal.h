@@ -152,7 +152,8 @@ WsParts ws_parts(int64_t capacity);
 // (at most 56 of 12 int32 per block) and their staging values (at most the
 // whole ghost shell, 4 fields per point)
 constexpr int LIFT_ITEMS_PER_BLOCK = 56;
-size_t lift_items_bytes(int64_t capacity);
+size_t lift_list_bytes(int64_t capacity);   // the items alone
+size_t lift_items_bytes(int64_t capacity);  // the items and the block order
 size_t lift_ws_bytes(int64_t capacity, int bs, int ng, size_t es);
 
 }  // namespace wacm
@@ -193,6 +194,9 @@ struct wacm_grid {
   int wavelet = 0;
   int32_t* d_lift = nullptr;
   int64_t n_lift = 0;
+  int64_t n_lift_face = 0;  // the first items: the lifted points of the face star
+  int32_t* d_lift_blocks = nullptr;  // active blocks, those next to a coarser leaf first
+  int64_t n_lift_fine = 0;           // how many are next to a coarser leaf
   size_t lift_items_cap = 0;
   void* d_lift_tmp = nullptr;
   size_t lift_tmp_cap = 0;
@@ -247,6 +251,12 @@ hipError_t launch_filter(const wacm_grid* g, void* U, int level, hipStream_t st)
 // CDF 4/4 (lifting.hip): the lifted ghost phase after the CDF 4/0 fill, and
 // the parents of a merge list of n families (already in d_list)
 hipError_t launch_lift_sync(const wacm_grid* g, void* U, hipStream_t st);
+// the CDF 4/0 fill a lifted stage needs: every ghost of the blocks list[0..nf)
+// (those next to a coarser leaf), the face star of the others
+hipError_t launch_sync_lifted_stage(const wacm_grid* g, void* U, const int32_t* list, int64_t nf,
+                                    hipStream_t st);
+// the lifted phase of the face star only (the points a stage reads)
+hipError_t launch_lift_sync_face(const wacm_grid* g, void* U, hipStream_t st);
 hipError_t launch_lift_coarsen(const wacm_grid* g, void* U, int64_t nparents, hipStream_t st);
 // RK4 with CDF 4/4 ghosts: every stage input synchronised in full, the rhs
 // from its own ghost layers; work = 3 padded registers (lift_work_bytes)

@@ -26,7 +26,7 @@ static int g_cap = 0;
 
 namespace wacm {
 int lift_items(const wacm_grid* g, const std::vector<Tab>& tabs, std::vector<int32_t>& it,
-               int64_t& pts, std::string& err);
+               int64_t& pts, int64_t& n_face, std::string& err);
 }
 
 // The CDF 4/4 lifted ghost-phase items: every ghost point whose owner is finer
@@ -43,16 +43,17 @@ static int check_lift(const wacm_grid& g, const std::vector<wacm::Tab>& tabs) {
   L.fstride = (int64_t)P * P * P;
   L.bstride = 4 * L.fstride;
   std::vector<int32_t> it;
-  int64_t pts = 0;
+  int64_t pts = 0, n_face = 0;
   std::string err;
-  if (lift_items(&g, tabs, it, pts, err)) {
+  if (lift_items(&g, tabs, it, pts, n_face, err)) {
     std::fprintf(stderr, "lift items: %s\n", err.c_str());
     return 10;
   }
   std::vector<int> tab_of(g_cap, -1);
   for (size_t ib = 0; ib < tabs.size(); ++ib) tab_of[tabs[ib].meta[0]] = (int)ib;
-  std::set<std::tuple<int, int, int, int>> covered;
+  std::set<std::tuple<int, int, int, int>> covered, covered_face;
   int64_t npts = 0;
+  if (n_face < 0 || n_face > (int64_t)(it.size() / 12)) return 19;
   for (size_t w = 0; w < it.size() / 12; ++w) {
     const int32_t* e = &it[12 * w];
     if (e[0] < 0 || e[0] >= g_cap || tab_of[e[0]] < 0 || e[7] < 0 || e[7] >= g_cap) return 11;
@@ -67,6 +68,7 @@ static int check_lift(const wacm_grid& g, const std::vector<wacm::Tab>& tabs) {
               k < -ng || k >= bs + ng)
             return 13;
           if (!covered.insert({e[0], i, j, k}).second) return 14;
+          if ((int64_t)w < n_face) covered_face.insert({e[0], i, j, k});
           const int c[3] = {e[8] + 2 * dx, e[9] + 2 * dy, e[10] + 2 * dz};
           for (int d = 0; d < 3; ++d)
             if (c[d] - 6 < -ng || c[d] + 6 > bs + ng - 1) return 15;
@@ -90,8 +92,15 @@ static int check_lift(const wacm_grid& g, const std::vector<wacm::Tab>& tabs) {
           const int r = region_of(i, bs) + 3 * region_of(j, bs) + 9 * region_of(k, bs);
           if (r == 13 || tabs[ib].kind[r] <= 0) continue;
           if (!covered.count({tabs[ib].meta[0], i, j, k})) return 18;
+          // the first n_face items hold exactly the face-star points (one
+          // index outside [0, bs), at depth <= 3)
+          const int out = (i < 0 || i >= bs) + (j < 0 || j >= bs) + (k < 0 || k >= bs);
+          const bool star = out == 1 && i >= -3 && i < bs + 3 && j >= -3 && j < bs + 3 &&
+                            k >= -3 && k < bs + 3;
+          if (star != (covered_face.count({tabs[ib].meta[0], i, j, k}) > 0)) return 20;
         }
-  std::printf("lift items %zu, points %lld\n", it.size() / 12, (long long)pts);
+  std::printf("lift items %zu (face star %lld), points %lld\n", it.size() / 12,
+              (long long)n_face, (long long)pts);
   return 0;
 }
 
