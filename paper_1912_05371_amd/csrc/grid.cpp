@@ -1,7 +1,12 @@
 // Host-side block tree of libwacm: leaf index, 2:1 checks and the per-block
 // neighbour tables the kernels use to resolve ghost points (Sec. 4.1-4.2).
+#include <unistd.h>
+
 #include <algorithm>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <numeric>
 #include <thread>
 
@@ -124,31 +129,108 @@ static int build_range(const wacm_grid* g, Tab* tabs, int64_t i0, int64_t i1, in
   return WACM_OK;
 }
 
-// The blocks are split into contiguous runs built by up to 8 threads (each
-// block's table depends only on the read-only leaf index); the error
-// reported is that of the first failing block in active order, whatever the
-// thread count.  `tabs` keeps its allocation from call to call.
+// A fixed team of 7 worker threads for the table builds: spawning threads
+// on every adaptation pass costs about as much as building a small grid's
+// tables.  run(n, f) calls f(k) for k in [0, n), on the workers and the
+// calling thread, and returns when all have finished; calls are serialised.
+// In a process forked after the team started (its workers are not there)
+// the calls run on the calling thread alone.
+class BuildTeam {
+ public:
+  static BuildTeam& get() {
+    static BuildTeam team;
+    return team;
+  }
+  void run(int n, const std::function<void(int)>& f) {
+    std::lock_guard<std::mutex> call(call_mu_);
+    if (getpid() != pid_ || th_.empty() || n <= 1) {
+      for (int k = 0; k < n; ++k) f(k);
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      job_ = &f;
+      njob_ = n;
+      next_ = 0;
+      left_ = n;
+      ++gen_;
+    }
+    cv_.notify_all();
+    work();
+    std::unique_lock<std::mutex> lk(mu_);
+    done_cv_.wait(lk, [&] { return left_ == 0; });
+    job_ = nullptr;
+  }
+  ~BuildTeam() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+
+ private:
+  BuildTeam() : pid_(getpid()) {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const unsigned nw = std::min(7u, hw - 1);
+    for (unsigned w = 0; w < nw; ++w) th_.emplace_back([this] { loop(); });
+  }
+  // take indices of the current job until none is left
+  void work() {
+    for (;;) {
+      int k;
+      const std::function<void(int)>* f;
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (!job_ || next_ >= njob_) return;
+        k = next_++;
+        f = job_;
+      }
+      (*f)(k);
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--left_ == 0) done_cv_.notify_all();
+    }
+  }
+  void loop() {
+    uint64_t seen = 0;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+      }
+      work();
+    }
+  }
+  const pid_t pid_;
+  std::mutex call_mu_, mu_;
+  std::condition_variable cv_, done_cv_;
+  std::vector<std::thread> th_;
+  const std::function<void(int)>* job_ = nullptr;
+  int njob_ = 0, next_ = 0, left_ = 0;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
+// The blocks are split into contiguous runs (at most 8, of at least 256
+// blocks) built by the team (each block's table depends only on the
+// read-only leaf index); the error reported is that of the first failing
+// block in active order, whatever the split.  `tabs` keeps its allocation
+// from call to call.
 int build_tables(wacm_grid* g, std::vector<Tab>& tabs, std::string& err) {
   const int64_t nb = g->nb;
   tabs.resize(nb);
-  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-  const int64_t nt = std::max<int64_t>(1, std::min<int64_t>({8, hw, (nb + 255) / 256}));
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(8, (nb + 255) / 256));
   std::vector<int> rc(nt, WACM_OK);
   std::vector<int64_t> bad(nt, -1);
   std::vector<std::string> msg(nt);
-  auto run = [&](int64_t k) {
+  BuildTeam::get().run(nt, [&](int k) {
     const int64_t i0 = nb * k / nt, i1 = nb * (k + 1) / nt;
     rc[k] = build_range(g, tabs.data(), i0, i1, bad[k], msg[k]);
-  };
-  if (nt == 1) {
-    run(0);
-  } else {
-    std::vector<std::thread> th;
-    for (int64_t k = 1; k < nt; ++k) th.emplace_back(run, k);
-    run(0);
-    for (auto& x : th) x.join();
-  }
-  for (int64_t k = 0; k < nt; ++k)  // runs are in active order
+  });
+  for (int k = 0; k < nt; ++k)  // runs are in active order
     if (rc[k] != WACM_OK) {
       err = msg[k];
       return rc[k];

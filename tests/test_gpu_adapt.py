@@ -275,6 +275,12 @@ def test_adaptive_driver_matches_oracle(orc):
         assert merged == len(passes)
         assert e < 1e-12
         assert abs(float(t_dev.item()) - t) <= 1e-12 * t
+        # every phase split into host and device time that add up to its wall time
+        for rec in timings.values():
+            assert rec["host"] >= 0.0 and rec["device"] >= 0.0
+            assert abs(rec["host"] + rec["device"] - rec["wall"]) <= 1e-9 * max(rec["wall"], 1.0)
+        host_ms, dev_ms = gg.adapt_timing()
+        assert host_ms > 0.0 and dev_ms >= 0.0
 
 
 @pytest.fixture(scope="module")
