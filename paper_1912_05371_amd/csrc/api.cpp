@@ -77,7 +77,7 @@ void free_dev(wacm_grid* g) {
   }
   g->ws = nullptr;
   g->d_lift = nullptr;
-  g->d_lift_blocks = nullptr;
+  g->d_lift_mask = nullptr;
   g->d_lift_tmp = nullptr;
   g->lift_items_cap = g->lift_tmp_cap = 0;
   g->n_lift = 0;
@@ -335,7 +335,7 @@ int wacm_set_wavelet(wacm_grid* g, int32_t wavelet, void* ws, size_t ws_bytes) {
   }
   const int old = g->wavelet;
   int32_t* old_items = g->d_lift;
-  int32_t* old_blocks = g->d_lift_blocks;
+  int32_t* old_mask = g->d_lift_mask;
   void* old_tmp = g->d_lift_tmp;
   const size_t old_icap = g->lift_items_cap, old_tcap = g->lift_tmp_cap;
   g->wavelet = wavelet;
@@ -343,12 +343,12 @@ int wacm_set_wavelet(wacm_grid* g, int32_t wavelet, void* ws, size_t ws_bytes) {
     const size_t ib = lift_items_bytes(g->d.capacity);
     g->d_lift = static_cast<int32_t*>(ws);
     g->lift_items_cap = lift_list_bytes(g->d.capacity);
-    g->d_lift_blocks = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + g->lift_items_cap);
+    g->d_lift_mask = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + g->lift_items_cap);
     g->d_lift_tmp = static_cast<char*>(ws) + ib;
     g->lift_tmp_cap = ws_bytes - ib;
   } else {
     g->d_lift = nullptr;
-    g->d_lift_blocks = nullptr;
+    g->d_lift_mask = nullptr;
     g->d_lift_tmp = nullptr;
     g->lift_items_cap = g->lift_tmp_cap = 0;
   }
@@ -356,7 +356,7 @@ int wacm_set_wavelet(wacm_grid* g, int32_t wavelet, void* ws, size_t ws_bytes) {
   if (int rc = build_lift(g, g->h_tab, err)) {
     g->wavelet = old;
     g->d_lift = old_items;
-    g->d_lift_blocks = old_blocks;
+    g->d_lift_mask = old_mask;
     g->d_lift_tmp = old_tmp;
     g->lift_items_cap = old_icap;
     g->lift_tmp_cap = old_tcap;

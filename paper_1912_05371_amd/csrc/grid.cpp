@@ -361,7 +361,8 @@ size_t lift_list_bytes(int64_t cap) {
   return up256(sizeof(int32_t) * 12 * LIFT_ITEMS_PER_BLOCK * (size_t)cap);
 }
 
-// the items, then the active blocks in the order the lifted step syncs them
+// the items, then a region mask per block (the ghost regions the face-star
+// lifted values read)
 size_t lift_items_bytes(int64_t cap) {
   return lift_list_bytes(cap) + up256(sizeof(int32_t) * (size_t)cap);
 }
@@ -396,24 +397,37 @@ int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
     err = "lifted ghost items exceed the wavelet workspace";
     return WACM_E_CAPACITY;
   }
-  // the active blocks next to a coarser leaf (a lifted value reads their
-  // padded arrays), then the others
-  std::vector<int32_t> order;
-  order.reserve(tabs.size());
-  int64_t nfine = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (size_t ib = 0; ib < tabs.size(); ++ib) {
-      bool next_to_coarser = false;
-      for (int r = 0; r < 27; ++r)
-        next_to_coarser = next_to_coarser || (r != 13 && tabs[ib].kind[r] < 0);
-      if (next_to_coarser == (pass == 0)) order.push_back((int32_t)ib);
+  // per active block, the ghost regions of its padded array that the
+  // face-star lifted values read: the 13-point stencils of an item's outputs
+  // cover [f0 - 6, f0 + 2 (n - 1) + 6] of the finer leaf on each axis
+  std::vector<int32_t> slot_ib((size_t)g->d.capacity, -1);
+  for (size_t ib = 0; ib < tabs.size(); ++ib) slot_ib[tabs[ib].meta[0]] = (int32_t)ib;
+  std::vector<int32_t> mask(tabs.size(), 0);
+  const int bs = g->d.bs;
+  for (int64_t w = 0; w < n_face; ++w) {
+    const int32_t* e = &it[12 * w];
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      const int f0 = e[8 + d] - 6, f1 = e[8 + d] + 2 * (e[4 + d] - 1) + 6;
+      lo[d] = f0 < 0 ? 0 : (f0 < bs ? 1 : 2);
+      hi[d] = f1 < 0 ? 0 : (f1 < bs ? 1 : 2);
     }
-    if (pass == 0) nfine = (int64_t)order.size();
+    int32_t bits = 0;
+    for (int rz = lo[2]; rz <= hi[2]; ++rz)
+      for (int ry = lo[1]; ry <= hi[1]; ++ry)
+        for (int rx = lo[0]; rx <= hi[0]; ++rx) bits |= int32_t(1) << (rx + 3 * ry + 9 * rz);
+    const int32_t fb = slot_ib[e[7]];
+    if (fb < 0) {
+      g->n_lift = -1;
+      err = "lifted item reads an inactive slot";
+      return WACM_E_INVAL;
+    }
+    mask[fb] |= bits;
   }
   hipError_t e = hipSuccess;
   if (ibytes > 0) e = hipMemcpy(g->d_lift, it.data(), ibytes, hipMemcpyHostToDevice);
-  if (e == hipSuccess && g->d_lift_blocks)
-    e = hipMemcpy(g->d_lift_blocks, order.data(), sizeof(int32_t) * order.size(),
+  if (e == hipSuccess && g->d_lift_mask && !mask.empty())
+    e = hipMemcpy(g->d_lift_mask, mask.data(), sizeof(int32_t) * mask.size(),
                   hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     // no usable items: the lifted phase refuses to run until a rebuild works
@@ -423,7 +437,6 @@ int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
   }
   g->n_lift = (int64_t)it.size() / 12;
   g->n_lift_face = n_face;
-  g->n_lift_fine = nfine;
   return WACM_OK;
 }
 

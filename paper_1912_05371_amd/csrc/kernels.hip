@@ -40,25 +40,32 @@ __device__ __forceinline__ T wave_min(T v) {
 // Point-wise ghost fill: mode 0 every ghost point of all ng layers, mode 1 the
 // depth-3 face star (the points the rhs stencils read).  With skip_coarser,
 // points of regions that lie in a coarser leaf are left to
-// sync_coarser_kernel.  With `list`, the blocks list[0..nb) only.
+// sync_coarser_kernel.  With `mask` (mode 0): only the face star and the
+// regions r with bit r of mask[block] set.
 template <typename T>
 __global__ __launch_bounds__(NT_GEN) void sync_kernel(const Tab* __restrict__ tab, int64_t nb,
                                                       T* __restrict__ U, Layout L, int bs,
                                                       int mode, int skip_coarser,
-                                                      const int32_t* __restrict__ list) {
+                                                      const int32_t* __restrict__ mask) {
   __shared__ Tab st;
   const int npts = mode == 1 ? 18 * bs * bs : L.P * L.P * L.P - bs * bs * bs;
   for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
     __syncthreads();
-    load_tab(tab + (list ? list[ib] : ib), st);
+    load_tab(tab + ib, st);
     __syncthreads();
     T* dst = U + (int64_t)st.meta[0] * L.bstride;
+    const int32_t want = mask ? mask[ib] : -1;
     for (int p = threadIdx.x; p < npts; p += blockDim.x) {
       int i, j, k;
       shell_point(p, bs, L.ng, L.P, mode, i, j, k);
-      if (skip_coarser &&
-          st.kind[region_of(i, bs) + 3 * region_of(j, bs) + 9 * region_of(k, bs)] < 0)
-        continue;
+      const int r = region_of(i, bs) + 3 * region_of(j, bs) + 9 * region_of(k, bs);
+      if (skip_coarser && st.kind[r] < 0) continue;
+      if (mask && !((want >> r) & 1)) {
+        // outside the regions asked for: only the depth-3 face star
+        const int out = (i < 0 || i >= bs) + (j < 0 || j >= bs) + (k < 0 || k >= bs);
+        if (out != 1 || i < -3 || i >= bs + 3 || j < -3 || j >= bs + 3 || k < -3 || k >= bs + 3)
+          continue;
+      }
       T v[4];
       ghost_value<T>(st, bs, L, U, i, j, k, v);
       const int64_t o = ((int64_t)(k + L.ng) * L.P + (j + L.ng)) * L.P + (i + L.ng);
@@ -1739,22 +1746,19 @@ hipError_t launch_sync_lattice(const wacm_grid* g, void* U, hipStream_t st) {
                                 : sync_lattice_t(g, (float*)U, st);
 }
 
-// The CDF 4/0 phase of a lifted stage's sync: the blocks a lifted value
-// reads from (those next to a coarser leaf, list[0..nf)) get every ghost
-// point, the others only the face star a stage reads; regions in a coarser
-// leaf (all in the first group) by the region kernel.
+// The CDF 4/0 phase of a lifted stage's sync: every block's face star (what
+// the stage reads) and the whole ghost regions of its mask (what the
+// face-star lifted values read from its padded array); regions in a coarser
+// leaf by the region kernel.
 template <typename T>
-static hipError_t sync_lifted_stage_t(const wacm_grid* g, T* U, const int32_t* list, int64_t nf,
+static hipError_t sync_lifted_stage_t(const wacm_grid* g, T* U, const int32_t* mask,
                                       hipStream_t st) {
   if (g->nb == 0) return hipSuccess;
-  if (g->d.ng > SC_MAXG || !list) return sync_t(g, U, 0, st);
-  const Layout L = pool_layout(g);
-  if (nf > 0)
-    sync_kernel<T><<<grid_for(nf, 8), NT_GEN, 0, st>>>(g->d_tab, nf, U, L, g->d.bs, 0, 1, list);
-  if (g->nb > nf)
-    sync_kernel<T><<<grid_for(g->nb - nf, 8), NT_GEN, 0, st>>>(g->d_tab, g->nb - nf, U, L,
-                                                                g->d.bs, 1, 0, list + nf);
-  if (g->n_cregion > 0) {
+  if (g->d.ng > SC_MAXG || !mask) return sync_t(g, U, 0, st);
+  const bool split = g->n_cregion > 0;
+  sync_kernel<T><<<grid_for(g->nb, 8), NT_GEN, 0, st>>>(g->d_tab, g->nb, U, pool_layout(g),
+                                                        g->d.bs, 0, split ? 1 : 0, mask);
+  if (split) {
     switch (g->d.bs) {
       case 16:
         sync_coarser_launch<T, 16>(g, U, st);
@@ -1772,10 +1776,10 @@ static hipError_t sync_lifted_stage_t(const wacm_grid* g, T* U, const int32_t* l
   return hipGetLastError();
 }
 
-hipError_t launch_sync_lifted_stage(const wacm_grid* g, void* U, const int32_t* list, int64_t nf,
+hipError_t launch_sync_lifted_stage(const wacm_grid* g, void* U, const int32_t* mask,
                                     hipStream_t st) {
-  return g->d.dtype == WACM_F64 ? sync_lifted_stage_t(g, (double*)U, list, nf, st)
-                                : sync_lifted_stage_t(g, (float*)U, list, nf, st);
+  return g->d.dtype == WACM_F64 ? sync_lifted_stage_t(g, (double*)U, mask, st)
+                                : sync_lifted_stage_t(g, (float*)U, mask, st);
 }
 
 hipError_t launch_sync(const wacm_grid* g, void* U, int face_only, hipStream_t st) {

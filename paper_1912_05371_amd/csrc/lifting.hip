@@ -210,10 +210,10 @@ hipError_t launch_lift_coarsen(const wacm_grid* g, void* U, int64_t nparents, hi
 // Classical RK4 with CDF 4/4 ghosts.  The CDF 4/0 step reads same-level
 // halos in place and fills face halos next to other levels itself; with the
 // lifted restriction every stage input is instead synchronised (the CDF 4/0
-// fill: every ghost of the blocks next to a coarser leaf, whose padded
-// arrays the lifted values read, the face star of the others; then the
-// lifted phase of the face star) and the fused stage kernel reads its halos
-// from those ghost layers: per stage a sync and one stage kernel, with
+// fill of every face star and of the ghost regions the face-star lifted
+// values read from finer leaves' padded arrays; then the lifted phase of the
+// face star) and the fused stage kernel reads its halos from those ghost
+// layers: per stage a sync and one stage kernel, with
 // the CDF 4/0 step's register arrangement (Y2/Y4, Y3 and W) in the padded
 // pool layout in `work`.
 // --------------------------------------------------------------------------
@@ -247,7 +247,7 @@ static hipError_t rk4_lifted_t(const wacm_grid* g, const wacm_params* p, double*
   // phase), then the fused stage reading its ghost layers; t and dt stay on
   // the device
   auto stage = [&](int s, T* in, T* out) {
-    hipError_t r = launch_sync_lifted_stage(g, in, g->d_lift_blocks, g->n_lift_fine, st);
+    hipError_t r = launch_sync_lifted_stage(g, in, g->d_lift_mask, st);
     if (r == hipSuccess) r = launch_lift_sync_face(g, in, st);
     if (r == hipSuccess) r = launch_stage_owng(g, p, s, t_dev, dt_dev, in, U, out, Wr, dus, st);
     return r;

@@ -153,7 +153,7 @@ WsParts ws_parts(int64_t capacity);
 // whole ghost shell, 4 fields per point)
 constexpr int LIFT_ITEMS_PER_BLOCK = 56;
 size_t lift_list_bytes(int64_t capacity);   // the items alone
-size_t lift_items_bytes(int64_t capacity);  // the items and the block order
+size_t lift_items_bytes(int64_t capacity);  // the items and the region masks
 size_t lift_ws_bytes(int64_t capacity, int bs, int ng, size_t es);
 
 }  // namespace wacm
@@ -195,8 +195,9 @@ struct wacm_grid {
   int32_t* d_lift = nullptr;
   int64_t n_lift = 0;
   int64_t n_lift_face = 0;  // the first items: the lifted points of the face star
-  int32_t* d_lift_blocks = nullptr;  // active blocks, those next to a coarser leaf first
-  int64_t n_lift_fine = 0;           // how many are next to a coarser leaf
+  // per active block, the ghost regions (bit r of 27) a face-star lifted
+  // value reads from its padded array
+  int32_t* d_lift_mask = nullptr;
   size_t lift_items_cap = 0;
   void* d_lift_tmp = nullptr;
   size_t lift_tmp_cap = 0;
@@ -251,9 +252,9 @@ hipError_t launch_filter(const wacm_grid* g, void* U, int level, hipStream_t st)
 // CDF 4/4 (lifting.hip): the lifted ghost phase after the CDF 4/0 fill, and
 // the parents of a merge list of n families (already in d_list)
 hipError_t launch_lift_sync(const wacm_grid* g, void* U, hipStream_t st);
-// the CDF 4/0 fill a lifted stage needs: every ghost of the blocks list[0..nf)
-// (those next to a coarser leaf), the face star of the others
-hipError_t launch_sync_lifted_stage(const wacm_grid* g, void* U, const int32_t* list, int64_t nf,
+// the CDF 4/0 fill a lifted stage needs: every block's face star, and the
+// whole ghost regions in mask[b] (those the face-star lifted values read)
+hipError_t launch_sync_lifted_stage(const wacm_grid* g, void* U, const int32_t* mask,
                                     hipStream_t st);
 // the lifted phase of the face star only (the points a stage reads)
 hipError_t launch_lift_sync_face(const wacm_grid* g, void* U, hipStream_t st);
