@@ -361,10 +361,78 @@ size_t lift_list_bytes(int64_t cap) {
   return up256(sizeof(int32_t) * 12 * LIFT_ITEMS_PER_BLOCK * (size_t)cap);
 }
 
-// the items, then a region mask per block (the ghost regions the face-star
-// lifted values read)
+// the items, then the read boxes of every block (lift_read_boxes)
 size_t lift_items_bytes(int64_t cap) {
-  return lift_list_bytes(cap) + up256(sizeof(int32_t) * (size_t)cap);
+  return lift_list_bytes(cap) + up256(sizeof(int32_t) * LIFT_BOX_WORDS * (size_t)cap);
+}
+
+// Per active block (table order), the part of each ghost region of its
+// padded array that the face-star lifted values read: an item's outputs are
+// centred on the finer leaf's points f0, f0 + 2, ..., whose 13-point stencils
+// cover [f0 - 6, f0 + 2 (n - 1) + 6] on each axis; per region the bounding
+// box of those boxes' intersections with it, packed as in LIFT_BOX_WORDS.
+int lift_read_boxes(const wacm_grid* g, const std::vector<Tab>& tabs,
+                    const std::vector<int32_t>& it, int64_t n_face, std::vector<int32_t>& box,
+                    std::string& err) {
+  const int bs = g->d.bs, ng = g->d.ng;
+  if (bs > 32 || ng > 32) {
+    err = "read boxes need bs and ng of at most 32";
+    return WACM_E_INVAL;
+  }
+  std::vector<int32_t> slot_ib((size_t)g->d.capacity, -1);
+  for (size_t ib = 0; ib < tabs.size(); ++ib) slot_ib[tabs[ib].meta[0]] = (int32_t)ib;
+  // per (block, region): lowest and highest block-local index on each axis
+  std::vector<int16_t> lh(tabs.size() * 27 * 6, 0);
+  box.assign(tabs.size() * LIFT_BOX_WORDS, 0);
+  for (int64_t w = 0; w < n_face; ++w) {
+    const int32_t* e = &it[12 * w];
+    const int32_t fb = e[7] >= 0 && e[7] < g->d.capacity ? slot_ib[e[7]] : -1;
+    if (fb < 0) {
+      err = "lifted item reads an inactive slot";
+      return WACM_E_INVAL;
+    }
+    int a0[3], a1[3];
+    for (int d = 0; d < 3; ++d) {
+      a0[d] = e[8 + d] - 6;
+      a1[d] = e[8 + d] + 2 * (e[4 + d] - 1) + 6;
+    }
+    for (int r = 0; r < 27; ++r) {
+      if (r == 13) continue;
+      const int rr[3] = {r % 3, (r / 3) % 3, r / 9};
+      int lo[3], hi[3];
+      bool hit = true;
+      for (int d = 0; d < 3; ++d) {
+        const int r0 = rr[d] == 0 ? -ng : (rr[d] == 1 ? 0 : bs);
+        const int r1 = rr[d] == 0 ? -1 : (rr[d] == 1 ? bs - 1 : bs + ng - 1);
+        lo[d] = std::max(r0, a0[d]);
+        hi[d] = std::min(r1, a1[d]);
+        hit = hit && lo[d] <= hi[d];
+      }
+      if (!hit) continue;
+      int32_t& have = box[(size_t)fb * LIFT_BOX_WORDS + 13];
+      int16_t* b = &lh[((size_t)fb * 27 + r) * 6];
+      for (int d = 0; d < 3; ++d) {
+        const bool first = !((have >> r) & 1);
+        b[2 * d] = (int16_t)(first ? lo[d] : std::min<int>(b[2 * d], lo[d]));
+        b[2 * d + 1] = (int16_t)(first ? hi[d] : std::max<int>(b[2 * d + 1], hi[d]));
+      }
+      have |= int32_t(1) << r;
+    }
+  }
+  for (size_t ib = 0; ib < tabs.size(); ++ib)
+    for (int r = 0; r < 27; ++r) {
+      if (r == 13 || !((box[ib * LIFT_BOX_WORDS + 13] >> r) & 1)) continue;
+      const int rr[3] = {r % 3, (r / 3) % 3, r / 9};
+      const int16_t* b = &lh[(ib * 27 + r) * 6];
+      int32_t v = 0;
+      for (int d = 0; d < 3; ++d) {
+        const int r0 = rr[d] == 0 ? -ng : (rr[d] == 1 ? 0 : bs);
+        v |= (int32_t)(b[2 * d] - r0) << (10 * d);
+        v |= (int32_t)(b[2 * d + 1] - r0) << (10 * d + 5);
+      }
+      box[ib * LIFT_BOX_WORDS + r] = v;
+    }
+  return WACM_OK;
 }
 
 size_t lift_ws_bytes(int64_t cap, int bs, int ng, size_t es) {
@@ -397,32 +465,10 @@ int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
     err = "lifted ghost items exceed the wavelet workspace";
     return WACM_E_CAPACITY;
   }
-  // per active block, the ghost regions of its padded array that the
-  // face-star lifted values read: the 13-point stencils of an item's outputs
-  // cover [f0 - 6, f0 + 2 (n - 1) + 6] of the finer leaf on each axis
-  std::vector<int32_t> slot_ib((size_t)g->d.capacity, -1);
-  for (size_t ib = 0; ib < tabs.size(); ++ib) slot_ib[tabs[ib].meta[0]] = (int32_t)ib;
-  std::vector<int32_t> mask(tabs.size(), 0);
-  const int bs = g->d.bs;
-  for (int64_t w = 0; w < n_face; ++w) {
-    const int32_t* e = &it[12 * w];
-    int lo[3], hi[3];
-    for (int d = 0; d < 3; ++d) {
-      const int f0 = e[8 + d] - 6, f1 = e[8 + d] + 2 * (e[4 + d] - 1) + 6;
-      lo[d] = f0 < 0 ? 0 : (f0 < bs ? 1 : 2);
-      hi[d] = f1 < 0 ? 0 : (f1 < bs ? 1 : 2);
-    }
-    int32_t bits = 0;
-    for (int rz = lo[2]; rz <= hi[2]; ++rz)
-      for (int ry = lo[1]; ry <= hi[1]; ++ry)
-        for (int rx = lo[0]; rx <= hi[0]; ++rx) bits |= int32_t(1) << (rx + 3 * ry + 9 * rz);
-    const int32_t fb = slot_ib[e[7]];
-    if (fb < 0) {
-      g->n_lift = -1;
-      err = "lifted item reads an inactive slot";
-      return WACM_E_INVAL;
-    }
-    mask[fb] |= bits;
+  std::vector<int32_t> mask;
+  if (int rc = lift_read_boxes(g, tabs, it, n_face, mask, err)) {
+    g->n_lift = -1;
+    return rc;
   }
   hipError_t e = hipSuccess;
   if (ibytes > 0) e = hipMemcpy(g->d_lift, it.data(), ibytes, hipMemcpyHostToDevice);

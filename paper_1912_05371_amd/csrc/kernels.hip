@@ -40,31 +40,53 @@ __device__ __forceinline__ T wave_min(T v) {
 // Point-wise ghost fill: mode 0 every ghost point of all ng layers, mode 1 the
 // depth-3 face star (the points the rhs stencils read).  With skip_coarser,
 // points of regions that lie in a coarser leaf are left to
-// sync_coarser_kernel.  With `mask` (mode 0): only the face star and the
-// regions r with bit r of mask[block] set.
+// sync_coarser_kernel.  With `box` (the lifted step's read boxes,
+// LIFT_BOX_WORDS per block; mode 0): only the points inside a region's box,
+// and the face star of regions in a coarser leaf unless those are skipped;
+// the rest of the face star is read in place (same level) or overwritten by
+// the lifted phase (finer leaf).  A block without boxes visits its face star
+// alone, or nothing.
 template <typename T>
 __global__ __launch_bounds__(NT_GEN) void sync_kernel(const Tab* __restrict__ tab, int64_t nb,
                                                       T* __restrict__ U, Layout L, int bs,
                                                       int mode, int skip_coarser,
-                                                      const int32_t* __restrict__ mask) {
+                                                      const int32_t* __restrict__ box) {
   __shared__ Tab st;
-  const int npts = mode == 1 ? 18 * bs * bs : L.P * L.P * L.P - bs * bs * bs;
+  __shared__ int32_t sbox[LIFT_BOX_WORDS];
   for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
     __syncthreads();
     load_tab(tab + ib, st);
+    if (box && threadIdx.x < LIFT_BOX_WORDS)
+      sbox[threadIdx.x] = box[ib * LIFT_BOX_WORDS + threadIdx.x];
     __syncthreads();
     T* dst = U + (int64_t)st.meta[0] * L.bstride;
-    const int32_t want = mask ? mask[ib] : -1;
+    const int32_t have = box ? sbox[13] : 0;
+    if (box && have == 0 && skip_coarser) continue;
+    const int md = box && have == 0 ? 1 : mode;
+    const int npts = md == 1 ? 18 * bs * bs : L.P * L.P * L.P - bs * bs * bs;
     for (int p = threadIdx.x; p < npts; p += blockDim.x) {
       int i, j, k;
-      shell_point(p, bs, L.ng, L.P, mode, i, j, k);
+      shell_point(p, bs, L.ng, L.P, md, i, j, k);
       const int r = region_of(i, bs) + 3 * region_of(j, bs) + 9 * region_of(k, bs);
       if (skip_coarser && st.kind[r] < 0) continue;
-      if (mask && !((want >> r) & 1)) {
-        // outside the regions asked for: only the depth-3 face star
-        const int out = (i < 0 || i >= bs) + (j < 0 || j >= bs) + (k < 0 || k >= bs);
-        if (out != 1 || i < -3 || i >= bs + 3 || j < -3 || j >= bs + 3 || k < -3 || k >= bs + 3)
-          continue;
+      if (box) {
+        bool in = false;
+        if ((have >> r) & 1) {
+          const int32_t b = sbox[r];
+          const int q[3] = {i, j, k};
+          in = true;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const int o = q[d] - (q[d] < 0 ? -L.ng : (q[d] < bs ? 0 : bs));
+            in = in && o >= ((b >> (10 * d)) & 31) && o <= ((b >> (10 * d + 5)) & 31);
+          }
+        }
+        if (!in) {
+          const int out = (i < 0 || i >= bs) + (j < 0 || j >= bs) + (k < 0 || k >= bs);
+          if (st.kind[r] >= 0 || out != 1 || i < -3 || i >= bs + 3 || j < -3 || j >= bs + 3 ||
+              k < -3 || k >= bs + 3)
+            continue;
+        }
       }
       T v[4];
       ghost_value<T>(st, bs, L, U, i, j, k, v);
@@ -333,7 +355,13 @@ struct FaceDesc {
   int32_t fs, sd, s0, s1, mode;
 };
 
-template <typename T, int BS, bool GHOSTS>
+// Where a stage reads the depth-3 halo of a face: HALO_NB same-level faces
+// from the neighbour's interior, the others from the face-halo buffer;
+// HALO_OWN every face from the input's own ghost layers; HALO_MIX same-level
+// faces from the neighbour's interior, the others from the own ghost layers.
+enum { HALO_NB = 0, HALO_OWN = 1, HALO_MIX = 2 };
+
+template <typename T, int BS, int HALO>
 __device__ __forceinline__ FaceDesc<T> face_desc(const Tab& tb, const StageArgs<T>& a, int f,
                                                  bool xin) {
   const int axis = f >> 1, side = f & 1;
@@ -342,9 +370,11 @@ __device__ __forceinline__ FaceDesc<T> face_desc(const Tab& tb, const StageArgs<
   const int sa = sx[axis], st0 = sx[axis == 0 ? 1 : 0], st1 = sx[axis == 2 ? 1 : 2];
   const int slot = tb.meta[0];
   const int64_t org = ((int64_t)L.ng * L.P + L.ng) * L.P + L.ng;  // local (0,0,0)
+  const int r = (axis == 0 ? 2 * side : 1) + 3 * (axis == 1 ? 2 * side : 1) +
+                9 * (axis == 2 ? 2 * side : 1);
   FaceDesc<T> fd;
   fd.mode = 0;
-  if (GHOSTS) {
+  if (HALO == HALO_OWN || (HALO == HALO_MIX && tb.kind[r] != 0)) {
     fd.ptr = a.in + (int64_t)slot * L.bstride + org + (int64_t)(side ? BS : -1) * sa;
     fd.fs = (int)L.fstride;
     fd.sd = side ? sa : -sa;
@@ -352,8 +382,6 @@ __device__ __forceinline__ FaceDesc<T> face_desc(const Tab& tb, const StageArgs<
     fd.s1 = st1;
     return fd;
   }
-  const int r = (axis == 0 ? 2 * side : 1) + 3 * (axis == 1 ? 2 * side : 1) +
-                9 * (axis == 2 ? 2 * side : 1);
   if (tb.kind[r] == 0 && xin) {
     const T* nb = a.in + (int64_t)tb.slot[r][0] * L.bstride;
     fd.fs = (int)L.fstride;
@@ -423,8 +451,9 @@ __device__ __forceinline__ void ntstore(T v, T* p, int nt) {
 // CU for the penalized FP64 variant at the cost of a few spills (measured
 // faster than one workgroup per CU without spills).
 // MODEX = MODE (0 rhs only, 1..4 RK stage) or 10 + MODE: the RK stage with
-// every register in the padded pool layout and the input's halos read from
-// its own synchronised ghost layers (the lifted-wavelet step).
+// every register in the padded pool layout, same-level halos read from the
+// neighbours' interiors and the others from the input's own synchronised
+// ghost layers (the lifted-wavelet step).
 template <typename T, int BS, int TY, int MODEX, bool PEN, bool PREF>
 __global__ __launch_bounds__(BS* TY) __attribute__((amdgpu_waves_per_eu(TY == BS ? (BS == 16 ? 2 : 1) : (sizeof(T) == 8 ? 2 : 3))))
 void stage_kernel(StageArgs<T> a) {
@@ -433,7 +462,7 @@ void stage_kernel(StageArgs<T> a) {
   static_assert(NH <= NT || TY == BS, "halo points per plane exceed the threads");
   constexpr int MODE = MODEX % 10;
   constexpr bool OWNG = MODEX >= 10;
-  constexpr bool GH = MODE == 0 || OWNG;
+  constexpr int HALO = OWNG ? HALO_MIX : (MODE == 0 ? HALO_OWN : HALO_NB);
   // the stage registers between stages are x-split; U^n is the pool or, from
   // the second step of a multi-step call on, an x-split register too
   const bool xin = !OWNG && (MODE >= 2 || (MODE == 1 && a.Lin.xs != 0));
@@ -514,7 +543,7 @@ void stage_kernel(StageArgs<T> a) {
     const int64_t ibk = a.blist ? a.blist[boff + il] : il;
     const int y0 = (int)(item - il * NTY) * TY;
     const int y = y0 + yl;
-    if (tid < 6) fds[tid] = face_desc<T, BS, GH>(a.tab[ibk], a, tid, xin);
+    if (tid < 6) fds[tid] = face_desc<T, BS, HALO>(a.tab[ibk], a, tid, xin);
     if (tid < 5) meta[tid] = a.tab[ibk].meta[tid];
     lds_barrier();
     if (dyn && tid == 0) qpend = atomicAdd(a.queue + qh * QSTRIDE, 1);
@@ -1746,18 +1775,18 @@ hipError_t launch_sync_lattice(const wacm_grid* g, void* U, hipStream_t st) {
                                 : sync_lattice_t(g, (float*)U, st);
 }
 
-// The CDF 4/0 phase of a lifted stage's sync: every block's face star (what
-// the stage reads) and the whole ghost regions of its mask (what the
-// face-star lifted values read from its padded array); regions in a coarser
-// leaf by the region kernel.
+// The CDF 4/0 phase of a lifted stage's sync: the read boxes (what the
+// face-star lifted values read from a block's padded array) and every region
+// in a coarser leaf (whole, by the region kernel); the stage reads same-level
+// halos in place and the lifted phase writes the finer ones.
 template <typename T>
-static hipError_t sync_lifted_stage_t(const wacm_grid* g, T* U, const int32_t* mask,
+static hipError_t sync_lifted_stage_t(const wacm_grid* g, T* U, const int32_t* box,
                                       hipStream_t st) {
   if (g->nb == 0) return hipSuccess;
-  if (g->d.ng > SC_MAXG || !mask) return sync_t(g, U, 0, st);
+  if (g->d.ng > SC_MAXG || !box) return sync_t(g, U, 0, st);
   const bool split = g->n_cregion > 0;
   sync_kernel<T><<<grid_for(g->nb, 8), NT_GEN, 0, st>>>(g->d_tab, g->nb, U, pool_layout(g),
-                                                        g->d.bs, 0, split ? 1 : 0, mask);
+                                                        g->d.bs, 0, split ? 1 : 0, box);
   if (split) {
     switch (g->d.bs) {
       case 16:
@@ -1776,10 +1805,10 @@ static hipError_t sync_lifted_stage_t(const wacm_grid* g, T* U, const int32_t* m
   return hipGetLastError();
 }
 
-hipError_t launch_sync_lifted_stage(const wacm_grid* g, void* U, const int32_t* mask,
+hipError_t launch_sync_lifted_stage(const wacm_grid* g, void* U, const int32_t* box,
                                     hipStream_t st) {
-  return g->d.dtype == WACM_F64 ? sync_lifted_stage_t(g, (double*)U, mask, st)
-                                : sync_lifted_stage_t(g, (float*)U, mask, st);
+  return g->d.dtype == WACM_F64 ? sync_lifted_stage_t(g, (double*)U, box, st)
+                                : sync_lifted_stage_t(g, (float*)U, box, st);
 }
 
 hipError_t launch_sync(const wacm_grid* g, void* U, int face_only, hipStream_t st) {
@@ -1881,11 +1910,12 @@ static StageArgs<T> base_args(const wacm_grid* g, const wacm_params* p) {
   return a;
 }
 
-// One RK stage s (1..4) of the fused kernel whose input carries its own
-// synchronised ghost layers: input, U^n, output and accumulator in the
-// padded pool layout, no face-halo buffer (the lifted-wavelet step, whose
-// stage inputs are synchronised in full before each stage).  Tiles of 8
-// rows; early epilogue loads for FP32.
+// One RK stage s (1..4) of the fused kernel for the lifted-wavelet step:
+// input, U^n and output in the padded pool layout, the accumulator compact
+// (bs^3 values per field, from the start of its padded-size register); same-level
+// halos from the neighbours' interiors, the halos of faces next to another
+// level from the input's own ghost layers (filled before each stage), no
+// face-halo buffer.  Tiles of 8 rows; early epilogue loads for FP32.
 template <typename T, int BS, int S>
 static hipError_t stage_owng_bs(const StageArgs<T>& a, int wg_per_cu, hipStream_t st) {
   constexpr bool PREF = sizeof(T) == 4;
@@ -1907,8 +1937,13 @@ static hipError_t stage_owng_t(const wacm_grid* g, const wacm_params* p, int s,
   a.Lun = L;
   a.out = out;
   a.Lout = L;
+  // the accumulator is never synchronised: compact, [c][z][y][x]
   a.acc = acc;
-  a.Lacc = L;
+  a.Lacc.P = g->d.bs;
+  a.Lacc.ng = 0;
+  a.Lacc.fstride = (int64_t)g->d.bs * g->d.bs * g->d.bs;
+  a.Lacc.bstride = 4 * a.Lacc.fstride;
+  a.Lacc.xs = 0;
   a.dus = dus;
   a.t_dev = t_dev;
   a.dt_dev = dt_dev;

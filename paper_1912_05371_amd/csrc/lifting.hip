@@ -241,11 +241,12 @@ static hipError_t rk4_lifted_t(const wacm_grid* g, const wacm_params* p, double*
   const LiftWork wp = lift_work(g);
   T* Ya = (T*)((char*)work + wp.y);  // Y2, then Y4
   T* Yb = (T*)((char*)work + wp.k);  // Y3
-  T* Wr = (T*)((char*)work + wp.a);  // W = (U^n + Y2)/3 + dt/3 k2
+  T* Wr = (T*)((char*)work + wp.a);  // W = (U^n + Y2)/3 + dt/3 k2, compact layout
   hipError_t e;
-  // each stage input synchronised in full (CDF 4/0 fill, then the lifted
-  // phase), then the fused stage reading its ghost layers; t and dt stay on
-  // the device
+  // per stage: the CDF 4/0 fill of the input's ghosts that the stage and the
+  // face-star lifted values read, the lifted values of the face star, then
+  // the fused stage (same-level halos in place, the others from the ghost
+  // layers); t and dt stay on the device
   auto stage = [&](int s, T* in, T* out) {
     hipError_t r = launch_sync_lifted_stage(g, in, g->d_lift_mask, st);
     if (r == hipSuccess) r = launch_lift_sync_face(g, in, st);

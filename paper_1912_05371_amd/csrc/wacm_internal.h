@@ -152,8 +152,15 @@ WsParts ws_parts(int64_t capacity);
 // (at most 56 of 12 int32 per block) and their staging values (at most the
 // whole ghost shell, 4 fields per point)
 constexpr int LIFT_ITEMS_PER_BLOCK = 56;
+// Read boxes of the lifted step's ghost fill, LIFT_BOX_WORDS int32 per active
+// block: word r (r != 13) the box of ghost region r (region index rx + 3 ry +
+// 9 rz, 0 below, 1 inside, 2 above the block on each axis) that the
+// face-star lifted values read, as offsets from the region's first point
+// (bits 10d..10d+4 the lowest, 10d+5..10d+9 the highest along axis d); word
+// 13 the bit set of the regions that have a box.
+constexpr int LIFT_BOX_WORDS = 27;
 size_t lift_list_bytes(int64_t capacity);   // the items alone
-size_t lift_items_bytes(int64_t capacity);  // the items and the region masks
+size_t lift_items_bytes(int64_t capacity);  // the items and the read boxes
 size_t lift_ws_bytes(int64_t capacity, int bs, int ng, size_t es);
 
 }  // namespace wacm
@@ -195,8 +202,7 @@ struct wacm_grid {
   int32_t* d_lift = nullptr;
   int64_t n_lift = 0;
   int64_t n_lift_face = 0;  // the first items: the lifted points of the face star
-  // per active block, the ghost regions (bit r of 27) a face-star lifted
-  // value reads from its padded array
+  // per active block, the read boxes of its ghost regions (LIFT_BOX_WORDS)
   int32_t* d_lift_mask = nullptr;
   size_t lift_items_cap = 0;
   void* d_lift_tmp = nullptr;
@@ -252,15 +258,18 @@ hipError_t launch_filter(const wacm_grid* g, void* U, int level, hipStream_t st)
 // CDF 4/4 (lifting.hip): the lifted ghost phase after the CDF 4/0 fill, and
 // the parents of a merge list of n families (already in d_list)
 hipError_t launch_lift_sync(const wacm_grid* g, void* U, hipStream_t st);
-// the CDF 4/0 fill a lifted stage needs: every block's face star, and the
-// whole ghost regions in mask[b] (those the face-star lifted values read)
-hipError_t launch_sync_lifted_stage(const wacm_grid* g, void* U, const int32_t* mask,
+// the CDF 4/0 fill a lifted stage needs: the regions in a coarser leaf and
+// the read boxes `box` (LIFT_BOX_WORDS per block: what the face-star lifted
+// values read)
+hipError_t launch_sync_lifted_stage(const wacm_grid* g, void* U, const int32_t* box,
                                     hipStream_t st);
 // the lifted phase of the face star only (the points a stage reads)
 hipError_t launch_lift_sync_face(const wacm_grid* g, void* U, hipStream_t st);
 hipError_t launch_lift_coarsen(const wacm_grid* g, void* U, int64_t nparents, hipStream_t st);
-// RK4 with CDF 4/4 ghosts: every stage input synchronised in full, the rhs
-// from its own ghost layers; work = 3 padded registers (lift_work_bytes)
+// RK4 with CDF 4/4 ghosts: before each stage the ghosts it and the lifted
+// values read are filled, then the fused stage reads same-level halos in
+// place and the others from the input's ghost layers; work = 3 padded
+// registers (lift_work_bytes)
 hipError_t launch_rk4_lifted(const wacm_grid* g, const wacm_params* p, double* t_dev,
                              double* dt_dev, void* U, void* work, const void* dus, int dt_mode,
                              int64_t nsteps, hipStream_t st);

@@ -27,13 +27,17 @@ static int g_cap = 0;
 namespace wacm {
 int lift_items(const wacm_grid* g, const std::vector<Tab>& tabs, std::vector<int32_t>& it,
                int64_t& pts, int64_t& n_face, std::string& err);
+int lift_read_boxes(const wacm_grid* g, const std::vector<Tab>& tabs,
+                    const std::vector<int32_t>& it, int64_t n_face, std::vector<int32_t>& box,
+                    std::string& err);
 }
 
 // The CDF 4/4 lifted ghost-phase items: every ghost point whose owner is finer
 // is the output of exactly one item, no other point is, every output is
 // centred on the point the resolver gives for that ghost point (the finer
-// owner's coincident fine point), and every 13-point stencil stays inside the
-// source's padded array.
+// owner's coincident fine point), every 13-point stencil stays inside the
+// source's padded array, and the ghost points the face-star stencils read
+// lie in the read boxes the lifted step fills.
 static int check_lift(const wacm_grid& g, const std::vector<wacm::Tab>& tabs) {
   using namespace wacm;
   const int bs = g.d.bs, ng = g.d.ng, P = g.P;
@@ -99,8 +103,48 @@ static int check_lift(const wacm_grid& g, const std::vector<wacm::Tab>& tabs) {
                             k >= -3 && k < bs + 3;
           if (star != (covered_face.count({tabs[ib].meta[0], i, j, k}) > 0)) return 20;
         }
-  std::printf("lift items %zu (face star %lld), points %lld\n", it.size() / 12,
-              (long long)n_face, (long long)pts);
+  // the read boxes of the lifted step's ghost fill: each inside its region,
+  // and every ghost point of a finer leaf's padded array that a face-star
+  // stencil reads inside the box of its region
+  std::vector<int32_t> box;
+  if (lift_read_boxes(&g, tabs, it, n_face, box, err)) {
+    std::fprintf(stderr, "read boxes: %s\n", err.c_str());
+    return 21;
+  }
+  if (box.size() != tabs.size() * LIFT_BOX_WORDS) return 21;
+  auto rstart = [&](int q) { return q < 0 ? -ng : (q < bs ? 0 : bs); };
+  for (size_t ib = 0; ib < tabs.size(); ++ib)
+    for (int r = 0; r < 27; ++r) {
+      if (r == 13 || !((box[ib * LIFT_BOX_WORDS + 13] >> r) & 1)) continue;
+      const int rr[3] = {r % 3, (r / 3) % 3, r / 9};
+      for (int d = 0; d < 3; ++d) {
+        const int lo = (box[ib * LIFT_BOX_WORDS + r] >> (10 * d)) & 31;
+        const int hi = (box[ib * LIFT_BOX_WORDS + r] >> (10 * d + 5)) & 31;
+        if (lo > hi || hi >= (rr[d] == 1 ? bs : ng)) return 22;
+      }
+    }
+  int64_t nread = 0;
+  for (int64_t w = 0; w < n_face; ++w) {
+    const int32_t* e = &it[12 * w];
+    const int fb = tab_of[e[7]];
+    if (fb < 0) return 23;
+    const int32_t* bx = &box[(size_t)fb * LIFT_BOX_WORDS];
+    for (int k = e[10] - 6; k <= e[10] + 2 * (e[6] - 1) + 6; ++k)
+      for (int j = e[9] - 6; j <= e[9] + 2 * (e[5] - 1) + 6; ++j)
+        for (int i = e[8] - 6; i <= e[8] + 2 * (e[4] - 1) + 6; ++i) {
+          const int r = region_of(i, bs) + 3 * region_of(j, bs) + 9 * region_of(k, bs);
+          if (r == 13) continue;
+          ++nread;
+          if (!((bx[13] >> r) & 1)) return 24;
+          const int q[3] = {i, j, k};
+          for (int d = 0; d < 3; ++d) {
+            const int o = q[d] - rstart(q[d]);
+            if (o < ((bx[r] >> (10 * d)) & 31) || o > ((bx[r] >> (10 * d + 5)) & 31)) return 24;
+          }
+        }
+  }
+  std::printf("lift items %zu (face star %lld), points %lld, ghost reads %lld\n", it.size() / 12,
+              (long long)n_face, (long long)pts, (long long)nread);
   return 0;
 }
 

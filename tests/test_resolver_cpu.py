@@ -98,7 +98,9 @@ def test_unbalanced_tables_rejected(orc, harness, tmp_path):
 def test_lift_items_match_resolver(harness, tmp_path, bs):
     """CDF 4/4 lifted ghost items (host side): exactly the ghost points whose
     owner is finer, each centred on the resolver's coincident fine point, with
-    every stencil inside the source's 6 ghost layers."""
+    every stencil inside the source's 6 ghost layers; the read boxes of the
+    lifted step's ghost fill hold every ghost point a face-star stencil
+    reads."""
     for seed in range(2):
         lev, ix, iy, iz = inputs.random_balanced_leaves(70 + seed, 1, 4, 150)
         lf = tmp_path / "leaves.txt"
