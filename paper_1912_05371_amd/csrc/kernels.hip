@@ -754,6 +754,14 @@ void stage_kernel(StageArgs<T> a) {
           if (MODE == 2) ntstore((u0 + val[c]) * T(1.0 / 3.0) + fA * r[c], accb + c * afs + z * azs, a.nt);
           outb[c * ofs + z * ozs] = u0 + fB * r[c];
         }
+        // a padded output's rows are written whole as in stage 4 (the next
+        // stage's fill rewrites every ghost point that is read)
+        const int gx = a.Lout.ng;
+        if (OWNG && (x < gx || x >= BS - gx)) {
+          const int off = x < gx ? -gx : gx;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) outb[c * ofs + z * ozs + off] = T(0);
+        }
       }
       if (z + 1 < BS) {
         // plane z+1 into the other slab: it was last read before this
