@@ -32,8 +32,8 @@ constexpr double LIFT_TAP[13] = {-1.0 / 512,  0.0,         18.0 / 512,  -16.0 / 
 // fresh).  Each output is a z-march over the 13 fine planes around it: for
 // every fine plane an x pass on the fine rows into LDS, a y pass per output
 // column into a register ring of the last 13 planes, and the z pass once the
-// ring holds an output's 13 planes; the 4 fields go through each plane
-// together.
+// ring holds an output's 13 planes.  A workgroup takes NF of the 4 fields of
+// an item at a time (one work unit).
 //
 // mode 0: `items` holds 12 int32 per item (dst slot, i0, j0, k0, nx, ny, nz,
 //         src slot, fx0, fy0, fz0, base); outputs to `out` at 4 * base.
@@ -41,18 +41,21 @@ constexpr double LIFT_TAP[13] = {-1.0 / 512,  0.0,         18.0 / 512,  -16.0 / 
 //         child slots, unused); item w is octant w % 8 of parent w / 8, a box
 //         of (bs/2)^3 outputs at the octant's offset, centred on the child's
 //         even points from (0, 0, 0); outputs into U at the parent.
-template <typename T, int BS>
+template <typename T, int BS, int NF>
 __global__ __launch_bounds__(NT_GEN) void lift_box_kernel(const int32_t* __restrict__ items,
                                                           int64_t n, const T* U, Layout L,
                                                           T* out, int mode) {
   constexpr int NM = BS / 2;           // largest box edge
   constexpr int NROW = 2 * NM + 11;    // fine rows a box needs
-  __shared__ T xq[4][NROW * NM];       // x pass of the current fine plane, 4 fields
+  constexpr int NU = 4 / NF;           // work units per item
+  __shared__ T xq[NF][NROW * NM];      // x pass of the current fine plane
   const int tid = threadIdx.x;
   T h[13];
 #pragma unroll
   for (int q = 0; q < 13; ++q) h[q] = T(LIFT_TAP[q]);
-  for (int64_t w = blockIdx.x; w < n; w += gridDim.x) {
+  for (int64_t u = blockIdx.x; u < n * NU; u += gridDim.x) {
+    const int64_t w = u / NU;
+    const int c0 = (int)(u - w * NU) * NF;  // first field of this unit
     int dslot, i0, j0, k0, nx, ny, nz, sslot, fx0, fy0, fz0;
     int64_t base = 0;
     if (mode == 0) {
@@ -69,19 +72,19 @@ __global__ __launch_bounds__(NT_GEN) void lift_box_kernel(const int32_t* __restr
       nx = ny = nz = NM;
       fx0 = fy0 = fz0 = 0;
     }
-    const T* src = U + (int64_t)sslot * L.bstride;
+    const T* src = U + (int64_t)sslot * L.bstride + c0 * L.fstride;
     const int nrow = 2 * ny + 11, nplane = 2 * nz + 11, nxp = nrow * nx;
     const bool own = tid < nx * ny;
     const int dx = own ? tid % nx : 0, dy = own ? tid / nx : 0;
-    T ring[4][13];
+    T ring[NF][13];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < NF; ++c)
 #pragma unroll
       for (int q = 0; q < 13; ++q) ring[c][q] = T(0);
     for (int zf = 0; zf < nplane; ++zf) {
       const int z = fz0 - 6 + zf;
       __syncthreads();  // xq is free again
-      for (int it = tid; it < 4 * nxp; it += NT_GEN) {
+      for (int it = tid; it < NF * nxp; it += NT_GEN) {
         const int c = it / nxp, rem = it - c * nxp;
         const int yf = rem / nx, ox = rem - yf * nx;
         const int y = fy0 - 6 + yf;
@@ -98,7 +101,7 @@ __global__ __launch_bounds__(NT_GEN) void lift_box_kernel(const int32_t* __restr
         const bool emit = zf >= 12 && ((zf - 12) & 1) == 0;
         const int k = (zf - 12) >> 1;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < NF; ++c) {
           T v = T(0);
 #pragma unroll
           for (int q = 0; q < 13; ++q)
@@ -111,10 +114,11 @@ __global__ __launch_bounds__(NT_GEN) void lift_box_kernel(const int32_t* __restr
 #pragma unroll
             for (int q = 0; q < 13; ++q)
               if (q != 1 && q != 11) o += h[q] * ring[c][q];
+            const int cf = c0 + c;
             if (mode == 0)
-              out[base + ((int64_t)(c * nz + k) * ny + dy) * nx + dx] = o;
+              out[base + ((int64_t)(cf * nz + k) * ny + dy) * nx + dx] = o;
             else
-              out[(int64_t)dslot * L.bstride + c * L.fstride +
+              out[(int64_t)dslot * L.bstride + cf * L.fstride +
                   ((int64_t)(k0 + k + L.ng) * L.P + (j0 + dy + L.ng)) * L.P + (i0 + dx + L.ng)] = o;
           }
         }
@@ -157,10 +161,14 @@ static unsigned lift_grid(int64_t n) {
   return (unsigned)(n < cap ? (n > 0 ? n : 1) : cap);
 }
 
+// two fields per work unit: measured a little faster than one or four (the
+// kernel is bound by its gathers, not by its occupancy)
 template <typename T, int BS>
 static hipError_t lift_box_t(const wacm_grid* g, const int32_t* items, int64_t n, T* U, T* out,
                              int mode, hipStream_t st) {
-  lift_box_kernel<T, BS><<<lift_grid(n), NT_GEN, 0, st>>>(items, n, U, lift_layout(g), out, mode);
+  constexpr int NF = 2;
+  lift_box_kernel<T, BS, NF><<<lift_grid(n * (4 / NF)), NT_GEN, 0, st>>>(items, n, U, lift_layout(g),
+                                                                        out, mode);
   return hipGetLastError();
 }
 
@@ -209,13 +217,14 @@ hipError_t launch_lift_coarsen(const wacm_grid* g, void* U, int64_t nparents, hi
 // --------------------------------------------------------------------------
 // Classical RK4 with CDF 4/4 ghosts.  The CDF 4/0 step reads same-level
 // halos in place and fills face halos next to other levels itself; with the
-// lifted restriction every stage input is instead synchronised (the CDF 4/0
-// fill of every face star and of the ghost regions the face-star lifted
-// values read from finer leaves' padded arrays; then the lifted phase of the
-// face star) and the fused stage kernel reads its halos from those ghost
-// layers: per stage a sync and one stage kernel, with
-// the CDF 4/0 step's register arrangement (Y2/Y4, Y3 and W) in the padded
-// pool layout in `work`.
+// lifted restriction each stage input's ghost layers are filled first (the
+// CDF 4/0 values of the regions in a coarser leaf and of the boxes the
+// face-star lifted values read from finer leaves' padded arrays; then the
+// lifted phase of the face star), and the fused stage kernel reads
+// same-level halos in place and the others from those ghost layers: per
+// stage a fill and one stage kernel, with the CDF 4/0 step's register
+// arrangement (Y2/Y4, Y3 and W) in `work`, Y2/Y4 and Y3 in the padded pool
+// layout, W compact.
 // --------------------------------------------------------------------------
 struct LiftWork {
   size_t y, k, a, total;
