@@ -664,8 +664,8 @@ def lifting_timings(seed: int):
     """CDF 4/4 (lifted restriction) on a random octree with 6 ghost layers
     (bs 24, levels 3-6, ~4000 blocks, FP64): the full ghost sync with CDF 4/0
     and with CDF 4/4 (the lifted phase on top), and one RK4 step with each
-    (CDF 4/4: per stage a full sync and the fused stage reading its ghost
-    layers)."""
+    (CDF 4/4: per stage the ghost fill of what the stage and the face-star
+    lifted values read, the lifted face star, and the fused stage)."""
     import torch
 
     from paper_1912_05371_amd import cases, inputs, wacm
