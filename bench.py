@@ -724,7 +724,7 @@ def mr_timings(seed: int, n: int = 256, nf: int = 4, nlev: int = 5):
     g.manual_seed(seed)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     pts = sum((n >> m) ** 3 for m in range(nlev)) * nf
-    out = {"n": n, "fields": nf, "levels": nlev, "dtype": "f64"}
+    out = {"n": n, "fields": nf, "levels": nlev, "dtypes": ["f64", "f32 (keys ending in _f32)"]}
     for tdt, es, suffix in ((torch.float64, 8, ""), (torch.float32, 4, "_f32")):
         u = torch.randn((nf, n, n, n), dtype=tdt, device="cuda", generator=g)
         work = wacm.mr_work(u)
