@@ -361,9 +361,10 @@ size_t lift_list_bytes(int64_t cap) {
   return up256(sizeof(int32_t) * 12 * LIFT_ITEMS_PER_BLOCK * (size_t)cap);
 }
 
-// the items, then the read boxes of every block (lift_read_boxes)
+// the items, then the read boxes of every block (lift_read_boxes) and the
+// table index of every pool slot
 size_t lift_items_bytes(int64_t cap) {
-  return lift_list_bytes(cap) + up256(sizeof(int32_t) * LIFT_BOX_WORDS * (size_t)cap);
+  return lift_list_bytes(cap) + up256(sizeof(int32_t) * (LIFT_BOX_WORDS + 1) * (size_t)cap);
 }
 
 // Per active block (table order), the part of each ghost region of its
@@ -470,10 +471,16 @@ int build_lift(wacm_grid* g, const std::vector<Tab>& tabs, std::string& err) {
     g->n_lift = -1;
     return rc;
   }
+  // table index of every pool slot (-1: inactive), after the boxes
+  std::vector<int32_t> slot_ib((size_t)g->d.capacity, -1);
+  for (size_t ib = 0; ib < tabs.size(); ++ib) slot_ib[tabs[ib].meta[0]] = (int32_t)ib;
   hipError_t e = hipSuccess;
   if (ibytes > 0) e = hipMemcpy(g->d_lift, it.data(), ibytes, hipMemcpyHostToDevice);
   if (e == hipSuccess && g->d_lift_mask && !mask.empty())
     e = hipMemcpy(g->d_lift_mask, mask.data(), sizeof(int32_t) * mask.size(),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess && g->d_lift_mask)
+    e = hipMemcpy(lift_slot_tab(g), slot_ib.data(), sizeof(int32_t) * slot_ib.size(),
                   hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     // no usable items: the lifted phase refuses to run until a rebuild works

@@ -41,11 +41,12 @@ __device__ __forceinline__ T wave_min(T v) {
 // depth-3 face star (the points the rhs stencils read).  With skip_coarser,
 // points of regions that lie in a coarser leaf are left to
 // sync_coarser_kernel.  With `box` (the lifted step's read boxes,
-// LIFT_BOX_WORDS per block; mode 0): only the points inside a region's box,
-// and the face star of regions in a coarser leaf unless those are skipped;
-// the rest of the face star is read in place (same level) or overwritten by
-// the lifted phase (finer leaf).  A block without boxes visits its face star
-// alone, or nothing.
+// LIFT_BOX_WORDS per block; mode 0): only the points inside the boxes of
+// regions in a finer leaf (the lifted phase reads same-level ones from the
+// neighbours' interiors), and the face star of regions in a coarser leaf
+// unless those are skipped; the rest of the face star is read in place (same
+// level) or overwritten by the lifted phase (finer leaf).  A block without
+// such boxes visits its face star alone, or nothing.
 template <typename T>
 __global__ __launch_bounds__(NT_GEN) void sync_kernel(const Tab* __restrict__ tab, int64_t nb,
                                                       T* __restrict__ U, Layout L, int bs,
@@ -60,7 +61,10 @@ __global__ __launch_bounds__(NT_GEN) void sync_kernel(const Tab* __restrict__ ta
       sbox[threadIdx.x] = box[ib * LIFT_BOX_WORDS + threadIdx.x];
     __syncthreads();
     T* dst = U + (int64_t)st.meta[0] * L.bstride;
-    const int32_t have = box ? sbox[13] : 0;
+    int32_t have = 0;  // boxes of regions in a finer leaf (uniform)
+    if (box)
+      for (int r = 0; r < 27; ++r)
+        if (r != 13 && st.kind[r] > 0) have |= sbox[13] & (int32_t(1) << r);
     if (box && have == 0 && skip_coarser) continue;
     const int md = box && have == 0 ? 1 : mode;
     const int npts = md == 1 ? 18 * bs * bs : L.P * L.P * L.P - bs * bs * bs;
@@ -1783,10 +1787,11 @@ hipError_t launch_sync_lattice(const wacm_grid* g, void* U, hipStream_t st) {
                                 : sync_lattice_t(g, (float*)U, st);
 }
 
-// The CDF 4/0 phase of a lifted stage's sync: the read boxes (what the
-// face-star lifted values read from a block's padded array) and every region
-// in a coarser leaf (whole, by the region kernel); the stage reads same-level
-// halos in place and the lifted phase writes the finer ones.
+// The CDF 4/0 phase of a lifted stage's sync: the read boxes of regions in a
+// finer leaf (what the face-star lifted values read there from a block's
+// padded array) and every region in a coarser leaf (whole, by the region
+// kernel); the stage and the lifted values read same-level values in place,
+// and the lifted phase writes the finer face halos.
 template <typename T>
 static hipError_t sync_lifted_stage_t(const wacm_grid* g, T* U, const int32_t* box,
                                       hipStream_t st) {

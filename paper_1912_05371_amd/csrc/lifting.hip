@@ -44,12 +44,20 @@ constexpr double LIFT_TAP[13] = {-1.0 / 512,  0.0,         18.0 / 512,  -16.0 / 
 template <typename T, int BS, int NF>
 __global__ __launch_bounds__(NT_GEN) void lift_box_kernel(const int32_t* __restrict__ items,
                                                           int64_t n, const T* U, Layout L,
-                                                          T* out, int mode) {
+                                                          T* out, int mode,
+                                                          const Tab* __restrict__ tab,
+                                                          const int32_t* __restrict__ stab) {
   constexpr int NM = BS / 2;           // largest box edge
   constexpr int NROW = 2 * NM + 11;    // fine rows a box needs
   constexpr int NU = 4 / NF;           // work units per item
   __shared__ T xq[NF][NROW * NM];      // x pass of the current fine plane
+  __shared__ Tab ft;                   // the finer leaf's table (in-place reads)
+  __shared__ int64_t rowo[3][NROW];    // per fine row of the plane: offsets of x = 0
   const int tid = threadIdx.x;
+  // mode 0 with `tab`: values of the finer leaf's ghost regions whose level-J
+  // box is a leaf are read from that leaf's interior (the same values its
+  // ghost fill would copy there); the other ghost regions from its array
+  const bool inplace = mode == 0 && tab != nullptr;
   T h[13];
 #pragma unroll
   for (int q = 0; q < 13; ++q) h[q] = T(LIFT_TAP[q]);
@@ -72,7 +80,14 @@ __global__ __launch_bounds__(NT_GEN) void lift_box_kernel(const int32_t* __restr
       nx = ny = nz = NM;
       fx0 = fy0 = fz0 = 0;
     }
-    const T* src = U + (int64_t)sslot * L.bstride + c0 * L.fstride;
+    const T* src = U + c0 * L.fstride;
+    if (inplace) {
+      __syncthreads();  // ft is free again
+      const int32_t* ts = reinterpret_cast<const int32_t*>(tab + stab[sslot]);
+      int32_t* td = reinterpret_cast<int32_t*>(&ft);
+      for (int q = tid; q < (int)(sizeof(Tab) / 4); q += NT_GEN) td[q] = ts[q];
+      __syncthreads();
+    }
     const int nrow = 2 * ny + 11, nplane = 2 * nz + 11, nxp = nrow * nx;
     const bool own = tid < nx * ny;
     const int dx = own ? tid % nx : 0, dy = own ? tid / nx : 0;
@@ -83,17 +98,40 @@ __global__ __launch_bounds__(NT_GEN) void lift_box_kernel(const int32_t* __restr
       for (int q = 0; q < 13; ++q) ring[c][q] = T(0);
     for (int zf = 0; zf < nplane; ++zf) {
       const int z = fz0 - 6 + zf;
-      __syncthreads();  // xq is free again
+      // element offsets of each fine row's point x = 0 for x < 0, 0 <= x < bs
+      // and x >= bs (the three regions along x); the last plane's x pass,
+      // which read them, ended before its second barrier
+      if (tid < 3 * nrow) {
+        const int rx = tid / nrow, yf = tid - rx * nrow;
+        const int y = fy0 - 6 + yf;
+        int64_t o = (int64_t)sslot * L.bstride + ((int64_t)(z + L.ng) * L.P + (y + L.ng)) * L.P + L.ng;
+        if (inplace) {
+          const int ry = y < 0 ? 0 : (y < BS ? 1 : 2), rz = z < 0 ? 0 : (z < BS ? 1 : 2);
+          const int r = rx + 3 * ry + 9 * rz;
+          if (r != 13 && ft.kind[r] == 0) {
+            const int sy = ry == 0 ? BS : (ry == 2 ? -BS : 0);
+            const int sz = rz == 0 ? BS : (rz == 2 ? -BS : 0);
+            o = (int64_t)ft.slot[r][0] * L.bstride +
+                ((int64_t)(z + sz + L.ng) * L.P + (y + sy + L.ng)) * L.P + L.ng +
+                (rx == 0 ? BS : (rx == 2 ? -BS : 0));
+          }
+        }
+        rowo[rx][yf] = o;
+      }
+      __syncthreads();  // xq is free again, rowo is written
       for (int it = tid; it < NF * nxp; it += NT_GEN) {
         const int c = it / nxp, rem = it - c * nxp;
         const int yf = rem / nx, ox = rem - yf * nx;
-        const int y = fy0 - 6 + yf;
-        const T* row = src + c * L.fstride + ((int64_t)(z + L.ng) * L.P + (y + L.ng)) * L.P +
-                       (fx0 + 2 * ox - 6 + L.ng);
+        const T* sc = src + c * L.fstride;
+        const int64_t r0 = rowo[0][yf], r1 = rowo[1][yf], r2 = rowo[2][yf];
+        const int x0 = fx0 + 2 * ox - 6;
         T v = T(0);
 #pragma unroll
         for (int q = 0; q < 13; ++q)
-          if (q != 1 && q != 11) v += h[q] * row[q];
+          if (q != 1 && q != 11) {
+            const int x = x0 + q;
+            v += h[q] * sc[(x < 0 ? r0 : (x < BS ? r1 : r2)) + x];
+          }
         xq[c][yf * NM + ox] = v;
       }
       __syncthreads();
@@ -165,53 +203,56 @@ static unsigned lift_grid(int64_t n) {
 // kernel is bound by its gathers, not by its occupancy)
 template <typename T, int BS>
 static hipError_t lift_box_t(const wacm_grid* g, const int32_t* items, int64_t n, T* U, T* out,
-                             int mode, hipStream_t st) {
+                             int mode, bool inplace, hipStream_t st) {
   constexpr int NF = 2;
-  lift_box_kernel<T, BS, NF><<<lift_grid(n * (4 / NF)), NT_GEN, 0, st>>>(items, n, U, lift_layout(g),
-                                                                        out, mode);
+  lift_box_kernel<T, BS, NF><<<lift_grid(n * (4 / NF)), NT_GEN, 0, st>>>(
+      items, n, U, lift_layout(g), out, mode, inplace ? g->d_tab : nullptr,
+      inplace ? lift_slot_tab(g) : nullptr);
   return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t lift_box(const wacm_grid* g, const int32_t* items, int64_t n, T* U, T* out,
-                           int mode, hipStream_t st) {
+                           int mode, bool inplace, hipStream_t st) {
   switch (g->d.bs) {
     case 24:
-      return lift_box_t<T, 24>(g, items, n, U, out, mode, st);
+      return lift_box_t<T, 24>(g, items, n, U, out, mode, inplace, st);
     case 32:
-      return lift_box_t<T, 32>(g, items, n, U, out, mode, st);
+      return lift_box_t<T, 32>(g, items, n, U, out, mode, inplace, st);
     default:
       return hipErrorInvalidValue;  // CDF 4/4 needs ng >= 6, hence bs >= 18
   }
 }
 
-// the first n items of the list (all of them, or the face star's)
+// the first n items of the list (all of them, or the face star's); inplace:
+// same-level values read from the neighbours' interiors
 template <typename T>
-static hipError_t lift_sync_t(const wacm_grid* g, T* U, int64_t n, hipStream_t st) {
+static hipError_t lift_sync_t(const wacm_grid* g, T* U, int64_t n, bool inplace, hipStream_t st) {
   if (g->n_lift < 0) return hipErrorOutOfMemory;  // the last item build failed
   if (n == 0) return hipSuccess;
+  if (inplace && !lift_slot_tab(g)) return hipErrorInvalidValue;
   T* tmp = (T*)g->d_lift_tmp;
-  hipError_t e = lift_box<T>(g, g->d_lift, n, U, tmp, 0, st);
+  hipError_t e = lift_box<T>(g, g->d_lift, n, U, tmp, 0, inplace, st);
   if (e != hipSuccess) return e;
   lift_scatter_kernel<T><<<lift_grid(n), NT_GEN, 0, st>>>(g->d_lift, n, tmp, U, lift_layout(g));
   return hipGetLastError();
 }
 
 hipError_t launch_lift_sync(const wacm_grid* g, void* U, hipStream_t st) {
-  return g->d.dtype == WACM_F64 ? lift_sync_t(g, (double*)U, g->n_lift, st)
-                                : lift_sync_t(g, (float*)U, g->n_lift, st);
+  return g->d.dtype == WACM_F64 ? lift_sync_t(g, (double*)U, g->n_lift, false, st)
+                                : lift_sync_t(g, (float*)U, g->n_lift, false, st);
 }
 
 hipError_t launch_lift_sync_face(const wacm_grid* g, void* U, hipStream_t st) {
-  return g->d.dtype == WACM_F64 ? lift_sync_t(g, (double*)U, g->n_lift_face, st)
-                                : lift_sync_t(g, (float*)U, g->n_lift_face, st);
+  return g->d.dtype == WACM_F64 ? lift_sync_t(g, (double*)U, g->n_lift_face, true, st)
+                                : lift_sync_t(g, (float*)U, g->n_lift_face, true, st);
 }
 
 hipError_t launch_lift_coarsen(const wacm_grid* g, void* U, int64_t nparents, hipStream_t st) {
   if (nparents == 0) return hipSuccess;
   return g->d.dtype == WACM_F64
-             ? lift_box<double>(g, g->d_list, 8 * nparents, (double*)U, (double*)U, 1, st)
-             : lift_box<float>(g, g->d_list, 8 * nparents, (float*)U, (float*)U, 1, st);
+             ? lift_box<double>(g, g->d_list, 8 * nparents, (double*)U, (double*)U, 1, false, st)
+             : lift_box<float>(g, g->d_list, 8 * nparents, (float*)U, (float*)U, 1, false, st);
 }
 
 // --------------------------------------------------------------------------

@@ -160,7 +160,7 @@ constexpr int LIFT_ITEMS_PER_BLOCK = 56;
 // 13 the bit set of the regions that have a box.
 constexpr int LIFT_BOX_WORDS = 27;
 size_t lift_list_bytes(int64_t capacity);   // the items alone
-size_t lift_items_bytes(int64_t capacity);  // the items and the read boxes
+size_t lift_items_bytes(int64_t capacity);  // the items, read boxes, slot map
 size_t lift_ws_bytes(int64_t capacity, int bs, int ng, size_t es);
 
 }  // namespace wacm
@@ -202,12 +202,20 @@ struct wacm_grid {
   int32_t* d_lift = nullptr;
   int64_t n_lift = 0;
   int64_t n_lift_face = 0;  // the first items: the lifted points of the face star
-  // per active block, the read boxes of its ghost regions (LIFT_BOX_WORDS)
+  // per active block, the read boxes of its ghost regions (LIFT_BOX_WORDS),
+  // then per pool slot its table index (lift_slot_tab)
   int32_t* d_lift_mask = nullptr;
   size_t lift_items_cap = 0;
   void* d_lift_tmp = nullptr;
   size_t lift_tmp_cap = 0;
 };
+
+namespace wacm {
+// the table index of every pool slot (-1: inactive), kept after the read boxes
+inline int32_t* lift_slot_tab(const wacm_grid* g) {
+  return g->d_lift_mask ? g->d_lift_mask + (size_t)LIFT_BOX_WORDS * g->d.capacity : nullptr;
+}
+}  // namespace wacm
 
 namespace wacm {
 
