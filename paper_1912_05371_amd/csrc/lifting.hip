@@ -41,7 +41,7 @@ constexpr double LIFT_TAP[13] = {-1.0 / 512,  0.0,         18.0 / 512,  -16.0 / 
 //         child slots, unused); item w is octant w % 8 of parent w / 8, a box
 //         of (bs/2)^3 outputs at the octant's offset, centred on the child's
 //         even points from (0, 0, 0); outputs into U at the parent.
-template <typename T, int BS, int NF>
+template <typename T, int BS, int NF, bool INPLACE>
 __global__ __launch_bounds__(NT_GEN) void lift_box_kernel(const int32_t* __restrict__ items,
                                                           int64_t n, const T* U, Layout L,
                                                           T* out, int mode,
@@ -54,10 +54,10 @@ __global__ __launch_bounds__(NT_GEN) void lift_box_kernel(const int32_t* __restr
   __shared__ Tab ft;                   // the finer leaf's table (in-place reads)
   __shared__ int64_t rowo[3][NROW];    // per fine row of the plane: offsets of x = 0
   const int tid = threadIdx.x;
-  // mode 0 with `tab`: values of the finer leaf's ghost regions whose level-J
+  // INPLACE (mode 0): values of the finer leaf's ghost regions whose level-J
   // box is a leaf are read from that leaf's interior (the same values its
   // ghost fill would copy there); the other ghost regions from its array
-  const bool inplace = mode == 0 && tab != nullptr;
+  constexpr bool inplace = INPLACE;
   T h[13];
 #pragma unroll
   for (int q = 0; q < 13; ++q) h[q] = T(LIFT_TAP[q]);
@@ -101,20 +101,18 @@ __global__ __launch_bounds__(NT_GEN) void lift_box_kernel(const int32_t* __restr
       // element offsets of each fine row's point x = 0 for x < 0, 0 <= x < bs
       // and x >= bs (the three regions along x); the last plane's x pass,
       // which read them, ended before its second barrier
-      if (tid < 3 * nrow) {
+      if (inplace && tid < 3 * nrow) {
         const int rx = tid / nrow, yf = tid - rx * nrow;
         const int y = fy0 - 6 + yf;
         int64_t o = (int64_t)sslot * L.bstride + ((int64_t)(z + L.ng) * L.P + (y + L.ng)) * L.P + L.ng;
-        if (inplace) {
-          const int ry = y < 0 ? 0 : (y < BS ? 1 : 2), rz = z < 0 ? 0 : (z < BS ? 1 : 2);
-          const int r = rx + 3 * ry + 9 * rz;
-          if (r != 13 && ft.kind[r] == 0) {
-            const int sy = ry == 0 ? BS : (ry == 2 ? -BS : 0);
-            const int sz = rz == 0 ? BS : (rz == 2 ? -BS : 0);
-            o = (int64_t)ft.slot[r][0] * L.bstride +
-                ((int64_t)(z + sz + L.ng) * L.P + (y + sy + L.ng)) * L.P + L.ng +
-                (rx == 0 ? BS : (rx == 2 ? -BS : 0));
-          }
+        const int ry = y < 0 ? 0 : (y < BS ? 1 : 2), rz = z < 0 ? 0 : (z < BS ? 1 : 2);
+        const int r = rx + 3 * ry + 9 * rz;
+        if (r != 13 && ft.kind[r] == 0) {
+          const int sy = ry == 0 ? BS : (ry == 2 ? -BS : 0);
+          const int sz = rz == 0 ? BS : (rz == 2 ? -BS : 0);
+          o = (int64_t)ft.slot[r][0] * L.bstride +
+              ((int64_t)(z + sz + L.ng) * L.P + (y + sy + L.ng)) * L.P + L.ng +
+              (rx == 0 ? BS : (rx == 2 ? -BS : 0));
         }
         rowo[rx][yf] = o;
       }
@@ -123,15 +121,24 @@ __global__ __launch_bounds__(NT_GEN) void lift_box_kernel(const int32_t* __restr
         const int c = it / nxp, rem = it - c * nxp;
         const int yf = rem / nx, ox = rem - yf * nx;
         const T* sc = src + c * L.fstride;
-        const int64_t r0 = rowo[0][yf], r1 = rowo[1][yf], r2 = rowo[2][yf];
-        const int x0 = fx0 + 2 * ox - 6;
+        const int x0 = fx0 + 2 * ox - 6;  // the taps' window is x0..x0+12
         T v = T(0);
+        if constexpr (inplace) {
+          const int64_t r0 = rowo[0][yf], r1 = rowo[1][yf], r2 = rowo[2][yf];
 #pragma unroll
-        for (int q = 0; q < 13; ++q)
-          if (q != 1 && q != 11) {
-            const int x = x0 + q;
-            v += h[q] * sc[(x < 0 ? r0 : (x < BS ? r1 : r2)) + x];
-          }
+          for (int q = 0; q < 13; ++q)
+            if (q != 1 && q != 11) {
+              const int x = x0 + q;
+              v += h[q] * sc[(x < 0 ? r0 : (x < BS ? r1 : r2)) + x];
+            }
+        } else {
+          const int y = fy0 - 6 + yf;
+          const T* row = sc + (int64_t)sslot * L.bstride +
+                         ((int64_t)(z + L.ng) * L.P + (y + L.ng)) * L.P + L.ng + x0;
+#pragma unroll
+          for (int q = 0; q < 13; ++q)
+            if (q != 1 && q != 11) v += h[q] * row[q];
+        }
         xq[c][yf * NM + ox] = v;
       }
       __syncthreads();
@@ -205,9 +212,12 @@ template <typename T, int BS>
 static hipError_t lift_box_t(const wacm_grid* g, const int32_t* items, int64_t n, T* U, T* out,
                              int mode, bool inplace, hipStream_t st) {
   constexpr int NF = 2;
-  lift_box_kernel<T, BS, NF><<<lift_grid(n * (4 / NF)), NT_GEN, 0, st>>>(
-      items, n, U, lift_layout(g), out, mode, inplace ? g->d_tab : nullptr,
-      inplace ? lift_slot_tab(g) : nullptr);
+  if (inplace)
+    lift_box_kernel<T, BS, NF, true><<<lift_grid(n * (4 / NF)), NT_GEN, 0, st>>>(
+        items, n, U, lift_layout(g), out, mode, g->d_tab, lift_slot_tab(g));
+  else
+    lift_box_kernel<T, BS, NF, false><<<lift_grid(n * (4 / NF)), NT_GEN, 0, st>>>(
+        items, n, U, lift_layout(g), out, mode, nullptr, nullptr);
   return hipGetLastError();
 }
 

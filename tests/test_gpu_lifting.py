@@ -128,12 +128,13 @@ def test_cdf44_needs_six_ghost_layers_and_guards():
     g6.filter_blocks(pool, -1)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_cdf44_rk4_step_matches_oracle(orc, prec):
+@pytest.mark.parametrize("prec,bs", [("f64", 24), ("f32", 24), ("f64", 32)])
+def test_cdf44_rk4_step_matches_oracle(orc, prec, bs):
     """RK4 steps with the lifted ghosts: each step from the oracle's state with
     the oracle's CFL time step (per-step gate), then two free-running steps
     with the device's own CFL step against two oracle steps."""
-    c = octree24()
+    c = octree24() if bs == 24 else cases.random_octree(bs=32, ng=6, target=80, j0=1, jmax=3,
+                                                         seed=23)
     og, gg = build(orc, c, wacm.F64 if prec == "f64" else wacm.F32)
     U = c.padded()
     work = gg.work()
@@ -152,7 +153,7 @@ def test_cdf44_rk4_step_matches_oracle(orc, prec):
         worst = max(worst, e)
         t += dt
         assert abs(float(t_dev.item()) - t) <= 1e-15 * t
-    log(f"CDF 4/4 RK4 {prec}: worst per-step rel err {worst:.2e}")
+    log(f"CDF 4/4 RK4 {prec} bs {bs} ({c.nb} blocks): worst per-step rel err {worst:.2e}")
     assert worst < (1e-12 if prec == "f64" else 1e-5)
     if prec == "f64":
         # n steps in one call = n single calls, bitwise; CFL time step on the device
