@@ -1187,6 +1187,16 @@ __global__ __launch_bounds__(BS* BS) void detail_kernel(const Tab* __restrict__ 
   const bool oddij = ((i | j) & 1) != 0;
   for (int mm = 0; mm < S; ++mm) {
     const int kc = 2 * mm - 2;  // coarse plane
+    const int ko = kc - 3;      // odd fine plane whose prediction this plane completes
+    // this thread's points of the fine planes kc and ko, loaded before the
+    // x pass so that their latency overlaps it
+    T ue[4], uo[4];
+    const bool he = kc >= 0 && kc < BS, ho = ko >= 0 && ko < BS;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      ue[c] = he ? at(c, i, j, kc) : T(0);
+      uo[c] = ho ? at(c, i, j, ko) : T(0);
+    }
     // x pass on the coarse rows j' = 2 jj - 2 of plane kc; the buffer of
     // plane mm - 2 is free: every thread has passed plane mm - 1's barrier
     T(*xb)[S * BS] = xp[mm & 1];
@@ -1220,19 +1230,18 @@ __global__ __launch_bounds__(BS* BS) void detail_kernel(const Tab* __restrict__ 
     }
     // z pass: the even fine plane kc and the odd fine plane kc - 3 (taps
     // kc-6, kc-4, kc-2, kc = coarse planes mm-3 .. mm)
-    if (kc >= 0 && kc < BS) {
+    if (he) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const T u = at(c, i, j, kc);
+        const T u = ue[c];
         umc[c] = fmax(umc[c], fabs((double)u));
         if (oddij) dmc[c] = fmax(dmc[c], fabs((double)(u - y0[c])));
       }
     }
-    const int ko = kc - 3;
-    if (ko >= 0 && ko < BS) {
+    if (ho) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const T u = at(c, i, j, ko);
+        const T u = uo[c];
         const T pr = w0 * y3[c] + w1 * y2[c] + w1 * y1[c] + w0 * y0[c];
         umc[c] = fmax(umc[c], fabs((double)u));
         dmc[c] = fmax(dmc[c], fabs((double)(u - pr)));
