@@ -968,17 +968,19 @@ void nlface_kernel(const Tab* __restrict__ tab,
 // --------------------------------------------------------------------------
 // reductions (FP64 accumulation, fixed order -> deterministic)
 // --------------------------------------------------------------------------
-// per block: max over interior points of |u|^2 -> part[ib]
-template <typename T>
+// per block: max over interior points of |u|^2 -> part[ib]; the block edge
+// is a template constant, so that the index arithmetic needs no division
+template <typename T, int bs>
 __global__ __launch_bounds__(NT_GEN) void maxu_kernel(const Tab* __restrict__ tab, int64_t nb,
-                                                      const T* __restrict__ U, Layout L, int bs,
+                                                      const T* __restrict__ U, Layout L,
                                                       double* __restrict__ part) {
   __shared__ double red[NT_GEN / 64];
-  const int n3 = bs * bs * bs;
+  constexpr int n3 = bs * bs * bs;
   for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
     const T* b = U + (int64_t)tab[ib].meta[0] * L.bstride;
     double m = 0.0;
-    for (int q = threadIdx.x; q < n3; q += blockDim.x) {
+#pragma unroll 4
+    for (int q = threadIdx.x; q < n3; q += NT_GEN) {
       const int i = q % bs, j = (q / bs) % bs, k = q / (bs * bs);
       const int64_t o = ((int64_t)(k + L.ng) * L.P + (j + L.ng)) * L.P + (i + L.ng);
       const double u = b[o], v = b[o + L.fstride], w = b[o + 2 * L.fstride];
@@ -1026,21 +1028,21 @@ __global__ void advance_time(double* t, const double* dt) {
 // sum chi(u-us) x3 (times h^3/C_eta), sum |u|^2 (times h^3/2), number of
 // NaN or Inf values]; the maxima ignore NaN, the count sees it
 constexpr int NDIAG = 10;
-template <typename T>
+template <typename T, int bs>
 __global__ __launch_bounds__(NT_GEN) void diag_kernel(const Tab* __restrict__ tab, int64_t nb,
-                                                      const T* __restrict__ U, Layout L, int bs,
+                                                      const T* __restrict__ U, Layout L,
                                                       const T* __restrict__ dus, double Ldom,
                                                       wacm_params p, double t,
                                                       double* __restrict__ part) {
   __shared__ double red[NDIAG][NT_GEN];
-  const int n3 = bs * bs * bs;
+  constexpr int n3 = bs * bs * bs;
   for (int64_t ib = blockIdx.x; ib < nb; ib += gridDim.x) {
     const int32_t* m = tab[ib].meta;
     const int slot = m[0], J = m[1];
     const double h = Ldom / (double(int64_t(1) << J) * bs);
     const T* b = U + (int64_t)slot * L.bstride;
     double acc[NDIAG] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int q = threadIdx.x; q < n3; q += blockDim.x) {
+    for (int q = threadIdx.x; q < n3; q += NT_GEN) {
       const int i = q % bs, j = (q / bs) % bs, k = q / (bs * bs);
       const int64_t o = ((int64_t)(k + L.ng) * L.P + (j + L.ng)) * L.P + (i + L.ng);
       double u[4];
@@ -2022,8 +2024,20 @@ template <typename T>
 static hipError_t dt_t(const wacm_grid* g, const wacm_params* p, const T* U, double* dt_dev,
                        hipStream_t st) {
   if (g->nb == 0) return hipSuccess;
-  maxu_kernel<T><<<grid_for(g->nb, 8), NT_GEN, 0, st>>>(g->d_tab, g->nb, U, pool_layout(g),
-                                                        g->d.bs, g->d_part);
+  const unsigned grid = grid_for(g->nb, 8);
+  switch (g->d.bs) {
+    case 16:
+      maxu_kernel<T, 16><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, pool_layout(g), g->d_part);
+      break;
+    case 24:
+      maxu_kernel<T, 24><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, pool_layout(g), g->d_part);
+      break;
+    case 32:
+      maxu_kernel<T, 32><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, pool_layout(g), g->d_part);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   const double hmin = g->d.L / (double(int64_t(1) << g->jfine) * g->d.bs);
   dt_finalize<<<1, NT_GEN, 0, st>>>(g->d_part, g->nb, *p, hmin, dt_dev);
   return hipGetLastError();
@@ -2174,8 +2188,24 @@ template <typename T>
 static hipError_t diag_t(const wacm_grid* g, const wacm_params* p, double t, const T* U,
                          const T* dus, double* out, hipStream_t st) {
   if (g->nb == 0) return hipSuccess;
-  diag_kernel<T><<<grid_for(g->nb, 8), NT_GEN, 0, st>>>(g->d_tab, g->nb, U, pool_layout(g),
-                                                        g->d.bs, dus, g->d.L, *p, t, g->d_part);
+  const unsigned grid = grid_for(g->nb, 8);
+  const Layout L = pool_layout(g);
+  switch (g->d.bs) {
+    case 16:
+      diag_kernel<T, 16><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, L, dus, g->d.L, *p, t,
+                                                   g->d_part);
+      break;
+    case 24:
+      diag_kernel<T, 24><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, L, dus, g->d.L, *p, t,
+                                                   g->d_part);
+      break;
+    case 32:
+      diag_kernel<T, 32><<<grid, NT_GEN, 0, st>>>(g->d_tab, g->nb, U, L, dus, g->d.L, *p, t,
+                                                   g->d_part);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   diag_finalize<<<1, NT_GEN, 0, st>>>(g->d_part, g->nb, out);
   return hipGetLastError();
 }
