@@ -913,6 +913,9 @@ def main():
     ap.add_argument("--mr-only", action="store_true",
                     help="time only the multiresolution transform (256^3 x 4, 5 levels) and "
                          "print its figures")
+    ap.add_argument("--lifting-only", action="store_true",
+                    help="time only the CDF 4/0 and CDF 4/4 syncs and RK4 steps on the "
+                         "4012-block octree with 6 ghost layers and print them")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -935,6 +938,9 @@ def main():
         if args.copy_probe > 0:
             copy_probe(args.copy_probe)
         print(json.dumps({"mr_transform": mr_timings(args.seed)}), flush=True)
+        return
+    if args.lifting_only:
+        print(json.dumps({"cdf44": lifting_timings(args.seed)}), flush=True)
         return
     t0 = time.perf_counter()
     case = build_case(args.target, args.seed)
