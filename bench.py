@@ -940,6 +940,8 @@ def main():
         print(json.dumps({"mr_transform": mr_timings(args.seed)}), flush=True)
         return
     if args.lifting_only:
+        if args.copy_probe > 0:
+            copy_probe(args.copy_probe)
         print(json.dumps({"cdf44": lifting_timings(args.seed)}), flush=True)
         return
     t0 = time.perf_counter()
